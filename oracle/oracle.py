@@ -1,0 +1,279 @@
+"""ctypes front end of the FP64 CPU oracle (``sdmm_oracle.c``).
+
+TEST INFRASTRUCTURE: imported only by the tests, the package smoke check and the
+benchmark's CPU-baseline leg. It shares no code with the GPU library and does not import
+the product package. Arguments are numpy arrays; this module only marshals them.
+
+The arithmetic lives in ``sdmm_oracle.c``; see its header for the paper passages each
+function follows and the readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sdmm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD_PARAMS = (
+    1, 2, 4, 8, 16, 32)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, FP64 throughout."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Opts(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
+        ("estep_jacobian", C.c_int32), ("euclidean", C.c_int32), ("min_samples", C.c_int32),
+        ("reserved", C.c_int32),
+        ("eta", C.c_double), ("rm_alpha", C.c_double), ("rm_beta", C.c_double),
+        ("prior_scale", C.c_double), ("prior_q", C.c_double), ("prior_a", C.c_double),
+        ("prior_b", C.c_double * 5), ("dead_threshold", C.c_double),
+    ]
+
+
+@dataclass
+class Opts:
+    """Fit options. Defaults: the paper's prior constants q = 1/K, a = 5/K,
+    B = a diag(0.1, 0.1, 1, 1, 1) 1e-4 and Robbins-Monro alpha = 0.5, beta = 0.1 (Sec. 4.3)."""
+    K: int = 16
+    iters: int = 1
+    eta_mode: int = 0          # 0: constant eta after the first batch; 1: (rm_beta j + 1)^-rm_alpha
+    eta: float = 1.0
+    rm_alpha: float = 0.5
+    rm_beta: float = 0.1
+    prior_mode: int = 0        # 0: beta_j = eta_j / M_j; 1: beta_j = prior_scale
+    prior_scale: float = 0.0
+    prior_q: float | None = None
+    prior_a: float | None = None
+    prior_b: tuple | None = None
+    estep_jacobian: int = 0
+    euclidean: int = 0
+    min_samples: int = 16
+    dead_threshold: float = 1e-12
+
+    def to_c(self) -> _Opts:
+        q = 1.0 / self.K if self.prior_q is None else self.prior_q
+        a = 5.0 / self.K if self.prior_a is None else self.prior_a
+        b = tuple(a * v * 1e-4 for v in (0.1, 0.1, 1, 1, 1)) if self.prior_b is None else tuple(self.prior_b)
+        o = _Opts()
+        o.K, o.iters, o.eta_mode, o.prior_mode = self.K, self.iters, self.eta_mode, self.prior_mode
+        o.estep_jacobian, o.euclidean, o.min_samples = self.estep_jacobian, self.euclidean, self.min_samples
+        o.eta, o.rm_alpha, o.rm_beta, o.prior_scale = self.eta, self.rm_alpha, self.rm_beta, self.prior_scale
+        o.prior_q, o.prior_a = q, a
+        for i in range(5):
+            o.prior_b[i] = b[i]
+        o.dead_threshold = self.dead_threshold
+        return o
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        d, i32, i64, vp = C.c_double, C.c_int32, C.c_int64, C.c_void_p
+        P = C.POINTER
+        _lib.orc_frame.argtypes = [vp, vp]
+        _lib.orc_log_map.argtypes = [vp, vp, vp]
+        _lib.orc_exp_map.argtypes = [vp, vp, vp]
+        _lib.orc_transfer_jacobian.argtypes = [vp, vp, vp]
+        _lib.orc_eta.argtypes = [P(_Opts), i32]
+        _lib.orc_eta.restype = d
+        _lib.orc_cell_stats.argtypes = [P(_Opts), i32, vp, i64, i64, i64, vp, vp, vp, vp,
+                                        vp, vp, vp, vp, vp, vp]
+        _lib.orc_responsibilities.argtypes = [P(_Opts), i32, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_fit.argtypes = [P(_Opts), i32, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_objective.argtypes = [P(_Opts), i32, vp, i64, i64, i64, vp, vp, vp, vp, d]
+        _lib.orc_objective.restype = d
+        _lib.orc_grad.argtypes = [P(_Opts), i32, vp, i64, i64, i64, vp, vp, vp, vp, d, vp, vp, vp, vp]
+        _lib.orc_condition.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_pdf_conditioned.argtypes = [i32, vp, vp, vp, vp, vp]
+        _lib.orc_pdf_conditioned.restype = d
+        _lib.orc_pdf.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, i32, vp, vp]
+        _lib.orc_sample.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp]
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "arrays must be C-contiguous"
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --- maps -----------------------------------------------------------------
+
+def frame(mu):
+    mu = _f64(mu)
+    R = np.zeros(9)
+    lib().orc_frame(_p(mu), _p(R))
+    return R.reshape(3, 3)
+
+
+def log_map(mu, w):
+    R = _f64(frame(mu))
+    w = _f64(w)
+    nu = np.zeros(2)
+    lib().orc_log_map(_p(R), _p(w), _p(nu))
+    return nu
+
+
+def exp_map(mu, nu):
+    R = _f64(frame(mu))
+    nu = _f64(nu)
+    w = np.zeros(3)
+    lib().orc_exp_map(_p(R), _p(nu), _p(w))
+    return w
+
+
+def transfer_jacobian(mu, m):
+    mu, m = _f64(mu), _f64(m)
+    J = np.zeros(4)
+    lib().orc_transfer_jacobian(_p(mu), _p(m), _p(J))
+    return J.reshape(2, 2)
+
+
+def eta(opts: Opts, j: int) -> float:
+    o = opts.to_c()
+    return lib().orc_eta(C.byref(o), j)
+
+
+# --- mixtures -------------------------------------------------------------
+
+def new_state(n_cells: int, K: int) -> dict:
+    return {"s0": np.zeros(n_cells * K), "s2": np.zeros(n_cells * K * 15),
+            "sw": np.zeros(n_cells), "step": np.zeros(n_cells, dtype=np.int32)}
+
+
+def fit(opts: Opts, offsets, samples, mix: dict, state: dict) -> np.ndarray:
+    """``opts.iters`` E+M iterations on one batch; ``mix`` (pi, mu_dir, mu_pos, cov) and
+    ``state`` (s0, s2, sw, step) are updated in place. Returns per-cell status bits."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    n_cells = offsets.shape[0] - 1
+    status = np.zeros(n_cells, dtype=np.int32)
+    for key in ("pi", "mu_dir", "mu_pos", "cov"):
+        assert mix[key].dtype == np.float64 and mix[key].flags["C_CONTIGUOUS"]
+    o = opts.to_c()
+    rc = lib().orc_fit(C.byref(o), n_cells, _p(offsets), _p(samples), samples.shape[1],
+                       _p(mix["pi"]), _p(mix["mu_dir"]), _p(mix["mu_pos"]), _p(mix["cov"]),
+                       _p(state["s0"]), _p(state["s2"]), _p(state["sw"]), _p(state["step"]),
+                       _p(status))
+    if rc != 0:
+        raise ValueError("orc_fit failed (%d)" % rc)
+    return status
+
+
+def _cell_params(mix, c, K):
+    s = slice(c * K, (c + 1) * K)
+    return (_f64(mix["pi"][s]), _f64(mix["mu_dir"].reshape(-1, 3)[s]), _f64(mix["mu_pos"].reshape(-1, 3)[s]),
+            _f64(mix["cov"].reshape(-1, 15)[s]))
+
+
+def cell_stats(opts: Opts, samples, i0, i1, mix, cell=0):
+    """Unnormalised statistics of samples [i0, i1) about the cell's current parameters."""
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    K = opts.K
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    S0, S1, S2 = np.zeros(K), np.zeros(K * 5), np.zeros(K * 15)
+    W, LL = np.zeros(1), np.zeros(1)
+    M = np.zeros(1, dtype=np.int64)
+    o = opts.to_c()
+    st = lib().orc_cell_stats(C.byref(o), K, _p(samples), samples.shape[1], i0, i1, _p(pi), _p(mud),
+                              _p(mux), _p(cov), _p(S0), _p(S1), _p(S2), _p(W), _p(M), _p(LL))
+    return {"S0": S0, "S1": S1.reshape(K, 5), "S2": S2.reshape(K, 15), "W": W[0], "M": int(M[0]),
+            "LL": LL[0], "status": st}
+
+
+def responsibilities(opts: Opts, w, p, mix, cell=0):
+    K = opts.K
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    r = np.zeros(K)
+    o = opts.to_c()
+    lib().orc_responsibilities(C.byref(o), K, _p(_f64(w)), _p(_f64(p)), _p(pi), _p(mud), _p(mux),
+                               _p(cov), _p(r))
+    return r
+
+
+def objective(opts: Opts, samples, i0, i1, mix, beta, cell=0) -> float:
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    K = opts.K
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    o = opts.to_c()
+    return lib().orc_objective(C.byref(o), K, _p(samples), samples.shape[1], i0, i1, _p(pi), _p(mud),
+                               _p(mux), _p(cov), beta)
+
+
+def grad(opts: Opts, samples, i0, i1, mix, beta, cell=0) -> dict:
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    K = opts.K
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    ga, gx, gd, gL = np.zeros(K), np.zeros(3 * K), np.zeros(2 * K), np.zeros(15 * K)
+    o = opts.to_c()
+    st = lib().orc_grad(C.byref(o), K, _p(samples), samples.shape[1], i0, i1, _p(pi), _p(mud), _p(mux),
+                        _p(cov), beta, _p(ga), _p(gx), _p(gd), _p(gL))
+    if st:
+        raise ValueError("orc_grad status %d" % st)
+    return {"alpha": ga, "mu_pos": gx.reshape(K, 3), "delta": gd.reshape(K, 2), "L": gL.reshape(K, 15)}
+
+
+def condition(K, mix, cell, x):
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    pic, m, Sc = np.zeros(K), np.zeros(2 * K), np.zeros(3 * K)
+    rc = lib().orc_condition(K, _p(pi), _p(mux), _p(cov), _p(_f64(x)), _p(pic), _p(m), _p(Sc))
+    if rc:
+        raise ValueError("conditioning failed")
+    return pic, m.reshape(K, 2), Sc.reshape(K, 3)
+
+
+def pdf_conditioned(K, mud, pic, m, Sc, w) -> float:
+    return lib().orc_pdf_conditioned(K, _p(_f64(mud)), _p(_f64(pic)), _p(_f64(m)), _p(_f64(Sc)),
+                                     _p(_f64(w)))
+
+
+def pdf(K, mix, qpos, qcell, dirs):
+    """dirs: (nq, nd, 3). Returns (nq, nd) FP64 pdf values."""
+    qpos = _f64(qpos)
+    qcell = np.ascontiguousarray(qcell, dtype=np.int32)
+    dirs = _f64(dirs)
+    nq, nd = dirs.shape[0], dirs.shape[1]
+    out = np.zeros((nq, nd))
+    rc = lib().orc_pdf(K, _p(_f64(mix["pi"])), _p(_f64(mix["mu_dir"])), _p(_f64(mix["mu_pos"])),
+                       _p(_f64(mix["cov"])), nq, _p(qpos), _p(qcell), nd, _p(dirs), _p(out))
+    if rc:
+        raise ValueError("orc_pdf failed")
+    return out
+
+
+def sample(K, mix, qpos, qcell, uniforms):
+    """uniforms: (nq, ns, 3) in [0,1). Returns dirs (nq,ns,3), pdf (nq,ns), comp, valid."""
+    qpos = _f64(qpos)
+    qcell = np.ascontiguousarray(qcell, dtype=np.int32)
+    u = _f64(uniforms)
+    nq, ns = u.shape[0], u.shape[1]
+    dirs, pdfv = np.zeros((nq, ns, 3)), np.zeros((nq, ns))
+    comp = np.zeros((nq, ns), dtype=np.int32)
+    valid = np.zeros((nq, ns), dtype=np.uint8)
+    rc = lib().orc_sample(K, _p(_f64(mix["pi"])), _p(_f64(mix["mu_dir"])), _p(_f64(mix["mu_pos"])),
+                          _p(_f64(mix["cov"])), nq, _p(qpos), _p(qcell), ns, _p(u), _p(dirs), _p(pdfv),
+                          _p(comp), _p(valid))
+    if rc:
+        raise ValueError("orc_sample failed")
+    return dirs, pdfv, comp, valid

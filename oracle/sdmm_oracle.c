@@ -1,0 +1,857 @@
+/*
+ * sdmm_oracle.c -- plain, slow, FP64, single-threaded CPU reference ("the oracle")
+ * for the spatio-directional mixture (SDMM) path of Dodik, Papas, Oztireli and
+ * Mueller, "Path Guiding Using Spatio-Directional Mixture Models" (arXiv 2111.13094).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg load this library. The GPU library shares no code,
+ * header, table or helper with it, and neither includes the other.
+ *
+ * What it computes, in the paper's order (section numbers are the paper's):
+ *   - tangent-space log / exp maps of the sphere, with positions as translations
+ *     (Sec. 3.1, log-map and exp-map equations, "Additional dimensions");
+ *   - weighted sufficient statistics with responsibilities from tangent densities
+ *     (Sec. 3.2, sufficient-statistics equation);
+ *   - the M-step: weights, tangent-space mean update through the exp map, covariance
+ *     computed in the old frame and carried to the new one by the first-order
+ *     Jacobian (Sec. 3.2 mean update; Sec. 3.4 "Efficient tangent-space covariance
+ *     update"; Appendix A);
+ *   - Robbins-Monro averaging of the statistics and the normaliser across batches,
+ *     and the MAP (Dirichlet / inverse-Wishart) updates (Sec. 4.3);
+ *   - closed-form Gaussian conditioning on the position, the solid-angle pdf and
+ *     sampling with the cut-locus discard (Sec. 3.1 density and sampling paragraphs,
+ *     Sec. 3.2 first paragraph, Sec. 3.3);
+ *   - the penalised log-likelihood that the MAP update maximises and its gradient.
+ *
+ * Readings where the paper is silent or garbled (each one is listed with its reason
+ * in the design notes): the frame R_mu is the branchless orthonormal basis of Duff et
+ * al. 2017 with rows (t1, t2, mu); the solid-angle density divides the tangent density
+ * by sinc|nu|; the corrected Jacobians of Appendix A; the Robbins-Monro weight eta_j
+ * weights the new batch for every statistic; the prior strength is beta_j = eta_j / M_j
+ * unless a fixed value is given; statistics are carried to the new frame after every
+ * M-step with the first moment reset to zero; the prior is added after the transfer;
+ * antipodal log-map input maps to (pi, 0).
+ *
+ * Layouts (shared as an interface with the GPU library, written independently):
+ *   samples   float32 structure-of-arrays [7][N]: dir x,y,z, pos x,y,z, weight
+ *   cov       5x5 symmetric packed lower triangle, row-major, index d(d+1)/2+e (d>=e),
+ *             coordinate order (nu_u, nu_v, x, y, z)
+ *   per cell  K components, component index fastest.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define TRI(d, e) ((d) * ((d) + 1) / 2 + (e))
+#define ORC_KMAX 64
+
+/* per-cell status bits (the same values the GPU library reports) */
+#define ORC_SKIPPED_FEW 1
+#define ORC_SKIPPED_ZERO_W 2
+#define ORC_BAD_INPUT 4
+#define ORC_DEAD_COMPONENT 8
+#define ORC_CHOL_FAIL_KEPT_PREV 16
+#define ORC_BAD_PARAMS 32
+
+typedef struct {
+    int32_t K;
+    int32_t iters;          /* E+M iterations on the given batch */
+    int32_t eta_mode;       /* 0: eta_j = eta for j>0; 1: eta_j = (rm_beta*j+1)^-rm_alpha */
+    int32_t prior_mode;     /* 0: beta_j = eta_j / M_j; 1: beta_j = prior_scale */
+    int32_t estep_jacobian; /* 1: responsibilities from solid-angle densities */
+    int32_t euclidean;      /* 1: the two directional coordinates are plain R^2 */
+    int32_t min_samples;    /* cells with fewer positive-weight samples are skipped */
+    int32_t reserved;
+    double eta, rm_alpha, rm_beta, prior_scale;
+    double prior_q, prior_a, prior_b[5];
+    double dead_threshold;
+} orc_opts;
+
+/* ------------------------------------------------------------------------- */
+/* small dense helpers                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Cholesky factor of an n x n SPD matrix in packed lower storage. -1 if not SPD. */
+static int chol_packed(int n, const double *A, double *L)
+{
+    for (int d = 0; d < n; ++d) {
+        for (int e = 0; e <= d; ++e) {
+            double s = A[TRI(d, e)];
+            for (int f = 0; f < e; ++f) s -= L[TRI(d, f)] * L[TRI(e, f)];
+            if (d == e) {
+                if (!(s > 0.0) || !isfinite(s)) return -1;
+                L[TRI(d, d)] = sqrt(s);
+            } else {
+                L[TRI(d, e)] = s / L[TRI(e, e)];
+            }
+        }
+    }
+    return 0;
+}
+
+/* solve L z = y for lower-triangular packed L */
+static void forward_solve(int n, const double *L, const double *y, double *z)
+{
+    for (int d = 0; d < n; ++d) {
+        double s = y[d];
+        for (int e = 0; e < d; ++e) s -= L[TRI(d, e)] * z[e];
+        z[d] = s / L[TRI(d, d)];
+    }
+}
+
+/* full inverse of an SPD matrix from its Cholesky factor, dense n x n row-major */
+static void spd_inverse(int n, const double *L, double *Ainv)
+{
+    double col[8], z[8], x[8];
+    for (int j = 0; j < n; ++j) {
+        for (int d = 0; d < n; ++d) col[d] = (d == j) ? 1.0 : 0.0;
+        forward_solve(n, L, col, z);
+        /* back substitution L^T x = z */
+        for (int d = n - 1; d >= 0; --d) {
+            double s = z[d];
+            for (int e = d + 1; e < n; ++e) s -= L[TRI(e, d)] * x[e];
+            x[d] = s / L[TRI(d, d)];
+        }
+        for (int d = 0; d < n; ++d) Ainv[d * n + j] = x[d];
+    }
+}
+
+static double log_det_from_chol(int n, const double *L)
+{
+    double s = 0.0;
+    for (int d = 0; d < n; ++d) s += log(L[TRI(d, d)]);
+    return 2.0 * s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* tangent-space maps (Sec. 3.1)                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Frame R_mu: rows (t1, t2, mu), so R_mu mu = (0,0,1). The paper only asks for "the
+ * rotation that takes mu to +z"; this is the branchless basis of Duff et al. 2017. */
+void orc_frame(const double mu[3], double R[9])
+{
+    double sgn = copysign(1.0, mu[2]);
+    double a = -1.0 / (sgn + mu[2]);
+    double b = mu[0] * mu[1] * a;
+    R[0] = 1.0 + sgn * mu[0] * mu[0] * a;
+    R[1] = sgn * b;
+    R[2] = -sgn * mu[0];
+    R[3] = b;
+    R[4] = sgn + mu[1] * mu[1] * a;
+    R[5] = -mu[1];
+    R[6] = mu[0];
+    R[7] = mu[1];
+    R[8] = mu[2];
+}
+
+/* log map, Sec. 3.1: nu = (w'_x, w'_y) / sinc(acos w'_z) with w' = R w, written with
+ * theta = atan2(|w'_xy|, w'_z) so that theta / sin(theta) = theta / |w'_xy|. */
+void orc_log_map(const double R[9], const double w[3], double nu[2])
+{
+    double x = R[0] * w[0] + R[1] * w[1] + R[2] * w[2];
+    double y = R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
+    double z = R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
+    double s = hypot(x, y);
+    if (s > 0.0) {
+        double th = atan2(s, z);
+        nu[0] = th / s * x;
+        nu[1] = th / s * y;
+    } else if (z >= 0.0) {
+        nu[0] = 0.0; /* w = mu */
+        nu[1] = 0.0;
+    } else {
+        nu[0] = ORC_PI; /* antipode: the cut locus; reading (pi, 0) */
+        nu[1] = 0.0;
+    }
+}
+
+/* exp map, Sec. 3.1: w = R^-1 (nu sinc|nu|, cos|nu|) */
+void orc_exp_map(const double R[9], const double nu[2], double w[3])
+{
+    double r = hypot(nu[0], nu[1]);
+    double sc = (r > 0.0) ? sin(r) / r : 1.0;
+    double v[3] = {nu[0] * sc, nu[1] * sc, cos(r)};
+    for (int j = 0; j < 3; ++j) w[j] = R[j] * v[0] + R[3 + j] * v[1] + R[6 + j] * v[2];
+}
+
+/* (cos r - sinc r) / r^2, the scalar of the exp-map Jacobian (Appendix A) */
+static double exp_jac_scalar(double r)
+{
+    if (r < 1e-2) {
+        double r2 = r * r;
+        return -1.0 / 3.0 + r2 / 30.0 - r2 * r2 / 840.0;
+    }
+    return (cos(r) - sin(r) / r) / (r * r);
+}
+
+/* d(nu sinc|nu|, cos|nu|)/d nu, a 3x2 matrix (Appendix A, with its two printed typos
+ * corrected: off-diagonals are nu_x nu_y c and entry (2,2) is sinc + nu_y^2 c). */
+static void exp_jac_local(const double nu[2], double M[6])
+{
+    double r = hypot(nu[0], nu[1]);
+    double s = (r > 0.0) ? sin(r) / r : 1.0;
+    double c = exp_jac_scalar(r);
+    M[0] = s + nu[0] * nu[0] * c;
+    M[1] = nu[0] * nu[1] * c;
+    M[2] = nu[0] * nu[1] * c;
+    M[3] = s + nu[1] * nu[1] * c;
+    M[4] = -nu[0] * s;
+    M[5] = -nu[1] * s;
+}
+
+/* First-order transfer between tangent spaces (Sec. 3.4): the Jacobian of
+ * log_{mu_new} o exp_{mu} at nu = m, where mu_new = exp_mu(m). At that point
+ * d log_{mu_new}/d w = rows (t1, t2) of R_{mu_new}, and d exp_mu/d nu = R_mu^T M(m). */
+void orc_transfer_jacobian(const double mu[3], const double m[2], double J[4])
+{
+    double R[9], Rn[9], mun[3], M[6];
+    orc_frame(mu, R);
+    orc_exp_map(R, m, mun);
+    double nn = sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
+    for (int i = 0; i < 3; ++i) mun[i] /= nn;
+    orc_frame(mun, Rn);
+    exp_jac_local(m, M);
+    double RtM[6]; /* 3x2: R^T M */
+    for (int j = 0; j < 3; ++j)
+        for (int b = 0; b < 2; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += R[3 * i + j] * M[2 * i + b];
+            RtM[2 * j + b] = s;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += Rn[3 * a + j] * RtM[2 * j + b];
+            J[2 * a + b] = s;
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* per-component model pieces                                                 */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double R[9];
+    double L[15];
+    double logc; /* log pi - 0.5 log det Sigma - (5/2) log 2 pi */
+    int ok;
+} comp_t;
+
+static int setup_components(int K, const double *pi, const double *mud, const double *cov,
+                            comp_t *c)
+{
+    int bad = 0;
+    for (int k = 0; k < K; ++k) {
+        orc_frame(mud + 3 * k, c[k].R);
+        c[k].ok = (chol_packed(5, cov + 15 * k, c[k].L) == 0) && isfinite(pi[k]) && pi[k] >= 0.0;
+        if (!c[k].ok) {
+            bad = 1;
+            continue;
+        }
+        c[k].logc = log(pi[k]) - 0.5 * log_det_from_chol(5, c[k].L) - 2.5 * log(2.0 * ORC_PI);
+    }
+    return bad;
+}
+
+/* y = (log_mu w, p - mu_x), Sec. 3.1 "Additional dimensions" */
+static void tangent_coords(const orc_opts *o, const comp_t *c, const double *mud, const double *mux,
+                           const double w[3], const double p[3], double y[5])
+{
+    if (o->euclidean) {
+        y[0] = w[0] - mud[0];
+        y[1] = w[1] - mud[1];
+    } else {
+        orc_log_map(c->R, w, y);
+    }
+    for (int d = 0; d < 3; ++d) y[2 + d] = p[d] - mux[d];
+}
+
+/* log of the component density used in the E-step: the tangent density of Sec. 3.1,
+ * or, with estep_jacobian, the solid-angle density (tangent density / sinc|nu|). */
+static double comp_log_density(const orc_opts *o, const comp_t *c, const double y[5])
+{
+    double z[5];
+    forward_solve(5, c->L, y, z);
+    double q = 0.0;
+    for (int d = 0; d < 5; ++d) q += z[d] * z[d];
+    double l = c->logc - 0.5 * q;
+    if (o->estep_jacobian && !o->euclidean) {
+        double r = hypot(y[0], y[1]);
+        if (r > 0.0) l -= log(sin(r) / r);
+    }
+    return l;
+}
+
+static int sample_is_bad(const float *smp, int64_t N, int64_t i)
+{
+    for (int a = 0; a < 7; ++a)
+        if (!isfinite((double)smp[a * N + i])) return 1;
+    return smp[6 * N + i] < 0.0f;
+}
+
+static void load_sample(const float *smp, int64_t N, int64_t i, double w[3], double p[3], double *wt)
+{
+    for (int d = 0; d < 3; ++d) {
+        w[d] = (double)smp[d * N + i];
+        p[d] = (double)smp[(3 + d) * N + i];
+    }
+    *wt = (double)smp[6 * N + i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* E-step statistics (Sec. 3.2)                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Unnormalised statistics of samples [i0, i1) about the current parameters:
+ * S0_k = sum w r, S1_k = sum w r y, S2_k = sum w r y y^T (packed), W = sum w,
+ * M = #{w > 0}, LL = sum w log p(y). Returns status bits for bad input / params. */
+int orc_cell_stats(const orc_opts *o, int32_t K, const float *smp, int64_t N, int64_t i0,
+                   int64_t i1, const double *pi, const double *mud, const double *mux,
+                   const double *cov, double *S0, double *S1, double *S2, double *W,
+                   int64_t *M, double *LL)
+{
+    comp_t c[ORC_KMAX];
+    double l[ORC_KMAX], y[ORC_KMAX][5];
+    memset(S0, 0, sizeof(double) * K);
+    memset(S1, 0, sizeof(double) * K * 5);
+    memset(S2, 0, sizeof(double) * K * 15);
+    *W = 0.0;
+    *M = 0;
+    *LL = 0.0;
+    for (int64_t i = i0; i < i1; ++i)
+        if (sample_is_bad(smp, N, i)) return ORC_BAD_INPUT;
+    if (setup_components(K, pi, mud, cov, c)) return ORC_BAD_PARAMS;
+    for (int64_t i = i0; i < i1; ++i) {
+        double w[3], p[3], wt;
+        load_sample(smp, N, i, w, p, &wt);
+        *W += wt;
+        if (wt > 0.0) *M += 1;
+        double lmax = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            tangent_coords(o, &c[k], mud + 3 * k, mux + 3 * k, w, p, y[k]);
+            l[k] = comp_log_density(o, &c[k], y[k]);
+            if (l[k] > lmax) lmax = l[k];
+        }
+        double den = 0.0;
+        for (int k = 0; k < K; ++k) den += exp(l[k] - lmax);
+        *LL += wt * (lmax + log(den));
+        for (int k = 0; k < K; ++k) {
+            double r = exp(l[k] - lmax) / den; /* responsibility */
+            double wr = wt * r;
+            S0[k] += wr;
+            for (int d = 0; d < 5; ++d) {
+                S1[5 * k + d] += wr * y[k][d];
+                for (int e = 0; e <= d; ++e) S2[15 * k + TRI(d, e)] += wr * y[k][d] * y[k][e];
+            }
+        }
+    }
+    return 0;
+}
+
+/* responsibilities of one sample (for the "sum to one" pin) */
+int orc_responsibilities(const orc_opts *o, int32_t K, const double w[3], const double p[3],
+                         const double *pi, const double *mud, const double *mux,
+                         const double *cov, double *r)
+{
+    comp_t c[ORC_KMAX];
+    double l[ORC_KMAX], y[5];
+    if (setup_components(K, pi, mud, cov, c)) return ORC_BAD_PARAMS;
+    double lmax = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        tangent_coords(o, &c[k], mud + 3 * k, mux + 3 * k, w, p, y);
+        l[k] = comp_log_density(o, &c[k], y);
+        if (l[k] > lmax) lmax = l[k];
+    }
+    double den = 0.0;
+    for (int k = 0; k < K; ++k) den += exp(l[k] - lmax);
+    for (int k = 0; k < K; ++k) r[k] = exp(l[k] - lmax) / den;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Robbins-Monro blend and MAP M-step (Sec. 3.2, 3.4, 4.3)                    */
+/* ------------------------------------------------------------------------- */
+
+double orc_eta(const orc_opts *o, int32_t j)
+{
+    if (j == 0) return 1.0;
+    if (o->eta_mode == 0) return o->eta;
+    return pow(o->rm_beta * (double)j + 1.0, -o->rm_alpha);
+}
+
+static int cell_mstep(const orc_opts *o, int K, int64_t M, double W, const double *S0,
+                      const double *S1, const double *S2, double *pi, double *mud, double *mux,
+                      double *cov, double *s0, double *s2, double *sw, int32_t *step)
+{
+    int status = 0;
+    const int j = *step;
+    const double eta = orc_eta(o, j);
+    const double beta = (o->prior_mode == 0) ? eta / (double)M : o->prior_scale;
+
+    /* Robbins-Monro averaging of S0, S1, S2 and the normaliser (Sec. 4.3). The carried
+     * first moment is zero: it was taken about the mean it produced. */
+    double hW = (j == 0) ? W : (1.0 - eta) * (*sw) + eta * W;
+    double hS0[ORC_KMAX], hS1[ORC_KMAX][5], hS2[ORC_KMAX][15];
+    for (int k = 0; k < K; ++k) {
+        hS0[k] = (j == 0) ? S0[k] : (1.0 - eta) * s0[k] + eta * S0[k];
+        for (int d = 0; d < 5; ++d) hS1[k][d] = (j == 0) ? S1[5 * k + d] : eta * S1[5 * k + d];
+        for (int t = 0; t < 15; ++t)
+            hS2[k][t] = (j == 0) ? S2[15 * k + t] : (1.0 - eta) * s2[15 * k + t] + eta * S2[15 * k + t];
+    }
+
+    double sum_bar0 = 0.0;
+    for (int k = 0; k < K; ++k) sum_bar0 += hS0[k] / hW;
+
+    for (int k = 0; k < K; ++k) {
+        double bar0 = hS0[k] / hW;
+        if (!(bar0 > o->dead_threshold)) {
+            /* dead component: mean and covariance kept; its statistics are kept as blended */
+            status |= ORC_DEAD_COMPONENT;
+            s0[k] = hS0[k];
+            for (int t = 0; t < 15; ++t) s2[15 * k + t] = hS2[k][t];
+            continue;
+        }
+        double m[5];
+        for (int d = 0; d < 5; ++d) m[d] = hS1[k][d] / hS0[k];
+
+        /* mean update: directional part through the exp map of the old frame (Sec. 3.2),
+         * positional part as a translation */
+        double mu_old[3] = {mud[3 * k], mud[3 * k + 1], mud[3 * k + 2]};
+        double mu_new[3];
+        double J[4];
+        if (o->euclidean) {
+            mu_new[0] = mu_old[0] + m[0];
+            mu_new[1] = mu_old[1] + m[1];
+            mu_new[2] = mu_old[2];
+            J[0] = 1.0; J[1] = 0.0; J[2] = 0.0; J[3] = 1.0;
+        } else {
+            double R[9];
+            orc_frame(mu_old, R);
+            orc_exp_map(R, m, mu_new);
+            double nn = sqrt(mu_new[0] * mu_new[0] + mu_new[1] * mu_new[1] + mu_new[2] * mu_new[2]);
+            for (int i = 0; i < 3; ++i) mu_new[i] /= nn;
+            orc_transfer_jacobian(mu_old, m, J);
+        }
+
+        /* scatter about the new mean, still in the old frame (Sec. 3.2, params-from-stats) */
+        double C[5][5];
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e <= d; ++e) {
+                double v = hS2[k][TRI(d, e)] - hS1[k][d] * hS1[k][e] / hS0[k];
+                C[d][e] = v;
+                C[e][d] = v;
+            }
+        /* first-order transfer to the new frame, T = blkdiag(J, I3) (Sec. 3.4) */
+        double T[5][5] = {{0}};
+        T[0][0] = J[0]; T[0][1] = J[1]; T[1][0] = J[2]; T[1][1] = J[3];
+        T[2][2] = 1.0; T[3][3] = 1.0; T[4][4] = 1.0;
+        double TC[5][5], Cn[5][5];
+        for (int a = 0; a < 5; ++a)
+            for (int b = 0; b < 5; ++b) {
+                double s = 0.0;
+                for (int q = 0; q < 5; ++q) s += T[a][q] * C[q][b];
+                TC[a][b] = s;
+            }
+        for (int a = 0; a < 5; ++a)
+            for (int b = 0; b < 5; ++b) {
+                double s = 0.0;
+                for (int q = 0; q < 5; ++q) s += TC[a][q] * T[b][q];
+                Cn[a][b] = s;
+            }
+
+        /* MAP covariance (Sec. 4.3): (beta B + S2/W) / (beta a + S0/W), B diagonal */
+        double Sig[15], Lt[15];
+        double den = beta * o->prior_a + bar0;
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e <= d; ++e) {
+                double v = 0.5 * (Cn[d][e] + Cn[e][d]) / hW;
+                if (d == e) v += beta * o->prior_b[d];
+                Sig[TRI(d, e)] = v / den;
+            }
+
+        for (int i = 0; i < 3; ++i) {
+            mud[3 * k + i] = mu_new[i];
+            mux[3 * k + i] += m[2 + i];
+        }
+        if (chol_packed(5, Sig, Lt) == 0) {
+            memcpy(cov + 15 * k, Sig, sizeof(Sig));
+        } else {
+            status |= ORC_CHOL_FAIL_KEPT_PREV;
+        }
+        /* carried statistics, now about the new mean in the new frame */
+        s0[k] = hS0[k];
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e <= d; ++e) s2[15 * k + TRI(d, e)] = 0.5 * (Cn[d][e] + Cn[e][d]);
+    }
+
+    /* MAP weights (Sec. 4.3) */
+    double wden = (double)K * beta * o->prior_q + sum_bar0;
+    for (int k = 0; k < K; ++k) pi[k] = (beta * o->prior_q + hS0[k] / hW) / wden;
+
+    *sw = hW;
+    *step = j + 1;
+    return status;
+}
+
+/* Gate, Sec. 4.2: a cell is updated only with at least min_samples vertices. */
+static int gate(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0, int64_t i1,
+                const double *pi, const double *cov, int64_t *M, double *W)
+{
+    for (int64_t i = i0; i < i1; ++i)
+        if (sample_is_bad(smp, N, i)) return ORC_BAD_INPUT;
+    for (int k = 0; k < K; ++k) {
+        double L[15];
+        if (chol_packed(5, cov + 15 * k, L) != 0 || !isfinite(pi[k]) || pi[k] < 0.0)
+            return ORC_BAD_PARAMS;
+    }
+    *M = 0;
+    *W = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        double wt = (double)smp[6 * N + i];
+        *W += wt;
+        if (wt > 0.0) *M += 1;
+    }
+    if (*M < o->min_samples) return ORC_SKIPPED_FEW;
+    if (!(*W > 0.0)) return ORC_SKIPPED_ZERO_W;
+    return 0;
+}
+
+/* Fit: o->iters E+M iterations of every cell on the given batch. Parameters and the
+ * averaged statistics are updated in place; status[c] receives the OR of the cell's
+ * status bits over the iterations. */
+int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const float *smp, int64_t N,
+            double *pi, double *mud, double *mux, double *cov, double *s0, double *s2, double *sw,
+            int32_t *step, int32_t *status)
+{
+    const int K = o->K;
+    if (K < 1 || K > ORC_KMAX) return -1;
+    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const int64_t i0 = offsets[c], i1 = offsets[c + 1];
+        const int64_t ck = (int64_t)c * K;
+        status[c] = 0;
+        for (int it = 0; it < o->iters; ++it) {
+            int64_t M;
+            double W, LL;
+            int g = gate(o, K, smp, N, i0, i1, pi + ck, cov + 15 * ck, &M, &W);
+            if (g) {
+                status[c] |= g;
+                break;
+            }
+            orc_cell_stats(o, K, smp, N, i0, i1, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck,
+                           S0, S1, S2, &W, &M, &LL);
+            status[c] |= cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
+                                    cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* penalised log-likelihood and its gradient                                  */
+/* ------------------------------------------------------------------------- */
+
+/* F = sum_i (w_i/W) log sum_k pi_k N5(y_ik; 0, Sigma_k)
+ *     + sum_k [ beta q log pi_k - (beta a / 2) log det Sigma_k - (beta / 2) tr(B Sigma_k^-1) ],
+ * the function whose maximiser is the MAP update of Sec. 4.3 (Dirichlet prior on the
+ * weights, inverse-Wishart prior on the covariances, no prior on the means). */
+double orc_objective(const orc_opts *o, int32_t K, const float *smp, int64_t N, int64_t i0,
+                     int64_t i1, const double *pi, const double *mud, const double *mux,
+                     const double *cov, double beta)
+{
+    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15], W, LL;
+    int64_t M;
+    if (orc_cell_stats(o, K, smp, N, i0, i1, pi, mud, mux, cov, S0, S1, S2, &W, &M, &LL)) return NAN;
+    double F = LL / W;
+    for (int k = 0; k < K; ++k) {
+        double L[15], Si[25];
+        chol_packed(5, cov + 15 * k, L);
+        spd_inverse(5, L, Si);
+        double tr = 0.0;
+        for (int d = 0; d < 5; ++d) tr += o->prior_b[d] * Si[d * 5 + d];
+        F += beta * o->prior_q * log(pi[k]) - 0.5 * beta * o->prior_a * log_det_from_chol(5, L) -
+             0.5 * beta * tr;
+    }
+    return F;
+}
+
+/* d nu / d delta for nu = log_{mu(delta)}(w), mu(delta) = exp_mu(delta), frame rebuilt by
+ * orc_frame at mu(delta); evaluated at delta = 0 by the chain rule through the frame. */
+static void dlog_ddelta(const double mu[3], const double R[9], const double w[3], double D[4])
+{
+    const double sgn = copysign(1.0, mu[2]);
+    const double a = -1.0 / (sgn + mu[2]);
+    const double a2 = a * a;
+    const double nx = mu[0], ny = mu[1];
+    /* partial derivatives of the frame rows with respect to mu (3x3 each, row-major) */
+    const double db[3] = {ny * a, nx * a, nx * ny * a2};
+    const double dt1[9] = {2.0 * sgn * nx * a, 0.0, sgn * nx * nx * a2,
+                           sgn * db[0], sgn * db[1], sgn * db[2],
+                           -sgn, 0.0, 0.0};
+    const double dt2[9] = {db[0], db[1], db[2],
+                           0.0, 2.0 * ny * a, ny * ny * a2,
+                           0.0, -1.0, 0.0};
+    double x = R[0] * w[0] + R[1] * w[1] + R[2] * w[2];
+    double y = R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
+    double z = R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
+    double s = hypot(x, y);
+    double th = atan2(s, z);
+    for (int jj = 0; jj < 2; ++jj) {
+        const double *dmu = R + 3 * jj; /* d mu / d delta_j at 0 = t_j */
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            double g1 = 0.0, g2 = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                g1 += dt1[3 * i + q] * dmu[q];
+                g2 += dt2[3 * i + q] * dmu[q];
+            }
+            dx += g1 * w[i];
+            dy += g2 * w[i];
+            dz += dmu[i] * w[i];
+        }
+        double f, df;
+        if (s > 1e-6) {
+            double ds = (x * dx + y * dy) / s;
+            double dth = (z * ds - s * dz) / (s * s + z * z);
+            f = th / s;
+            df = dth / s - th * ds / (s * s);
+        } else {
+            f = 1.0; /* theta/s -> 1; its first-order change is O(theta) -> dropped */
+            df = 0.0;
+        }
+        D[0 * 2 + jj] = df * x + f * dx;
+        D[1 * 2 + jj] = df * y + f * dy;
+    }
+}
+
+/* Gradient of F at the current parameters with respect to the weight logits
+ * (pi = softmax(alpha)), the positional means, a tangent perturbation delta of the
+ * directional mean (mu(delta) = exp_mu(delta)), and the Cholesky factor L of Sigma
+ * (packed lower). Outputs per component: g_alpha[K], g_mux[3K], g_delta[2K], g_L[15K]. */
+int orc_grad(const orc_opts *o, int32_t K, const float *smp, int64_t N, int64_t i0, int64_t i1,
+             const double *pi, const double *mud, const double *mux, const double *cov, double beta,
+             double *g_alpha, double *g_mux, double *g_delta, double *g_L)
+{
+    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15], W, LL;
+    int64_t M;
+    int st = orc_cell_stats(o, K, smp, N, i0, i1, pi, mud, mux, cov, S0, S1, S2, &W, &M, &LL);
+    if (st) return st;
+    comp_t c[ORC_KMAX];
+    setup_components(K, pi, mud, cov, c);
+    double Si[ORC_KMAX][25];
+    double sum0 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        spd_inverse(5, c[k].L, Si[k]);
+        sum0 += S0[k] / W;
+    }
+    for (int k = 0; k < K; ++k) {
+        double b0 = S0[k] / W;
+        g_alpha[k] = b0 + beta * o->prior_q - pi[k] * (sum0 + K * beta * o->prior_q);
+        /* d/d mu_x: [Sigma^-1 S1bar]_x */
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+            for (int e = 0; e < 5; ++e) s += Si[k][(2 + d) * 5 + e] * S1[5 * k + e] / W;
+            g_mux[3 * k + d] = s;
+        }
+        /* G = 1/2 Sigma^-1 (S2bar + beta B) Sigma^-1 - 1/2 (S0bar + beta a) Sigma^-1 */
+        double A[25], G[25];
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e < 5; ++e) {
+                int dd = d > e ? d : e, ee = d > e ? e : d;
+                A[d * 5 + e] = S2[15 * k + TRI(dd, ee)] / W + ((d == e) ? beta * o->prior_b[d] : 0.0);
+            }
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e < 5; ++e) {
+                double s = 0.0;
+                for (int p = 0; p < 5; ++p)
+                    for (int q = 0; q < 5; ++q) s += Si[k][d * 5 + p] * A[p * 5 + q] * Si[k][q * 5 + e];
+                G[d * 5 + e] = 0.5 * s - 0.5 * (b0 + beta * o->prior_a) * Si[k][d * 5 + e];
+            }
+        /* dF/dL = tril(2 G L) */
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e <= d; ++e) {
+                double s = 0.0;
+                for (int p = e; p < 5; ++p) s += G[d * 5 + p] * c[k].L[TRI(p, e)];
+                g_L[15 * k + TRI(d, e)] = 2.0 * s;
+            }
+        g_delta[2 * k] = 0.0;
+        g_delta[2 * k + 1] = 0.0;
+    }
+    /* d/d delta: -sum_i (w_i/W) r_ik (d nu_ik/d delta)^T [Sigma_k^-1 y_ik]_nu */
+    double l[ORC_KMAX], y[ORC_KMAX][5];
+    for (int64_t i = i0; i < i1; ++i) {
+        double w[3], p[3], wt;
+        load_sample(smp, N, i, w, p, &wt);
+        if (wt == 0.0) continue;
+        double lmax = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            tangent_coords(o, &c[k], mud + 3 * k, mux + 3 * k, w, p, y[k]);
+            l[k] = comp_log_density(o, &c[k], y[k]);
+            if (l[k] > lmax) lmax = l[k];
+        }
+        double den = 0.0;
+        for (int k = 0; k < K; ++k) den += exp(l[k] - lmax);
+        for (int k = 0; k < K; ++k) {
+            double wr = wt / W * exp(l[k] - lmax) / den;
+            double u0 = 0.0, u1 = 0.0;
+            for (int e = 0; e < 5; ++e) {
+                u0 += Si[k][0 * 5 + e] * y[k][e];
+                u1 += Si[k][1 * 5 + e] * y[k][e];
+            }
+            double D[4];
+            if (o->euclidean) {
+                D[0] = -1.0; D[1] = 0.0; D[2] = 0.0; D[3] = -1.0;
+            } else {
+                dlog_ddelta(mud + 3 * k, c[k].R, w, D);
+            }
+            g_delta[2 * k] -= wr * (D[0] * u0 + D[2] * u1);
+            g_delta[2 * k + 1] -= wr * (D[1] * u0 + D[3] * u1);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* conditioning, pdf and sampling (Sec. 3.1, 3.2, 3.3)                        */
+/* ------------------------------------------------------------------------- */
+
+/* Closed-form conditioning of one cell's joint mixture on the position x:
+ * pi'_k ∝ pi_k N3(x - mu_x; 0, Sigma_xx), m_k = Sigma_nx Sigma_xx^-1 (x - mu_x),
+ * Sigma'_k = Sigma_nn - Sigma_nx Sigma_xx^-1 Sigma_xn (packed 2x2). */
+int orc_condition(int32_t K, const double *pi, const double *mux, const double *cov,
+                  const double x[3], double *pic, double *m, double *Sc)
+{
+    double lw[ORC_KMAX], lmax = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const double *S = cov + 15 * k;
+        double Sxx[6], Lxx[6], Sxxi[9];
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e <= d; ++e) Sxx[TRI(d, e)] = S[TRI(2 + d, 2 + e)];
+        if (chol_packed(3, Sxx, Lxx) != 0) return -1;
+        spd_inverse(3, Lxx, Sxxi);
+        double dx[3], u[3];
+        for (int d = 0; d < 3; ++d) dx[d] = x[d] - mux[3 * k + d];
+        forward_solve(3, Lxx, dx, u);
+        double q = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        lw[k] = log(pi[k]) - 0.5 * q - 0.5 * log_det_from_chol(3, Lxx) - 1.5 * log(2.0 * ORC_PI);
+        if (lw[k] > lmax) lmax = lw[k];
+        /* A = Sigma_nx Sigma_xx^-1 (2x3); Sigma_nx[a][d] = S[TRI(2+d, a)] */
+        double A[6];
+        for (int a = 0; a < 2; ++a)
+            for (int d = 0; d < 3; ++d) {
+                double s = 0.0;
+                for (int e = 0; e < 3; ++e) s += S[TRI(2 + e, a)] * Sxxi[e * 3 + d];
+                A[3 * a + d] = s;
+            }
+        for (int a = 0; a < 2; ++a) m[2 * k + a] = A[3 * a] * dx[0] + A[3 * a + 1] * dx[1] + A[3 * a + 2] * dx[2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b <= a; ++b) {
+                double s = S[TRI(a, b)];
+                for (int d = 0; d < 3; ++d) s -= A[3 * a + d] * S[TRI(2 + d, b)];
+                Sc[3 * k + TRI(a, b)] = s;
+            }
+    }
+    double den = 0.0;
+    for (int k = 0; k < K; ++k) den += exp(lw[k] - lmax);
+    for (int k = 0; k < K; ++k) pic[k] = exp(lw[k] - lmax) / den;
+    return 0;
+}
+
+/* Solid-angle pdf of the conditioned mixture (Sec. 3.1 mixture pdf), with the
+ * change of variables dividing by sinc|nu| and a zero contribution at or beyond the
+ * cut locus |nu| >= pi (1 - 1e-6). */
+double orc_pdf_conditioned(int32_t K, const double *mud, const double *pic, const double *m,
+                           const double *Sc, const double w[3])
+{
+    double p = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (pic[k] == 0.0) continue;
+        double R[9], nu[2], L[3], d[2], z[2];
+        orc_frame(mud + 3 * k, R);
+        orc_log_map(R, w, nu);
+        double r = hypot(nu[0], nu[1]);
+        if (r >= ORC_PI * (1.0 - 1e-6)) continue;
+        if (chol_packed(2, Sc + 3 * k, L) != 0) continue;
+        d[0] = nu[0] - m[2 * k];
+        d[1] = nu[1] - m[2 * k + 1];
+        forward_solve(2, L, d, z);
+        double q = z[0] * z[0] + z[1] * z[1];
+        double pt = exp(-0.5 * q) / (2.0 * ORC_PI * L[0] * L[2]);
+        double sinc = (r > 0.0) ? sin(r) / r : 1.0;
+        p += pic[k] * pt / sinc;
+    }
+    return p;
+}
+
+/* Conditioned pdf for many (query, direction) pairs: query q lies in cell qcell[q];
+ * directions dirs[(q*nd + t)*3 ...] (array of structures, 3 doubles). */
+int orc_pdf(int32_t K, const double *pi, const double *mud, const double *mux, const double *cov,
+            int64_t nq, const double *qpos, const int32_t *qcell, int32_t nd, const double *dirs,
+            double *pdf_out)
+{
+    double pic[ORC_KMAX], m[2 * ORC_KMAX], Sc[3 * ORC_KMAX];
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t ck = (int64_t)qcell[q] * K;
+        if (orc_condition(K, pi + ck, mux + 3 * ck, cov + 15 * ck, qpos + 3 * q, pic, m, Sc)) return -1;
+        for (int t = 0; t < nd; ++t)
+            pdf_out[q * nd + t] = orc_pdf_conditioned(K, mud + 3 * ck, pic, m, Sc, dirs + 3 * (q * nd + t));
+    }
+    return 0;
+}
+
+/* Sampling (Sec. 3.1): component by the CDF of pi' (lowest index on ties), nu from the
+ * component's conditional Gaussian by Box-Muller with u1 mapped to (0,1], discard when
+ * |nu| >= pi, w = exp_mu(nu), and the pdf of the whole conditioned mixture at w.
+ * uniforms[(q*ns + t)*3 + {0,1,2}] in [0,1). Invalid draws give dir 0, pdf 0, valid 0. */
+int orc_sample(int32_t K, const double *pi, const double *mud, const double *mux, const double *cov,
+               int64_t nq, const double *qpos, const int32_t *qcell, int32_t ns,
+               const double *uniforms, double *dirs_out, double *pdf_out, int32_t *comp_out,
+               uint8_t *valid_out)
+{
+    double pic[ORC_KMAX], m[2 * ORC_KMAX], Sc[3 * ORC_KMAX];
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t ck = (int64_t)qcell[q] * K;
+        if (orc_condition(K, pi + ck, mux + 3 * ck, cov + 15 * ck, qpos + 3 * q, pic, m, Sc)) return -1;
+        for (int t = 0; t < ns; ++t) {
+            const double *u = uniforms + 3 * (q * ns + t);
+            int64_t o = q * ns + t;
+            int sel = -1;
+            double cdf = 0.0;
+            for (int k = 0; k < K; ++k) {
+                cdf += pic[k];
+                if (u[0] < cdf) {
+                    sel = k;
+                    break;
+                }
+            }
+            if (sel < 0)
+                for (int k = K - 1; k >= 0; --k)
+                    if (pic[k] > 0.0) {
+                        sel = k;
+                        break;
+                    }
+            comp_out[o] = sel;
+            double L[3];
+            chol_packed(2, Sc + 3 * sel, L);
+            double rad = sqrt(-2.0 * log(1.0 - u[1]));
+            double z0 = rad * cos(2.0 * ORC_PI * u[2]), z1 = rad * sin(2.0 * ORC_PI * u[2]);
+            double nu[2] = {m[2 * sel] + L[0] * z0, m[2 * sel + 1] + L[1] * z0 + L[2] * z1};
+            if (hypot(nu[0], nu[1]) >= ORC_PI) {
+                valid_out[o] = 0;
+                pdf_out[o] = 0.0;
+                dirs_out[3 * o] = dirs_out[3 * o + 1] = dirs_out[3 * o + 2] = 0.0;
+                continue;
+            }
+            double R[9], w[3];
+            orc_frame(mud + 3 * (ck + sel), R);
+            orc_exp_map(R, nu, w);
+            valid_out[o] = 1;
+            for (int d = 0; d < 3; ++d) dirs_out[3 * o + d] = w[d];
+            pdf_out[o] = orc_pdf_conditioned(K, mud + 3 * ck, pic, m, Sc, w);
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,408 @@
+"""Pins for the oracle's EM: statistics (Sec. 3.2), the M-step with the first-order
+covariance transfer (Sec. 3.4), Robbins-Monro averaging and MAP updates (Sec. 4.3).
+
+Checks are against an independent textbook weighted MAP-EM (Euclidean special case),
+closed forms (K = 1), invariances the method must have, and the MAP objective."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.stats import multivariate_normal
+
+from paper_2111_13094_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _tri(d, e):
+    return d * (d + 1) // 2 + e
+
+
+def _unpack(c):
+    S = np.zeros((5, 5))
+    for d in range(5):
+        for e in range(d + 1):
+            S[d, e] = S[e, d] = c[_tri(d, e)]
+    return S
+
+
+def _pack(S):
+    return np.array([S[d, e] for d in range(5) for e in range(d + 1)])
+
+
+def _single_cell(n=2048, K=16, seed=3, parallax=True, zero_frac=0.1, sigma=1.5):
+    wl = synth.workload("single", seed=seed)
+    b = synth.make_batch(seed + 7, [n], wl["box_lo"], wl["box_size"], wl["lobes"], parallax=parallax,
+                         weight_sigma=sigma, zero_frac=zero_frac)
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    return b, mix
+
+
+# --- golden constants -------------------------------------------------------
+
+def test_paper_constants(orc):
+    g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    o = orc.Opts(K=g["K"]).to_c()
+    assert o.prior_q == pytest.approx(g["prior_q"], rel=1e-15)
+    assert o.prior_a == pytest.approx(g["prior_a"], rel=1e-15)
+    assert list(o.prior_b) == pytest.approx(g["prior_b_diag"], rel=1e-14)
+    opts = orc.Opts(K=16, eta_mode=1, rm_alpha=g["rm_alpha"], rm_beta=g["rm_beta"])
+    for j, e in enumerate(g["eta_j_0_to_5"]):
+        assert orc.eta(opts, j) == pytest.approx(e, rel=1e-15)
+    # the Robbins-Monro conditions of Sec. 4.3: sum eta = inf, sum eta^2 < inf needs alpha in (0.5, 1];
+    # alpha = 0.5 sits at the boundary (sum eta^2 diverges logarithmically), as the paper chooses.
+    from scipy.stats import chi2
+    assert chi2.ppf(0.9, 3) == pytest.approx(g["chi2_3_inv_0p9"], rel=1e-7)
+    assert synth.CHI2_3_INV_090 == pytest.approx(g["chi2_3_inv_0p9"], rel=1e-7)
+    mix = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), 16)
+    assert mix["cov"][0] == pytest.approx(g["init_sigma2_dir"], rel=1e-15)
+
+
+# --- P3 responsibilities ------------------------------------------------------
+
+def test_responsibilities_sum_to_one(orc):
+    b, mix = _single_cell(256)
+    o = orc.Opts(K=16)
+    for i in range(0, 256, 7):
+        r = orc.responsibilities(o, b.samples[0:3, i], b.samples[3:6, i], mix)
+        assert abs(r.sum() - 1.0) < 1e-14 and (r >= 0).all()
+
+
+# --- P4 Euclidean special case = textbook weighted MAP-EM ---------------------
+
+def _textbook_step(X, w, pi, mu, Sig, beta, q, a, B):
+    """Weighted MAP-EM step of a Gaussian mixture in R^5 with a Dirichlet prior on the
+    weights and an inverse-Wishart-type prior on the covariances (Gauvain and Lee)."""
+    K = pi.size
+    logp = np.stack([np.log(pi[k]) + multivariate_normal(mu[k], Sig[k]).logpdf(X) for k in range(K)], 1)
+    r = np.exp(logp - logp.max(1, keepdims=True))
+    r /= r.sum(1, keepdims=True)
+    W = w.sum()
+    wr = w[:, None] * r
+    N0 = wr.sum(0) / W
+    mu_new = (wr.T @ X) / wr.sum(0)[:, None]
+    Sig_new = np.zeros_like(Sig)
+    for k in range(K):
+        D = X - mu_new[k]
+        Sig_new[k] = ((wr[:, k, None] * D).T @ D / W + beta * np.diag(B)) / (N0[k] + beta * a)
+    pi_new = (N0 + beta * q) / (N0.sum() + K * beta * q)
+    return pi_new, mu_new, Sig_new
+
+
+def _euclid_problem(seed=11, n=1500, K=4):
+    rng = np.random.default_rng(seed)
+    centres = rng.normal(size=(K, 5)) * 2.0
+    lab = rng.integers(0, K, n)
+    X = centres[lab] + rng.normal(size=(n, 5)) * 0.5
+    w = np.exp(rng.normal(size=n))
+    w[rng.random(n) < 0.1] = 0.0
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:2] = X[:, 0:2].T
+    smp[3:6] = X[:, 2:5].T
+    smp[6] = w
+    X = np.concatenate([smp[0:2].T, smp[3:6].T], 1).astype(np.float64)
+    w = smp[6].astype(np.float64)
+    pi = np.full(K, 1.0 / K)
+    mu = X[rng.choice(n, K, replace=False)]
+    Sig = np.stack([np.eye(5)] * K)
+    mix = {"pi": pi.copy(), "mu_dir": np.concatenate([mu[:, 0:2], np.zeros((K, 1))], 1).ravel(),
+           "mu_pos": mu[:, 2:5].copy().ravel(), "cov": np.concatenate([_pack(S) for S in Sig])}
+    return smp, X, w, (pi, mu, Sig), mix
+
+
+def test_euclidean_mode_equals_textbook_map_em(orc):
+    smp, X, w, (pi, mu, Sig), mix = _euclid_problem()
+    K = pi.size
+    beta = 0.3
+    opts = orc.Opts(K=K, iters=1, euclidean=1, prior_mode=1, prior_scale=beta, min_samples=16)
+    o = opts.to_c()
+    B = np.array(o.prior_b)
+    st = orc.new_state(1, K)
+    off = np.array([0, X.shape[0]])
+    for it in range(6):
+        pi, mu, Sig = _textbook_step(X, w, pi, mu, Sig, beta, o.prior_q, o.prior_a, B)
+        status = orc.fit(opts, off, smp, mix, st)
+        assert status[0] == 0
+        got_mu = np.concatenate([mix["mu_dir"].reshape(K, 3)[:, :2], mix["mu_pos"].reshape(K, 3)], 1)
+        assert np.allclose(mix["pi"], pi, rtol=1e-10, atol=1e-14)
+        assert np.allclose(got_mu, mu, rtol=1e-10, atol=1e-12)
+        got_S = np.stack([_unpack(c) for c in mix["cov"].reshape(K, 15)])
+        assert np.allclose(got_S, Sig, rtol=1e-9, atol=1e-13)
+
+
+def test_euclidean_mode_objective_is_monotone_and_stationary(orc):
+    smp, X, w, _, mix = _euclid_problem(seed=12, n=1200, K=3)
+    K = 3
+    beta = 0.05
+    opts = orc.Opts(K=K, iters=1, euclidean=1, prior_mode=1, prior_scale=beta)
+    st = orc.new_state(1, K)
+    off = np.array([0, X.shape[0]])
+    F = [orc.objective(opts, smp, 0, X.shape[0], mix, beta)]
+    for it in range(400):
+        orc.fit(opts, off, smp, mix, st)
+        F.append(orc.objective(opts, smp, 0, X.shape[0], mix, beta))
+    F = np.array(F)
+    assert (np.diff(F) >= -1e-12 * np.abs(F[1:])).all(), np.diff(F).min()
+    g = orc.grad(opts, smp, 0, X.shape[0], mix, beta)
+    for key in ("alpha", "mu_pos", "delta", "L"):
+        assert np.abs(g[key]).max() < 1e-8, (key, np.abs(g[key]).max())
+
+
+# --- P5 K = 1 closed forms ----------------------------------------------------
+
+def test_single_component_closed_forms(orc):
+    rng = np.random.default_rng(21)
+    n = 3000
+    lobe = _unit(np.array([0.2, -0.7, 0.5]))
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = synth.sample_vmf(rng, np.tile(lobe, (n, 1)), np.full(n, 4.0)).T
+    smp[3:6] = rng.random((3, n))
+    smp[6] = synth.draw_weights(rng, n)
+    mix = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), 1)
+    beta = 0.01
+    opts = orc.Opts(K=1, iters=1, prior_mode=1, prior_scale=beta)
+    o = opts.to_c()
+    st = orc.new_state(1, 1)
+    orc.fit(opts, np.array([0, n]), smp, mix, st)
+    w = smp[6].astype(np.float64)
+    P = smp[3:6].T.astype(np.float64)
+    W = w.sum()
+    mean = (w[:, None] * P).sum(0) / W
+    assert mix["pi"][0] == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(mix["mu_pos"], mean, rtol=1e-12)
+    D = P - mean
+    scatter = (w[:, None] * D).T @ D / W
+    Sxx = (scatter + beta * np.diag(o.prior_b[2:5])) / (1.0 + beta * o.prior_a)
+    S = _unpack(mix["cov"])
+    assert np.allclose(S[2:, 2:], Sxx, rtol=1e-11)
+    # directional fixed point = weighted Karcher mean: sum_i w_i log_mu(w_i) = 0, written in
+    # world coordinates as theta_i (w_i - cos theta_i mu) / sin theta_i.
+    for it in range(100):
+        orc.fit(opts, np.array([0, n]), smp, mix, st)
+    mu = mix["mu_dir"]
+    Wd = smp[0:3].T.astype(np.float64)
+    cos = Wd @ mu
+    proj = Wd - cos[:, None] * mu
+    sin = np.linalg.norm(proj, axis=1)
+    th = np.arctan2(sin, cos)
+    v = (w * th / sin)[:, None] * proj
+    assert np.linalg.norm(v.sum(0)) / W < 1e-10
+
+
+# --- P10 invariances ----------------------------------------------------------
+
+def _fit_copy(orc, opts, off, smp, mix, st=None):
+    mix = synth.copy_mix(mix)
+    st = orc.new_state(off.size - 1, opts.K) if st is None else {k: v.copy() for k, v in st.items()}
+    s = orc.fit(opts, off, smp, mix, st)
+    return mix, st, s
+
+
+def test_weight_scale_invariance(orc):
+    b, mix = _single_cell(1024)
+    opts = orc.Opts(K=16, iters=3)
+    off = b.offsets
+    m1, s1, _ = _fit_copy(orc, opts, off, b.samples, mix)
+    smp = b.samples.copy()
+    smp[6] *= 4.0  # exact in float32
+    m2, s2, _ = _fit_copy(orc, opts, off, smp, mix)
+    for k in m1:
+        assert np.allclose(m1[k], m2[k], rtol=1e-13, atol=1e-15)
+
+
+def test_zero_weight_samples_are_inert(orc):
+    b, mix = _single_cell(1024, zero_frac=0.3)
+    opts = orc.Opts(K=16, iters=3)
+    m1, s1, _ = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    keep = b.samples[6] > 0
+    smp = np.ascontiguousarray(b.samples[:, keep])
+    m2, s2, _ = _fit_copy(orc, opts, np.array([0, smp.shape[1]]), smp, mix)
+    for k in m1:
+        assert np.array_equal(m1[k], m2[k]), k
+
+
+def test_sample_permutation_invariance(orc):
+    b, mix = _single_cell(1024)
+    opts = orc.Opts(K=16, iters=3)
+    m1, _, _ = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    perm = np.random.default_rng(5).permutation(b.samples.shape[1])
+    m2, _, _ = _fit_copy(orc, opts, b.offsets, np.ascontiguousarray(b.samples[:, perm]), mix)
+    for k in m1:
+        assert np.allclose(m1[k], m2[k], rtol=1e-10, atol=1e-12), k
+
+
+def _world_tangent_cov(mu, cov_packed, orc):
+    """Directional covariance and direction-position cross covariance as world-space
+    tangent vectors (independent of the frame chosen about mu)."""
+    R = orc.frame(mu)
+    E = R[:2].T  # 3x2, columns t1, t2
+    S = _unpack(cov_packed)
+    return E @ S[:2, :2] @ E.T, E @ S[:2, 2:]
+
+
+def test_global_rotation_equivariance(orc):
+    """Rotating every direction and every directional mean rotates the fitted model
+    (world-space means and tangent covariances) and leaves pdf values unchanged."""
+    b, mix = _single_cell(1500)
+    opts = orc.Opts(K=16, iters=4)
+    ang = 0.7
+    Q = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+    Q = Q @ np.array([[1, 0, 0], [0, np.cos(0.4), -np.sin(0.4)], [0, np.sin(0.4), np.cos(0.4)]])
+    m1, _, _ = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    smp = b.samples.copy()
+    smp[0:3] = (Q @ b.samples[0:3].astype(np.float64)).astype(np.float32)
+    # rotating float32 directions introduces float32 rounding: compare the unrotated fit
+    # on the same rounded directions rotated back.
+    back = np.ascontiguousarray(b.samples.copy())
+    back[0:3] = (Q.T @ smp[0:3].astype(np.float64)).astype(np.float32)
+    m1, _, _ = _fit_copy(orc, opts, b.offsets, back, mix)
+    mixr = synth.copy_mix(mix)
+    mixr["mu_dir"] = (mix["mu_dir"].reshape(-1, 3) @ Q.T).ravel()
+    m2, _, _ = _fit_copy(orc, opts, b.offsets, smp, mixr)
+    assert np.allclose(m1["pi"], m2["pi"], rtol=1e-5)
+    assert np.allclose(m1["mu_dir"].reshape(-1, 3) @ Q.T, m2["mu_dir"].reshape(-1, 3), atol=1e-5)
+    assert np.allclose(m1["mu_pos"], m2["mu_pos"], atol=1e-5)
+    for k in range(16):
+        A1, X1 = _world_tangent_cov(m1["mu_dir"][3 * k:3 * k + 3], m1["cov"][15 * k:15 * k + 15], orc)
+        A2, X2 = _world_tangent_cov(m2["mu_dir"][3 * k:3 * k + 3], m2["cov"][15 * k:15 * k + 15], orc)
+        assert np.allclose(Q @ A1 @ Q.T, A2, atol=1e-5 * np.abs(A1).max())
+        assert np.allclose(Q @ X1, X2, atol=1e-5 * max(np.abs(X1).max(), 1e-6))
+    x = np.array([0.4, 0.5, 0.6])
+    dirs = _unit(np.random.default_rng(3).normal(size=(50, 3)))
+    p1 = orc.pdf(16, m1, x[None], np.array([0]), dirs[None])
+    p2 = orc.pdf(16, m2, x[None], np.array([0]), (dirs @ Q.T)[None])
+    assert np.allclose(p1, p2, rtol=1e-4)
+
+
+def test_exact_rotation_equivariance_of_pdf(orc):
+    """Evaluating a fixed model: rotating the directional means and the query directions
+    by a rotation about z that maps the frame onto itself leaves pdf values unchanged to
+    rounding (1e-10)."""
+    b, mix = _single_cell(1000)
+    opts = orc.Opts(K=16, iters=3)
+    m1, _, _ = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    x = np.array([0.3, 0.6, 0.4])
+    dirs = _unit(np.random.default_rng(4).normal(size=(64, 3)))
+    p1 = orc.pdf(16, m1, x[None], np.array([0]), dirs[None])
+    # a quarter turn about z permutes coordinates exactly
+    Q = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    m2 = synth.copy_mix(m1)
+    m2["mu_dir"] = (m1["mu_dir"].reshape(-1, 3) @ Q.T).ravel()
+    # Sigma is stored in each mean's frame; re-express it in the rotated mean's frame
+    for k in range(16):
+        R1 = orc.frame(m1["mu_dir"][3 * k:3 * k + 3])
+        R2 = orc.frame(m2["mu_dir"][3 * k:3 * k + 3])
+        G = R2[:2] @ Q @ R1[:2].T  # 2x2 frame change
+        T = np.eye(5)
+        T[:2, :2] = G
+        S = _unpack(m1["cov"][15 * k:15 * k + 15])
+        m2["cov"][15 * k:15 * k + 15] = _pack(T @ S @ T.T)
+    p2 = orc.pdf(16, m2, x[None], np.array([0]), (dirs @ Q.T)[None])
+    assert np.allclose(p1, p2, rtol=1e-10, atol=1e-14)
+
+
+def test_cell_independence(orc):
+    wl = synth.workload("cells4k", scale=8 / 4096)
+    b = synth.workload_batch(wl)
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    C = wl["grid"].n_cells
+    opts = orc.Opts(K=16, iters=2)
+    mall, sall, stat = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    for c in range(C):
+        i0, i1 = b.offsets[c], b.offsets[c + 1]
+        sub = np.ascontiguousarray(b.samples[:, i0:i1])
+        mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix.items()}
+        mm, ss, s = _fit_copy(orc, opts, np.array([0, i1 - i0]), sub, mc)
+        assert s[0] == stat[c]
+        for k in mm:
+            assert np.array_equal(mm[k], mall[k].reshape(C, -1)[c])
+
+
+# --- gating and status --------------------------------------------------------
+
+def test_gating_statuses_leave_cells_untouched(orc):
+    wl = synth.workload("cells4k", scale=8 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    smp = b.samples.copy()
+    off = b.offsets
+    smp[6, off[1] + 3] = np.nan                 # cell 1: bad input
+    smp[6, off[2] + 5] = -1.0                   # cell 2: negative weight
+    smp[6, off[3]:off[4]] = 0.0                 # cell 3: all weights zero -> too few
+    smp[6, off[4] + 20:off[5]] = 0.0            # cell 4: 20 positive samples at most
+    smp[6, off[4]:off[4] + 20] = 1.0
+    cov_bad = mix["cov"].reshape(C, 16, 15).copy()
+    cov_bad[5, 3, 0] = -1.0                     # cell 5: non-SPD covariance
+    mix["cov"] = cov_bad.ravel()
+    opts = orc.Opts(K=16, iters=2)
+    m, s, stat = _fit_copy(orc, opts, off, smp, mix)
+    assert stat[1] == orc.BAD_INPUT and stat[2] == orc.BAD_INPUT
+    assert stat[3] == orc.SKIPPED_FEW
+    assert stat[4] & (orc.SKIPPED_FEW | orc.SKIPPED_ZERO_W) == 0
+    assert stat[5] == orc.BAD_PARAMS
+    for c in (1, 2, 3, 5):
+        for k in m:
+            assert np.array_equal(m[k].reshape(C, -1)[c], mix[k].reshape(C, -1)[c])
+        assert s["step"][c] == 0
+    assert stat[0] in (0, orc.DEAD_COMPONENT)
+    m0, _, _ = _fit_copy(orc, opts, off, b.samples, synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16))
+    for k in m:  # cell 0 (clean) identical to a clean run
+        assert np.array_equal(m[k].reshape(C, -1)[0], m0[k].reshape(C, -1)[0])
+    smp2 = smp.copy()
+    smp2[6, off[4]:off[4] + 20] = 0.0
+    smp2[6, off[4]:off[4] + 15] = 1.0
+    _, _, stat2 = _fit_copy(orc, opts, off, smp2, synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16))
+    assert stat2[4] == orc.SKIPPED_FEW
+
+
+# --- P11 Robbins-Monro special cases -----------------------------------------
+
+def test_eta_one_equals_independent_single_batch_step(orc):
+    wl = synth.workload("single", scale=1024 / 16384)
+    b0 = synth.workload_batch(wl, 0)
+    b1 = synth.workload_batch(wl, 1)
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    opts = orc.Opts(K=16, iters=1, eta_mode=0, eta=1.0)
+    m, st, _ = _fit_copy(orc, opts, b0.offsets, b0.samples, mix)
+    m_a, _, _ = _fit_copy(orc, opts, b1.offsets, b1.samples, m, st)
+    m_b, _, _ = _fit_copy(orc, opts, b1.offsets, b1.samples, m)  # fresh state (j = 0)
+    for k in m_a:
+        assert np.array_equal(m_a[k], m_b[k]), k
+
+
+def test_repeated_batch_with_small_eta_reaches_the_batch_em_fixed_point(orc):
+    b, mix = _single_cell(1024, K=4, parallax=False)
+    mix = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), 4)
+    beta = 1e-3
+    batch = orc.Opts(K=4, iters=600, eta_mode=0, eta=1.0, prior_mode=1, prior_scale=beta)
+    mb, _, _ = _fit_copy(orc, batch, b.offsets, b.samples, mix)
+    step = orc.Opts(K=4, iters=1500, eta_mode=0, eta=0.1, prior_mode=1, prior_scale=beta)
+    ms, _, _ = _fit_copy(orc, step, b.offsets, b.samples, mix)
+    assert np.allclose(mb["pi"], ms["pi"], atol=1e-7)
+    assert np.allclose(mb["mu_dir"], ms["mu_dir"], atol=1e-7)
+    assert np.allclose(mb["mu_pos"], ms["mu_pos"], atol=1e-7)
+    assert np.allclose(mb["cov"], ms["cov"], atol=1e-7)
+
+
+# --- P13 tangent-mode monotonicity (first-order M-step is not exact) ---------
+
+def test_tangent_mode_objective_nearly_monotone(orc):
+    b, mix = _single_cell(2048, parallax=True)
+    beta = 1.0 / 2048
+    opts = orc.Opts(K=16, iters=1, prior_mode=1, prior_scale=beta)
+    st = orc.new_state(1, 16)
+    n = b.samples.shape[1]
+    F = [orc.objective(opts, b.samples, 0, n, mix, beta)]
+    for it in range(30):
+        orc.fit(opts, b.offsets, b.samples, mix, st)
+        F.append(orc.objective(opts, b.samples, 0, n, mix, beta))
+    F = np.array(F)
+    dips = np.diff(F) / np.abs(F[1:])
+    assert dips.min() >= -1e-6, dips.min()
+    assert F[-1] > F[0]
