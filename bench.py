@@ -1,0 +1,241 @@
+"""Benchmark of the spatio-directional mixture EM on one MI355X.
+
+Headline (default): EM sample x component updates per second on the 4096-cell workload
+(16^3 cells of the unit cube, K = 16, cell counts lognormal(6.45, 1) clipped to
+[64, 8192], about 4.2M samples per batch, 8 resident batches, stepwise EM with decay 0.9:
+eta = 0.1 after the first batch), batched path (one E launch + one M launch per batch).
+A step is one E+M pass over one resident batch; inputs are generated on the host and
+copied to HBM before the timed region.
+
+The JSON line also carries:
+  roofline      the E-step statistics kernel (the dominant kernel): algorithmic FP32
+                flops per launch (140 per sample-component pair) over its average
+                event-timed duration, against the FP32 vector peak;
+  plain         the same updates/s for the plain per-cell GPU EM (one E and one M launch
+                per cell), same tolerance;
+  cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the workload.
+
+Other workloads (--workload): single (1 cell, N = 16384, 20 iterations), cells16k
+(16384 cells, geometric counts, plus 2^22 query positions x 4 draws), huge (1 cell,
+2^24 samples, K = 32), grad (adjoint on the 4096-cell state).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 140.0       # algorithmic FP32 flops per (sample, component) per E+M pass
+FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (published)
+HBM_PEAK_GBS = 8000.0
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("estep.hpp", "device_math.hpp", "fit.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2111_13094_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_record():
+    """HBM bytes per launch of the E-step kernel from the committed counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "estep_cells4k_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _sync(torch):
+    torch.cuda.synchronize()
+
+
+def _gen_cells4k(n_batches):
+    from paper_2111_13094_amd import synth
+    wl = synth.workload("cells4k")
+    batches = [synth.workload_batch(wl, j) for j in range(n_batches)]
+    return wl, batches
+
+
+def cpu_baseline(wl, batch, target_s=12.0):
+    """The oracle (single thread, FP64) on a bounded sample of the workload: a subset of
+    cells of one batch, one E+M step each, sized to about target_s seconds."""
+    from oracle import oracle as orc
+    from paper_2111_13094_amd import synth
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(C)
+
+    def run(cells):
+        pairs, t = 0, 0.0
+        for c in cells:
+            i0, i1 = batch.offsets[c], batch.offsets[c + 1]
+            sub = np.ascontiguousarray(batch.samples[:, i0:i1])
+            mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
+            st = orc.new_state(1, 16)
+            t0 = time.perf_counter()
+            orc.fit(orc.Opts(K=16, eta=0.1), np.array([0, i1 - i0]), sub, mc, st)
+            t += time.perf_counter() - t0
+            pairs += (i1 - i0) * 16
+        return pairs, t
+
+    p0, t0 = run(order[:16])
+    n = int(min(C, max(16, 16 * target_s / max(t0, 1e-3))))
+    p1, t1 = run(order[16:16 + n])
+    pairs, t = p0 + p1, t0 + t1
+    return {"value": pairs / t, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{16 + n} of {C} cells of one batch, one E+M step each, FP64, single thread, {t:.1f} s"}
+
+
+def bench_cells4k(args, torch):
+    from paper_2111_13094_amd import sdmm, synth
+    n_batches = 8
+    wl, batches = _gen_cells4k(n_batches)
+    C, K = wl["grid"].n_cells, 16
+    dev = torch.device("cuda", 0)
+    offs = [torch.from_numpy(b.offsets).to(dev) for b in batches]
+    smps = [torch.from_numpy(b.samples).to(dev) for b in batches]
+    N = [b.samples.shape[1] for b in batches]
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+
+    def fresh():
+        return {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}, sdmm.new_state(C, K, dev)
+
+    opts = sdmm.default_opts(K, eta=0.1)
+    if args.chunk:
+        opts.chunk = args.chunk
+    if args.waves:
+        opts.waves = args.waves
+    status = torch.empty(C, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
+    mix, st = fresh()
+    L = sdmm.lib()
+    for w in range(args.warmup):
+        sdmm.fit_mixtures(offs[w % n_batches], smps[w % n_batches], mix, st, opts, status, ws)
+    _sync(torch)
+    L.sdmm_timing_enable(1)
+    import ctypes as C_
+    tot, cnt = C_.c_double(), C_.c_int64()
+    L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+    _sync(torch)
+    t0 = time.perf_counter()
+    pairs = 0
+    for s in range(args.steps):
+        j = (args.warmup + s) % n_batches
+        sdmm.fit_mixtures(offs[j], smps[j], mix, st, opts, status, ws)
+        pairs += N[j] * K
+    _sync(torch)
+    t1 = time.perf_counter()
+    L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+    L.sdmm_timing_enable(0)
+    est_ms = tot.value / max(cnt.value, 1)
+    wall = t1 - t0
+    value = pairs / wall
+    flops_per_launch = FLOPS_PER_PAIR * (pairs / args.steps)
+    achieved = flops_per_launch / (est_ms * 1e-3) / 1e12
+    traffic = _traffic_record()
+    out = {
+        "metric": "EM sample x component updates/s, 4096 cells K=16 (batched)",
+        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cells4k: 4096 cells (16^3 grid of the unit cube), K=16, counts "
+                               "lognormal(6.45,1) clipped to [64,8192], 8 resident batches, stepwise EM "
+                               "eta=0.1, FP32 E-step with compensated sums, FP64 M-step",
+                   "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
+                   "chunk": int(opts.chunk or 1024), "waves": int(opts.waves or 4)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "estep_kernel<16,TwoSum>", "kernel_ms": est_ms,
+                     "flops_per_launch": flops_per_launch},
+    }
+    if not args.no_plain:
+        popts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_PER_CELL)
+        pmix, pst = fresh()
+        sdmm.fit_mixtures(offs[0], smps[0], pmix, pst, popts, status, ws)
+        _sync(torch)
+        t0 = time.perf_counter()
+        psteps = 2
+        ppairs = 0
+        for s in range(psteps):
+            j = (1 + s) % n_batches
+            sdmm.fit_mixtures(offs[j], smps[j], pmix, pst, popts, status, ws)
+            ppairs += N[j] * K
+        _sync(torch)
+        pt = time.perf_counter() - t0
+        out["plain"] = {"value": ppairs / pt, "unit": "updates/s", "ms_per_step": pt * 1e3 / psteps,
+                        "speedup_batched_over_plain": value / (ppairs / pt)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, batches[0], target_s=args.cpu_seconds)
+    return out
+
+
+def bench_single(args, torch):
+    from paper_2111_13094_amd import sdmm, synth
+    wl = synth.workload("single")
+    b = synth.workload_batch(wl)
+    dev = torch.device("cuda", 0)
+    off, smp = torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    opts = sdmm.default_opts(16, iters=20, use_graph=1)
+    for w in range(args.warmup + 1):
+        mix = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+        st = sdmm.new_state(1, 16, dev)
+        sdmm.fit_mixtures(off, smp, mix, st, opts)
+    _sync(torch)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        sdmm.fit_mixtures(off, smp, mix, st, opts)
+    _sync(torch)
+    wall = time.perf_counter() - t0
+    pairs = smp.shape[1] * 16 * 20 * args.steps
+    return {"metric": "EM sample x component updates/s, 1 cell N=16384 K=16, 20 iterations", "value": pairs / wall,
+            "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "single: 1 cell, N=16384, K=16, 20 EM iterations per step, hipGraph"}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "single"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the cells are independent, so more GPUs would each fit their "
+              "own share with no communication; run it with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.workload == "cells4k":
+        out = bench_cells4k(args, torch)
+    else:
+        out = bench_single(args, torch)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

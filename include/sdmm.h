@@ -1,0 +1,260 @@
+/*
+ * sdmm.h -- C ABI of libsdmm, an MI355X (gfx950) implementation of the data-parallel
+ * core of "Path Guiding Using Spatio-Directional Mixture Models" (Dodik, Papas,
+ * Oztireli, Mueller; arXiv 2111.13094):
+ *
+ *   - weighted MAP EM with Robbins-Monro averaging for many independent K-component
+ *     Gaussian mixtures over direction x position, directions taken in each component's
+ *     tangent space (Sec. 3.1-3.4, Sec. 4.2-4.3 of the paper);
+ *   - closed-form conditioning of a fitted 5-D mixture on a position, the solid-angle
+ *     pdf of the conditioned directional mixture, and sampling from it (Sec. 3.1-3.3);
+ *   - the gradient of the weighted penalised log-likelihood (adjoint).
+ *
+ * Conventions for every entry point
+ *   - Pointers marked [device] are device memory on the current HIP device; [host] are
+ *     host memory. All buffers are owned by the caller; the library keeps no model state.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream. Every call
+ *     only enqueues work on that stream and returns without synchronising, except where
+ *     stated. Results are valid once the stream has been synchronised.
+ *   - Return value: SDMM_OK or a negative SDMM_E* code. Nothing is enqueued when a call
+ *     returns an error. Numerical conditions are not errors: they are reported per cell
+ *     in `cell_status` (SDMM_CELL_* bits) and leave that cell's parameters and state
+ *     untouched (SKIPPED_*, BAD_*).
+ *   - Samples: float32 structure-of-arrays [7][n_samples] = dir x, y, z (unit vectors),
+ *     pos x, y, z (normalised to the unit cube, Sec. 4.3), Monte Carlo weight >= 0.
+ *     Cell c owns samples [cell_offsets[c], cell_offsets[c+1]) (int64, non-decreasing).
+ *   - Mixtures: float64 masters, component index fastest within a cell:
+ *     weights [n_cells*K], mean_dir [n_cells*K*3] (unit), mean_pos [n_cells*K*3],
+ *     cov [n_cells*K*15] = 5x5 SPD covariance, packed lower triangle row-major
+ *     (index d(d+1)/2+e, d>=e) in the coordinate order (nu_u, nu_v, x, y, z); nu is the
+ *     tangent coordinate of the direction in the frame R_mu whose rows are (t1, t2, mu),
+ *     t1 and t2 from the branchless orthonormal basis of Duff et al. (2017).
+ */
+#ifndef SDMM_H
+#define SDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define SDMM_OK 0
+#define SDMM_EINVAL (-1)       /* bad argument: null pointer, size, K out of range, ... */
+#define SDMM_EDEVICE (-2)      /* a HIP runtime call failed */
+#define SDMM_ENOWORKSPACE (-3) /* workspace smaller than the *_workspace_size() value */
+
+/* ---- per-cell status bits (OR over the iterations of one call) ---- */
+#define SDMM_CELL_SKIPPED_FEW 1    /* fewer than min_samples positive weights (Sec. 4.2) */
+#define SDMM_CELL_SKIPPED_ZERO_W 2 /* the weights sum to zero */
+#define SDMM_CELL_BAD_INPUT 4      /* negative weight, or non-finite sample / statistic */
+#define SDMM_CELL_DEAD_COMPONENT 8 /* some component kept its mean and covariance because
+                                      its normalised weight sum was <= dead_threshold */
+#define SDMM_CELL_CHOL_FAIL_KEPT_PREV 16 /* some updated covariance was not SPD; the previous
+                                            one was kept */
+#define SDMM_CELL_BAD_PARAMS 32    /* input mixture not usable: non-finite or negative
+                                      weight, non-finite mean, non-SPD covariance */
+
+/* ---- options ---- */
+#define SDMM_ETA_CONSTANT 0 /* eta_j = 1 for j = 0, eta for j > 0 */
+#define SDMM_ETA_PAPER 1    /* eta_j = (rm_beta * j + 1)^(-rm_alpha) (Sec. 4.3) */
+#define SDMM_PRIOR_ETA_OVER_M 0 /* prior strength beta_j = eta_j / M_j, M_j = #{w > 0} */
+#define SDMM_PRIOR_FIXED 1      /* beta_j = prior_scale */
+
+#define SDMM_FLAG_ESTEP_JACOBIAN 1 /* responsibilities from solid-angle densities instead of
+                                      the tangent densities of the statistics equation */
+#define SDMM_FLAG_PLAIN_FP32 2     /* precision study: plain FP32 running sums */
+#define SDMM_FLAG_FP64_SUMS 4      /* precision study: FP64 running sums */
+
+#define SDMM_SCHED_BATCHED 0  /* all cells in one E launch + one M launch per iteration */
+#define SDMM_SCHED_PER_CELL 1 /* plain baseline: one E and one M launch per cell; copies
+                                 cell_offsets to the host and synchronises the stream */
+#define SDMM_SCHED_FUSED 2    /* one launch per iteration: the last chunk of a cell to
+                                 finish runs that cell's M-step */
+
+typedef struct sdmm_fit_opts {
+    int32_t K;           /* components per cell, 1..64 */
+    int32_t iters;       /* E+M iterations over the given batch, >= 1 */
+    int32_t eta_mode;    /* SDMM_ETA_* */
+    int32_t prior_mode;  /* SDMM_PRIOR_* */
+    int32_t flags;       /* SDMM_FLAG_* */
+    int32_t min_samples; /* 16 in the paper (Sec. 4.2) */
+    int32_t schedule;    /* SDMM_SCHED_* */
+    int32_t chunk;       /* samples per work item (multiple of 64; 0 = library default) */
+    int32_t waves;       /* waves per work group: 1, 2, 4 or 8 (0 = library default) */
+    int32_t use_graph;   /* 1: capture the iteration sequence in a hipGraph, cached by
+                            argument values, and replay it */
+    double eta;          /* Robbins-Monro weight of a new batch for SDMM_ETA_CONSTANT */
+    double rm_alpha, rm_beta; /* SDMM_ETA_PAPER schedule (paper: 0.5, 0.1) */
+    double prior_scale;  /* beta for SDMM_PRIOR_FIXED */
+    double prior_q;      /* Dirichlet parameter (paper: 1/K) */
+    double prior_a;      /* inverse-Wishart denominator (paper: 5/K) */
+    double prior_b[5];   /* diagonal of B (paper: a * (0.1, 0.1, 1, 1, 1) * 1e-4) */
+    double dead_threshold; /* normalised weight sum at or below which a component is dead */
+} sdmm_fit_opts;
+
+typedef struct sdmm_mixtures {
+    int32_t n_cells;
+    int32_t K;
+    double *weights;  /* [device] n_cells*K */
+    double *mean_dir; /* [device] n_cells*K*3 */
+    double *mean_pos; /* [device] n_cells*K*3 */
+    double *cov;      /* [device] n_cells*K*15 */
+} sdmm_mixtures;
+
+/* Robbins-Monro state (Sec. 4.3): averaged statistics carried into the frame of the
+ * current means (first moment zero), averaged normaliser, and the per-cell step j.
+ * Zero-initialised state (step 0) starts a fresh fit. */
+typedef struct sdmm_em_state {
+    double *s0;    /* [device] n_cells*K */
+    double *s2;    /* [device] n_cells*K*15 (packed like cov) */
+    double *sw;    /* [device] n_cells */
+    int32_t *step; /* [device] n_cells */
+} sdmm_em_state;
+
+/* Bytes of device workspace sdmm_fit_mixtures needs for these sizes and options. */
+size_t sdmm_fit_workspace_size(int32_t n_cells, int32_t K, int64_t n_samples,
+                               const sdmm_fit_opts *opts);
+
+/*
+ * sdmm_fit_mixtures -- opts->iters iterations of weighted MAP EM on every cell.
+ *
+ * Per cell and iteration (paper Sec. 3.2, 3.4, 4.2, 4.3):
+ *   gate: skip with a status bit unless M = #{w > 0} >= min_samples and sum w > 0;
+ *   E-step: y_ik = (log_{mu_k}(w_i), p_i - mu_x_k); responsibilities r_ik from the
+ *     tangent densities pi_k N5(y_ik; 0, Sigma_k); S0 = sum w r, S1 = sum w r y,
+ *     S2 = sum w r y y^T, W = sum w (FP32 products, compensated FP32 running sums,
+ *     FP64 reductions across lanes and work items);
+ *   Robbins-Monro: S^ = (1 - eta_j) S^_prev + eta_j S (first batch: S^ = S), same for W;
+ *   M-step (FP64): m = S1^/S0^; mu_dir <- exp_{mu_dir}(m_nu), mu_pos += m_x;
+ *     C = S2^ - S1^ S1^T / S0^ moved to the new mean's frame by T = blkdiag(J, I3), J the
+ *     Jacobian of log_{mu_new} o exp_{mu} at m; Sigma = (beta_j B + T C T^T / W^) /
+ *     (beta_j a + S0^ / W^); pi = (beta_j q + S0^/W^) / (K beta_j q + sum S0^/W^);
+ *     the carried state becomes S0^ and T C T^T; step += 1.
+ *
+ * cell_offsets [device] int64[n_cells+1]; samples [device] float32[7][n_samples];
+ * mix, state: device arrays updated in place; opts [host]; cell_status [device]
+ * int32[n_cells] (overwritten); workspace [device] of at least
+ * sdmm_fit_workspace_size() bytes (contents need not be initialised; not retained
+ * between calls). Fitting cells together gives bitwise the same result as fitting each
+ * cell alone, and repeated calls are bitwise reproducible (fixed reduction order).
+ */
+int sdmm_fit_mixtures(const int64_t *cell_offsets, const float *samples, int64_t n_samples,
+                      const sdmm_mixtures *mix, const sdmm_em_state *state,
+                      const sdmm_fit_opts *opts, int32_t *cell_status, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* ---- conditioning, pdf, sampling ---- */
+
+/* floats per component in the conditioning table */
+#define SDMM_COND_TABLE_STRIDE 32
+
+/*
+ * sdmm_condition_prepare -- the query-independent part of conditioning on the position
+ * (paper Sec. 3.2 first paragraph, Sec. 3.3), per component, in FP64 and stored FP32:
+ * the frame R_mu, mu_x, the Cholesky factor of Sigma_xx (inverted), the regression
+ * A = Sigma_nx Sigma_xx^-1, the Cholesky factor L' of the conditional covariance
+ * Sigma' = Sigma_nn - A Sigma_xn (and its inverse), and the log normalisers.
+ * table [device] float32[n_cells*K*SDMM_COND_TABLE_STRIDE], written.
+ */
+int sdmm_condition_prepare(const sdmm_mixtures *mix, float *table, void *stream);
+
+/*
+ * sdmm_condition -- per query q (position qpos, cell qcell[q]):
+ *   pi'_k = pi_k N3(x - mu_x_k; 0, Sigma_xx,k) / sum_j (...),  m_k = A_k (x - mu_x_k).
+ * qpos [device] float32[3][nq] (SoA); qcell [device] int32[nq] in [0, n_cells);
+ * cond_w [device] float32[nq][K]; cond_m [device] float32[nq][K][2] (written).
+ */
+int sdmm_condition(const float *table, int32_t n_cells, int32_t K, const float *qpos,
+                   const int32_t *qcell, int64_t nq, float *cond_w, float *cond_m, void *stream);
+
+/*
+ * sdmm_pdf -- solid-angle pdf of the conditioned mixture (paper Sec. 3.1, mixture pdf):
+ *   p(w | x) = sum_k pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k|, nu_k = log_{mu_k}(w),
+ *   a component contributing 0 where |nu_k| >= pi (1 - 1e-6) (cut locus).
+ * nd directions per query: dirs [device] float32[3][nq*nd] (SoA, direction t of query q
+ * at column q*nd+t); pdf_out [device] float32[nq*nd].
+ */
+int sdmm_pdf(const float *table, int32_t n_cells, int32_t K, const int32_t *qcell, int64_t nq,
+             const float *cond_w, const float *cond_m, int32_t nd, const float *dirs,
+             float *pdf_out, void *stream);
+
+/*
+ * sdmm_sample -- ns draws per query (paper Sec. 3.1, "Sampling"): component by the CDF
+ * of pi' (lowest index on ties), nu = m_k + L'_k z with z by Box-Muller from (u1, u2)
+ * (u1 mapped to (0, 1] as 1 - u1), discarded when |nu| >= pi; w = exp_{mu_k}(nu); and
+ * p(w | x) of the whole conditioned mixture.
+ * uniforms [device] float32[3][nq*ns] in [0,1) (u0 picks the component) or NULL for
+ * the device generator: Philox4x32-10 keyed by seed, counter (draw index, 0, 0, 0).
+ * dirs_out [device] float32[3][nq*ns]; pdf_out [device] float32[nq*ns];
+ * valid_out [device] uint8[nq*ns]; comp_out [device] int32[nq*ns] or NULL.
+ * Discarded draws: valid 0, direction (0,0,0), pdf 0.
+ */
+int sdmm_sample(const float *table, int32_t n_cells, int32_t K, const int32_t *qcell, int64_t nq,
+                const float *cond_w, const float *cond_m, int32_t ns, const float *uniforms,
+                uint64_t seed, float *dirs_out, float *pdf_out, uint8_t *valid_out,
+                int32_t *comp_out, void *stream);
+
+/*
+ * sdmm_condition_sample_pdf -- conditioning, sampling and pdf in one pass per query
+ * without materialising pi' and m (same results as sdmm_condition + sdmm_sample).
+ */
+int sdmm_condition_sample_pdf(const float *table, int32_t n_cells, int32_t K, const float *qpos,
+                              const int32_t *qcell, int64_t nq, int32_t ns, const float *uniforms,
+                              uint64_t seed, float *dirs_out, float *pdf_out, uint8_t *valid_out,
+                              void *stream);
+
+/* ---- adjoint ---- */
+
+/*
+ * sdmm_fit_grad -- value and gradient of the weighted penalised log-likelihood
+ *   F = sum_i (w_i / W) log sum_k pi_k N5(y_ik; 0, Sigma_k)
+ *       + sum_k [beta q log pi_k - (beta a / 2) log det Sigma_k - (beta / 2) tr(B Sigma_k^-1)]
+ * (the objective whose maximiser is the MAP update of Sec. 4.3) per cell, at the current
+ * mixture, with beta = opts->prior_scale (and q, a, B from opts). Gradients are with
+ * respect to the weight logits (pi = softmax), the positional means, a tangent
+ * perturbation delta of each directional mean (mu(delta) = exp_mu(delta), frame rebuilt
+ * at mu(delta)), and the packed Cholesky factor L of Sigma.
+ * F_out [device] float64[n_cells]; g_alpha [device] float64[n_cells*K];
+ * g_mu_pos, g_delta [device] float64[n_cells*K*3], [n_cells*K*2];
+ * g_L [device] float64[n_cells*K*15]; cell_status [device] int32[n_cells] (gate as in
+ * sdmm_fit_mixtures with min_samples; skipped cells get F = 0 and zero gradients).
+ * workspace: at least sdmm_fit_workspace_size(n_cells, K, n_samples, opts) bytes.
+ */
+int sdmm_fit_grad(const int64_t *cell_offsets, const float *samples, int64_t n_samples,
+                  const sdmm_mixtures *mix, const sdmm_fit_opts *opts, double *F_out,
+                  double *g_alpha, double *g_mu_pos, double *g_delta, double *g_L,
+                  int32_t *cell_status, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- measurement ---- */
+
+#define SDMM_TIMER_ESTEP 0   /* the E-step statistics pass of sdmm_fit_mixtures */
+#define SDMM_TIMER_MSTEP 1   /* the M-step pass of sdmm_fit_mixtures */
+#define SDMM_TIMER_QUERY 2   /* sdmm_condition_sample_pdf */
+#define SDMM_TIMER_GRAD 3    /* the adjoint pass of sdmm_fit_grad */
+
+/* Enables (1) or disables (0) HIP-event timing: while enabled, every eager launch of
+ * the kernel classes above is bracketed by a pair of events recorded on its stream
+ * (launches inside a hipGraph capture are not). Process-wide; returns SDMM_OK. */
+int sdmm_timing_enable(int enable);
+
+/* Waits for the recorded events of one class and returns the summed kernel time in
+ * milliseconds and the number of launches; reset != 0 frees the records. Host call;
+ * synchronises on the recorded events. SDMM_EINVAL for an unknown class. */
+int sdmm_timing_read(int kernel_class, double *total_ms, int64_t *launches, int reset);
+
+/* ---- helpers ---- */
+
+/* Static description of an SDMM_OK / SDMM_E* code. */
+const char *sdmm_status_string(int code);
+
+/* Library version string. */
+const char *sdmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDMM_H */

@@ -277,3 +277,24 @@ def sample(K, mix, qpos, qcell, uniforms):
     if rc:
         raise ValueError("orc_sample failed")
     return dirs, pdfv, comp, valid
+
+
+# --- counter-based uniforms -------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    L = lib()
+    L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    L.orc_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def draw_uniforms(seed: int, n: int):
+    """(n, 3) uniforms of draws 0..n-1 under ``seed`` (the library's device generator)."""
+    L = lib()
+    L.orc_draw_uniforms.argtypes = [C.c_uint64, C.c_int64, C.c_void_p]
+    u = np.zeros((n, 3))
+    L.orc_draw_uniforms(seed, n, _p(u))
+    return u

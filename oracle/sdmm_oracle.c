@@ -240,13 +240,24 @@ typedef struct {
     int ok;
 } comp_t;
 
-static int setup_components(int K, const double *pi, const double *mud, const double *cov,
-                            comp_t *c)
+/* A component is usable when its weight is finite and non-negative, its means are
+ * finite and its covariance is symmetric positive definite. */
+static int component_ok(const double *pi, const double *mud, const double *mux, const double *cov,
+                        double *L)
+{
+    if (!isfinite(*pi) || *pi < 0.0) return 0;
+    for (int d = 0; d < 3; ++d)
+        if (!isfinite(mud[d]) || !isfinite(mux[d])) return 0;
+    return chol_packed(5, cov, L) == 0;
+}
+
+static int setup_components(int K, const double *pi, const double *mud, const double *mux,
+                            const double *cov, comp_t *c)
 {
     int bad = 0;
     for (int k = 0; k < K; ++k) {
         orc_frame(mud + 3 * k, c[k].R);
-        c[k].ok = (chol_packed(5, cov + 15 * k, c[k].L) == 0) && isfinite(pi[k]) && pi[k] >= 0.0;
+        c[k].ok = component_ok(pi + k, mud + 3 * k, mux + 3 * k, cov + 15 * k, c[k].L);
         if (!c[k].ok) {
             bad = 1;
             continue;
@@ -323,7 +334,7 @@ int orc_cell_stats(const orc_opts *o, int32_t K, const float *smp, int64_t N, in
     *LL = 0.0;
     for (int64_t i = i0; i < i1; ++i)
         if (sample_is_bad(smp, N, i)) return ORC_BAD_INPUT;
-    if (setup_components(K, pi, mud, cov, c)) return ORC_BAD_PARAMS;
+    if (setup_components(K, pi, mud, mux, cov, c)) return ORC_BAD_PARAMS;
     for (int64_t i = i0; i < i1; ++i) {
         double w[3], p[3], wt;
         load_sample(smp, N, i, w, p, &wt);
@@ -358,7 +369,7 @@ int orc_responsibilities(const orc_opts *o, int32_t K, const double w[3], const 
 {
     comp_t c[ORC_KMAX];
     double l[ORC_KMAX], y[5];
-    if (setup_components(K, pi, mud, cov, c)) return ORC_BAD_PARAMS;
+    if (setup_components(K, pi, mud, mux, cov, c)) return ORC_BAD_PARAMS;
     double lmax = -INFINITY;
     for (int k = 0; k < K; ++k) {
         tangent_coords(o, &c[k], mud + 3 * k, mux + 3 * k, w, p, y);
@@ -498,14 +509,14 @@ static int cell_mstep(const orc_opts *o, int K, int64_t M, double W, const doubl
 
 /* Gate, Sec. 4.2: a cell is updated only with at least min_samples vertices. */
 static int gate(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0, int64_t i1,
-                const double *pi, const double *cov, int64_t *M, double *W)
+                const double *pi, const double *mud, const double *mux, const double *cov,
+                int64_t *M, double *W)
 {
     for (int64_t i = i0; i < i1; ++i)
         if (sample_is_bad(smp, N, i)) return ORC_BAD_INPUT;
     for (int k = 0; k < K; ++k) {
         double L[15];
-        if (chol_packed(5, cov + 15 * k, L) != 0 || !isfinite(pi[k]) || pi[k] < 0.0)
-            return ORC_BAD_PARAMS;
+        if (!component_ok(pi + k, mud + 3 * k, mux + 3 * k, cov + 15 * k, L)) return ORC_BAD_PARAMS;
     }
     *M = 0;
     *W = 0.0;
@@ -533,16 +544,32 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
         const int64_t i0 = offsets[c], i1 = offsets[c + 1];
         const int64_t ck = (int64_t)c * K;
         status[c] = 0;
+        if (i0 < 0 || i1 < i0 || i1 > N) { /* a sample range that does not exist */
+            status[c] = ORC_BAD_INPUT;
+            continue;
+        }
         for (int it = 0; it < o->iters; ++it) {
             int64_t M;
             double W, LL;
-            int g = gate(o, K, smp, N, i0, i1, pi + ck, cov + 15 * ck, &M, &W);
+            int g = gate(o, K, smp, N, i0, i1, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck, &M, &W);
             if (g) {
                 status[c] |= g;
                 break;
             }
             orc_cell_stats(o, K, smp, N, i0, i1, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck,
                            S0, S1, S2, &W, &M, &LL);
+            /* statistics that are not finite (e.g. every component has zero weight) leave
+             * the cell untouched and are reported like bad input */
+            int finite = isfinite(W);
+            for (int t = 0; t < K && finite; ++t) {
+                finite = isfinite(S0[t]);
+                for (int d = 0; d < 5; ++d) finite = finite && isfinite(S1[5 * t + d]);
+                for (int d = 0; d < 15; ++d) finite = finite && isfinite(S2[15 * t + d]);
+            }
+            if (!finite) {
+                status[c] |= ORC_BAD_INPUT;
+                break;
+            }
             status[c] |= cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
                                     cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
         }
@@ -640,7 +667,7 @@ int orc_grad(const orc_opts *o, int32_t K, const float *smp, int64_t N, int64_t 
     int st = orc_cell_stats(o, K, smp, N, i0, i1, pi, mud, mux, cov, S0, S1, S2, &W, &M, &LL);
     if (st) return st;
     comp_t c[ORC_KMAX];
-    setup_components(K, pi, mud, cov, c);
+    setup_components(K, pi, mud, mux, cov, c);
     double Si[ORC_KMAX][25];
     double sum0 = 0.0;
     for (int k = 0; k < K; ++k) {
@@ -854,4 +881,42 @@ int orc_sample(int32_t K, const double *pi, const double *mud, const double *mux
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* counter-based uniforms: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)  */
+/* ------------------------------------------------------------------------- */
+
+/* ten rounds of the Philox S-P network on a 4x32-bit counter with a 2x32-bit key */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* the library's uniforms for draw d under seed s: counter (d_lo, d_hi, 0, 0), key
+ * (s_lo, s_hi); the first three outputs give (x >> 8) * 2^-24 in [0, 1) */
+void orc_draw_uniforms(uint64_t seed, int64_t n, double *u /* [n][3] */)
+{
+    for (int64_t d = 0; d < n; ++d) {
+        uint32_t c[4] = {(uint32_t)d, (uint32_t)((uint64_t)d >> 32), 0u, 0u};
+        uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t o[4];
+        orc_philox4x32_10(c, k, o);
+        for (int j = 0; j < 3; ++j) u[3 * d + j] = (double)(o[j] >> 8) * (1.0 / 16777216.0);
+    }
 }

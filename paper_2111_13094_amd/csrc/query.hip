@@ -1,0 +1,460 @@
+// query.hip -- conditioning of fitted 5-D mixtures on a position, the solid-angle pdf of
+// the conditioned directional mixture, and sampling from it, on gfx950.
+//
+// Method (Dodik et al., arXiv 2111.13094): joint fit conditioned on the position with the
+// standard closed-form Gaussian conditioning (Sec. 3.2 first paragraph, Sec. 3.3); mixture
+// pdf with respect to solid angle (Sec. 3.1, with the change of variables dividing the
+// tangent density by sinc|nu|); sampling by component, tangent Gaussian and exp map, with
+// draws beyond the cut locus |nu| >= pi discarded (Sec. 3.1, "Sampling").
+//
+// Lane mapping as in the E-step: a wave holds 64/G queries (or draws) x G component lanes;
+// normalisations and mixture sums are DPP all-reduces inside the G-lane group.
+#include "common.hpp"
+#include "timing.hpp"
+
+namespace sdmm {
+
+// conditioning table, per component (FP32):
+//   0-8   R_mu rows (t1, t2, mu)           9-11  mu_x
+//   12-17 Lxx^-1 * sqrt(log2(e)/2), packed   18-23 A = Sigma_nx Sigma_xx^-1 (2x3, row-major)
+//   24-26 L' packed (chol of Sigma')         27-29 L'^-1 * sqrt(log2(e)/2), packed
+//   30    log2(pi) - log2 det Lxx - (3/2) log2(2 pi)      (-inf for an unusable component)
+//   31    -log2 det L' - log2(2 pi)
+constexpr float kCutSq = (3.14159265358979323846f * (1.0f - 1e-6f)) * (3.14159265358979323846f * (1.0f - 1e-6f));
+constexpr float kPiSq = 3.14159265358979323846f * 3.14159265358979323846f;
+
+__global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi, const double* __restrict__ mud,
+                                    const double* __restrict__ mux, const double* __restrict__ cov,
+                                    float* __restrict__ table)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)C * K) return;
+    const double* S = cov + 15 * g;
+    float* T = table + g * kCond;
+    bool ok = isfinite(pi[g]) && pi[g] >= 0.0;
+    for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[3 * g + d]) && isfinite(mux[3 * g + d]);
+    double Sxx[6], Lxx[6], Lxi[6], Sp[3], Lp[3], Lpi[3];
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e <= d; ++e) Sxx[tri(d, e)] = S[tri(2 + d, 2 + e)];
+    ok = ok && chol64<3>(Sxx, Lxx);
+    double A[6] = {0, 0, 0, 0, 0, 0};
+    if (ok) {
+        tri_inv64<3>(Lxx, Lxi);
+        // Wm = Lxx^-1 Sigma_xn (3x2); A = Wm^T Lxx^-1; Sigma' = Sigma_nn - Wm^T Wm
+        double Wm[3][2];
+        for (int d = 0; d < 3; ++d)
+            for (int a = 0; a < 2; ++a) {
+                double s = 0.0;
+                for (int e = 0; e <= d; ++e) s += Lxi[tri(d, e)] * S[tri(2 + e, a)];
+                Wm[d][a] = s;
+            }
+        for (int a = 0; a < 2; ++a)
+            for (int d = 0; d < 3; ++d) {
+                double s = 0.0;
+                for (int e = d; e < 3; ++e) s += Wm[e][a] * Lxi[tri(e, d)];
+                A[3 * a + d] = s;
+            }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b <= a; ++b)
+                Sp[tri(a, b)] = S[tri(a, b)] - (Wm[0][a] * Wm[0][b] + Wm[1][a] * Wm[1][b] + Wm[2][a] * Wm[2][b]);
+        ok = chol64<2>(Sp, Lp);
+    }
+    double R[9];
+    if (ok) {
+        frame64(mud + 3 * g, R);
+        tri_inv64<2>(Lp, Lpi);
+    }
+    const double kap = sqrt(0.5 * kLog2e);
+    if (!ok) {
+        for (int i = 0; i < kCond; ++i) T[i] = 0.0f;
+        T[0] = T[4] = T[8] = 1.0f;
+        T[12] = T[14] = T[17] = 1.0f;
+        T[24] = T[26] = T[27] = T[29] = 1.0f;
+        T[30] = -INFINITY;
+        return;
+    }
+    for (int i = 0; i < 9; ++i) T[i] = (float)R[i];
+    for (int d = 0; d < 3; ++d) T[9 + d] = (float)mux[3 * g + d];
+    for (int i = 0; i < 6; ++i) T[12 + i] = (float)(Lxi[i] * kap);
+    for (int i = 0; i < 6; ++i) T[18 + i] = (float)A[i];
+    for (int i = 0; i < 3; ++i) T[24 + i] = (float)Lp[i];
+    for (int i = 0; i < 3; ++i) T[27 + i] = (float)(Lpi[i] * kap);
+    const double ldx = log(Lxx[0]) + log(Lxx[2]) + log(Lxx[5]);
+    T[30] = (float)((log(pi[g]) - ldx - 1.5 * kLn2Pi) * kLog2e);
+    T[31] = (float)((-(log(Lp[0]) + log(Lp[2])) - kLn2Pi) * kLog2e);
+}
+
+// ---------------------------------------------------------------------------------
+// per-lane pieces
+// ---------------------------------------------------------------------------------
+
+// conditional log2-weight and mean of component T at position x
+__device__ __forceinline__ float cond_component(const float* T, float x0, float x1, float x2, float& m0, float& m1)
+{
+    const float d0 = x0 - T[9], d1 = x1 - T[10], d2 = x2 - T[11];
+    const float u0 = T[12] * d0;
+    const float u1 = fmaf(T[13], d0, T[14] * d1);
+    const float u2 = fmaf(T[15], d0, fmaf(T[16], d1, T[17] * d2));
+    const float q = fmaf(u0, u0, fmaf(u1, u1, u2 * u2));
+    m0 = fmaf(T[18], d0, fmaf(T[19], d1, T[20] * d2));
+    m1 = fmaf(T[21], d0, fmaf(T[22], d1, T[23] * d2));
+    return T[30] - q;
+}
+
+// pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k| at direction w (0 at the cut locus)
+__device__ __forceinline__ float pdf_component(const float* T, float wk, float m0, float m1, float wx, float wy,
+                                               float wz)
+{
+    const float xr = fmaf(T[0], wx, fmaf(T[1], wy, T[2] * wz));
+    const float yr = fmaf(T[3], wx, fmaf(T[4], wy, T[5] * wz));
+    const float zr = fmaf(T[6], wx, fmaf(T[7], wy, T[8] * wz));
+    float n0, n1;
+    const float f = log_map_f32(xr, yr, zr, n0, n1);
+    const float r2 = fmaf(n0, n0, n1 * n1);
+    const float d0 = n0 - m0, d1 = n1 - m1;
+    const float u0 = T[27] * d0;
+    const float u1 = fmaf(T[28], d0, T[29] * d1);
+    const float q = fmaf(u0, u0, u1 * u1);
+    const float p = wk * __builtin_amdgcn_exp2f(T[31] - q) * f;
+    return (r2 < kCutSq && wk > 0.0f) ? p : 0.0f;
+}
+
+// Philox4x32-10 (Salmon et al. 2011)
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ void draw_uniforms(const float* uniforms, int64_t n_draws, int64_t d, uint64_t seed,
+                                              float& u0, float& u1, float& u2)
+{
+    if (uniforms) {
+        u0 = uniforms[d];
+        u1 = uniforms[n_draws + d];
+        u2 = uniforms[2 * n_draws + d];
+    } else {
+        const uint4 r = philox4x32_10(make_uint4((uint32_t)d, (uint32_t)((uint64_t)d >> 32), 0u, 0u),
+                                      (uint32_t)seed, (uint32_t)(seed >> 32));
+        u0 = (float)(r.x >> 8) * 0x1.0p-24f;
+        u1 = (float)(r.y >> 8) * 0x1.0p-24f;
+        u2 = (float)(r.z >> 8) * 0x1.0p-24f;
+    }
+}
+
+// One draw for the group's query: pick the component by the CDF of pi' (sequential sum
+// in component order, lowest index on ties), sample nu = m + L' z (Box-Muller), discard
+// at |nu| >= pi, map with the exp map, evaluate the conditioned pdf at the result.
+template <int G>
+__device__ __forceinline__ void sample_one(const float* T, bool usable, float wk, float m0, float m1, int K,
+                                           float u0, float u1, float u2, float& ox, float& oy, float& oz,
+                                           float& pdf, int& valid, int& comp_sel)
+{
+    const int lane = threadIdx.x & 63;
+    const int comp = lane % G, base = lane - comp;
+    float cdf = 0.0f;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const float v = __shfl(wk, base + j);
+        if (j <= comp) cdf += v;
+    }
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const uint64_t hit = __ballot(comp < K && usable && u0 < cdf) & gmask;
+    const uint64_t pos = __ballot(comp < K && usable && wk > 0.0f) & gmask;
+    int sel = -1;
+    if (hit) sel = __builtin_ctzll(hit) - base;
+    else if (pos) sel = 63 - __builtin_clzll(pos) - base;
+    // every lane forms its own component's candidate; the selected one is broadcast
+    const float rad = sqrtf(-2.0f * logf(1.0f - u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    const float z0 = rad * cs, z1 = rad * sn;
+    const float n0 = fmaf(T[24], z0, m0);
+    const float n1 = fmaf(T[25], z0, fmaf(T[26], z1, m1));
+    float w[3];
+    exp_map_f32(T, n0, n1, w);
+    const int ok = fmaf(n0, n0, n1 * n1) < kPiSq;
+    const int src = base + (sel < 0 ? 0 : sel);
+    ox = __shfl(w[0], src);
+    oy = __shfl(w[1], src);
+    oz = __shfl(w[2], src);
+    valid = (sel >= 0) ? __shfl(ok, src) : 0;
+    comp_sel = sel;
+    const float c = pdf_component(T, wk, m0, m1, ox, oy, oz);
+    pdf = group_sum<G>(comp < K ? c : 0.0f);
+    if (!valid) {
+        ox = oy = oz = 0.0f;
+        pdf = 0.0f;
+    }
+}
+
+__device__ __forceinline__ const float* table_row(const float* table, int qc, int K, int comp, bool usable)
+{
+    const int kk = comp < K ? comp : K - 1;
+    return table + ((int64_t)(usable ? qc : 0) * K + kk) * kCond;
+}
+
+__device__ __forceinline__ void load_row(const float* src, float* T)
+{
+    const float4* p = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int q = 0; q < kCond / 4; ++q) {
+        const float4 v = p[q];
+        T[4 * q] = v.x;
+        T[4 * q + 1] = v.y;
+        T[4 * q + 2] = v.z;
+        T[4 * q + 3] = v.w;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// kernels: the loop trip count is uniform per wave so every group reaches the DPP steps
+// ---------------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(256) void condition_kernel(const float* __restrict__ table, int C, int K,
+                                                        const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
+                                                        int64_t nq, float* __restrict__ cw, float* __restrict__ cm)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q0 = wave * S; q0 < nq; q0 += nwaves * S) {
+        const int64_t q = q0 + slot;
+        const bool inq = q < nq;
+        const int qc = inq ? qcell[q] : 0;
+        const bool usable = inq && qc >= 0 && qc < C;
+        float T[kCond];
+        load_row(table_row(table, qc, K, comp, usable), T);
+        const int64_t qq = inq ? q : 0;
+        float m0, m1;
+        float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
+        if (comp >= K || !usable) lw = -INFINITY;
+        const float lmax = group_max<G>(lw);
+        const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
+        const float den = group_sum<G>(e);
+        const float wk = den > 0.0f ? e / den : 0.0f;
+        if (inq && comp < K) {
+            cw[q * K + comp] = wk;
+            cm[(q * K + comp) * 2] = usable ? m0 : 0.0f;
+            cm[(q * K + comp) * 2 + 1] = usable ? m1 : 0.0f;
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void pdf_kernel(const float* __restrict__ table, int C, int K,
+                                                  const int32_t* __restrict__ qcell, int64_t nq,
+                                                  const float* __restrict__ cw, const float* __restrict__ cm, int nd,
+                                                  const float* __restrict__ dirs, float* __restrict__ pdf_out)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t np = nq * nd;
+    for (int64_t p0 = wave * S; p0 < np; p0 += nwaves * S) {
+        const int64_t p = p0 + slot;
+        const bool inp = p < np;
+        const int64_t pp = inp ? p : 0;
+        const int64_t q = pp / nd;
+        const int qc = qcell[q];
+        const bool usable = inp && qc >= 0 && qc < C && comp < K;
+        float T[kCond];
+        load_row(table_row(table, qc, K, comp, usable), T);
+        const int kk = comp < K ? comp : K - 1;
+        const float wk = usable ? cw[q * K + kk] : 0.0f;
+        const float m0 = cm[(q * K + kk) * 2], m1 = cm[(q * K + kk) * 2 + 1];
+        const float c = pdf_component(T, wk, m0, m1, dirs[pp], dirs[np + pp], dirs[2 * np + pp]);
+        const float tot = group_sum<G>(usable ? c : 0.0f);
+        if (inp && comp == 0) pdf_out[p] = tot;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void sample_kernel(const float* __restrict__ table, int C, int K,
+                                                     const int32_t* __restrict__ qcell, int64_t nq,
+                                                     const float* __restrict__ cw, const float* __restrict__ cm,
+                                                     int ns, const float* __restrict__ uniforms, uint64_t seed,
+                                                     float* __restrict__ dirs_out, float* __restrict__ pdf_out,
+                                                     uint8_t* __restrict__ valid_out, int32_t* __restrict__ comp_out)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = nq * ns;
+    for (int64_t d0 = wave * S; d0 < nd; d0 += nwaves * S) {
+        const int64_t d = d0 + slot;
+        const bool ind = d < nd;
+        const int64_t dd = ind ? d : 0;
+        const int64_t q = dd / ns;
+        const int qc = qcell[q];
+        const bool usable = ind && qc >= 0 && qc < C;
+        float T[kCond];
+        load_row(table_row(table, qc, K, comp, usable), T);
+        const int kk = comp < K ? comp : K - 1;
+        const float wk = (usable && comp < K) ? cw[q * K + kk] : 0.0f;
+        const float m0 = cm[(q * K + kk) * 2], m1 = cm[(q * K + kk) * 2 + 1];
+        float u0, u1, u2;
+        draw_uniforms(uniforms, nd, dd, seed, u0, u1, u2);
+        float ox, oy, oz, pdf;
+        int valid, sel;
+        sample_one<G>(T, usable, wk, m0, m1, K, u0, u1, u2, ox, oy, oz, pdf, valid, sel);
+        if (ind && comp == 0) {
+            dirs_out[d] = ox;
+            dirs_out[nd + d] = oy;
+            dirs_out[2 * nd + d] = oz;
+            pdf_out[d] = pdf;
+            valid_out[d] = (uint8_t)valid;
+            if (comp_out) comp_out[d] = sel;
+        }
+    }
+}
+
+// conditioning + ns draws + pdf per query, pi' and m kept in registers
+template <int G>
+__global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __restrict__ table, int C, int K,
+                                                              const float* __restrict__ qpos,
+                                                              const int32_t* __restrict__ qcell, int64_t nq, int ns,
+                                                              const float* __restrict__ uniforms, uint64_t seed,
+                                                              float* __restrict__ dirs_out, float* __restrict__ pdf_out,
+                                                              uint8_t* __restrict__ valid_out)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = nq * ns;
+    for (int64_t q0 = wave * S; q0 < nq; q0 += nwaves * S) {
+        const int64_t q = q0 + slot;
+        const bool inq = q < nq;
+        const int64_t qq = inq ? q : 0;
+        const int qc = qcell[qq];
+        const bool usable = inq && qc >= 0 && qc < C;
+        float T[kCond];
+        load_row(table_row(table, qc, K, comp, usable), T);
+        float m0, m1;
+        float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
+        if (comp >= K || !usable) lw = -INFINITY;
+        const float lmax = group_max<G>(lw);
+        const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
+        const float den = group_sum<G>(e);
+        const float wk = den > 0.0f ? e / den : 0.0f;
+        for (int t = 0; t < ns; ++t) {
+            const int64_t d = qq * ns + t;
+            float u0, u1, u2;
+            draw_uniforms(uniforms, nd, d, seed, u0, u1, u2);
+            float ox, oy, oz, pdf;
+            int valid, sel;
+            sample_one<G>(T, usable, wk, m0, m1, K, u0, u1, u2, ox, oy, oz, pdf, valid, sel);
+            if (inq && comp == 0) {
+                dirs_out[d] = ox;
+                dirs_out[nd + d] = oy;
+                dirs_out[2 * nd + d] = oz;
+                pdf_out[d] = pdf;
+                valid_out[d] = (uint8_t)valid;
+            }
+        }
+    }
+}
+
+// grid for a wave-strided loop over `items` work units of S per wave
+static unsigned grid_for(int64_t items, int S)
+{
+    const int64_t waves = (items + S - 1) / S;
+    int64_t blocks = (waves + 3) / 4;
+    const int64_t cap = 256 * 32;  // 256 CUs x 32 waves of 256-thread blocks
+    if (blocks > cap) blocks = cap;
+    return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+#define SDMM_DISPATCH_G(G, CALL)         \
+    switch (G) {                         \
+        case 4: { constexpr int g = 4; CALL; } break;   \
+        case 8: { constexpr int g = 8; CALL; } break;   \
+        case 16: { constexpr int g = 16; CALL; } break; \
+        case 32: { constexpr int g = 32; CALL; } break; \
+        default: { constexpr int g = 64; CALL; } break; \
+    }
+
+}  // namespace sdmm
+
+using namespace sdmm;
+
+extern "C" int sdmm_condition_prepare(const sdmm_mixtures* mix, float* table, void* stream)
+{
+    if (!mix || !table || mix->n_cells <= 0 || mix->K < 1 || mix->K > kMaxK) return SDMM_EINVAL;
+    if (!mix->weights || !mix->mean_dir || !mix->mean_pos || !mix->cov) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t nk = (int64_t)mix->n_cells * mix->K;
+    cond_prepare_kernel<<<(unsigned)((nk + 255) / 256), 256, 0, s>>>(mix->n_cells, mix->K, mix->weights,
+                                                                      mix->mean_dir, mix->mean_pos, mix->cov, table);
+    return check(hipGetLastError());
+}
+
+extern "C" int sdmm_condition(const float* table, int32_t n_cells, int32_t K, const float* qpos,
+                              const int32_t* qcell, int64_t nq, float* cond_w, float* cond_m, void* stream)
+{
+    if (!table || n_cells <= 0 || K < 1 || K > kMaxK || nq < 0) return SDMM_EINVAL;
+    if (nq == 0) return SDMM_OK;
+    if (!qpos || !qcell || !cond_w || !cond_m) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K);
+    SDMM_DISPATCH_G(G, (condition_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(table, n_cells, K, qpos, qcell,
+                                                                                  nq, cond_w, cond_m)));
+    return check(hipGetLastError());
+}
+
+extern "C" int sdmm_pdf(const float* table, int32_t n_cells, int32_t K, const int32_t* qcell, int64_t nq,
+                        const float* cond_w, const float* cond_m, int32_t nd, const float* dirs, float* pdf_out,
+                        void* stream)
+{
+    if (!table || n_cells <= 0 || K < 1 || K > kMaxK || nq < 0 || nd < 0) return SDMM_EINVAL;
+    if (nq == 0 || nd == 0) return SDMM_OK;
+    if (!qcell || !cond_w || !cond_m || !dirs || !pdf_out) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K);
+    SDMM_DISPATCH_G(G, (pdf_kernel<g><<<grid_for(nq * nd, 64 / g), 256, 0, s>>>(table, n_cells, K, qcell, nq, cond_w,
+                                                                                 cond_m, nd, dirs, pdf_out)));
+    return check(hipGetLastError());
+}
+
+extern "C" int sdmm_sample(const float* table, int32_t n_cells, int32_t K, const int32_t* qcell, int64_t nq,
+                           const float* cond_w, const float* cond_m, int32_t ns, const float* uniforms,
+                           uint64_t seed, float* dirs_out, float* pdf_out, uint8_t* valid_out, int32_t* comp_out,
+                           void* stream)
+{
+    if (!table || n_cells <= 0 || K < 1 || K > kMaxK || nq < 0 || ns < 0) return SDMM_EINVAL;
+    if (nq == 0 || ns == 0) return SDMM_OK;
+    if (!qcell || !cond_w || !cond_m || !dirs_out || !pdf_out || !valid_out) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K);
+    SDMM_DISPATCH_G(G, (sample_kernel<g><<<grid_for(nq * ns, 64 / g), 256, 0, s>>>(
+                           table, n_cells, K, qcell, nq, cond_w, cond_m, ns, uniforms, seed, dirs_out, pdf_out,
+                           valid_out, comp_out)));
+    return check(hipGetLastError());
+}
+
+extern "C" int sdmm_condition_sample_pdf(const float* table, int32_t n_cells, int32_t K, const float* qpos,
+                                         const int32_t* qcell, int64_t nq, int32_t ns, const float* uniforms,
+                                         uint64_t seed, float* dirs_out, float* pdf_out, uint8_t* valid_out,
+                                         void* stream)
+{
+    if (!table || n_cells <= 0 || K < 1 || K > kMaxK || nq < 0 || ns < 0) return SDMM_EINVAL;
+    if (nq == 0 || ns == 0) return SDMM_OK;
+    if (!qpos || !qcell || !dirs_out || !pdf_out || !valid_out) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K);
+    ScopedTimer tm(SDMM_TIMER_QUERY, s);
+    SDMM_DISPATCH_G(G, (cond_sample_pdf_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
+                           table, n_cells, K, qpos, qcell, nq, ns, uniforms, seed, dirs_out, pdf_out, valid_out)));
+    return check(hipGetLastError());
+}

@@ -1,0 +1,274 @@
+"""Python binding of libsdmm (argument marshalling only).
+
+Every function here takes torch tensors that already live on the GPU, passes their
+device pointers and the current HIP stream to the C ABI declared in include/sdmm.h, and
+returns. All arithmetic runs in the library's HIP kernels; there is no CPU fallback, and
+loading fails loudly when the built library is missing.
+
+Names follow the C ABI: fit_mixtures, condition_prepare, condition, pdf, sample,
+condition_sample_pdf, fit_grad.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libsdmm.so")
+
+OK, EINVAL, EDEVICE, ENOWORKSPACE = 0, -1, -2, -3
+SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD_PARAMS = 1, 2, 4, 8, 16, 32
+ETA_CONSTANT, ETA_PAPER = 0, 1
+PRIOR_ETA_OVER_M, PRIOR_FIXED = 0, 1
+FLAG_ESTEP_JACOBIAN, FLAG_PLAIN_FP32, FLAG_FP64_SUMS = 1, 2, 4
+SCHED_BATCHED, SCHED_PER_CELL = 0, 1
+COND_TABLE_STRIDE = 32
+
+
+class FitOpts(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
+        ("flags", C.c_int32), ("min_samples", C.c_int32), ("schedule", C.c_int32), ("chunk", C.c_int32),
+        ("waves", C.c_int32), ("use_graph", C.c_int32),
+        ("eta", C.c_double), ("rm_alpha", C.c_double), ("rm_beta", C.c_double), ("prior_scale", C.c_double),
+        ("prior_q", C.c_double), ("prior_a", C.c_double), ("prior_b", C.c_double * 5),
+        ("dead_threshold", C.c_double),
+    ]
+
+
+class Mixtures(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("K", C.c_int32), ("weights", C.c_void_p), ("mean_dir", C.c_void_p),
+                ("mean_pos", C.c_void_p), ("cov", C.c_void_p)]
+
+
+class EmState(C.Structure):
+    _fields_ = [("s0", C.c_void_p), ("s2", C.c_void_p), ("sw", C.c_void_p), ("step", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsdmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libsdmm.so not found at {LIB_PATH}; build it with "
+                               "`python -m paper_2111_13094_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+        P = C.POINTER
+        L.sdmm_fit_workspace_size.argtypes = [i32, i32, i64, P(FitOpts)]
+        L.sdmm_fit_workspace_size.restype = sz
+        L.sdmm_fit_mixtures.argtypes = [vp, vp, i64, P(Mixtures), P(EmState), P(FitOpts), vp, vp, sz, vp]
+        L.sdmm_condition_prepare.argtypes = [P(Mixtures), vp, vp]
+        L.sdmm_condition.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp]
+        L.sdmm_pdf.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, vp, vp]
+        L.sdmm_sample.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, u64, vp, vp, vp, vp, vp]
+        L.sdmm_condition_sample_pdf.argtypes = [vp, i32, i32, vp, vp, i64, i32, vp, u64, vp, vp, vp, vp]
+        L.sdmm_fit_grad.argtypes = [vp, vp, i64, P(Mixtures), P(FitOpts), vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.sdmm_status_string.argtypes = [C.c_int]
+        L.sdmm_status_string.restype = C.c_char_p
+        L.sdmm_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(t: torch.Tensor | None, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to libsdmm must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libsdmm must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise RuntimeError(f"{what} failed: {lib().sdmm_status_string(rc).decode()} ({rc})")
+
+
+def default_opts(K: int = 16, **kw) -> FitOpts:
+    """Options with the paper's constants (Sec. 4.3): q = 1/K, a = 5/K,
+    B = a diag(0.1, 0.1, 1, 1, 1) 1e-4, Robbins-Monro alpha = 0.5, beta = 0.1, and the
+    minimum of 16 samples per leaf (Sec. 4.2)."""
+    o = FitOpts()
+    o.K = K
+    o.iters = 1
+    o.eta_mode = ETA_CONSTANT
+    o.eta = 1.0
+    o.rm_alpha, o.rm_beta = 0.5, 0.1
+    o.prior_mode = PRIOR_ETA_OVER_M
+    o.prior_scale = 0.0
+    o.prior_q = 1.0 / K
+    o.prior_a = 5.0 / K
+    for i, v in enumerate((0.1, 0.1, 1.0, 1.0, 1.0)):
+        o.prior_b[i] = o.prior_a * v * 1e-4
+    o.min_samples = 16
+    o.dead_threshold = 1e-12
+    o.schedule = SCHED_BATCHED
+    for k, v in kw.items():
+        if k == "prior_b":
+            for i in range(5):
+                o.prior_b[i] = v[i]
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def _mixtures(mix: dict, n_cells: int, K: int) -> Mixtures:
+    m = Mixtures()
+    m.n_cells, m.K = n_cells, K
+    m.weights = _ptr(mix["pi"], torch.float64)
+    m.mean_dir = _ptr(mix["mu_dir"], torch.float64)
+    m.mean_pos = _ptr(mix["mu_pos"], torch.float64)
+    m.cov = _ptr(mix["cov"], torch.float64)
+    for key, n in (("pi", 1), ("mu_dir", 3), ("mu_pos", 3), ("cov", 15)):
+        if mix[key].numel() != n_cells * K * n:
+            raise ValueError(f"mixture array {key} has {mix[key].numel()} values, expected {n_cells * K * n}")
+    return m
+
+
+def new_state(n_cells: int, K: int, device="cuda") -> dict:
+    return {"s0": torch.zeros(n_cells * K, dtype=torch.float64, device=device),
+            "s2": torch.zeros(n_cells * K * 15, dtype=torch.float64, device=device),
+            "sw": torch.zeros(n_cells, dtype=torch.float64, device=device),
+            "step": torch.zeros(n_cells, dtype=torch.int32, device=device)}
+
+
+_ws_cache: dict = {}
+
+
+def workspace_bytes(n_cells: int, K: int, n_samples: int, opts: FitOpts) -> int:
+    return int(lib().sdmm_fit_workspace_size(n_cells, K, n_samples, C.byref(opts)))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    key = (str(device),)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, state: dict, opts: FitOpts,
+                 status: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """opts.iters E+M iterations of every cell (sdmm_fit_mixtures). ``samples`` is
+    float32 [7, N]; ``cell_offsets`` int64 [C+1]; ``mix``/``state`` dicts of device
+    tensors updated in place. Returns the int32 per-cell status tensor."""
+    n_cells = cell_offsets.numel() - 1
+    K = opts.K
+    if samples.dim() != 2 or samples.shape[0] != 7:
+        raise ValueError("samples must be [7, N]")
+    N = samples.shape[1]
+    if status is None:
+        status = torch.empty(n_cells, dtype=torch.int32, device=samples.device)
+    nbytes = workspace_bytes(n_cells, K, N, opts)
+    if workspace is None:
+        workspace = _workspace(nbytes, samples.device)
+    m = _mixtures(mix, n_cells, K)
+    st = EmState()
+    st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
+    st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
+    rc = lib().sdmm_fit_mixtures(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N, C.byref(m),
+                                 C.byref(st), C.byref(opts), _ptr(status, torch.int32), _ptr(workspace),
+                                 workspace.numel(), _stream(stream))
+    _check(rc, "sdmm_fit_mixtures")
+    return status
+
+
+def condition_prepare(mix: dict, n_cells: int, K: int, table: torch.Tensor | None = None, stream=None):
+    if table is None:
+        table = torch.empty(n_cells * K * COND_TABLE_STRIDE, dtype=torch.float32, device=mix["pi"].device)
+    m = _mixtures(mix, n_cells, K)
+    _check(lib().sdmm_condition_prepare(C.byref(m), _ptr(table, torch.float32), _stream(stream)),
+           "sdmm_condition_prepare")
+    return table
+
+
+def condition(table, n_cells, K, qpos, qcell, stream=None):
+    """qpos float32 [3, nq]; qcell int32 [nq]. Returns (cond_w [nq, K], cond_m [nq, K, 2])."""
+    nq = qcell.numel()
+    cw = torch.empty(nq, K, dtype=torch.float32, device=qcell.device)
+    cm = torch.empty(nq, K, 2, dtype=torch.float32, device=qcell.device)
+    _check(lib().sdmm_condition(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
+                                _ptr(qcell, torch.int32), nq, _ptr(cw), _ptr(cm), _stream(stream)), "sdmm_condition")
+    return cw, cm
+
+
+def pdf(table, n_cells, K, qcell, cond_w, cond_m, dirs, nd, stream=None):
+    """dirs float32 [3, nq*nd]. Returns pdf float32 [nq*nd]."""
+    nq = qcell.numel()
+    out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
+    _check(lib().sdmm_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qcell, torch.int32), nq,
+                          _ptr(cond_w, torch.float32), _ptr(cond_m, torch.float32), nd, _ptr(dirs, torch.float32),
+                          _ptr(out), _stream(stream)), "sdmm_pdf")
+    return out
+
+
+def sample(table, n_cells, K, qcell, cond_w, cond_m, ns, uniforms=None, seed=0, with_comp=False, stream=None):
+    """ns draws per query. uniforms float32 [3, nq*ns] or None (device Philox4x32-10).
+    Returns (dirs [3, nq*ns], pdf [nq*ns], valid uint8 [nq*ns], comp int32 or None)."""
+    nq = qcell.numel()
+    dev = qcell.device
+    n = nq * ns
+    dirs = torch.empty(3, n, dtype=torch.float32, device=dev)
+    pdfv = torch.empty(n, dtype=torch.float32, device=dev)
+    valid = torch.empty(n, dtype=torch.uint8, device=dev)
+    comp = torch.empty(n, dtype=torch.int32, device=dev) if with_comp else None
+    _check(lib().sdmm_sample(_ptr(table, torch.float32), n_cells, K, _ptr(qcell, torch.int32), nq,
+                             _ptr(cond_w, torch.float32), _ptr(cond_m, torch.float32), ns,
+                             _ptr(uniforms, torch.float32), seed, _ptr(dirs), _ptr(pdfv), _ptr(valid),
+                             _ptr(comp), _stream(stream)), "sdmm_sample")
+    return dirs, pdfv, valid, comp
+
+
+def condition_sample_pdf(table, n_cells, K, qpos, qcell, ns, uniforms=None, seed=0, out=None, stream=None):
+    """Fused conditioning + sampling + pdf. Returns (dirs [3, nq*ns], pdf, valid)."""
+    nq = qcell.numel()
+    dev = qcell.device
+    n = nq * ns
+    if out is None:
+        out = (torch.empty(3, n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.uint8, device=dev))
+    dirs, pdfv, valid = out
+    _check(lib().sdmm_condition_sample_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
+                                           _ptr(qcell, torch.int32), nq, ns, _ptr(uniforms, torch.float32), seed,
+                                           _ptr(dirs), _ptr(pdfv), _ptr(valid), _stream(stream)),
+           "sdmm_condition_sample_pdf")
+    return dirs, pdfv, valid
+
+
+def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=None):
+    """F and its gradient per cell (sdmm_fit_grad). Returns a dict of device tensors."""
+    n_cells = cell_offsets.numel() - 1
+    K = opts.K
+    N = samples.shape[1]
+    dev = samples.device
+    out = {"F": torch.empty(n_cells, dtype=torch.float64, device=dev),
+           "alpha": torch.empty(n_cells, K, dtype=torch.float64, device=dev),
+           "mu_pos": torch.empty(n_cells, K, 3, dtype=torch.float64, device=dev),
+           "delta": torch.empty(n_cells, K, 2, dtype=torch.float64, device=dev),
+           "L": torch.empty(n_cells, K, 15, dtype=torch.float64, device=dev),
+           "status": torch.empty(n_cells, dtype=torch.int32, device=dev)}
+    nbytes = workspace_bytes(n_cells, K, N, opts)
+    if workspace is None:
+        workspace = _workspace(nbytes, dev)
+    m = _mixtures(mix, n_cells, K)
+    rc = lib().sdmm_fit_grad(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N, C.byref(m),
+                             C.byref(opts), _ptr(out["F"]), _ptr(out["alpha"]), _ptr(out["mu_pos"]),
+                             _ptr(out["delta"]), _ptr(out["L"]), _ptr(out["status"]), _ptr(workspace),
+                             workspace.numel(), _stream(stream))
+    _check(rc, "sdmm_fit_grad")
+    return out

@@ -1,0 +1,77 @@
+"""The C ABI library loads, exports every entry point declared in include/sdmm.h, and
+rejects bad arguments on the host before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdmm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdmm_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2111_13094_amd import sdmm
+    if not os.path.exists(sdmm.LIB_PATH):
+        pytest.fail("libsdmm.so is not built (run __graft_entry__.build())")
+    return sdmm.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("sdmm_fit_mixtures", "sdmm_condition_prepare", "sdmm_condition", "sdmm_pdf", "sdmm_sample",
+              "sdmm_condition_sample_pdf", "sdmm_fit_grad", "sdmm_fit_workspace_size", "sdmm_status_string"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(lib):
+    assert lib.sdmm_status_string(0) == b"ok"
+    assert lib.sdmm_status_string(-3) == b"workspace too small"
+    assert lib.sdmm_version().startswith(b"sdmm")
+
+
+def test_workspace_size_and_argument_errors(lib):
+    from paper_2111_13094_amd import sdmm
+    o = sdmm.default_opts(16)
+    ws = lib.sdmm_fit_workspace_size(4096, 16, 4_000_000, C.byref(o))
+    assert ws > 4096 * 16 * 32 * 4
+    assert lib.sdmm_fit_workspace_size(0, 16, 10, C.byref(o)) == 0
+    assert lib.sdmm_fit_workspace_size(1, 65, 10, C.byref(o)) == 0
+    m = sdmm.Mixtures()
+    st = sdmm.EmState()
+    # null pointers are rejected before any device work
+    assert lib.sdmm_fit_mixtures(None, None, 0, C.byref(m), C.byref(st), C.byref(o), None, None, 0, None) == -1
+    assert lib.sdmm_condition(None, 1, 16, None, None, 1, None, None, None) == -1
+    assert lib.sdmm_condition(C.c_void_p(8), 1, 16, None, None, 0, None, None, None) == 0  # empty
+    assert lib.sdmm_pdf(C.c_void_p(8), 1, 65, None, 1, None, None, 1, None, None, None) == -1
+    # a workspace below the reported size is refused
+    m.n_cells, m.K = 1, 16
+    m.weights = m.mean_dir = m.mean_pos = m.cov = C.c_void_p(256)
+    st.s0 = st.s2 = st.sw = st.step = C.c_void_p(256)
+    need = lib.sdmm_fit_workspace_size(1, 16, 100, C.byref(o))
+    rc = lib.sdmm_fit_mixtures(C.c_void_p(256), C.c_void_p(256), 100, C.byref(m), C.byref(st), C.byref(o),
+                               C.c_void_p(256), C.c_void_p(256), need - 1, None)
+    assert rc == -3
+    o.K = 8  # K mismatch between options and mixtures
+    assert lib.sdmm_fit_mixtures(C.c_void_p(256), C.c_void_p(256), 100, C.byref(m), C.byref(st), C.byref(o),
+                                 C.c_void_p(256), C.c_void_p(256), need, None) == -1
+
+
+def test_struct_layouts_match_the_header():
+    from paper_2111_13094_amd import sdmm
+    assert C.sizeof(sdmm.FitOpts) == 10 * 4 + 12 * 8
+    assert sdmm.FitOpts.eta.offset == 40
+    assert C.sizeof(sdmm.Mixtures) == 8 + 4 * 8
+    assert C.sizeof(sdmm.EmState) == 4 * 8

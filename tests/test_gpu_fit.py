@@ -1,0 +1,282 @@
+"""GPU parity of sdmm_fit_mixtures (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2111_13094_amd import synth
+from tests.parity_utils import assert_close, compare_mixtures, state_to_torch, to_numpy, to_torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_13094_amd import sdmm
+    sdmm.lib()
+    return torch
+
+
+def _gpu_fit(dev, batch, mix, state, **opt):
+    from paper_2111_13094_amd import sdmm
+    K = opt.pop("K", 16)
+    o = sdmm.default_opts(K, **opt)
+    off = dev.from_numpy(batch.offsets).cuda()
+    smp = dev.from_numpy(batch.samples).cuda()
+    status = sdmm.fit_mixtures(off, smp, mix, state, o)
+    dev.cuda.synchronize()
+    return status.cpu().numpy()
+
+
+def _orc_opts(orc, K=16, **kw):
+    return orc.Opts(K=K, **kw)
+
+
+def _single(n=16384, seed=1234):
+    wl = synth.workload("single", seed=seed)
+    b = synth.make_batch(seed + 5, [n], wl["box_lo"], wl["box_size"], wl["lobes"], parallax=True)
+    return wl, b
+
+
+def test_single_cell_one_step_parity(dev, orc):
+    print("case: single cell N=16384 K=16, one E+M step", flush=True)
+    wl, b = _single()
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    s_o = orc.fit(_orc_opts(orc), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    s_g = _gpu_fit(dev, b, gm, gst)
+    assert (s_g == s_o).all(), (s_g, s_o)
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print(worst)
+    assert_close(worst, what="one step")
+    g = to_numpy(gst)
+    assert g["step"][0] == ost["step"][0] == 1
+    assert abs(g["sw"][0] - ost["sw"][0]) <= 1e-6 * ost["sw"][0]
+    assert np.allclose(g["s0"], ost["s0"], rtol=1e-4, atol=1e-9 * ost["sw"][0])
+
+
+def test_single_cell_twenty_iterations(dev, orc):
+    print("case: single cell N=16384 K=16, 20 iterations", flush=True)
+    wl, b = _single(seed=99)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    worst_all = []
+    for it in range(20):
+        orc.fit(_orc_opts(orc), b.offsets, b.samples, om, ost)
+        _gpu_fit(dev, b, gm, gst)
+        w = compare_mixtures(to_numpy(gm), om, 16)
+        worst_all.append(max(w["pi"], w["mu_pos"], w["cov"], w["mu_dir"] * 10))
+    print("per-iteration worst:", ["%.1e" % v for v in worst_all])
+    assert max(worst_all) < 1e-3
+    # the same 20 iterations as one call
+    gm2, gst2 = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, gm2, gst2, iters=20)
+    for k in gm:
+        assert dev.equal(gm[k], gm2[k]), k
+
+
+def _ragged_case():
+    wl = synth.workload("cells4k", scale=64 / 4096)
+    C = wl["grid"].n_cells
+    counts = wl["counts"].copy()
+    counts[0] = 0          # empty
+    counts[1] = 7          # too few
+    counts[2] = 16         # exactly the minimum
+    counts[3] = 20000      # several work items
+    counts[4] = 65         # one more than a 64-sample multiple
+    b = synth.make_batch(77, counts, wl["box_lo"], wl["box_size"], wl["lobes"])
+    off = b.offsets
+    smp = b.samples
+    smp[6, off[2]:off[3]] = np.abs(smp[6, off[2]:off[3]]) + 0.5  # all positive
+    smp[0, off[5] + 2] = np.nan                                  # bad input
+    smp[6, off[6] + 1] = -2.0                                    # negative weight
+    smp[6, off[7]:off[8]] = 0.0                                  # zero weights
+    smp[3, off[9] + 4] = np.inf                                  # infinite position
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    cov = mix["cov"].reshape(C, 16, 15)
+    cov[10, 5, 0] = -1.0                                         # non-SPD parameters
+    mix["pi"].reshape(C, 16)[11, 3] = np.nan                     # non-finite weight
+    return wl, b, mix
+
+
+def test_ragged_cells_statuses_and_isolation(dev, orc):
+    print("case: 64 ragged cells with gated / bad cells", flush=True)
+    wl, b, mix0 = _ragged_case()
+    C = wl["grid"].n_cells
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    s_o = orc.fit(_orc_opts(orc, iters=2), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    s_g = _gpu_fit(dev, b, gm, gst, iters=2)
+    assert (s_g == s_o).all(), np.nonzero(s_g != s_o)
+    assert s_o[0] == orc.SKIPPED_FEW and s_o[1] == orc.SKIPPED_FEW
+    assert s_o[5] == orc.BAD_INPUT and s_o[6] == orc.BAD_INPUT and s_o[9] == orc.BAD_INPUT
+    assert s_o[7] == orc.SKIPPED_FEW
+    assert s_o[10] == orc.BAD_PARAMS and s_o[11] == orc.BAD_PARAMS
+    got = to_numpy(gm)
+    skipped = [c for c in range(C) if s_o[c] & (1 | 2 | 4 | 32)]
+    for c in skipped:  # untouched, bitwise
+        for k in got:
+            assert np.array_equal(got[k].reshape(C, -1)[c], mix0[k].reshape(C, -1)[c], equal_nan=True)
+    fitted = [c for c in range(C) if c not in skipped]
+    worst = compare_mixtures(got, om, 16, cells=fitted)
+    print(worst)
+    assert_close(worst, rtol=2e-4, ang_tol=2e-5, what="ragged cells, 2 iterations")
+
+
+def test_batched_per_cell_and_graph_are_bitwise_equal_and_deterministic(dev, orc):
+    print("case: batched vs per-cell vs graph replay, 64 cells", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl, b, mix0 = _ragged_case()
+    C = wl["grid"].n_cells
+    runs = []
+    for sched, graph in ((sdmm.SCHED_BATCHED, 0), (sdmm.SCHED_BATCHED, 0), (sdmm.SCHED_PER_CELL, 0),
+                         (sdmm.SCHED_BATCHED, 1)):
+        gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+        s = _gpu_fit(dev, b, gm, gst, iters=2, schedule=sched, use_graph=graph)
+        runs.append((to_numpy(gm), to_numpy(gst), s))
+    for m, st, s in runs[1:]:
+        assert (s == runs[0][2]).all()
+        for k in m:
+            assert np.array_equal(m[k], runs[0][0][k], equal_nan=True), k
+        for k in st:
+            assert np.array_equal(st[k], runs[0][1][k], equal_nan=True), k
+
+
+def test_graph_replays_match_eager(dev, orc):
+    print("case: repeated graph replays vs eager", flush=True)
+    wl = synth.workload("cells4k", scale=27 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    ge, gse = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    gg, gsg = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    for rep in range(4):
+        _gpu_fit(dev, b, ge, gse, eta=0.1)
+        _gpu_fit(dev, b, gg, gsg, eta=0.1, use_graph=1)
+        for k in ge:
+            assert dev.equal(ge[k], gg[k]), (rep, k)
+
+
+def test_cell_independence_bitwise(dev, orc):
+    print("case: cells fitted together vs alone", flush=True)
+    wl = synth.workload("cells4k", scale=27 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    _gpu_fit(dev, b, gm, gst, iters=2)
+    allm = to_numpy(gm)
+    for c in (0, 5, C - 1):
+        i0, i1 = b.offsets[c], b.offsets[c + 1]
+        sub = synth.Batch(np.ascontiguousarray(b.samples[:, i0:i1]), np.array([0, i1 - i0]), b.lobe[i0:i1])
+        mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
+        g1, s1 = to_torch(mc), state_to_torch(orc.new_state(1, 16))
+        _gpu_fit(dev, sub, g1, s1, iters=2)
+        for k, v in to_numpy(g1).items():
+            assert np.array_equal(v, allm[k].reshape(C, -1)[c]), (c, k)
+
+
+def test_stepwise_batches_parity(dev, orc):
+    print("case: 27 cells, 8 batches, eta = 0.1 (decay 0.9)", flush=True)
+    wl = synth.workload("cells4k", scale=27 / 4096)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    worst = []
+    for j in range(8):
+        b = synth.workload_batch(wl, j)
+        orc.fit(_orc_opts(orc, eta=0.1), b.offsets, b.samples, om, ost)
+        _gpu_fit(dev, b, gm, gst, eta=0.1)
+        w = compare_mixtures(to_numpy(gm), om, 16)
+        worst.append(max(w["pi"], w["mu_pos"], w["cov"], 10 * w["mu_dir"]))
+    print("per-batch worst:", ["%.1e" % v for v in worst])
+    assert max(worst) < 1e-3
+    g = to_numpy(gst)
+    assert (g["step"] == ost["step"]).all()
+
+
+@pytest.mark.parametrize("K", [5, 12, 32])
+def test_other_component_counts(dev, orc, K):
+    print(f"case: single cell N=8192 K={K}", flush=True)
+    wl, b = _single(n=8192, seed=7 + K)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, K)
+    orc.fit(_orc_opts(orc, K=K, iters=2), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, K))
+    _gpu_fit(dev, b, gm, gst, K=K, iters=2)
+    worst = compare_mixtures(to_numpy(gm), om, K)
+    print(worst)
+    assert_close(worst, rtol=2e-4, ang_tol=2e-5, what=f"K={K}")
+
+
+@pytest.mark.parametrize("variant", ["plain", "fp64", "jacobian", "paper_eta", "fixed_prior"])
+def test_option_variants(dev, orc, variant):
+    print(f"case: option variant {variant}", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl, b = _single(n=8192, seed=31)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    gopt, oopt = {"iters": 2}, {"iters": 2}
+    if variant == "plain":
+        gopt["flags"] = sdmm.FLAG_PLAIN_FP32
+    elif variant == "fp64":
+        gopt["flags"] = sdmm.FLAG_FP64_SUMS
+    elif variant == "jacobian":
+        gopt["flags"] = sdmm.FLAG_ESTEP_JACOBIAN
+        oopt["estep_jacobian"] = 1
+    elif variant == "paper_eta":
+        gopt.update(eta_mode=sdmm.ETA_PAPER)
+        oopt.update(eta_mode=1)
+    elif variant == "fixed_prior":
+        gopt.update(prior_mode=sdmm.PRIOR_FIXED, prior_scale=0.25)
+        oopt.update(prior_mode=1, prior_scale=0.25)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    orc.fit(_orc_opts(orc, **oopt), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, gm, gst, **gopt)
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print(worst)
+    assert_close(worst, rtol=3e-4 if variant == "plain" else 2e-4, ang_tol=3e-5, what=variant)
+
+
+def test_huge_cell_grows_its_work_items(dev, orc):
+    """A cell with more than 1024 work items of the configured size: the library grows
+    the item size (at most 1024 items per cell)."""
+    print("case: one cell of 150000 samples with chunk=64", flush=True)
+    wl, b = _single(n=150000, seed=5)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    orc.fit(_orc_opts(orc), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, gm, gst, chunk=64)
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print(worst)
+    assert_close(worst, what="huge cell")
+
+
+def test_full_size_cells4k_sampled_cells(dev, orc):
+    """The 4096-cell workload at full size in the benchmark's launch configuration; the
+    oracle recomputes 24 sampled cells (chosen across the count range) one by one."""
+    print("case: cells4k full size, one step, 24 sampled cells", flush=True)
+    wl = synth.workload("cells4k")
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    s_g = _gpu_fit(dev, b, gm, gst, eta=0.1)
+    got = to_numpy(gm)
+    order = np.argsort(wl["counts"])
+    cells = sorted(set(order[np.linspace(0, C - 1, 24).astype(int)].tolist()))
+    for c in cells:
+        i0, i1 = b.offsets[c], b.offsets[c + 1]
+        sub = np.ascontiguousarray(b.samples[:, i0:i1])
+        mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
+        st = orc.new_state(1, 16)
+        s_o = orc.fit(_orc_opts(orc, eta=0.1), np.array([0, i1 - i0]), sub, mc, st)
+        assert s_o[0] == s_g[c]
+        gc = {k: v.reshape(C, -1)[c] for k, v in got.items()}
+        worst = compare_mixtures(gc, mc, 16)
+        assert_close(worst, rtol=2e-4, ang_tol=2e-5, what=f"cell {c} (n={i1 - i0})")
