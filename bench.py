@@ -93,7 +93,7 @@ def cpu_baseline(wl, batch, target_s=12.0):
         return pairs, t
 
     p0, t0 = run(order[:16])
-    n = int(min(C, max(16, 16 * target_s / max(t0, 1e-3))))
+    n = int(min(C - 16, max(16, 16 * target_s / max(t0, 1e-3))))
     p1, t1 = run(order[16:16 + n])
     pairs, t = p0 + p1, t0 + t1
     return {"value": pairs / t, "unit": "updates/s", "cores": 1, "kind": "oracle",
@@ -180,6 +180,14 @@ def bench_cells4k(args, torch):
                         "speedup_batched_over_plain": value / (ppairs / pt)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, batches[0], target_s=args.cpu_seconds)
+    if args.copy_probe:
+        # a plain device copy of known size, to scale the HBM byte counters of a profiler run
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        _sync(torch)
+        out["copy_probe_bytes"] = src.numel() * 4
     return out
 
 
@@ -220,6 +228,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true", help="also run a device copy of known size")
+    ap.add_argument("--copy-probe-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the cells are independent, so more GPUs would each fit their "

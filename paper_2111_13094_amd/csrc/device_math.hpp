@@ -17,7 +17,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2Pi = 1.8378770664093453;  // log(2 pi)
 constexpr int kStats = 21;                     // S0, S1[5], S2[15] (packed)
-constexpr int kMirror = 32;                    // floats per component, E-step mirror
+constexpr int kMirror = 48;                    // floats per component, E-step mirror
 constexpr int kCond = 32;                      // floats per component, conditioning table
 constexpr int kMaxK = 64;
 
@@ -71,16 +71,26 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 constexpr int kDppMirror = 0x140;     // row_mirror
 
+// Maximum over the group, taken on an integer key that orders floats totally
+// (sign-magnitude to two's complement), so each step is one fused v_max_i32 with DPP.
+template <int CTRL>
+__device__ __forceinline__ int dpp_max_i32(int k)
+{
+    return max(k, __builtin_amdgcn_update_dpp(0, k, CTRL, 0xF, 0xF, true));
+}
+
 template <int G>
 __device__ __forceinline__ float group_max(float v)
 {
-    if constexpr (G >= 2) v = fmaxf(v, dpp_f32<kDppXor1>(v));
-    if constexpr (G >= 4) v = fmaxf(v, dpp_f32<kDppXor2>(v));
-    if constexpr (G >= 8) v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
-    if constexpr (G >= 16) v = fmaxf(v, dpp_f32<kDppMirror>(v));
-    if constexpr (G >= 32) v = fmaxf(v, __shfl_xor(v, 16));
-    if constexpr (G >= 64) v = fmaxf(v, __shfl_xor(v, 32));
-    return v;
+    const int iv = __float_as_int(v);
+    int k = iv ^ ((iv >> 31) & 0x7fffffff);
+    if constexpr (G >= 2) k = dpp_max_i32<kDppXor1>(k);
+    if constexpr (G >= 4) k = dpp_max_i32<kDppXor2>(k);
+    if constexpr (G >= 8) k = dpp_max_i32<kDppHalfMirror>(k);
+    if constexpr (G >= 16) k = dpp_max_i32<kDppMirror>(k);
+    if constexpr (G >= 32) k = max(k, __shfl_xor(k, 16));
+    if constexpr (G >= 64) k = max(k, __shfl_xor(k, 32));
+    return __int_as_float(k ^ ((k >> 31) & 0x7fffffff));
 }
 
 template <int G>
@@ -100,7 +110,8 @@ __device__ __forceinline__ float group_sum(float v)
 // nu = (theta / s) w'_xy. theta / s as a function of z = cos theta is smooth on [0, 1];
 // g(z) below is a degree-9 fit (max relative error 1.8e-7 in FP32 Horner form,
 // generated by gen_logmap_poly.py). For z < 0, theta = pi - theta(|z|), so
-// theta / s = pi / s - g(|z|). The exact antipode maps to (pi, 0).
+// theta / s = pi / s - g(|z|). A 1e-18 offset on w'_x (below the rounding of any x
+// that is not itself below 1e-11) keeps s > 0, so the exact antipode maps to (pi, 0).
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ float theta_over_sin_pos(float z)
 {
@@ -120,16 +131,13 @@ __device__ __forceinline__ float theta_over_sin_pos(float z)
 // returns f = theta / sin(theta) (= 1 / sinc |nu|) and writes nu
 __device__ __forceinline__ float log_map_f32(float x, float y, float z, float& n0, float& n1)
 {
+    x += 1e-18f;
     const float g = theta_over_sin_pos(fabsf(z));
     const float s2 = fmaf(x, x, y * y);
     const float rs = __builtin_amdgcn_rsqf(s2);
-    const bool neg = z < 0.0f;
-    const float f = neg ? fmaf(kPiF, rs, -g) : g;
+    const float f = z < 0.0f ? fmaf(kPiF, rs, -g) : g;
     n0 = f * x;
     n1 = f * y;
-    const bool anti = neg && (s2 == 0.0f);
-    n0 = anti ? kPiF : n0;
-    n1 = anti ? 0.0f : n1;
     return f;
 }
 

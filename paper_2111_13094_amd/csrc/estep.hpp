@@ -100,9 +100,11 @@ __device__ __forceinline__ void frame_twist64(const double mu[3], const double R
 
 // ---------------------------------------------------------------------------------
 // FP32 E-step mirror of one component: R (9), mu_x (3), Linv * sqrt(log2(e)/2) (15),
-// c * log2(e) with c = log pi - log det L - (5/2) log 2 pi (1), and the frame twist rates
-// (2) used by the adjoint. Returns false and writes an inert mirror (identity frame and
-// factor) when the component is unusable.
+// c * log2(e) with c = log pi - log det L - (5/2) log 2 pi (1), the frame twist rates (2)
+// used by the adjoint, and the FP32 rounding residues of R (9) and mu_x (3), with which
+// the adjoint pass forms tangent coordinates to FP32 relative accuracy (its gradients
+// are small differences near stationarity). Returns false and writes an inert mirror
+// (identity frame and factor) when the component is unusable.
 // ---------------------------------------------------------------------------------
 __device__ inline bool write_mirror(double pi, const double* mud, const double* mux, const double* cov,
                              float* out)
@@ -133,6 +135,9 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     out[28] = (float)phi[0];
     out[29] = (float)phi[1];
     out[30] = out[31] = 0.0f;
+    for (int i = 0; i < 9; ++i) out[32 + i] = (float)(R[i] - (double)out[i]);
+    for (int d = 0; d < 3; ++d) out[41 + d] = (float)(mux[d] - (double)out[9 + d]);
+    for (int i = 44; i < kMirror; ++i) out[i] = 0.0f;
     return true;
 }
 
@@ -220,9 +225,9 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
     const int kk = comp < K ? comp : K - 1;
 
     const float4* mp = reinterpret_cast<const float4*>(mirror_cell + (int64_t)kk * kMirror);
-    float P[32];
+    float P[44];
 #pragma unroll
-    for (int q = 0; q < (ADJ ? 8 : 7); ++q) {
+    for (int q = 0; q < (ADJ ? 11 : 7); ++q) {
         const float4 v = mp[q];
         P[4 * q] = v.x;
         P[4 * q + 1] = v.y;
@@ -243,22 +248,29 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
     const int64_t stride = (int64_t)nwaves * S;
     const int64_t steps = (n + stride - 1) / stride;
     const uint32_t last = (uint32_t)(n > 0 ? n - 1 : 0);
-    uint32_t i = (uint32_t)(wave * S + slot);
-    SampleRegs cur{};
-    if (steps > 0) cur = load_sample(ch, min(i, last));
-    for (int64_t it = 0; it < steps; ++it) {
-        const bool valid = i <= last;
-        const uint32_t inext = i + (uint32_t)stride;
-        const SampleRegs nxt = load_sample(ch, min(inext, last));  // prefetch the next step
+    const uint32_t ustride = (uint32_t)stride;
+
+    // one (sample, component) pair per lane
+    auto body = [&](const SampleRegs& cur, bool valid) {
         const float w = valid ? cur.w : 0.0f;
 
         // tangent coordinates y = (log_mu w, p - mu_x)
-        const float xr = fmaf(P[0], cur.ox, fmaf(P[1], cur.oy, P[2] * cur.oz));
-        const float yr = fmaf(P[3], cur.ox, fmaf(P[4], cur.oy, P[5] * cur.oz));
-        const float zr = fmaf(P[6], cur.ox, fmaf(P[7], cur.oy, P[8] * cur.oz));
+        float xr = fmaf(P[0], cur.ox, fmaf(P[1], cur.oy, P[2] * cur.oz));
+        float yr = fmaf(P[3], cur.ox, fmaf(P[4], cur.oy, P[5] * cur.oz));
+        float zr = fmaf(P[6], cur.ox, fmaf(P[7], cur.oy, P[8] * cur.oz));
+        if constexpr (ADJ) {  // add the residue of the FP32-rounded frame
+            xr += fmaf(P[32], cur.ox, fmaf(P[33], cur.oy, P[34] * cur.oz));
+            yr += fmaf(P[35], cur.ox, fmaf(P[36], cur.oy, P[37] * cur.oz));
+            zr += fmaf(P[38], cur.ox, fmaf(P[39], cur.oy, P[40] * cur.oz));
+        }
         float y0, y1;
         const float f = log_map_f32(xr, yr, zr, y0, y1);
-        const float y2 = cur.px - P[9], y3 = cur.py - P[10], y4 = cur.pz - P[11];
+        float y2 = cur.px - P[9], y3 = cur.py - P[10], y4 = cur.pz - P[11];
+        if constexpr (ADJ) {
+            y2 -= P[41];
+            y3 -= P[42];
+            y4 -= P[43];
+        }
 
         // log2 of pi_k N5(y; 0, Sigma_k) through the scaled inverse Cholesky factor
         const float z0 = P[12] * y0;
@@ -266,12 +278,11 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
         const float z2 = fmaf(P[15], y0, fmaf(P[16], y1, P[17] * y2));
         const float z3 = fmaf(P[18], y0, fmaf(P[19], y1, fmaf(P[20], y2, P[21] * y3)));
         const float z4 = fmaf(P[22], y0, fmaf(P[23], y1, fmaf(P[24], y2, fmaf(P[25], y3, P[26] * y4))));
-        float q = z0 * z0;
-        q = fmaf(z1, z1, q);
-        q = fmaf(z2, z2, q);
-        q = fmaf(z3, z3, q);
-        q = fmaf(z4, z4, q);
-        float l = c2 - q;
+        float l = fmaf(-z0, z0, c2);
+        l = fmaf(-z1, z1, l);
+        l = fmaf(-z2, z2, l);
+        l = fmaf(-z3, z3, l);
+        l = fmaf(-z4, z4, l);
         if constexpr (JAC) l += __log2f(f);  // solid-angle density: divide by sinc|nu| = times f
 
         // responsibilities: log-sum-exp across the component lanes of this sample
@@ -324,15 +335,28 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
             acc[NS - 2].add(wr * fmaf(D00, u0, D10 * u1));
             acc[NS - 1].add(wr * fmaf(D01, u0, D11 * u1));
         }
-
-        if ((it % kFoldEvery) == kFoldEvery - 1) {
+    };
+    auto fold_all = [&]() {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) acc[s].fold();
-            accll.fold();
-        }
-        cur = nxt;
-        i = inext;
+        for (int s = 0; s < NS; ++s) acc[s].fold();
+        accll.fold();
+    };
+
+    // two steps per trip with alternating prefetch registers (no register copies)
+    uint32_t i = (uint32_t)(wave * S + slot);
+    SampleRegs a{}, b{};
+    if (steps > 0) a = load_sample(ch, min(i, last));
+    int64_t it = 0;
+    for (; it + 1 < steps; it += 2) {
+        b = load_sample(ch, min(i + ustride, last));
+        body(a, i <= last);
+        i += ustride;
+        a = load_sample(ch, min(i + ustride, last));
+        body(b, i <= last);
+        i += ustride;
+        if (((it + 2) % kFoldEvery) == 0) fold_all();
     }
+    if (it < steps) body(a, i <= last);
 
     double v[NR];
 #pragma unroll
