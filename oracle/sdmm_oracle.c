@@ -540,14 +540,19 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
     const int K = o->K;
     if (K < 1 || K > ORC_KMAX) return -1;
     double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
+    /* the offsets must partition a prefix of the sample array: non-decreasing, from >= 0
+     * to <= N. An array that is not is rejected as a whole: every cell reports bad input
+     * and nothing changes (a decreasing entry says the batch itself is malformed). */
+    int offsets_ok = n_cells == 0 || (offsets[0] >= 0 && offsets[n_cells] <= N);
+    for (int32_t c = 0; c < n_cells && offsets_ok; ++c) offsets_ok = offsets[c + 1] >= offsets[c];
+    if (!offsets_ok) {
+        for (int32_t c = 0; c < n_cells; ++c) status[c] = ORC_BAD_INPUT;
+        return 0;
+    }
     for (int32_t c = 0; c < n_cells; ++c) {
         const int64_t i0 = offsets[c], i1 = offsets[c + 1];
         const int64_t ck = (int64_t)c * K;
         status[c] = 0;
-        if (i0 < 0 || i1 < i0 || i1 > N) { /* a sample range that does not exist */
-            status[c] = ORC_BAD_INPUT;
-            continue;
-        }
         for (int it = 0; it < o->iters; ++it) {
             int64_t M;
             double W, LL;

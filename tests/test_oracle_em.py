@@ -406,3 +406,34 @@ def test_tangent_mode_objective_nearly_monotone(orc):
     dips = np.diff(F) / np.abs(F[1:])
     assert dips.min() >= -1e-6, dips.min()
     assert F[-1] > F[0]
+
+
+def test_malformed_offsets_reject_the_whole_batch(orc):
+    """Offsets that decrease anywhere, start below 0 or end beyond the sample count make
+    every cell report BAD_INPUT and leave every parameter unchanged."""
+    wl = synth.workload("cells4k", scale=8 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    N = b.samples.shape[1]
+    bad = []
+    o1 = b.offsets.copy()
+    o1[3], o1[4] = o1[4], o1[3]
+    bad.append(o1)
+    o2 = b.offsets.copy()
+    o2[-1] = N + 1
+    bad.append(o2)
+    o3 = b.offsets.copy()
+    o3[0] = -1
+    bad.append(o3)
+    for off in bad:
+        m, s, stat = _fit_copy(orc, orc.Opts(K=16), off, b.samples, mix)
+        assert (stat == orc.BAD_INPUT).all()
+        for k in m:
+            assert np.array_equal(m[k], mix[k])
+        assert (s["step"] == 0).all()
+    # a prefix of the array is fine: samples after the last offset are not used
+    o4 = b.offsets.copy()
+    o4[-1] = o4[-2]
+    m, s, stat = _fit_copy(orc, orc.Opts(K=16), o4, b.samples, mix)
+    assert stat[-1] == orc.SKIPPED_FEW and (stat[:-1] & orc.BAD_INPUT == 0).all()
