@@ -62,11 +62,15 @@ def _sync(torch):
     torch.cuda.synchronize()
 
 
+_GEN_CACHE = {}
+
+
 def _gen_cells4k(n_batches):
     from paper_2111_13094_amd import synth
-    wl = synth.workload("cells4k")
-    batches = [synth.workload_batch(wl, j) for j in range(n_batches)]
-    return wl, batches
+    if n_batches not in _GEN_CACHE:
+        wl = synth.workload("cells4k")
+        _GEN_CACHE[n_batches] = (wl, [synth.workload_batch(wl, j) for j in range(n_batches)])
+    return _GEN_CACHE[n_batches]
 
 
 def cpu_baseline(wl, batch, target_s=12.0):
@@ -114,11 +118,11 @@ def bench_cells4k(args, torch):
     def fresh():
         return {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}, sdmm.new_state(C, K, dev)
 
-    opts = sdmm.default_opts(K, eta=0.1)
-    if args.chunk:
-        opts.chunk = args.chunk
-    if args.waves:
-        opts.waves = args.waves
+    opts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_FUSED if args.schedule == "fused" else sdmm.SCHED_BATCHED)
+    if args.min_range:
+        opts.min_range = args.min_range
+    if args.max_ranges:
+        opts.max_ranges = args.max_ranges
     status = torch.empty(C, dtype=torch.int32, device=dev)
     ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
     mix, st = fresh()
@@ -129,7 +133,9 @@ def bench_cells4k(args, torch):
     L.sdmm_timing_enable(1)
     import ctypes as C_
     tot, cnt = C_.c_double(), C_.c_int64()
+    mtot, mcnt = C_.c_double(), C_.c_int64()
     L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+    L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
     _sync(torch)
     t0 = time.perf_counter()
     pairs = 0
@@ -140,8 +146,10 @@ def bench_cells4k(args, torch):
     _sync(torch)
     t1 = time.perf_counter()
     L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+    L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
     L.sdmm_timing_enable(0)
     est_ms = tot.value / max(cnt.value, 1)
+    m_ms = mtot.value / max(mcnt.value, 1) if mcnt.value else None
     wall = t1 - t0
     value = pairs / wall
     flops_per_launch = FLOPS_PER_PAIR * (pairs / args.steps)
@@ -156,11 +164,14 @@ def bench_cells4k(args, torch):
                                "lognormal(6.45,1) clipped to [64,8192], 8 resident batches, stepwise EM "
                                "eta=0.1, FP32 E-step with compensated sums, FP64 M-step",
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
-                   "chunk": int(opts.chunk or 1024), "waves": int(opts.waves or 4)},
+                   "schedule": args.schedule, "min_range": int(opts.min_range or 256),
+                   "max_ranges": int(opts.max_ranges or 4096)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "estep_kernel<16,TwoSum>", "kernel_ms": est_ms,
-                     "flops_per_launch": flops_per_launch},
+                     "kernel": ("fused_kernel<16,TwoSum,false>" if args.schedule == "fused"
+                                else "estep_kernel<16,TwoSum,false,false>"),
+                     "kernel_ms": est_ms, "flops_per_launch": flops_per_launch},
+        "mstep_ms": m_ms,
     }
     if not args.no_plain:
         popts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_PER_CELL)
@@ -189,6 +200,92 @@ def bench_cells4k(args, torch):
         _sync(torch)
         out["copy_probe_bytes"] = src.numel() * 4
     return out
+
+
+def query_flops(K, ns):
+    """Algorithmic FP32 flops of the fused conditioning + sampling + pdf path per query
+    (an FMA counts 2): conditioning 31 per component (offset 3, L_xx^-1 d 9, |u|^2 5,
+    m = A d 10, log weight 1, softmax 3); per draw the component CDF (K), one candidate
+    (Box-Muller 4, nu = m + L' z 6, exp map 25, validity 3) and the pdf of the whole
+    mixture at the drawn direction, 56 per component (rotation 15, log map 25, |nu|^2 3,
+    nu - m 2, L'^-1 5, quadratic form 3, weight x exp x 1/sinc 2, sum 1)."""
+    return 31 * K + ns * (K + 38 + 56 * K)
+
+
+def bench_cells16k(args, torch):
+    """Conditioning + sampling + pdf on the 16384-cell workload (32x32x16 cells of the unit
+    cube, K = 16, geometric counts, 2^22 query positions sorted by cell, 4 draws each with
+    the device Philox generator), after one batched E+M step on the workload's samples."""
+    import ctypes as C_
+    from paper_2111_13094_amd import sdmm, synth
+    wl = synth.workload("cells16k")
+    b = synth.workload_batch(wl)
+    C, K, ns = wl["grid"].n_cells, 16, 4
+    dev = torch.device("cuda", 0)
+    off, smp = torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    mix = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+    st = sdmm.new_state(C, K, dev)
+    opts = sdmm.default_opts(K)
+    status = sdmm.fit_mixtures(off, smp, mix, st, opts)
+    _sync(torch)
+    table = sdmm.condition_prepare(mix, C, K)
+    qpos, qcell = synth.make_queries(7, wl["box_lo"], wl["box_size"], 256)
+    nq = qcell.size
+    qp = torch.from_numpy(np.ascontiguousarray(qpos.T)).to(dev)
+    qc = torch.from_numpy(qcell).to(dev)
+    out = (torch.empty(3, nq * ns, dtype=torch.float32, device=dev), torch.empty(nq * ns, dtype=torch.float32, device=dev),
+           torch.empty(nq * ns, dtype=torch.uint8, device=dev))
+    for w in range(args.warmup):
+        sdmm.condition_sample_pdf(table, C, K, qp, qc, ns, seed=w, out=out)
+    _sync(torch)
+    t_fit = fit_time(args, torch, off, smp, mix0, C, K, opts)
+    L = sdmm.lib()
+    L.sdmm_timing_enable(1)
+    tot, cnt = C_.c_double(), C_.c_int64()
+    L.sdmm_timing_read(2, C_.byref(tot), C_.byref(cnt), 1)
+    _sync(torch)
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        sdmm.condition_sample_pdf(table, C, K, qp, qc, ns, seed=1000 + s_, out=out)
+    _sync(torch)
+    wall = time.perf_counter() - t0
+    L.sdmm_timing_read(2, C_.byref(tot), C_.byref(cnt), 1)
+    L.sdmm_timing_enable(0)
+    k_ms = tot.value / max(cnt.value, 1)
+    fl = query_flops(K, ns) * nq
+    achieved = fl / (k_ms * 1e-3) / 1e12
+    valid_frac = float(out[2].float().mean().item())
+    return {"metric": "guided draws/s (conditioning + sampling + pdf), 16384 cells K=16, 4 draws per query",
+            "value": nq * ns * args.steps / wall, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "cells16k: 16384 cells (32x32x16), K=16, counts 16+Geom(1/1009)-1 clipped to "
+                                   "[16,32768], 2^22 query positions (256 per cell), 4 draws each (Philox4x32-10), "
+                                   "fused conditioning + sampling + pdf after one E+M step",
+                       "n_cells": C, "K": K, "queries": nq, "draws_per_query": ns,
+                       "samples": int(smp.shape[1]), "valid_fraction": valid_frac,
+                       "fitted_cells": int(((status.cpu().numpy() & (1 | 2 | 4 | 32)) == 0).sum())},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "cond_sample_pdf_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl},
+            "fit": {"value": smp.shape[1] * K / t_fit, "unit": "updates/s", "ms_per_step": t_fit * 1e3}}
+
+
+def fit_time(args, torch, off, smp, mix0, C, K, opts, steps=5):
+    """Average wall time of one batched E+M step from fresh mixtures and state."""
+    from paper_2111_13094_amd import sdmm
+    dev = smp.device
+    tot = 0.0
+    for _ in range(steps):
+        m = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+        s = sdmm.new_state(C, K, dev)
+        _sync(torch)
+        t1 = time.perf_counter()
+        sdmm.fit_mixtures(off, smp, m, s, opts)
+        _sync(torch)
+        tot += time.perf_counter() - t1
+    return tot / steps
 
 
 def bench_single(args, torch):
@@ -222,9 +319,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "single"])
-    ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "single"])
+    ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
+    ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
+    ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
+    ap.add_argument("--sweep", default="", help="comma-separated schedule:items points, e.g. batched:256,fused:512")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -240,8 +339,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.sweep:  # launch-configuration sweep on the cells4k workload, one line per point
+        for point in args.sweep.split(","):
+            sched, p = point.split(":")
+            args.schedule, args.min_range, args.max_ranges = sched, int(p), 1 << 20
+            args.no_plain = args.no_cpu = True
+            print(json.dumps(bench_cells4k(args, torch)), flush=True)
+        return
     if args.workload == "cells4k":
         out = bench_cells4k(args, torch)
+    elif args.workload == "cells16k":
+        out = bench_cells16k(args, torch)
     else:
         out = bench_single(args, torch)
     print(json.dumps(out))

@@ -68,11 +68,12 @@ extern "C" {
 #define SDMM_FLAG_PLAIN_FP32 2     /* precision study: plain FP32 running sums */
 #define SDMM_FLAG_FP64_SUMS 4      /* precision study: FP64 running sums */
 
-#define SDMM_SCHED_BATCHED 0  /* all cells in one E launch + one M launch per iteration */
+#define SDMM_SCHED_BATCHED 0  /* per iteration one E launch for all cells, then one M
+                                 launch for all cells */
 #define SDMM_SCHED_PER_CELL 1 /* plain baseline: one E and one M launch per cell; copies
                                  cell_offsets to the host and synchronises the stream */
-#define SDMM_SCHED_FUSED 2    /* one launch per iteration: the last chunk of a cell to
-                                 finish runs that cell's M-step */
+#define SDMM_SCHED_FUSED 2    /* one E+M launch per iteration: the last wave to finish a
+                                 cell's E-step items runs that cell's M-step */
 
 typedef struct sdmm_fit_opts {
     int32_t K;           /* components per cell, 1..64 */
@@ -82,8 +83,11 @@ typedef struct sdmm_fit_opts {
     int32_t flags;       /* SDMM_FLAG_* */
     int32_t min_samples; /* 16 in the paper (Sec. 4.2) */
     int32_t schedule;    /* SDMM_SCHED_* */
-    int32_t chunk;       /* samples per work item (multiple of 64; 0 = library default) */
-    int32_t waves;       /* waves per work group: 1, 2, 4 or 8 (0 = library default) */
+    int32_t min_range;   /* E-step work split: the samples are cut into ranges of
+                            P = max(min_range, ceil(N / max_ranges)) samples and each
+                            (cell, range) intersection is one wave's work item;
+                            0 = 256. Results do not depend on it beyond FP rounding. */
+    int32_t max_ranges;  /* upper bound on the number of ranges, 0 = 4096, at most 2^20 */
     int32_t use_graph;   /* 1: capture the iteration sequence in a hipGraph, cached by
                             argument values, and replay it */
     double eta;          /* Robbins-Monro weight of a new batch for SDMM_ETA_CONSTANT */
@@ -222,11 +226,55 @@ int sdmm_condition_sample_pdf(const float *table, int32_t n_cells, int32_t K, co
  * g_L [device] float64[n_cells*K*15]; cell_status [device] int32[n_cells] (gate as in
  * sdmm_fit_mixtures with min_samples; skipped cells get F = 0 and zero gradients).
  * workspace: at least sdmm_fit_workspace_size(n_cells, K, n_samples, opts) bytes.
+ * Precision: by default the pass forms tangent coordinates and products in FP32 with
+ * compensated sums and the quadratic form in FP64. With SDMM_FLAG_FP64_SUMS in
+ * opts->flags every per-sample quantity is FP64 (verification mode: about 4x slower).
+ * SDMM_FLAG_ESTEP_JACOBIAN is rejected (SDMM_EINVAL).
  */
 int sdmm_fit_grad(const int64_t *cell_offsets, const float *samples, int64_t n_samples,
                   const sdmm_mixtures *mix, const sdmm_fit_opts *opts, double *F_out,
                   double *g_alpha, double *g_mu_pos, double *g_delta, double *g_L,
                   int32_t *cell_status, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sdmm_mixture_from_params -- the unconstrained parameterisation for gradient-based
+ * refinement (the adjoint is derived from the MAP objective of Sec. 4.3; the paper itself
+ * has no gradients): per cell pi = softmax(alpha); mu_dir = exp_{mu0}(delta) with the
+ * exp map of Sec. 3.1 in the frame of mu0 (the fit's frame); mu_pos copied;
+ * Sigma = L L^T.
+ * alpha [device] float64[n_cells*K]; mu_dir0 [device] float64[n_cells*K*3] (normalised
+ * here); delta [device] float64[n_cells*K*2]; mu_pos [device] float64[n_cells*K*3];
+ * L [device] float64[n_cells*K*15] packed lower-triangular, row-major (index d(d+1)/2+e).
+ * out: mixtures of the same n_cells and K, written (caller-owned device arrays).
+ * jac_out [device] float64[n_cells*K*4] or NULL: the 2x2 Jacobian (row-major) of
+ * delta -> log_{mu_dir}(exp_{mu0}(delta)) (the first-order transfer of Sec. 3.4 at
+ * nu = delta), for sdmm_grad_to_params. Returns SDMM_EINVAL on bad sizes or NULL arrays.
+ */
+int sdmm_mixture_from_params(int32_t n_cells, int32_t K, const double *alpha, const double *mu_dir0,
+                             const double *delta, const double *mu_pos, const double *L,
+                             const sdmm_mixtures *out, double *jac_out, void *stream);
+
+/*
+ * sdmm_params_from_mixture -- the refinement parameters of a mixture: alpha = log pi and
+ * L = the packed Cholesky factor of Sigma (positive pivots); delta = 0 and mu_dir0 =
+ * mean_dir, mu_pos = mean_pos are the caller's to set. alpha [device] float64[n_cells*K],
+ * L [device] float64[n_cells*K*15], cell_status [device] int32[n_cells] or NULL
+ * (0, or SDMM_CELL_BAD_PARAMS for a cell with a non-SPD Sigma or a weight <= 0; its
+ * L rows are 0 and alpha may be -inf).
+ */
+int sdmm_params_from_mixture(const sdmm_mixtures *mix, double *alpha, double *L, int32_t *cell_status,
+                             void *stream);
+
+/*
+ * sdmm_grad_to_params -- pulls the gradients of sdmm_fit_grad (taken at the mixture that
+ * sdmm_mixture_from_params produced) back onto (delta, L), in place:
+ * g_delta := J^T g_delta; the columns e of g_L with L_ee < 0 change sign (sdmm_fit_grad
+ * differentiates with respect to the Cholesky factor of Sigma, whose pivots are positive).
+ * The alpha and mu_pos gradients need no change. Arrays as in sdmm_mixture_from_params;
+ * g_delta [device] float64[n_cells*K*2], g_L [device] float64[n_cells*K*15].
+ */
+int sdmm_grad_to_params(int32_t n_cells, int32_t K, const double *L, const double *jac, double *g_delta,
+                        double *g_L, void *stream);
 
 /* ---- measurement ---- */
 

@@ -27,41 +27,18 @@ struct StatePtrs {
     int32_t* step;
 };
 
-// Workspace: FP32 mirrors, per-cell flags, chunk tables and per-chunk FP64 records. The
-// record is sized for the larger (adjoint) pass so one workspace serves every call.
+// Workspace: FP32 mirrors, per-cell flags and arrival counters, the offsets check, and the
+// FP64 records of the E-step (one per record slot; C + W slots with W = ceil(N / P)).
+// Records are sized for the larger (adjoint) pass so one workspace serves every call.
 struct Layout {
-    size_t mirror, flags, chunk_start, chunk_cell, n_total, partial, total;
-    int64_t tmax;
+    size_t mirror, flags, arrive, global_ok, records, total;
+    int64_t P;  // samples per E-step work item, 2^ps
+    int ps;
+    int W;
     int ps_fit, ps_grad;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-inline int default_chunk(const sdmm_fit_opts* o) { return o->chunk > 0 ? o->chunk : 1024; }
-inline int default_waves(const sdmm_fit_opts* o) { return o->waves > 0 ? o->waves : 4; }
-
-inline Layout layout_for(int32_t C, int32_t K, int64_t N, int64_t chunk)
-{
-    Layout L{};
-    L.tmax = (int64_t)C + (N + chunk - 1) / chunk;
-    L.ps_fit = (kStats * K + 3 + 1) & ~1;
-    L.ps_grad = ((kStats + 2) * K + 4 + 1) & ~1;
-    size_t p = 0;
-    L.mirror = p;
-    p = align256(p + (size_t)C * K * kMirror * sizeof(float));
-    L.flags = p;
-    p = align256(p + (size_t)C * sizeof(int32_t));
-    L.chunk_start = p;
-    p = align256(p + (size_t)(C + 1) * sizeof(int32_t));
-    L.chunk_cell = p;
-    p = align256(p + (size_t)L.tmax * sizeof(int32_t));
-    L.n_total = p;
-    p = align256(p + sizeof(int32_t));
-    L.partial = p;
-    p = align256(p + (size_t)L.tmax * (size_t)L.ps_grad * sizeof(double));
-    L.total = p;
-    return L;
-}
 
 // component lanes per sample: K rounded up to a power of two, at least 4
 inline int group_for(int K)
@@ -70,6 +47,49 @@ inline int group_for(int K)
     while (G < K) G <<= 1;
     return G;
 }
+
+
+constexpr int kDefaultWaves = 4096;   // 256 CUs x 4 SIMDs x 4 waves
+constexpr int kDefaultMinSamplesPerWave = 256;
+
+inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o)
+{
+    Layout L{};
+    const int64_t wmax = o->max_ranges > 0 ? o->max_ranges : kDefaultWaves;
+    const int64_t pmin = o->min_range > 0 ? o->min_range : kDefaultMinSamplesPerWave;
+    int64_t P = (N + wmax - 1) / wmax;
+    if (P < pmin) P = pmin;
+    L.ps = 0;
+    while ((int64_t(1) << L.ps) < P) ++L.ps;  // a power of two: item maps are shifts
+    P = int64_t(1) << L.ps;
+    L.P = P;
+    L.W = N > 0 ? (int)((N + P - 1) / P) : 0;
+    const int G = group_for(K);  // records keep statistic s of component k at s * G + k
+    L.ps_fit = (kStats * G + 3 + 1) & ~1;
+    L.ps_grad = ((kStats + 2) * G + 4 + 1) & ~1;
+    size_t p = 0;
+    L.mirror = p;
+    p = align256(p + (size_t)C * K * kMirror * sizeof(float));
+    L.flags = p;
+    p = align256(p + (size_t)C * sizeof(int32_t));
+    L.arrive = p;
+    p = align256(p + (size_t)C * sizeof(int32_t));
+    L.global_ok = p;
+    p = align256(p + sizeof(int32_t));
+    L.records = p;
+    p = align256(p + ((size_t)C + (size_t)L.W) * (size_t)L.ps_grad * sizeof(double));
+    L.total = p;
+    return L;
+}
+
+// lanes per cell in the M-step and setup kernels: K rounded up to a power of two
+inline int group_pow2(int K)
+{
+    int G = 1;
+    while (G < K) G <<= 1;
+    return G;
+}
+
 
 inline int check(hipError_t e)
 {
@@ -104,8 +124,20 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
                       const sdmm_mixtures* mix, const sdmm_fit_opts* opts, const int32_t* cell_status,
                       const void* workspace, size_t workspace_bytes);
 
-// plan (chunk table, cleared status and flags) + FP32 mirrors, enqueued on s
-void launch_plan_prepare(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int64_t chunk, int32_t* status,
-                         char* ws, const Layout& L, hipStream_t s);
+typedef void (*EstepFn)(const float*, int64_t, const int64_t*, int, int, int64_t, int64_t, const float*, int, int,
+                        double*);
+
+// E-step kernel for G component lanes, running-sum variant, Jacobian option, adjoint pass
+EstepFn estep_function(int G, int acc, bool jac, bool adj);
+// FP64 adjoint pass for G component lanes
+EstepFn adj64_function(int G);
+
+// setup kernel: FP32 mirrors, status reset, per-cell flags and the offsets check
+void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws,
+                  const Layout& L, hipStream_t s);
+
+// E-step over the record slots [slot_lo, slot_hi) (slot = cell + sample range index)
+void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
+                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s);
 
 }  // namespace sdmm

@@ -70,13 +70,58 @@ struct RunSum<kAccFp64> {
     }
 };
 
-// statistics per component and the per-chunk record layout
+// statistics per component and the per-item record layout: statistic s of component k
+// at s * G + k (G = K rounded up to a power of two, at least 4), then the per-item extras
 template <bool ADJ>
 struct ChunkLayout {
     static constexpr int kNStat = ADJ ? 23 : 21;       // S0, S1[5], S2[15] (+ g_delta[2])
     static constexpr int kNRed = kNStat + (ADJ ? 4 : 3); // + W, M, negatives (+ LL)
-    static __host__ __device__ constexpr int record(int K) { return (kNStat * K + (kNRed - kNStat) + 1) & ~1; }
+    static __host__ __device__ constexpr int record(int G) { return (kNStat * G + (kNRed - kNStat) + 1) & ~1; }
 };
+
+// Sums the records of one cell's items [first, first + n_items) in item order, one
+// column per lane (all 64 lanes of the wave, which must be uniform in first/n_items),
+// with the loads of four items in flight, then hands lane k < G its component's
+// statistics S[s] = column s * G + k and every lane the extras X[i] = column NS * G + i.
+template <int G, int NS, int NX>
+__device__ __forceinline__ void sum_cell_records(const double* __restrict__ records, int64_t first, int64_t n_items,
+                                                 int PS, double (&S)[NS], double (&X)[NX])
+{
+    constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    int64_t j = 0;
+    for (; j + 4 <= n_items; j += 4) {
+        const double* r0 = records + (first + j) * PS;
+        double a[4][NQ];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) a[u][q] = (q * 64 + lane < NCOL) ? r0[u * PS + q * 64 + lane] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[q] += a[u][q];
+    }
+    for (; j < n_items; ++j) {
+        const double* r0 = records + (first + j) * PS;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q * 64 + lane < NCOL) v[q] += r0[q * 64 + lane];
+    }
+    const int k = lane % G;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) S[s] = __shfl(v[(s * G) / 64], (s * G) % 64 + k);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) X[i] = __shfl(v[(NS * G + i) / 64], (NS * G + i) % 64);
+}
+
+// Mirror slots: 0-8 R, 9-11 mu_x, 12-26 scaled Linv, 27 shifted log2 constant, 28-29 twist
+// rates, 30 the cell's log2 shift, 31 unused, 32-40 R residue, 41-43 mu_x residue,
+// 44-58 scaled Linv residue, 59 residue of the shifted log2 constant, 60-63 unused.
+constexpr int kMirShift = 30;
 
 // Twist of the frame about mu when mu moves along its own tangent directions:
 // phi_j = (d t1 / d mu . t_j) . t2 for the basis of frame64 (Duff et al. 2017), so that
@@ -100,14 +145,16 @@ __device__ __forceinline__ void frame_twist64(const double mu[3], const double R
 
 // ---------------------------------------------------------------------------------
 // FP32 E-step mirror of one component: R (9), mu_x (3), Linv * sqrt(log2(e)/2) (15),
-// c * log2(e) with c = log pi - log det L - (5/2) log 2 pi (1), the frame twist rates (2)
-// used by the adjoint, and the FP32 rounding residues of R (9) and mu_x (3), with which
-// the adjoint pass forms tangent coordinates to FP32 relative accuracy (its gradients
-// are small differences near stationarity). Returns false and writes an inert mirror
-// (identity frame and factor) when the component is unusable.
+// c * log2(e) with c = log pi - log det L - (5/2) log 2 pi (1, returned in c2 and shifted
+// per cell by set_mirror_shift), the frame twist rates (2) used by the adjoint, and the
+// FP32 rounding residues of R, mu_x, the scaled Linv and the shifted constant. With them
+// the adjoint pass forms tangent coordinates to FP32 relative accuracy and the quadratic
+// form in FP64 (its gradients are small differences near stationarity, and for strongly
+// correlated components the quadratic form cancels). Returns false and writes an inert
+// mirror (identity frame and factor) when the component is unusable.
 // ---------------------------------------------------------------------------------
 __device__ inline bool write_mirror(double pi, const double* mud, const double* mux, const double* cov,
-                             float* out)
+                                    float* out, double& c2)
 {
     bool ok = isfinite(pi) && pi >= 0.0;
     for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[d]) && isfinite(mux[d]);
@@ -118,6 +165,7 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
         out[0] = out[4] = out[8] = 1.0f;
         const int diag[5] = {0, 2, 5, 9, 14};
         for (int d = 0; d < 5; ++d) out[12 + diag[d]] = 1.0f;
+        c2 = -INFINITY;
         return false;
     }
     double R[9];
@@ -129,7 +177,8 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     for (int i = 0; i < 9; ++i) out[i] = (float)R[i];
     for (int d = 0; d < 3; ++d) out[9 + d] = (float)mux[d];
     for (int i = 0; i < 15; ++i) out[12 + i] = (float)(Li[i] * scale);
-    out[27] = (float)((log(pi) - logdet - 2.5 * kLn2Pi) * kLog2e);
+    c2 = (log(pi) - logdet - 2.5 * kLn2Pi) * kLog2e;
+    out[27] = (float)c2;
     double phi[2];
     frame_twist64(mud, R, phi);
     out[28] = (float)phi[0];
@@ -137,8 +186,21 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     out[30] = out[31] = 0.0f;
     for (int i = 0; i < 9; ++i) out[32 + i] = (float)(R[i] - (double)out[i]);
     for (int d = 0; d < 3; ++d) out[41 + d] = (float)(mux[d] - (double)out[9 + d]);
-    for (int i = 44; i < kMirror; ++i) out[i] = 0.0f;
+    for (int i = 0; i < 15; ++i) out[44 + i] = (float)(Li[i] * scale - (double)out[12 + i]);
+    for (int i = 59; i < kMirror; ++i) out[i] = 0.0f;
     return true;
+}
+
+// Shifts the log2 constants of one cell by (max over its components + 1), so that every
+// log2 density the E-step forms is negative (the maximum then reduces over the float bit
+// patterns as integers) and stays small where it matters (no rounding of a large common
+// constant). Inert components get -1. `shift` is the same for all lanes of the cell.
+__device__ inline void set_mirror_shift(float* out, double c2, double shift)
+{
+    const double v = isfinite(c2) ? c2 - shift : -1.0;
+    out[27] = (float)v;
+    out[59] = (float)(v - (double)out[27]);
+    out[kMirShift] = (float)shift;
 }
 
 struct SampleRegs {
@@ -167,14 +229,14 @@ __device__ __forceinline__ SampleRegs load_sample(const float* const* ch, uint32
 }
 
 // W = sum w (FP64 per lane), M = #{w > 0}, negatives = #{w < 0} over [s0, s1), one
-// sample per lane; every lane of the wave returns the wave's totals.
+// sample per lane of one wave; every lane returns the totals.
 __device__ __forceinline__ void weight_pass(const float* __restrict__ wch, int64_t s0, int64_t s1, double& W,
                                             double& M, double& neg)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     double sw = 0.0;
     int cnt = 0, ng = 0;
-    for (int64_t i = s0 + (int64_t)wave * 64 + lane; i < s1; i += (int64_t)nwaves * 64) {
+    for (int64_t i = s0 + lane; i < s1; i += 64) {
         const float w = wch[i];
         sw += (double)w;
         cnt += w > 0.0f;
@@ -210,24 +272,60 @@ __device__ __forceinline__ float dtheta_over_sin_dz(float z, float rs)
     return z < 0.0f ? fmaf(kPiF * z, rs * rs * rs, p) : p;
 }
 
-// E-step of one chunk [s0, s1) of a cell. mirror_cell points at the cell's K FP32
-// mirrors. Writes the chunk record part[] (FP64). lds: nwaves * kNRed * G doubles.
+// Maximum over the group of negative floats: for negative IEEE floats the integer order
+// of the bit patterns is reversed, so the float maximum is the integer minimum, one fused
+// v_min_i32 with DPP per step.
+template <int CTRL>
+__device__ __forceinline__ int dpp_min_i32(int k)
+{
+    return min(k, __builtin_amdgcn_update_dpp(0, k, CTRL, 0xF, 0xF, true));
+}
+
+template <int G>
+__device__ __forceinline__ float group_max_negative(float v)
+{
+    int k = __float_as_int(v);
+    if constexpr (G >= 2) k = dpp_min_i32<kDppXor1>(k);
+    if constexpr (G >= 4) k = dpp_min_i32<kDppXor2>(k);
+    if constexpr (G >= 8) k = dpp_min_i32<kDppHalfMirror>(k);
+    if constexpr (G >= 16) k = dpp_min_i32<kDppMirror>(k);
+    if constexpr (G >= 32) k = min(k, __shfl_xor(k, 16));
+    if constexpr (G >= 64) k = min(k, __shfl_xor(k, 32));
+    return __int_as_float(k);
+}
+
+// E-step work items of cell c: its samples [off[c], off[c+1]) cut from the cell's first
+// sample into ceil(n / P) items of at most P = 2^ps samples (one empty item for an empty
+// cell, so that every cell has a record and an M-step), item j in record slot first + j
+// with first = c + off[c] / P. False for a range outside [0, N] or a decreasing one.
+__device__ __forceinline__ bool cell_items(const int64_t* off, int64_t N, int c, int ps, int64_t& first,
+                                           int64_t& n_items)
+{
+    const int64_t c0 = off[c], c1 = off[c + 1];
+    if (!(c0 >= 0 && c1 >= c0 && c1 <= N)) return false;
+    first = c + (c0 >> ps);
+    n_items = c1 > c0 ? (c1 - c0 + (int64_t(1) << ps) - 1) >> ps : 1;
+    return true;
+}
+
+// E-step of one segment [s0, s1) of a cell by one wave. mirror_cell points at the cell's
+// K FP32 mirrors. Writes the segment record part[] (FP64) from lanes < G.
 template <int G, int ACC, bool JAC, bool ADJ>
-__device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64_t N, int64_t s0,
-                                            int64_t s1, const float* __restrict__ mirror_cell, int K,
-                                            double* __restrict__ part, double* lds)
+__device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int64_t N, int64_t s0, int64_t s1,
+                                              const float* __restrict__ mirror_cell, int K,
+                                              double* __restrict__ part)
 {
     using CL = ChunkLayout<ADJ>;
     constexpr int NS = CL::kNStat, NR = CL::kNRed;
     constexpr int S = 64 / G;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int comp = lane % G, slot = lane / G;
     const int kk = comp < K ? comp : K - 1;
 
     const float4* mp = reinterpret_cast<const float4*>(mirror_cell + (int64_t)kk * kMirror);
-    float P[44];
+    float P[60];
 #pragma unroll
-    for (int q = 0; q < (ADJ ? 11 : 7); ++q) {
+    for (int q = 0; q < (ADJ ? 15 : 7); ++q) {
         const float4 v = mp[q];
         P[4 * q] = v.x;
         P[4 * q + 1] = v.y;
@@ -236,7 +334,7 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
     }
     const float c2 = comp < K ? P[27] : -INFINITY;
 
-    // channel bases start at the chunk so that lane offsets fit in 32 bits
+    // channel bases start at the segment so that lane offsets fit in 32 bits
     const float* ch[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) ch[a] = smp + (int64_t)a * N + s0;
@@ -244,18 +342,16 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
     RunSum<ACC> acc[NS];
     RunSum<ACC> accll;
 
-    const int64_t n = s1 - s0;
-    const int64_t stride = (int64_t)nwaves * S;
-    const int64_t steps = (n + stride - 1) / stride;
-    const uint32_t last = (uint32_t)(n > 0 ? n - 1 : 0);
-    const uint32_t ustride = (uint32_t)stride;
+    const uint32_t n = (uint32_t)(s1 - s0);
+    const uint32_t last = n > 0 ? n - 1 : 0;
 
     // one (sample, component) pair per lane
     auto body = [&](const SampleRegs& cur, bool valid) {
         const float w = valid ? cur.w : 0.0f;
 
-        // tangent coordinates y = (log_mu w, p - mu_x)
-        float xr = fmaf(P[0], cur.ox, fmaf(P[1], cur.oy, P[2] * cur.oz));
+        // tangent coordinates y = (log_mu w, p - mu_x); the 1e-18 offset on w'_x keeps
+        // the antipode away from 0/0 in the log map
+        float xr = fmaf(P[0], cur.ox, fmaf(P[1], cur.oy, fmaf(P[2], cur.oz, 1e-18f)));
         float yr = fmaf(P[3], cur.ox, fmaf(P[4], cur.oy, P[5] * cur.oz));
         float zr = fmaf(P[6], cur.ox, fmaf(P[7], cur.oy, P[8] * cur.oz));
         if constexpr (ADJ) {  // add the residue of the FP32-rounded frame
@@ -264,7 +360,7 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
             zr += fmaf(P[38], cur.ox, fmaf(P[39], cur.oy, P[40] * cur.oz));
         }
         float y0, y1;
-        const float f = log_map_f32(xr, yr, zr, y0, y1);
+        const float f = log_map_f32_offset(xr, yr, zr, y0, y1);
         float y2 = cur.px - P[9], y3 = cur.py - P[10], y4 = cur.pz - P[11];
         if constexpr (ADJ) {
             y2 -= P[41];
@@ -272,22 +368,46 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
             y4 -= P[43];
         }
 
-        // log2 of pi_k N5(y; 0, Sigma_k) through the scaled inverse Cholesky factor
-        const float z0 = P[12] * y0;
-        const float z1 = fmaf(P[13], y0, P[14] * y1);
-        const float z2 = fmaf(P[15], y0, fmaf(P[16], y1, P[17] * y2));
-        const float z3 = fmaf(P[18], y0, fmaf(P[19], y1, fmaf(P[20], y2, P[21] * y3)));
-        const float z4 = fmaf(P[22], y0, fmaf(P[23], y1, fmaf(P[24], y2, fmaf(P[25], y3, P[26] * y4))));
-        float l = fmaf(-z0, z0, c2);
-        l = fmaf(-z1, z1, l);
-        l = fmaf(-z2, z2, l);
-        l = fmaf(-z3, z3, l);
-        l = fmaf(-z4, z4, l);
-        if constexpr (JAC) l += __log2f(f);  // solid-angle density: divide by sinc|nu| = times f
+        // shifted log2 of pi_k N5(y; 0, Sigma_k) through the scaled inverse Cholesky factor
+        float z0, z1, z2, z3, z4, l;
+        double ld = 0.0;
+        if constexpr (ADJ) {  // FP64 quadratic form from the hi/lo factor and constant
+            auto Lq = [&](int q) { return (double)P[12 + q] + (double)P[44 + q]; };
+            const double e0 = y0, e1 = y1, e2 = y2, e3 = y3, e4 = y4;
+            const double w0 = Lq(0) * e0;
+            const double w1 = fma(Lq(1), e0, Lq(2) * e1);
+            const double w2 = fma(Lq(3), e0, fma(Lq(4), e1, Lq(5) * e2));
+            const double w3 = fma(Lq(6), e0, fma(Lq(7), e1, fma(Lq(8), e2, Lq(9) * e3)));
+            const double w4 = fma(Lq(10), e0, fma(Lq(11), e1, fma(Lq(12), e2, fma(Lq(13), e3, Lq(14) * e4))));
+            const double c2d = comp < K ? (double)P[27] + (double)P[59] : -INFINITY;
+            ld = c2d - w0 * w0 - w1 * w1 - w2 * w2 - w3 * w3 - w4 * w4;
+            z0 = (float)w0;
+            z1 = (float)w1;
+            z2 = (float)w2;
+            z3 = (float)w3;
+            z4 = (float)w4;
+            l = (float)ld;
+        } else {
+            z0 = P[12] * y0;
+            z1 = fmaf(P[13], y0, P[14] * y1);
+            z2 = fmaf(P[15], y0, fmaf(P[16], y1, P[17] * y2));
+            z3 = fmaf(P[18], y0, fmaf(P[19], y1, fmaf(P[20], y2, P[21] * y3)));
+            z4 = fmaf(P[22], y0, fmaf(P[23], y1, fmaf(P[24], y2, fmaf(P[25], y3, P[26] * y4))));
+            l = fmaf(-z0, z0, c2);
+            l = fmaf(-z1, z1, l);
+            l = fmaf(-z2, z2, l);
+            l = fmaf(-z3, z3, l);
+            l = fmaf(-z4, z4, l);
+        }
+        if constexpr (JAC) l += __log2f(f);  // solid-angle density: times f (may be > 0)
 
         // responsibilities: log-sum-exp across the component lanes of this sample
-        const float lmax = group_max<G>(l);
-        const float e = __builtin_amdgcn_exp2f(l - lmax);
+        float lmax;
+        if constexpr (JAC) lmax = group_max<G>(l);
+        else lmax = group_max_negative<G>(l);
+        float e;
+        if constexpr (ADJ) e = __builtin_amdgcn_exp2f((float)(ld - (double)lmax));
+        else e = __builtin_amdgcn_exp2f(l - lmax);
         const float den = group_sum<G>(e);
         const float wr = w * (e * __builtin_amdgcn_rcpf(den));
 
@@ -315,9 +435,9 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
         acc[20].fma_add(t4, y4);
 
         if constexpr (ADJ) {
-            // log p(y_i) in nats (the same value in every lane of the group)
-            const float lse = (lmax + __log2f(den)) * 0.69314718056f;
-            accll.add(w * lse);
+            // shifted log2 p(y_i) (the same value in every lane of the group); the cell's
+            // shift is added back in FP64 by the gradient assembly
+            accll.add(w * (lmax + __log2f(den)));
             // u = L^-T z restricted to the two directional coordinates (scaled by
             // log2(e)/2, removed in FP64 by the gradient assembly)
             const float u0 = fmaf(P[12], z0, fmaf(P[13], z1, fmaf(P[15], z2, fmaf(P[18], z3, P[22] * z4))));
@@ -342,21 +462,26 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
         accll.fold();
     };
 
-    // two steps per trip with alternating prefetch registers (no register copies)
-    uint32_t i = (uint32_t)(wave * S + slot);
+    // full steps (every slot valid) two at a time with alternating prefetch registers,
+    // then at most three tail steps with the validity test
+    const uint32_t full = n / S, steps = (n + S - 1) / S;  // wave-uniform
+    uint32_t i = (uint32_t)slot;
+    uint32_t it = 0;
     SampleRegs a{}, b{};
-    if (steps > 0) a = load_sample(ch, min(i, last));
-    int64_t it = 0;
-    for (; it + 1 < steps; it += 2) {
-        b = load_sample(ch, min(i + ustride, last));
-        body(a, i <= last);
-        i += ustride;
-        a = load_sample(ch, min(i + ustride, last));
-        body(b, i <= last);
-        i += ustride;
+    if (n > 0) a = load_sample(ch, min(i, last));
+    for (; it + 2 <= full; it += 2) {
+        b = load_sample(ch, min(i + S, last));
+        body(a, true);
+        a = load_sample(ch, min(i + 2 * S, last));
+        body(b, true);
+        i += 2 * S;
         if (((it + 2) % kFoldEvery) == 0) fold_all();
     }
-    if (it < steps) body(a, i <= last);
+    for (; it < steps; ++it) {  // at most one full and one partial step
+        body(a, i <= last);
+        i += S;
+        a = load_sample(ch, min(i, last));
+    }
 
     double v[NR];
 #pragma unroll
@@ -375,18 +500,129 @@ __device__ __forceinline__ void estep_chunk(const float* __restrict__ smp, int64
     }
     if (lane < G) {
 #pragma unroll
-        for (int s = 0; s < NR; ++s) lds[(wave * NR + s) * G + comp] = v[s];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NR * G; idx += blockDim.x) {
-        const int s = idx / G, k = idx % G;
-        double tot = 0.0;
-        for (int wv = 0; wv < nwaves; ++wv) tot += lds[(wv * NR + s) * G + k];
-        if (s < NS) {
-            if (k < K) part[s * K + k] = tot;
-        } else if (k == 0) {
-            part[NS * K + (s - NS)] = tot;
+        for (int s = 0; s < NS; ++s) part[s * G + comp] = v[s];
+        if (comp == 0) {
+#pragma unroll
+            for (int s = NS; s < NR; ++s) part[NS * G + (s - NS)] = v[s];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// FP64 adjoint pass (verification mode): the same statistics, log-likelihood and
+// directional-mean gradient terms as estep_segment<G, *, false, true>, with the frame,
+// positional mean, scaled inverse factor and constant taken from their hi/lo FP32 pairs
+// and every per-pair quantity (rotation, log map, quadratic form, responsibilities,
+// products, sums) in FP64. Records have the adjoint layout.
+// ---------------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double group_max_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+template <int G>
+__device__ __forceinline__ double group_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int G>
+__device__ void estep_segment_adj64(const float* __restrict__ smp, int64_t N, int64_t s0, int64_t s1,
+                                    const float* __restrict__ mirror_cell, int K, double* __restrict__ part)
+{
+    using CL = ChunkLayout<true>;
+    constexpr int NS = CL::kNStat, NR = CL::kNRed;
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int comp = lane % G, slot = lane / G;
+    const int kk = comp < K ? comp : K - 1;
+    const float* P = mirror_cell + (int64_t)kk * kMirror;
+    double R[9], mx[3], Li[15];
+    for (int i = 0; i < 9; ++i) R[i] = (double)P[i] + (double)P[32 + i];
+    for (int d = 0; d < 3; ++d) mx[d] = (double)P[9 + d] + (double)P[41 + d];
+    for (int q = 0; q < 15; ++q) Li[q] = (double)P[12 + q] + (double)P[44 + q];
+    const double c2 = comp < K ? (double)P[27] + (double)P[59] : -INFINITY;
+    const double ph0 = P[28], ph1 = P[29];
+
+    double acc[NS];
+    for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+    double accll = 0.0;
+    const int64_t n = s1 - s0;
+    const int64_t steps = (n + S - 1) / S;
+    for (int64_t it = 0; it < steps; ++it) {
+        const int64_t ii = s0 + it * S + slot;
+        const bool valid = ii < s1;
+        const int64_t i = valid ? ii : s1 - 1;
+        const double ox = smp[i], oy = smp[N + i], oz = smp[2 * N + i];
+        const double px = smp[3 * N + i], py = smp[4 * N + i], pz = smp[5 * N + i];
+        const double w = valid ? (double)smp[6 * N + i] : 0.0;
+        // rotation into the component frame and the log map
+        const double xr = R[0] * ox + R[1] * oy + R[2] * oz;
+        const double yr = R[3] * ox + R[4] * oy + R[5] * oz;
+        const double zr = R[6] * ox + R[7] * oy + R[8] * oz;
+        const double s2 = xr * xr + yr * yr;
+        const double sn = sqrt(s2);
+        double f, fp, y0, y1;
+        if (sn > 0.0) {
+            f = atan2(sn, zr) / sn;
+            // d(theta / sin theta)/dz = (z f - 1) / s^2, with its series near z = 1
+            fp = (s2 < 1e-8 && zr > 0.0) ? -zr * (1.0 / 3.0 + 0.3 * s2) : (zr * f - 1.0) / s2;
+            y0 = f * xr;
+            y1 = f * yr;
+        } else {  // on the axis: the mean itself, or its antipode (cut locus, (pi, 0))
+            f = 1.0;
+            fp = -1.0 / 3.0;
+            y0 = zr > 0.0 ? 0.0 : kPi;
+            y1 = 0.0;
+        }
+        const double y[5] = {y0, y1, px - mx[0], py - mx[1], pz - mx[2]};
+        double z[5];
+        z[0] = Li[0] * y[0];
+        z[1] = Li[1] * y[0] + Li[2] * y[1];
+        z[2] = Li[3] * y[0] + Li[4] * y[1] + Li[5] * y[2];
+        z[3] = Li[6] * y[0] + Li[7] * y[1] + Li[8] * y[2] + Li[9] * y[3];
+        z[4] = Li[10] * y[0] + Li[11] * y[1] + Li[12] * y[2] + Li[13] * y[3] + Li[14] * y[4];
+        const double l = c2 - (z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3] + z[4] * z[4]);
+        const double lmax = group_max_f64<G>(l);
+        const double e = exp2(l - lmax);
+        const double den = group_sum_f64<G>(e);
+        const double wr = w * (e / den);
+        acc[0] += wr;
+        for (int d = 0; d < 5; ++d) acc[1 + d] += wr * y[d];
+        for (int d = 0; d < 5; ++d)
+            for (int b = 0; b <= d; ++b) acc[6 + tri(d, b)] += wr * y[d] * y[b];
+        accll += w * (lmax + log2(den));
+        // u = L^-T z on the directional coordinates (scaled like the FP32 pass)
+        const double u0 = Li[0] * z[0] + Li[1] * z[1] + Li[3] * z[2] + Li[6] * z[3] + Li[10] * z[4];
+        const double u1 = Li[2] * z[1] + Li[4] * z[2] + Li[7] * z[3] + Li[11] * z[4];
+        const double dx0 = ph0 * yr - zr, dx1 = ph1 * yr;
+        const double dy0 = -ph0 * xr, dy1 = -ph1 * xr - zr;
+        const double D00 = fp * xr * xr + f * dx0, D01 = fp * yr * xr + f * dx1;
+        const double D10 = fp * xr * yr + f * dy0, D11 = fp * yr * yr + f * dy1;
+        acc[NS - 2] += wr * (D00 * u0 + D10 * u1);
+        acc[NS - 1] += wr * (D01 * u0 + D11 * u1);
+    }
+    double v[NR];
+    for (int q = 0; q < NS; ++q) v[q] = acc[q];
+    double W, M, neg;
+    weight_pass(smp + 6 * N, s0, s1, W, M, neg);
+    v[NS] = slot == 0 ? W : 0.0;
+    v[NS + 1] = slot == 0 ? M : 0.0;
+    v[NS + 2] = slot == 0 ? neg : 0.0;
+    v[NS + 3] = accll;
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) v[q] += __shfl_xor(v[q], o);
+    }
+    if (lane < G) {
+        for (int q = 0; q < NS; ++q) part[q * G + comp] = v[q];
+        if (comp == 0)
+            for (int q = NS; q < NR; ++q) part[NS * G + (q - NS)] = v[q];
     }
 }
 

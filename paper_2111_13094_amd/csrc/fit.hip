@@ -5,14 +5,17 @@
 // (Sec. 3.2, 3.4), Robbins-Monro averaging and MAP updates (Sec. 4.3), one independent
 // mixture per spatial cell updated only with at least min_samples vertices (Sec. 4.2).
 //
-// Kernels per call:            plan (chunk table, status reset) -> prepare (FP32 mirrors)
-// per iteration (batched):     estep (all chunks of all cells) -> mstep (all cells)
-// per iteration (fused):       estep_fused (last chunk of a cell runs its M-step)
+// Kernels per call:  setup (FP32 mirrors, status reset, offset checks), then per
+// iteration: estep (persistent waves) -> mstep (grouped cells).
 //
-// E-step lane mapping: a wave holds 64/G sample slots x G component lanes (G = K rounded
-// up to a power of two); each lane evaluates one (sample, component) pair per step, the
-// log-sum-exp over components is a DPP all-reduce inside the G-lane group, and each lane
-// keeps its component's 21 running sums (FP32 block sums folded into a TwoSum pair).
+// E-step work split: each cell's samples are cut, from the cell's first sample, into
+// items of at most P = 2^ps samples; item j of cell c gets the record slot
+// c + off[c]/P + j. For non-decreasing offsets these slots increase strictly from cell to
+// cell and stay below C + ceil(N/P), so a wave recovers its cell from its slot by a
+// 64-ary search over c + off[c]/P. The wave streams its item with one (sample,
+// component) pair per lane (64/G sample slots x G component lanes) and writes one FP64
+// record; the M-step sums a cell's records in item order. A cell's results depend only
+// on its own samples and P, and items of at most P samples keep the waves balanced.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -27,150 +30,202 @@
 namespace sdmm {
 
 // ---------------------------------------------------------------------------------
-// plan: per-cell chunk counts, exclusive scan, chunk -> cell table; clears status/flags
+// group helpers: a group of GM consecutive lanes (GM a power of two) handles one cell
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void plan_kernel(const int64_t* __restrict__ off, int C, int64_t N,
-                                                    int64_t chunk, int32_t* __restrict__ chunk_start,
-                                                    int32_t* __restrict__ chunk_cell,
-                                                    int32_t* __restrict__ n_total,
-                                                    int32_t* __restrict__ status,
-                                                    int32_t* __restrict__ flags)
+__device__ __forceinline__ double group_sum_d(double v, int GM)
 {
-    __shared__ int32_t sums[1024];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int per = (C + nt - 1) / nt;
-    const int cb = min(C, tid * per), ce = min(C, cb + per);
-    int32_t local = 0;
-    for (int c = cb; c < ce; ++c) {
-        int64_t c0, c1;
-        const bool ok = cell_range(off, c, N, c0, c1);
-        local += (int32_t)chunks_for(c1 - c0, chunk);
-        status[c] = 0;
-        flags[c] = ok ? 0 : kFlagBadRange;
-    }
-    sums[tid] = local;
-    __syncthreads();
-    for (int d = 1; d < nt; d <<= 1) {
-        const int32_t v = tid >= d ? sums[tid - d] : 0;
-        __syncthreads();
-        sums[tid] += v;
-        __syncthreads();
-    }
-    int32_t base = sums[tid] - local;
-    for (int c = cb; c < ce; ++c) {
-        chunk_start[c] = base;
-        int64_t c0, c1;
-        cell_range(off, c, N, c0, c1);
-        const int32_t n = (int32_t)chunks_for(c1 - c0, chunk);
-        for (int32_t j = 0; j < n; ++j) chunk_cell[base + j] = c;
-        base += n;
-    }
-    if (tid == nt - 1) {
-        chunk_start[C] = sums[nt - 1];
-        *n_total = sums[nt - 1];
-    }
+    for (int o = 1; o < GM; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double group_max_d(double v, int GM)
+{
+    for (int o = 1; o < GM; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int group_or(int v, int GM)
+{
+    for (int o = 1; o < GM; o <<= 1) v |= __shfl_xor(v, o);
+    return v;
 }
 
-__global__ void prepare_kernel(int C, int K, const double* __restrict__ pi, const double* __restrict__ mud,
-                               const double* __restrict__ mux, const double* __restrict__ cov,
-                               float* __restrict__ mirror, int32_t* __restrict__ flags)
+// largest c in [0, C) with c + off[c] / 2^ps <= t (0 if none), by a 64-ary search of the wave
+__device__ __forceinline__ int find_slot_cell(const int64_t* __restrict__ off, int C, int ps, int64_t t)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)C * K) return;
-    const bool ok = write_mirror(pi[g], mud + 3 * g, mux + 3 * g, cov + 15 * g, mirror + g * kMirror);
-    if (!ok) atomicOr(&flags[g / K], kBadParams);
-}
-
-template <int G, int ACC, bool JAC>
-__global__ __launch_bounds__(256) void estep_kernel(const float* __restrict__ smp, int64_t N,
-                                                    const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ chunk_cell,
-                                                    const int32_t* __restrict__ chunk_start,
-                                                    const int32_t* __restrict__ n_total,
-                                                    const float* __restrict__ mirror, int K,
-                                                    int64_t chunk, int chunk_lo, int PS,
-                                                    double* __restrict__ partial)
-{
-    extern __shared__ double lds[];
-    const int t = chunk_lo + blockIdx.x;
-    if (t >= *n_total) return;
-    const int c = chunk_cell[t];
-    int64_t c0, c1;
-    cell_range(off, c, N, c0, c1);
-    const int64_t cs = chunk_size_for(c1 - c0, chunk);
-    const int64_t s0 = min(c1, c0 + (int64_t)(t - chunk_start[c]) * cs);
-    const int64_t s1 = min(c1, s0 + cs);
-    estep_chunk<G, ACC, JAC, false>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
-                             partial + (int64_t)t * PS, lds);
-}
-
-// ---------------------------------------------------------------------------------
-// M-step of one cell: reduce its chunk partials (fixed order), gate, Robbins-Monro
-// blend and MAP update per component (lane k), new FP32 mirror. One wave per cell.
-// ---------------------------------------------------------------------------------
-__device__ void mstep_cell(int c, const int32_t* __restrict__ chunk_start, const double* __restrict__ partial,
-                           int PS, const int32_t* __restrict__ flags, MixPtrs mix, StatePtrs st,
-                           const DevOpts& o, float* __restrict__ mirror, int32_t* __restrict__ status,
-                           double* red)
-{
-    const int K = o.K;
     const int lane = threadIdx.x & 63;
-    const int t0 = chunk_start[c], t1 = chunk_start[c + 1];
-    const int nv = kStats * K + 3;
-    for (int v = lane; v < nv; v += 64) {
-        double s = 0.0;
-        for (int t = t0; t < t1; ++t) s += partial[(int64_t)t * PS + v];
-        red[v] = s;
+    int a = 0, n = C;
+    while (n > 1) {
+        const int step = (n + 63) / 64;
+        const int idx = a + lane * step;
+        const bool le = idx < a + n && (int64_t)idx + (off[idx] >> ps) <= t;
+        const uint64_t m = __ballot(le);
+        const int j = m ? 63 - __builtin_clzll(m) : 0;
+        const int end = a + n;
+        a += j * step;
+        n = min(step, end - a);
     }
-    __syncthreads();
-    const double W = red[kStats * K], Mc = red[kStats * K + 1], negs = red[kStats * K + 2];
-    bool fin = isfinite(W);
-    for (int v = lane; v < kStats * K; v += 64) fin = fin && isfinite(red[v]);
-    fin = __all(fin);
-    int gate = 0;
-    if (negs > 0.0 || !fin || (flags[c] & kFlagBadRange)) gate = kBadInput;
-    else if (flags[c] & kBadParams) gate = kBadParams;
-    else if (Mc < (double)o.min_samples) gate = kSkippedFew;
-    else if (!(W > 0.0)) gate = kSkippedZeroW;
-    if (gate) {
-        if (lane == 0) status[c] |= gate;
+    return a;
+}
+
+// ---------------------------------------------------------------------------------
+// setup: FP32 mirrors with the per-cell shift, status reset, per-cell flags; the last
+// block checks that the offsets are non-decreasing within [0, N]
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ off, int64_t N, int C, int K,
+                                                    int GM, MixPtrs mix, float* __restrict__ mirror,
+                                                    int32_t* __restrict__ flags, int32_t* __restrict__ status,
+                                                    int32_t* __restrict__ arrive, int32_t* __restrict__ global_ok,
+                                                    int n_cell_blocks)
+{
+    if ((int)blockIdx.x == n_cell_blocks) {
+        __shared__ int bad;
+        if (threadIdx.x == 0) bad = 0;
+        __syncthreads();
+        int b = 0;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) b |= off[c + 1] < off[c];
+        if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;
+        if (b) atomicOr(&bad, 1);
+        __syncthreads();
+        if (threadIdx.x == 0) *global_ok = bad ? 0 : 1;
         return;
     }
-
-    const int j = st.step[c];
-    const double eta = j == 0 ? 1.0 : (o.eta_mode == 0 ? o.eta : pow(o.rm_beta * j + 1.0, -o.rm_alpha));
-    const double beta = o.prior_mode == 0 ? eta / Mc : o.prior_scale;
-    const double hW = j == 0 ? W : (1.0 - eta) * st.sw[c] + eta * W;
-
-    const int k = lane;
-    const bool act = k < K;
-    const int64_t g = (int64_t)c * K + (act ? k : 0);
-    double hS0 = 0.0, hS1[5], hS2[15];
-    if (act) {
-        hS0 = j == 0 ? red[k] : (1.0 - eta) * st.s0[g] + eta * red[k];
-        for (int d = 0; d < 5; ++d) hS1[d] = (j == 0 ? 1.0 : eta) * red[(1 + d) * K + k];
-        for (int q = 0; q < 15; ++q)
-            hS2[q] = j == 0 ? red[(6 + q) * K + k] : (1.0 - eta) * st.s2[g * 15 + q] + eta * red[(6 + q) * K + k];
+    const int per_block = blockDim.x / GM;
+    const int c = blockIdx.x * per_block + threadIdx.x / GM;
+    const int k = threadIdx.x % GM;
+    const bool active = c < C && k < K;
+    const int64_t g = (int64_t)c * K + k;
+    double c2 = -INFINITY;
+    bool ok = true;
+    float* out = mirror + g * kMirror;
+    if (active) ok = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    const double cmax = group_max_d(active && ok ? c2 : -INFINITY, GM);
+    const int bad = group_or(active && !ok ? 1 : 0, GM);
+    // the shift is an FP32 value, so adding it back in FP64 is exact
+    const float shift = isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f;
+    if (active) set_mirror_shift(out, c2, (double)shift);
+    if (c < C && k == 0) {
+        status[c] = 0;
+        arrive[c] = 0;
+        const int64_t c0 = off[c], c1 = off[c + 1];
+        flags[c] = ((c0 >= 0 && c1 >= c0 && c1 <= N) ? 0 : kFlagBadRange) | (bad ? kBadParams : 0);
     }
-    const double bar0 = hS0 / hW;
-    double sum0 = act ? bar0 : 0.0;
-    for (int ofs = 1; ofs < 64; ofs <<= 1) sum0 += __shfl_xor(sum0, ofs);
+}
 
-    bool dead = false, cholfail = false;
-    if (act) {
-        double mu[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
+// ---------------------------------------------------------------------------------
+// E-step: one wave per record slot t in [slot_lo, slot_hi)
+// ---------------------------------------------------------------------------------
+template <int G, int ACC, bool JAC, bool ADJ>
+__global__ __launch_bounds__(256) void estep_kernel(const float* __restrict__ smp, int64_t N,
+                                                    const int64_t* __restrict__ off, int C, int ps,
+                                                    int64_t slot_lo, int64_t slot_hi,
+                                                    const float* __restrict__ mirror, int K, int PS,
+                                                    double* __restrict__ records)
+{
+    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= slot_hi) return;
+    const int c = find_slot_cell(off, C, ps, t);
+    int64_t first, n_items;
+    if (!cell_items(off, N, c, ps, first, n_items)) return;
+    const int64_t j = t - first;
+    if (j < 0 || j >= n_items) return;  // a slot between two cells' items
+    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
+                                    records + t * PS);
+}
+
+// FP64 adjoint pass (verification mode), same work map as estep_kernel
+template <int G>
+__global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restrict__ smp, int64_t N,
+                                                          const int64_t* __restrict__ off, int C, int ps,
+                                                          int64_t slot_lo, int64_t slot_hi,
+                                                          const float* __restrict__ mirror, int K, int PS,
+                                                          double* __restrict__ records)
+{
+    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= slot_hi) return;
+    const int c = find_slot_cell(off, C, ps, t);
+    int64_t first, n_items;
+    if (!cell_items(off, N, c, ps, first, n_items)) return;
+    const int64_t j = t - first;
+    if (j < 0 || j >= n_items) return;
+    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    estep_segment_adj64<G>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, records + t * PS);
+}
+
+// ---------------------------------------------------------------------------------
+// M-step of one cell by one wave: all 64 lanes sum the cell's records (in item order,
+// column-parallel), then lanes k < G (lane k = component k) gate, blend (Robbins-Monro)
+// and update in FP64, and optionally write the next iteration's mirrors. cell_ok must
+// be uniform over the wave.
+// ---------------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
+                                           const double* __restrict__ records, int PS,
+                                           const int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
+                                           const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
+                                           float* __restrict__ mirror, int refresh_mirror,
+                                           int32_t* __restrict__ status)
+{
+    constexpr int GM = G;
+    const int K = o.K;
+    const int lane = threadIdx.x & 63;
+    const int k = lane;
+    const bool wave_ok = cell_ok;
+    cell_ok = cell_ok && lane < G;
+    const bool act = cell_ok && k < K;
+    const int kk = k < K ? k : 0;
+
+    // sum of the cell's records
+    double S[kStats], X[3];
+    int64_t first = 0, n_items = 0;
+    const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
+    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, S, X);
+    const double W = X[0], Mc = X[1], negs = X[2];
+    int fin = isfinite(W);
+    for (int s = 0; s < kStats; ++s) fin &= isfinite(S[s]) ? 1 : 0;
+    const int notfin = group_or(act && !fin ? 1 : 0, GM) | (!isfinite(W) ? 1 : 0);
+    int gate = 0;
+    if (cell_ok) {
+        const int fl = flags[c];
+        if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !*global_ok) gate = kBadInput;
+        else if (fl & kBadParams) gate = kBadParams;
+        else if (Mc < (double)o.min_samples) gate = kSkippedFew;
+        else if (!(W > 0.0)) gate = kSkippedZeroW;
+    }
+    const bool run = cell_ok && !gate;
+
+    const int j = run ? st.step[c] : 0;
+    const double eta = j == 0 ? 1.0 : (o.eta_mode == 0 ? o.eta : pow(o.rm_beta * j + 1.0, -o.rm_alpha));
+    const double beta = o.prior_mode == 0 ? eta / fmax(Mc, 1.0) : o.prior_scale;
+    const double hW = j == 0 ? W : (1.0 - eta) * (run ? st.sw[c] : 0.0) + eta * W;
+    const int64_t g = (int64_t)c * K + kk;
+
+    double hS0 = 0.0, hS1[5], hS2[15];
+    if (run && act) {
+        hS0 = j == 0 ? S[0] : (1.0 - eta) * st.s0[g] + eta * S[0];
+        for (int d = 0; d < 5; ++d) hS1[d] = (j == 0 ? 1.0 : eta) * S[1 + d];
+        for (int q = 0; q < 15; ++q) hS2[q] = j == 0 ? S[6 + q] : (1.0 - eta) * st.s2[g * 15 + q] + eta * S[6 + q];
+    }
+    const double bar0 = (run && act) ? hS0 / hW : 0.0;
+    const double sum0 = group_sum_d(bar0, GM);
+
+    int dead = 0, cholfail = 0;
+    if (run && act) {
+        const double mu[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
         if (!(bar0 > o.dead_threshold)) {
-            dead = true;
+            dead = 1;
             st.s0[g] = hS0;
             for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = hS2[q];
         } else {
             double m[5];
-            for (int d = 0; d < 5; ++d) m[d] = hS1[d] / hS0;
+            const double inv0 = 1.0 / hS0;
+            for (int d = 0; d < 5; ++d) m[d] = hS1[d] * inv0;
             double Ro[9], Rn[9], mun[3];
             frame64(mu, Ro);
             exp_map64(Ro, m[0], m[1], mun);
-            const double nn = sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
-            for (int i = 0; i < 3; ++i) mun[i] /= nn;
+            const double inn = 1.0 / sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
+            for (int i = 0; i < 3; ++i) mun[i] *= inn;
             frame64(mun, Rn);
             double J[4];
             transfer_jac64(Ro, Rn, m[0], m[1], J);
@@ -178,32 +233,31 @@ __device__ void mstep_cell(int c, const int32_t* __restrict__ chunk_start, const
             double Cm[5][5];
             for (int d = 0; d < 5; ++d)
                 for (int e = 0; e <= d; ++e) {
-                    const double v = hS2[tri(d, e)] - hS1[d] * hS1[e] / hS0;
+                    const double v = hS2[tri(d, e)] - hS1[d] * hS1[e] * inv0;
                     Cm[d][e] = v;
                     Cm[e][d] = v;
                 }
-            double Cn[5][5];
-            for (int a = 0; a < 5; ++a)
-                for (int b = 0; b < 5; ++b) Cn[a][b] = Cm[a][b];
+            double Tt[5][5];
             for (int b = 0; b < 5; ++b) {  // rows 0,1: J * C
                 const double r0 = J[0] * Cm[0][b] + J[1] * Cm[1][b];
                 const double r1 = J[2] * Cm[0][b] + J[3] * Cm[1][b];
-                Cn[0][b] = r0;
-                Cn[1][b] = r1;
+                Tt[0][b] = r0;
+                Tt[1][b] = r1;
+                for (int a = 2; a < 5; ++a) Tt[a][b] = Cm[a][b];
             }
-            double Tt[5][5];
             for (int a = 0; a < 5; ++a) {  // columns 0,1: (J C) J^T
-                Tt[a][0] = Cn[a][0] * J[0] + Cn[a][1] * J[1];
-                Tt[a][1] = Cn[a][0] * J[2] + Cn[a][1] * J[3];
-                for (int b = 2; b < 5; ++b) Tt[a][b] = Cn[a][b];
+                const double c0 = Tt[a][0] * J[0] + Tt[a][1] * J[1];
+                const double c1 = Tt[a][0] * J[2] + Tt[a][1] * J[3];
+                Tt[a][0] = c0;
+                Tt[a][1] = c1;
             }
             double Sig[15], Lt[15];
-            const double den = beta * o.prior_a + bar0;
+            const double iden = 1.0 / (beta * o.prior_a + bar0), ihW = 1.0 / hW;
             for (int d = 0; d < 5; ++d)
                 for (int e = 0; e <= d; ++e) {
-                    double v = 0.5 * (Tt[d][e] + Tt[e][d]) / hW;
+                    double v = 0.5 * (Tt[d][e] + Tt[e][d]) * ihW;
                     if (d == e) v += beta * o.prior_b[d];
-                    Sig[tri(d, e)] = v / den;
+                    Sig[tri(d, e)] = v * iden;
                 }
             for (int i = 0; i < 3; ++i) {
                 mix.mud[3 * g + i] = mun[i];
@@ -212,63 +266,200 @@ __device__ void mstep_cell(int c, const int32_t* __restrict__ chunk_start, const
             if (chol64<5>(Sig, Lt)) {
                 for (int q = 0; q < 15; ++q) mix.cov[g * 15 + q] = Sig[q];
             } else {
-                cholfail = true;
+                cholfail = 1;
             }
             st.s0[g] = hS0;
             for (int d = 0; d < 5; ++d)
                 for (int e = 0; e <= d; ++e) st.s2[g * 15 + tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
         }
-        const double pinew = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
-        mix.pi[g] = pinew;
-        write_mirror(pinew, mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, mirror + g * kMirror);
+        mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
-    const bool any_dead = __any(dead), any_chol = __any(cholfail);
-    if (lane == 0) {
-        st.sw[c] = hW;
-        st.step[c] = j + 1;
-        status[c] |= (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
+    const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
+    if (refresh_mirror) {  // mirrors for the next iteration of this call
+        double c2 = -INFINITY;
+        bool okm = true;
+        float* out = mirror + g * kMirror;
+        if (run && act) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+        const double cmax = group_max_d((run && act && okm) ? c2 : -INFINITY, GM);
+        if (run && act) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f));
+    }
+    if (cell_ok && k == 0) {
+        if (gate) {
+            status[c] |= gate;
+        } else {
+            st.sw[c] = hW;
+            st.step[c] = j + 1;
+            status[c] |= (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
+        }
     }
 }
 
-__global__ __launch_bounds__(64) void mstep_kernel(const int32_t* __restrict__ chunk_start,
-                                                   const double* __restrict__ partial, int PS,
-                                                   const int32_t* __restrict__ flags, MixPtrs mix,
-                                                   StatePtrs st, DevOpts o, float* __restrict__ mirror,
-                                                   int32_t* __restrict__ status, int cell_lo)
+// M-step of cells [cell_lo, cell_lo + n_cells), one cell per wave
+template <int G>
+__global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
+                                                    const double* __restrict__ records, int PS,
+                                                    const int32_t* __restrict__ flags,
+                                                    const int32_t* __restrict__ global_ok, MixPtrs mix,
+                                                    StatePtrs st, DevOpts o, float* __restrict__ mirror,
+                                                    int refresh_mirror, int32_t* __restrict__ status, int cell_lo,
+                                                    int n_cells)
 {
-    __shared__ double red[kStats * kMaxK + 4];
-    mstep_cell(cell_lo + blockIdx.x, chunk_start, partial, PS, flags, mix, st, o, mirror, status, red);
+    const int cl = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool cell_ok = cl < n_cells;
+    mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, records, PS, flags, global_ok, mix, st, o, mirror,
+                  refresh_mirror, status);
+}
+
+// ---------------------------------------------------------------------------------
+// Fused E+M: one wave per record slot as in estep_kernel; after writing its record a
+// wave counts itself into the cell's arrival counter (device-scope release before,
+// acquire after), and the wave that completes the count runs the cell's M-step on its
+// wave and resets the counter for the next launch. Every cell has at least
+// one item, so every cell gets its M-step. Offsets that are not non-decreasing within
+// [0, N] (checked by the setup kernel) turn every cell into BAD_INPUT.
+// ---------------------------------------------------------------------------------
+template <int G, int ACC, bool JAC>
+__global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ smp, int64_t N,
+                                                    const int64_t* __restrict__ off, int C, int ps,
+                                                    int64_t slot_hi, const float* __restrict__ mirror_in, int K,
+                                                    int PS, double* __restrict__ records,
+                                                    int32_t* __restrict__ arrive, const int32_t* __restrict__ flags,
+                                                    const int32_t* __restrict__ global_ok, MixPtrs mix, StatePtrs st,
+                                                    DevOpts o, float* __restrict__ mirror, int refresh_mirror,
+                                                    int32_t* __restrict__ status)
+{
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= slot_hi) return;
+    if (!*global_ok) {
+        if (t < C && lane == 0) status[t] = kBadInput;
+        return;
+    }
+    const int c = find_slot_cell(off, C, ps, t);
+    int64_t first, n_items;
+    if (!cell_items(off, N, c, ps, first, n_items)) return;
+    const int64_t j = t - first;
+    if (j < 0 || j >= n_items) return;
+    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    estep_segment<G, ACC, JAC, false>(smp, N, s0, s1, mirror_in + (int64_t)c * K * kMirror, K, records + t * PS);
+    __threadfence();
+    int done = 0;
+    if (lane == 0) done = atomicAdd(arrive + c, 1) == (int)n_items - 1;
+    if (!__builtin_amdgcn_readfirstlane(done)) return;
+    __threadfence();
+    mstep_cell<G>(off, N, c, true, ps, records, PS, flags, global_ok, mix, st, o, mirror, refresh_mirror, status);
+    if (lane == 0) arrive[c] = 0;
 }
 
 // ---------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------
-typedef void (*EstepFn)(const float*, int64_t, const int64_t*, const int32_t*, const int32_t*, const int32_t*,
-                        const float*, int, int64_t, int, int, double*);
-
-template <int G>
+template <int G, bool ADJ>
 static EstepFn estep_for_g(int acc, bool jac)
 {
-    if (jac) {
-        if (acc == kAccPlain) return estep_kernel<G, kAccPlain, true>;
-        if (acc == kAccFp64) return estep_kernel<G, kAccFp64, true>;
-        return estep_kernel<G, kAccTwoSum, true>;
+    if constexpr (ADJ) {
+        return estep_kernel<G, kAccTwoSum, false, true>;
+    } else {
+        if (jac) {
+            if (acc == kAccPlain) return estep_kernel<G, kAccPlain, true, false>;
+            if (acc == kAccFp64) return estep_kernel<G, kAccFp64, true, false>;
+            return estep_kernel<G, kAccTwoSum, true, false>;
+        }
+        if (acc == kAccPlain) return estep_kernel<G, kAccPlain, false, false>;
+        if (acc == kAccFp64) return estep_kernel<G, kAccFp64, false, false>;
+        return estep_kernel<G, kAccTwoSum, false, false>;
     }
-    if (acc == kAccPlain) return estep_kernel<G, kAccPlain, false>;
-    if (acc == kAccFp64) return estep_kernel<G, kAccFp64, false>;
-    return estep_kernel<G, kAccTwoSum, false>;
 }
 
-static EstepFn estep_for(int G, int acc, bool jac)
+typedef void (*FusedFn)(const float*, int64_t, const int64_t*, int, int, int64_t, const float*, int, int,
+                        double*, int32_t*, const int32_t*, const int32_t*, MixPtrs, StatePtrs, DevOpts, float*, int,
+                        int32_t*);
+typedef void (*MstepFn)(const int64_t*, int64_t, int, const double*, int, const int32_t*, const int32_t*, MixPtrs,
+                        StatePtrs, DevOpts, float*, int, int32_t*, int, int);
+
+static MstepFn mstep_function(int G)
 {
     switch (G) {
-        case 4: return estep_for_g<4>(acc, jac);
-        case 8: return estep_for_g<8>(acc, jac);
-        case 16: return estep_for_g<16>(acc, jac);
-        case 32: return estep_for_g<32>(acc, jac);
-        case 64: return estep_for_g<64>(acc, jac);
+        case 4: return mstep_kernel<4>;
+        case 8: return mstep_kernel<8>;
+        case 16: return mstep_kernel<16>;
+        case 32: return mstep_kernel<32>;
+        case 64: return mstep_kernel<64>;
     }
     return nullptr;
+}
+
+template <int G>
+static FusedFn fused_for_g(int acc, bool jac)
+{
+    if (jac) {
+        if (acc == kAccPlain) return fused_kernel<G, kAccPlain, true>;
+        if (acc == kAccFp64) return fused_kernel<G, kAccFp64, true>;
+        return fused_kernel<G, kAccTwoSum, true>;
+    }
+    if (acc == kAccPlain) return fused_kernel<G, kAccPlain, false>;
+    if (acc == kAccFp64) return fused_kernel<G, kAccFp64, false>;
+    return fused_kernel<G, kAccTwoSum, false>;
+}
+
+static FusedFn fused_function(int G, int acc, bool jac)
+{
+    switch (G) {
+        case 4: return fused_for_g<4>(acc, jac);
+        case 8: return fused_for_g<8>(acc, jac);
+        case 16: return fused_for_g<16>(acc, jac);
+        case 32: return fused_for_g<32>(acc, jac);
+        case 64: return fused_for_g<64>(acc, jac);
+    }
+    return nullptr;
+}
+
+EstepFn adj64_function(int G)
+{
+    switch (G) {
+        case 4: return estep_adj64_kernel<4>;
+        case 8: return estep_adj64_kernel<8>;
+        case 16: return estep_adj64_kernel<16>;
+        case 32: return estep_adj64_kernel<32>;
+        case 64: return estep_adj64_kernel<64>;
+    }
+    return nullptr;
+}
+
+EstepFn estep_function(int G, int acc, bool jac, bool adj)
+{
+    switch (G) {
+        case 4: return adj ? estep_for_g<4, true>(acc, jac) : estep_for_g<4, false>(acc, jac);
+        case 8: return adj ? estep_for_g<8, true>(acc, jac) : estep_for_g<8, false>(acc, jac);
+        case 16: return adj ? estep_for_g<16, true>(acc, jac) : estep_for_g<16, false>(acc, jac);
+        case 32: return adj ? estep_for_g<32, true>(acc, jac) : estep_for_g<32, false>(acc, jac);
+        case 64: return adj ? estep_for_g<64, true>(acc, jac) : estep_for_g<64, false>(acc, jac);
+    }
+    return nullptr;
+}
+
+void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws, const Layout& L,
+                  hipStream_t s)
+{
+    const int C = mix.n_cells, K = mix.K;
+    const int GM = group_pow2(K);
+    const int per_block = 256 / GM;
+    const int blocks = (C + per_block - 1) / per_block;
+    const MixPtrs mp{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov};
+    setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, mp, reinterpret_cast<float*>(ws + L.mirror),
+                                            reinterpret_cast<int32_t*>(ws + L.flags), status,
+                                            reinterpret_cast<int32_t*>(ws + L.arrive),
+                                            reinterpret_cast<int32_t*>(ws + L.global_ok), blocks);
+}
+
+void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
+                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s)
+{
+    if (slot_hi <= slot_lo) return;
+    const unsigned blocks = (unsigned)((slot_hi - slot_lo + 3) / 4);
+    hipLaunchKernelGGL(est, dim3(blocks), dim3(256), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
+                       reinterpret_cast<const float*>(ws + L.mirror), K, PS,
+                       reinterpret_cast<double*>(ws + L.records));
 }
 
 struct FitArgs {
@@ -282,62 +473,54 @@ struct FitArgs {
     char* ws;
 };
 
-void launch_plan_prepare(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int64_t chunk, int32_t* status,
-                         char* ws, const Layout& L, hipStream_t s)
-{
-    const int C = mix.n_cells, K = mix.K;
-    float* mirror = reinterpret_cast<float*>(ws + L.mirror);
-    int32_t* flags = reinterpret_cast<int32_t*>(ws + L.flags);
-    plan_kernel<<<1, 1024, 0, s>>>(off, C, N, chunk, reinterpret_cast<int32_t*>(ws + L.chunk_start),
-                                   reinterpret_cast<int32_t*>(ws + L.chunk_cell),
-                                   reinterpret_cast<int32_t*>(ws + L.n_total), status, flags);
-    const int64_t nk = (int64_t)C * K;
-    prepare_kernel<<<(unsigned)((nk + 255) / 256), 256, 0, s>>>(C, K, mix.weights, mix.mean_dir, mix.mean_pos,
-                                                                 mix.cov, mirror, flags);
-}
-
 static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_t>* host_off)
 {
     const int C = a.mix.n_cells, K = a.opts.K;
-    const int64_t chunk = default_chunk(&a.opts);
-    const int waves = default_waves(&a.opts);
-    const Layout L = layout_for(C, K, a.N, chunk);
-    float* mirror = reinterpret_cast<float*>(a.ws + L.mirror);
-    int32_t* flags = reinterpret_cast<int32_t*>(a.ws + L.flags);
-    int32_t* cstart = reinterpret_cast<int32_t*>(a.ws + L.chunk_start);
-    int32_t* ccell = reinterpret_cast<int32_t*>(a.ws + L.chunk_cell);
-    int32_t* ntot = reinterpret_cast<int32_t*>(a.ws + L.n_total);
-    double* partial = reinterpret_cast<double*>(a.ws + L.partial);
+    const Layout L = layout_for(C, K, a.N, &a.opts);
     const MixPtrs mp{a.mix.weights, a.mix.mean_dir, a.mix.mean_pos, a.mix.cov};
     const StatePtrs sp{a.st.s0, a.st.s2, a.st.sw, a.st.step};
     const DevOpts dopt = dev_opts(&a.opts);
-    const int G = group_for(K);
     const int acc = (a.opts.flags & SDMM_FLAG_PLAIN_FP32) ? kAccPlain
                     : (a.opts.flags & SDMM_FLAG_FP64_SUMS) ? kAccFp64 : kAccTwoSum;
     const bool jac = (a.opts.flags & SDMM_FLAG_ESTEP_JACOBIAN) != 0;
-    EstepFn est = estep_for(G, acc, jac);
-    const size_t lds = (size_t)waves * ChunkLayout<false>::kNRed * G * sizeof(double);
-    const int ps = L.ps_fit;
+    EstepFn est = estep_function(group_for(K), acc, jac, false);
+    FusedFn fused = fused_function(group_for(K), acc, jac);
+    MstepFn mstep = mstep_function(group_for(K));
+    float* mirror = reinterpret_cast<float*>(a.ws + L.mirror);
+    const int32_t* flags = reinterpret_cast<const int32_t*>(a.ws + L.flags);
+    const int32_t* gok = reinterpret_cast<const int32_t*>(a.ws + L.global_ok);
+    const double* rec = reinterpret_cast<const double*>(a.ws + L.records);
 
-    launch_plan_prepare(a.off, a.N, a.mix, chunk, a.status, a.ws, L, s);
+    launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s);
     for (int it = 0; it < a.opts.iters; ++it) {
+        const int refresh = it + 1 < a.opts.iters;
         if (a.opts.schedule == SDMM_SCHED_PER_CELL) {
-            int64_t t = 0;
+            // host_off is empty when the offsets failed the host check: the M-steps then
+            // only report BAD_INPUT (the setup kernel's check agrees)
             for (int c = 0; c < C; ++c) {
-                const int64_t nch = chunks_for((*host_off)[c + 1] - (*host_off)[c], chunk);
-                hipLaunchKernelGGL(est, dim3((unsigned)nch), dim3(waves * 64), lds, s, a.smp, a.N, a.off, ccell,
-                                   cstart, ntot, mirror, K, chunk, (int)t, ps, partial);
-                mstep_kernel<<<1, 64, 0, s>>>(cstart, partial, ps, flags, mp, sp, dopt, mirror, a.status, c);
-                t += nch;
+                if (!host_off->empty()) {
+                    const int64_t c0 = (*host_off)[c], c1 = (*host_off)[c + 1];
+                    const int64_t first = c + (c0 >> L.ps), n_items = c1 > c0 ? (c1 - c0 + L.P - 1) >> L.ps : 1;
+                    launch_estep(est, a.smp, a.N, a.off, C, K, L, first, first + n_items, L.ps_fit, a.ws, s);
+                }
+                hipLaunchKernelGGL(mstep, dim3(1), dim3(64), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok, mp, sp,
+                                   dopt, mirror, refresh, a.status, c, 1);
             }
-        } else {
+        } else if (a.opts.schedule == SDMM_SCHED_BATCHED) {
             {
                 ScopedTimer tm(SDMM_TIMER_ESTEP, s);
-                hipLaunchKernelGGL(est, dim3((unsigned)L.tmax), dim3(waves * 64), lds, s, a.smp, a.N, a.off, ccell,
-                                   cstart, ntot, mirror, K, chunk, 0, ps, partial);
+                launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s);
             }
             ScopedTimer tm(SDMM_TIMER_MSTEP, s);
-            mstep_kernel<<<C, 64, 0, s>>>(cstart, partial, ps, flags, mp, sp, dopt, mirror, a.status, 0);
+            hipLaunchKernelGGL(mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok,
+                               mp, sp, dopt, mirror, refresh, a.status, 0, C);
+        } else {
+            ScopedTimer tm(SDMM_TIMER_ESTEP, s);
+            const int64_t slots = (int64_t)C + L.W;
+            hipLaunchKernelGGL(fused, dim3((unsigned)((slots + 3) / 4)), dim3(256), 0, s, a.smp, a.N, a.off, C, L.ps,
+                               slots, mirror, K, L.ps_fit, reinterpret_cast<double*>(a.ws + L.records),
+                               reinterpret_cast<int32_t*>(a.ws + L.arrive), flags, gok, mp, sp, dopt, mirror, refresh,
+                               a.status);
         }
     }
     return check(hipGetLastError());
@@ -352,13 +535,11 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
     if (mix->n_cells <= 0 || mix->K != opts->K || opts->K < 1 || opts->K > kMaxK) return SDMM_EINVAL;
     if (opts->iters < 1 || opts->min_samples < 0) return SDMM_EINVAL;
     if (!mix->weights || !mix->mean_dir || !mix->mean_pos || !mix->cov) return SDMM_EINVAL;
-    const int64_t chunk = default_chunk(opts);
-    const int waves = default_waves(opts);
-    if (chunk < 64 || chunk % 64 != 0 || !(waves == 1 || waves == 2 || waves == 4)) return SDMM_EINVAL;
-    if ((int64_t)mix->n_cells + (n_samples + chunk - 1) / chunk > INT32_MAX) return SDMM_EINVAL;
-    // per-chunk lane offsets are 32-bit byte offsets
-    if (chunk_size_for(n_samples, chunk) * 4 > (int64_t)UINT32_MAX / 2) return SDMM_EINVAL;
-    if (workspace_bytes < layout_for(mix->n_cells, opts->K, n_samples, chunk).total) return SDMM_ENOWORKSPACE;
+    if (opts->min_range < 0 || opts->max_ranges < 0 || opts->max_ranges > (1 << 20)) return SDMM_EINVAL;
+    const Layout L = layout_for(mix->n_cells, opts->K, n_samples, opts);
+    // lane offsets inside a segment are 32-bit byte offsets; record slots are int32
+    if (L.P * 4 > (int64_t)INT32_MAX || (int64_t)mix->n_cells + L.W > INT32_MAX) return SDMM_EINVAL;
+    if (workspace_bytes < L.total) return SDMM_ENOWORKSPACE;
     return SDMM_OK;
 }
 
@@ -378,7 +559,7 @@ extern "C" size_t sdmm_fit_workspace_size(int32_t n_cells, int32_t K, int64_t n_
                                           const sdmm_fit_opts* opts)
 {
     if (n_cells <= 0 || K < 1 || K > kMaxK || n_samples < 0 || !opts) return 0;
-    return layout_for(n_cells, K, n_samples, default_chunk(opts)).total;
+    return layout_for(n_cells, K, n_samples, opts).total;
 }
 
 extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* samples, int64_t n_samples,
@@ -389,7 +570,9 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
     int rc = validate_fit_args(cell_offsets, samples, n_samples, mix, opts, cell_status, workspace, workspace_bytes);
     if (rc) return rc;
     if (!state || !state->s0 || !state->s2 || !state->sw || !state->step) return SDMM_EINVAL;
-    if (opts->schedule != SDMM_SCHED_BATCHED && opts->schedule != SDMM_SCHED_PER_CELL) return SDMM_EINVAL;
+    if (opts->schedule != SDMM_SCHED_BATCHED && opts->schedule != SDMM_SCHED_PER_CELL &&
+        opts->schedule != SDMM_SCHED_FUSED)
+        return SDMM_EINVAL;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     FitArgs a{cell_offsets, samples, n_samples, *mix, *state, *opts, cell_status,
@@ -402,8 +585,9 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
         if (rc) return rc;
         rc = check(hipStreamSynchronize(s));
         if (rc) return rc;
-        for (int c = 0; c < mix->n_cells; ++c)
-            if (host_off[c + 1] < host_off[c] || host_off[c] < 0 || host_off[c + 1] > n_samples) return SDMM_EINVAL;
+        bool ok = host_off[0] >= 0 && host_off[mix->n_cells] <= n_samples;
+        for (int c = 0; c < mix->n_cells && ok; ++c) ok = host_off[c + 1] >= host_off[c];
+        if (!ok) host_off.clear();
         return enqueue_fit(a, s, &host_off);
     }
 
@@ -444,4 +628,4 @@ extern "C" const char* sdmm_status_string(int code)
     return "unknown status";
 }
 
-extern "C" const char* sdmm_version(void) { return "sdmm-mi355x 0.1"; }
+extern "C" const char* sdmm_version(void) { return "sdmm-mi355x 0.2"; }

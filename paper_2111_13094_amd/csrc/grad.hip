@@ -4,7 +4,7 @@
 // the objective whose maximiser is the MAP update of Sec. 4.3 of Dodik et al. (Dirichlet
 // prior on the weights, inverse-Wishart prior on the covariances, none on the means).
 //
-// One pass over the samples (the E-step pass with two extra accumulators) gives, per
+// One pass over the samples (the E-step pass with extra accumulators) gives, per
 // component and about the current means, S0, S1, S2, sum w r (d nu / d delta)^T
 // [Sigma^-1 y]_nu, and per cell sum w log p. A per-cell FP64 assembly then forms
 //   dF/dalpha_k = S0_k/W + beta q - pi_k (sum_j S0_j/W + K beta q)        (pi = softmax alpha)
@@ -18,60 +18,57 @@
 
 namespace sdmm {
 
-template <int G>
-__global__ __launch_bounds__(256) void grad_estep_kernel(const float* __restrict__ smp, int64_t N,
-                                                         const int64_t* __restrict__ off,
-                                                         const int32_t* __restrict__ chunk_cell,
-                                                         const int32_t* __restrict__ chunk_start,
-                                                         const int32_t* __restrict__ n_total,
-                                                         const float* __restrict__ mirror, int K, int64_t chunk,
-                                                         int PS, double* __restrict__ partial)
+__device__ __forceinline__ double gsum(double v, int GM)
 {
-    extern __shared__ double lds[];
-    const int t = blockIdx.x;
-    if (t >= *n_total) return;
-    const int c = chunk_cell[t];
-    int64_t c0, c1;
-    cell_range(off, c, N, c0, c1);
-    const int64_t cs = chunk_size_for(c1 - c0, chunk);
-    const int64_t s0 = min(c1, c0 + (int64_t)(t - chunk_start[c]) * cs);
-    const int64_t s1 = min(c1, s0 + cs);
-    estep_chunk<G, kAccTwoSum, false, true>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
-                                            partial + (int64_t)t * PS, lds);
+    for (int o = 1; o < GM; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int gor(int v, int GM)
+{
+    for (int o = 1; o < GM; o <<= 1) v |= __shfl_xor(v, o);
+    return v;
 }
 
-__global__ __launch_bounds__(64) void grad_assemble_kernel(const int32_t* __restrict__ chunk_start,
-                                                           const double* __restrict__ partial, int PS,
-                                                           const int32_t* __restrict__ flags, MixPtrs mix, DevOpts o,
-                                                           double* __restrict__ F_out, double* __restrict__ g_alpha,
-                                                           double* __restrict__ g_mux, double* __restrict__ g_delta,
-                                                           double* __restrict__ g_L, int32_t* __restrict__ status)
+// one wave per cell: all lanes sum the cell's records, lane k = component k (k < G)
+template <int G>
+__global__ __launch_bounds__(256) void grad_assemble_kernel(const int64_t* __restrict__ off, int64_t N, int C,
+                                                            int ps, const double* __restrict__ records, int PS,
+                                                            const int32_t* __restrict__ flags,
+                                                            const int32_t* __restrict__ global_ok,
+                                                            const float* __restrict__ mirror, MixPtrs mix, DevOpts o,
+                                                            double* __restrict__ F_out, double* __restrict__ g_alpha,
+                                                            double* __restrict__ g_mux, double* __restrict__ g_delta,
+                                                            double* __restrict__ g_L, int32_t* __restrict__ status)
 {
     constexpr int NS = ChunkLayout<true>::kNStat;
-    __shared__ double red[NS * kMaxK + 4];
-    const int c = blockIdx.x;
+    constexpr int GM = G;
     const int K = o.K;
+    const int c0i = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int t0 = chunk_start[c], t1 = chunk_start[c + 1];
-    const int nv = NS * K + 4;
-    for (int v = lane; v < nv; v += 64) {
-        double s = 0.0;
-        for (int t = t0; t < t1; ++t) s += partial[(int64_t)t * PS + v];
-        red[v] = s;
-    }
-    __syncthreads();
-    const double W = red[NS * K], Mc = red[NS * K + 1], negs = red[NS * K + 2], LL = red[NS * K + 3];
-    bool fin = isfinite(W) && isfinite(LL);
-    for (int v = lane; v < NS * K; v += 64) fin = fin && isfinite(red[v]);
-    fin = __all(fin);
-    int gate = 0;
-    if (negs > 0.0 || !fin || (flags[c] & kFlagBadRange)) gate = kBadInput;
-    else if (flags[c] & kBadParams) gate = kBadParams;
-    else if (Mc < (double)o.min_samples) gate = kSkippedFew;
-    else if (!(W > 0.0)) gate = kSkippedZeroW;
+    const bool wave_ok = c0i < C;
+    const int c = wave_ok ? c0i : 0;
+    const bool cell_ok = wave_ok && lane < G;
     const int k = lane;
-    const bool act = k < K;
-    const int64_t g = (int64_t)c * K + (act ? k : 0);
+    const bool act = cell_ok && k < K;
+    const int kk = k < K ? k : 0;
+
+    double S[NS], X[4];
+    int64_t first = 0, n_items = 0;
+    const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
+    sum_cell_records<G, NS, 4>(records, first, have ? n_items : 0, PS, S, X);
+    const double W = X[0], Mc = X[1], negs = X[2], LL = X[3];
+    int fin = isfinite(W) && isfinite(LL);
+    for (int s = 0; s < NS; ++s) fin &= isfinite(S[s]) ? 1 : 0;
+    const int notfin = gor(act && !fin ? 1 : 0, GM) | (!(isfinite(W) && isfinite(LL)) ? 1 : 0);
+    int gate = 0;
+    if (cell_ok) {
+        const int fl = flags[c];
+        if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !*global_ok) gate = kBadInput;
+        else if (fl & kBadParams) gate = kBadParams;
+        else if (Mc < (double)o.min_samples) gate = kSkippedFew;
+        else if (!(W > 0.0)) gate = kSkippedZeroW;
+    }
+    const int64_t g = (int64_t)c * K + kk;
     if (gate) {
         if (act) {
             g_alpha[g] = 0.0;
@@ -79,16 +76,15 @@ __global__ __launch_bounds__(64) void grad_assemble_kernel(const int32_t* __rest
             for (int d = 0; d < 2; ++d) g_delta[2 * g + d] = 0.0;
             for (int q = 0; q < 15; ++q) g_L[15 * g + q] = 0.0;
         }
-        if (lane == 0) {
+        if (cell_ok && k == 0) {
             F_out[c] = 0.0;
             status[c] = gate;
         }
         return;
     }
     const double beta = o.prior_scale;
-    const double b0 = act ? red[k] / W : 0.0;
-    double sum0 = b0;
-    for (int ofs = 1; ofs < 64; ofs <<= 1) sum0 += __shfl_xor(sum0, ofs);
+    const double b0 = act ? S[0] / W : 0.0;
+    const double sum0 = gsum(b0, GM);
     double Fk = 0.0;
     if (act) {
         const double pik = mix.pi[g];
@@ -96,8 +92,7 @@ __global__ __launch_bounds__(64) void grad_assemble_kernel(const int32_t* __rest
         double L[15], Li[15];
         chol64<5>(mix.cov + 15 * g, L);
         tri_inv64<5>(L, Li);
-        // Sigma^-1 = Li^T Li (dense)
-        double Si[5][5];
+        double Si[5][5];  // Sigma^-1 = Li^T Li
         for (int d = 0; d < 5; ++d)
             for (int e = 0; e < 5; ++e) {
                 double s = 0.0;
@@ -106,14 +101,14 @@ __global__ __launch_bounds__(64) void grad_assemble_kernel(const int32_t* __rest
             }
         for (int d = 0; d < 3; ++d) {
             double s = 0.0;
-            for (int e = 0; e < 5; ++e) s += Si[2 + d][e] * red[(1 + e) * K + k] / W;
+            for (int e = 0; e < 5; ++e) s += Si[2 + d][e] * S[1 + e] / W;
             g_mux[3 * g + d] = s;
         }
         double A[5][5];
         for (int d = 0; d < 5; ++d)
             for (int e = 0; e < 5; ++e) {
                 const int dd = d > e ? d : e, ee = d > e ? e : d;
-                A[d][e] = red[(6 + tri(dd, ee)) * K + k] / W + (d == e ? beta * o.prior_b[d] : 0.0);
+                A[d][e] = S[6 + tri(dd, ee)] / W + (d == e ? beta * o.prior_b[d] : 0.0);
             }
         double SA[5][5], Gm[5][5];
         for (int d = 0; d < 5; ++d)
@@ -136,17 +131,19 @@ __global__ __launch_bounds__(64) void grad_assemble_kernel(const int32_t* __rest
             }
         // the device pass accumulated (log2(e)/2) Sigma^-1 y
         const double unscale = 1.0 / (0.5 * kLog2e);
-        g_delta[2 * g] = -red[21 * K + k] / W * unscale;
-        g_delta[2 * g + 1] = -red[22 * K + k] / W * unscale;
+        g_delta[2 * g] = -S[21] / W * unscale;
+        g_delta[2 * g + 1] = -S[22] / W * unscale;
         double logdet = 0.0;
         for (int d = 0; d < 5; ++d) logdet += 2.0 * log(L[tri(d, d)]);
         double tr = 0.0;
         for (int d = 0; d < 5; ++d) tr += o.prior_b[d] * Si[d][d];
         Fk = beta * o.prior_q * log(pik) - 0.5 * beta * o.prior_a * logdet - 0.5 * beta * tr;
     }
-    for (int ofs = 1; ofs < 64; ofs <<= 1) Fk += __shfl_xor(Fk, ofs);
-    if (lane == 0) {
-        F_out[c] = LL / W + Fk;
+    Fk = gsum(Fk, GM);
+    if (cell_ok && k == 0) {
+        // the pass accumulated shifted log2 densities; add the cell's shift back
+        const double shift = (double)mirror[(int64_t)c * K * kMirror + kMirShift];
+        F_out[c] = (LL + shift * W) / kLog2e / W + Fk;
         status[c] = 0;
     }
 }
@@ -166,30 +163,29 @@ extern "C" int sdmm_fit_grad(const int64_t* cell_offsets, const float* samples, 
     if (opts->flags & SDMM_FLAG_ESTEP_JACOBIAN) return SDMM_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int C = mix->n_cells, K = mix->K;
-    const int64_t chunk = default_chunk(opts);
-    const int waves = default_waves(opts);
-    const Layout L = layout_for(C, K, n_samples, chunk);
+    const Layout L = layout_for(C, K, n_samples, opts);
     char* ws = reinterpret_cast<char*>(workspace);
-    launch_plan_prepare(cell_offsets, n_samples, *mix, chunk, cell_status, ws, L, s);
-    const float* mirror = reinterpret_cast<const float*>(ws + L.mirror);
-    const int32_t* flags = reinterpret_cast<const int32_t*>(ws + L.flags);
-    const int32_t* cstart = reinterpret_cast<const int32_t*>(ws + L.chunk_start);
-    const int32_t* ccell = reinterpret_cast<const int32_t*>(ws + L.chunk_cell);
-    const int32_t* ntot = reinterpret_cast<const int32_t*>(ws + L.n_total);
-    double* partial = reinterpret_cast<double*>(ws + L.partial);
-    const int G = group_for(K);
-    const size_t lds = (size_t)waves * ChunkLayout<true>::kNRed * G * sizeof(double);
-    const dim3 grid((unsigned)L.tmax), block(waves * 64);
-    ScopedTimer tm(SDMM_TIMER_GRAD, s);
-    switch (G) {
-        case 4: grad_estep_kernel<4><<<grid, block, lds, s>>>(samples, n_samples, cell_offsets, ccell, cstart, ntot, mirror, K, chunk, L.ps_grad, partial); break;
-        case 8: grad_estep_kernel<8><<<grid, block, lds, s>>>(samples, n_samples, cell_offsets, ccell, cstart, ntot, mirror, K, chunk, L.ps_grad, partial); break;
-        case 16: grad_estep_kernel<16><<<grid, block, lds, s>>>(samples, n_samples, cell_offsets, ccell, cstart, ntot, mirror, K, chunk, L.ps_grad, partial); break;
-        case 32: grad_estep_kernel<32><<<grid, block, lds, s>>>(samples, n_samples, cell_offsets, ccell, cstart, ntot, mirror, K, chunk, L.ps_grad, partial); break;
-        default: grad_estep_kernel<64><<<grid, block, lds, s>>>(samples, n_samples, cell_offsets, ccell, cstart, ntot, mirror, K, chunk, L.ps_grad, partial); break;
+    launch_setup(cell_offsets, n_samples, *mix, cell_status, ws, L, s);
+    {
+        ScopedTimer tm(SDMM_TIMER_GRAD, s);
+        const EstepFn pass = (opts->flags & SDMM_FLAG_FP64_SUMS) ? adj64_function(group_for(K))
+                                                                 : estep_function(group_for(K), kAccTwoSum, false, true);
+        launch_estep(pass, samples, n_samples, cell_offsets, C,
+                     K, L, 0, (int64_t)C + L.W, L.ps_grad, ws, s);
     }
     const MixPtrs mp{mix->weights, mix->mean_dir, mix->mean_pos, mix->cov};
-    grad_assemble_kernel<<<C, 64, 0, s>>>(cstart, partial, L.ps_grad, flags, mp, dev_opts(opts), F_out, g_alpha,
-                                          g_mu_pos, g_delta, g_L, cell_status);
+    auto asm_fn = grad_assemble_kernel<16>;
+    switch (group_for(K)) {
+        case 4: asm_fn = grad_assemble_kernel<4>; break;
+        case 8: asm_fn = grad_assemble_kernel<8>; break;
+        case 16: asm_fn = grad_assemble_kernel<16>; break;
+        case 32: asm_fn = grad_assemble_kernel<32>; break;
+        default: asm_fn = grad_assemble_kernel<64>; break;
+    }
+    hipLaunchKernelGGL(asm_fn, dim3((C + 3) / 4), dim3(256), 0, s, cell_offsets, n_samples, C, L.ps,
+                       reinterpret_cast<const double*>(ws + L.records), L.ps_grad,
+                       reinterpret_cast<const int32_t*>(ws + L.flags),
+                       reinterpret_cast<const int32_t*>(ws + L.global_ok), reinterpret_cast<const float*>(ws + L.mirror),
+                       mp, dev_opts(opts), F_out, g_alpha, g_mu_pos, g_delta, g_L, cell_status);
     return check(hipGetLastError());
 }

@@ -23,15 +23,15 @@ SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD
 ETA_CONSTANT, ETA_PAPER = 0, 1
 PRIOR_ETA_OVER_M, PRIOR_FIXED = 0, 1
 FLAG_ESTEP_JACOBIAN, FLAG_PLAIN_FP32, FLAG_FP64_SUMS = 1, 2, 4
-SCHED_BATCHED, SCHED_PER_CELL = 0, 1
+SCHED_BATCHED, SCHED_PER_CELL, SCHED_FUSED = 0, 1, 2
 COND_TABLE_STRIDE = 32
 
 
 class FitOpts(C.Structure):
     _fields_ = [
         ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
-        ("flags", C.c_int32), ("min_samples", C.c_int32), ("schedule", C.c_int32), ("chunk", C.c_int32),
-        ("waves", C.c_int32), ("use_graph", C.c_int32),
+        ("flags", C.c_int32), ("min_samples", C.c_int32), ("schedule", C.c_int32), ("min_range", C.c_int32),
+        ("max_ranges", C.c_int32), ("use_graph", C.c_int32),
         ("eta", C.c_double), ("rm_alpha", C.c_double), ("rm_beta", C.c_double), ("prior_scale", C.c_double),
         ("prior_q", C.c_double), ("prior_a", C.c_double), ("prior_b", C.c_double * 5),
         ("dead_threshold", C.c_double),
@@ -69,6 +69,9 @@ def lib():
         L.sdmm_sample.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, u64, vp, vp, vp, vp, vp]
         L.sdmm_condition_sample_pdf.argtypes = [vp, i32, i32, vp, vp, i64, i32, vp, u64, vp, vp, vp, vp]
         L.sdmm_fit_grad.argtypes = [vp, vp, i64, P(Mixtures), P(FitOpts), vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.sdmm_mixture_from_params.argtypes = [i32, i32, vp, vp, vp, vp, vp, P(Mixtures), vp, vp]
+        L.sdmm_grad_to_params.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+        L.sdmm_params_from_mixture.argtypes = [P(Mixtures), vp, vp, vp, vp]
         L.sdmm_status_string.argtypes = [C.c_int]
         L.sdmm_status_string.restype = C.c_char_p
         L.sdmm_version.restype = C.c_char_p
@@ -272,3 +275,42 @@ def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=N
                              workspace.numel(), _stream(stream))
     _check(rc, "sdmm_fit_grad")
     return out
+
+
+def mixture_from_params(alpha, mu_dir0, delta, mu_pos, L, out=None, with_jac=True, stream=None):
+    """Mixture (pi, mu_dir, mu_pos, cov) from the refinement parameters
+    (sdmm_mixture_from_params); returns (mixture dict, 2x2 Jacobians or None)."""
+    n_cells, K = alpha.shape[0], alpha.shape[1]
+    dev = alpha.device
+    if out is None:
+        out = {"pi": torch.empty(n_cells * K, dtype=torch.float64, device=dev),
+               "mu_dir": torch.empty(n_cells * K * 3, dtype=torch.float64, device=dev),
+               "mu_pos": torch.empty(n_cells * K * 3, dtype=torch.float64, device=dev),
+               "cov": torch.empty(n_cells * K * 15, dtype=torch.float64, device=dev)}
+    jac = torch.empty(n_cells, K, 4, dtype=torch.float64, device=dev) if with_jac else None
+    m = _mixtures(out, n_cells, K)
+    rc = lib().sdmm_mixture_from_params(n_cells, K, _ptr(alpha), _ptr(mu_dir0), _ptr(delta), _ptr(mu_pos),
+                                        _ptr(L), C.byref(m), _ptr(jac) if jac is not None else None,
+                                        _stream(stream))
+    _check(rc, "sdmm_mixture_from_params")
+    return out, jac
+
+
+def grad_to_params(L, jac, g_delta, g_L, stream=None):
+    """In-place pull-back of sdmm_fit_grad's delta and L gradients (sdmm_grad_to_params)."""
+    n_cells, K = L.shape[0], L.shape[1]
+    rc = lib().sdmm_grad_to_params(n_cells, K, _ptr(L), _ptr(jac), _ptr(g_delta), _ptr(g_L), _stream(stream))
+    _check(rc, "sdmm_grad_to_params")
+
+
+def params_from_mixture(mix, n_cells, K, stream=None):
+    """Refinement parameters of a mixture (sdmm_params_from_mixture): returns
+    (alpha [C,K], L [C,K,15], status [C]) as device tensors."""
+    dev = mix["pi"].device
+    alpha = torch.empty(n_cells, K, dtype=torch.float64, device=dev)
+    L = torch.empty(n_cells, K, 15, dtype=torch.float64, device=dev)
+    status = torch.empty(n_cells, dtype=torch.int32, device=dev)
+    m = _mixtures(mix, n_cells, K)
+    rc = lib().sdmm_params_from_mixture(C.byref(m), _ptr(alpha), _ptr(L), _ptr(status), _stream(stream))
+    _check(rc, "sdmm_params_from_mixture")
+    return alpha, L, status

@@ -121,19 +121,26 @@ def test_ragged_cells_statuses_and_isolation(dev, orc):
         for k in got:
             assert np.array_equal(got[k].reshape(C, -1)[c], mix0[k].reshape(C, -1)[c], equal_nan=True)
     fitted = [c for c in range(C) if c not in skipped]
-    worst = compare_mixtures(got, om, 16, cells=fitted)
-    print(worst)
-    assert_close(worst, rtol=2e-4, ang_tol=2e-5, what="ragged cells, 2 iterations")
+    # A cell with as many samples as components (cell 2: 16) has prior-dominated
+    # covariances whose smallest eigenvalue is about beta B / (beta a + S0) ~ 1e-6 of the
+    # data scale; FP32 rounding of the scatter (2^-24 |y|^2 per term) then shows at ~1e-3
+    # in the oracle covariance's own metric, so such cells are held to 2e-3.
+    m_pos = np.array([(b.samples[6, b.offsets[c]:b.offsets[c + 1]] > 0).sum() for c in range(C)])
+    for c in fitted:
+        worst = compare_mixtures(got, om, 16, cells=[c])
+        print(c, m_pos[c], {k: "%.2e" % v for k, v in worst.items()})
+        loose = m_pos[c] < 64
+        assert_close(worst, rtol=2e-3 if loose else 2e-4, ang_tol=2e-5, what=f"ragged cell {c} (M={m_pos[c]})")
 
 
-def test_batched_per_cell_and_graph_are_bitwise_equal_and_deterministic(dev, orc):
-    print("case: batched vs per-cell vs graph replay, 64 cells", flush=True)
+def test_schedules_and_graph_are_bitwise_equal_and_deterministic(dev, orc):
+    print("case: fused vs split vs per-cell vs graph replay, 64 cells", flush=True)
     from paper_2111_13094_amd import sdmm
     wl, b, mix0 = _ragged_case()
     C = wl["grid"].n_cells
     runs = []
     for sched, graph in ((sdmm.SCHED_BATCHED, 0), (sdmm.SCHED_BATCHED, 0), (sdmm.SCHED_PER_CELL, 0),
-                         (sdmm.SCHED_BATCHED, 1)):
+                         (sdmm.SCHED_FUSED, 0), (sdmm.SCHED_BATCHED, 1), (sdmm.SCHED_FUSED, 1)):
         gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
         s = _gpu_fit(dev, b, gm, gst, iters=2, schedule=sched, use_graph=graph)
         runs.append((to_numpy(gm), to_numpy(gst), s))
@@ -242,19 +249,42 @@ def test_option_variants(dev, orc, variant):
     assert_close(worst, rtol=3e-4 if variant == "plain" else 2e-4, ang_tol=3e-5, what=variant)
 
 
-def test_huge_cell_grows_its_work_items(dev, orc):
-    """A cell with more than 1024 work items of the configured size: the library grows
-    the item size (at most 1024 items per cell)."""
-    print("case: one cell of 150000 samples with chunk=64", flush=True)
+@pytest.mark.parametrize("split", [dict(min_range=64), dict(max_ranges=3), dict(min_range=1 << 20)])
+def test_work_split_does_not_change_results(dev, orc, split):
+    """One cell of 150000 samples cut into 2344 items of 64 samples, 3 items of 50000, or
+    a single item: the records are summed in item order in FP64, so every split is
+    within the same tolerance of the oracle."""
+    print(f"case: one cell of 150000 samples, split {split}", flush=True)
     wl, b = _single(n=150000, seed=5)
     mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
     om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
     orc.fit(_orc_opts(orc), b.offsets, b.samples, om, ost)
     gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
-    _gpu_fit(dev, b, gm, gst, chunk=64)
+    _gpu_fit(dev, b, gm, gst, **split)
     worst = compare_mixtures(to_numpy(gm), om, 16)
     print(worst)
-    assert_close(worst, what="huge cell")
+    assert_close(worst, what=f"split {split}")
+
+
+def test_unsorted_offsets_mark_every_cell_bad_input(dev, orc):
+    """Offsets that decrease somewhere are rejected on the device: every cell reports
+    BAD_INPUT and no parameter changes, as in the oracle."""
+    print("case: 27 cells with decreasing offsets", flush=True)
+    wl = synth.workload("cells4k", scale=27 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    off = b.offsets.copy()
+    off[5], off[6] = off[6], off[5]
+    bad = synth.Batch(b.samples, off, b.lobe)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    s_o = orc.fit(_orc_opts(orc), bad.offsets, bad.samples, om, ost)
+    assert (s_o == orc.BAD_INPUT).all()
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    s_g = _gpu_fit(dev, bad, gm, gst)
+    assert (s_g == orc.BAD_INPUT).all()
+    for k, v in to_numpy(gm).items():
+        assert np.array_equal(v, mix0[k]), k
 
 
 def test_full_size_cells4k_sampled_cells(dev, orc):
