@@ -3,7 +3,8 @@
 Headline (default): EM sample x component updates per second on the 4096-cell workload
 (16^3 cells of the unit cube, K = 16, cell counts lognormal(6.45, 1) clipped to
 [64, 8192], about 4.2M samples per batch, 8 resident batches, stepwise EM with decay 0.9:
-eta = 0.1 after the first batch), batched path (one E launch + one M launch per batch).
+eta = 0.1 after the first batch), batched schedule (one E launch + one M launch per
+batch over all cells).
 A step is one E+M pass over one resident batch; inputs are generated on the host and
 copied to HBM before the timed region.
 
@@ -15,9 +16,12 @@ The JSON line also carries:
                 per cell), same tolerance;
   cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the workload.
 
-Other workloads (--workload): single (1 cell, N = 16384, 20 iterations), cells16k
-(16384 cells, geometric counts, plus 2^22 query positions x 4 draws), huge (1 cell,
-2^24 samples, K = 32), grad (adjoint on the 4096-cell state).
+Other workloads (--workload), each printing its own line: single (1 cell, N = 16384,
+20 iterations, hipGraph), cells16k (16384 cells, geometric counts, then 2^22 query
+positions x 4 draws through the fused conditioning + sampling + pdf kernel), huge
+(1 cell, 2^24 samples, K = 32, the three running-sum variants), grad (the adjoint on
+the 4096-cell state after 8 batches, plus 10 refinement steps). --sweep times launch
+configurations of the headline workload.
 """
 from __future__ import annotations
 
@@ -32,6 +36,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+# launch configurations the headline run lets the autotuner choose from (schedule, items)
+TUNE_CANDIDATES = [{"schedule": 0, "min_range": p} for p in (128, 256, 512)] + [{"schedule": 2, "min_range": 256}]
 
 FLOPS_PER_PAIR = 140.0       # algorithmic FP32 flops per (sample, component) per E+M pass
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (published)
@@ -123,6 +130,13 @@ def bench_cells4k(args, torch):
         opts.min_range = args.min_range
     if args.max_ranges:
         opts.max_ranges = args.max_ranges
+    tuned = None
+    if args.tune:  # the autotuner picks the launch configuration on the first batch (untimed)
+        from paper_2111_13094_amd import tune
+        m_t, s_t = fresh()
+        opts = tune.tune_fit(offs[0], smps[0], m_t, s_t, opts, candidates=TUNE_CANDIDATES, reps=3)
+        tuned = {"schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched", "items": int(opts.min_range)}
+        del m_t, s_t
     status = torch.empty(C, dtype=torch.int32, device=dev)
     ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
     mix, st = fresh()
@@ -164,15 +178,33 @@ def bench_cells4k(args, torch):
                                "lognormal(6.45,1) clipped to [64,8192], 8 resident batches, stepwise EM "
                                "eta=0.1, FP32 E-step with compensated sums, FP64 M-step",
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
-                   "schedule": args.schedule, "min_range": int(opts.min_range or 256),
-                   "max_ranges": int(opts.max_ranges or 4096)},
+                   "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
+                   "min_range": int(opts.min_range or 256), "max_ranges": int(opts.max_ranges or 65536),
+                   "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": ("fused_kernel<16,TwoSum,false>" if args.schedule == "fused"
+                     "kernel": ("fused_kernel<16,TwoSum,false>" if opts.schedule == sdmm.SCHED_FUSED
                                 else "estep_kernel<16,TwoSum,false,false>"),
                      "kernel_ms": est_ms, "flops_per_launch": flops_per_launch},
         "mstep_ms": m_ms,
     }
+    if args.graph:
+        # the same steps replayed through the library's hipGraph cache (one graph per
+        # batch, all captured before the timed region; no per-kernel events in a replay)
+        gopts = sdmm.FitOpts.from_buffer_copy(opts)
+        gopts.use_graph = 1
+        for j in range(n_batches):
+            sdmm.fit_mixtures(offs[j], smps[j], mix, st, gopts, status, ws)
+        _sync(torch)
+        t0 = time.perf_counter()
+        gpairs = 0
+        for s_ in range(args.steps):
+            j = (args.warmup + s_) % n_batches
+            sdmm.fit_mixtures(offs[j], smps[j], mix, st, gopts, status, ws)
+            gpairs += N[j] * K
+        _sync(torch)
+        gw = time.perf_counter() - t0
+        out["hipgraph"] = {"value": gpairs / gw, "unit": "updates/s", "ms_per_step": gw * 1e3 / args.steps}
     if not args.no_plain:
         popts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_PER_CELL)
         pmix, pst = fresh()
@@ -272,6 +304,101 @@ def bench_cells16k(args, torch):
             "fit": {"value": smp.shape[1] * K / t_fit, "unit": "updates/s", "ms_per_step": t_fit * 1e3}}
 
 
+def bench_grad(args, torch):
+    """Adjoint on the 4096-cell workload: the state after 8 stepwise batches, then the
+    FP32 gradient pass (value + gradient of the penalised log-likelihood per cell) timed
+    over the next batch, the FP64 verification pass timed once, and 10 Adam refinement
+    steps through the autograd binding with the change in F."""
+    import ctypes as C_
+    from paper_2111_13094_amd import autograd, sdmm, synth
+    n_batches = 9
+    wl, batches = _gen_cells4k(n_batches)
+    C, K = wl["grid"].n_cells, 16
+    dev = torch.device("cuda", 0)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    mix = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+    st = sdmm.new_state(C, K, dev)
+    opts = sdmm.default_opts(K, eta=0.1)
+    for j in range(8):
+        b = batches[j]
+        sdmm.fit_mixtures(torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev), mix, st, opts)
+    b = batches[8]
+    off, smp = torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev)
+    N = smp.shape[1]
+    gopts = sdmm.default_opts(K, prior_mode=sdmm.PRIOR_FIXED, prior_scale=1e-3)
+    for _ in range(args.warmup):
+        sdmm.fit_grad(off, smp, mix, gopts)
+    _sync(torch)
+    L = sdmm.lib()
+    L.sdmm_timing_enable(1)
+    tot, cnt = C_.c_double(), C_.c_int64()
+    L.sdmm_timing_read(3, C_.byref(tot), C_.byref(cnt), 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = sdmm.fit_grad(off, smp, mix, gopts)
+    _sync(torch)
+    wall = time.perf_counter() - t0
+    L.sdmm_timing_read(3, C_.byref(tot), C_.byref(cnt), 1)
+    k_ms = tot.value / max(cnt.value, 1)
+    g64 = sdmm.default_opts(K, prior_mode=sdmm.PRIOR_FIXED, prior_scale=1e-3, flags=sdmm.FLAG_FP64_SUMS)
+    sdmm.fit_grad(off, smp, mix, g64)
+    _sync(torch)
+    L.sdmm_timing_read(3, C_.byref(tot), C_.byref(cnt), 1)
+    k64_ms = tot.value / max(cnt.value, 1)
+    L.sdmm_timing_enable(0)
+    status = out["status"].cpu().numpy()
+    ok = (status & (1 | 2 | 4 | 32)) == 0
+    _, F0, F1, rst = autograd.refine(mix, C, K, off, smp, gopts, steps=10, lr=1e-4)
+    _sync(torch)
+    F0, F1 = F0.cpu().numpy(), F1.cpu().numpy()
+    good = ok & ((rst.cpu().numpy() & (1 | 2 | 4 | 32)) == 0)
+    fl = FLOPS_PER_PAIR * N * K
+    achieved = fl / (k_ms * 1e-3) / 1e12
+    return {"metric": "adjoint sample x component pairs/s, 4096 cells K=16 (value + gradient per cell)",
+            "value": N * K * args.steps / wall, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "grad: 4096-cell workload after 8 stepwise batches (eta=0.1), gradient of the "
+                                   "penalised log-likelihood on the 9th batch, fixed prior beta=1e-3",
+                       "n_cells": C, "K": K, "samples": int(N), "cells_with_gradient": int(ok.sum())},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "estep_kernel<16,TwoSum,false,true>", "kernel_ms": k_ms,
+                         "flops_per_launch": fl, "note": "140 flop/pair of the statistics pass; the adjoint "
+                                                         "terms are extra work not counted"},
+            "fp64_mode_ms": k64_ms,
+            "refinement": {"steps": 10, "optimizer": "Adam lr=1e-4", "cells": int(good.sum()),
+                           "mean_dF": float(np.mean((F1 - F0)[good])),
+                           "cells_improved": int(((F1 > F0) & good).sum())}}
+
+
+def bench_huge(args, torch):
+    """One cell of 2^24 samples, K = 32, lognormal(0, 2.5) weights: one batched E+M step
+    per timed step for each running-sum variant of the E-step (the precision study's
+    throughput side; its errors against the FP64 oracle come from the GPU test suite)."""
+    from paper_2111_13094_amd import sdmm, synth
+    wl = synth.workload("huge")
+    b = synth.workload_batch(wl)
+    K = 32
+    dev = torch.device("cuda", 0)
+    off, smp = torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    N = smp.shape[1]
+    res = {}
+    for name, flags in (("twosum", 0), ("plain", sdmm.FLAG_PLAIN_FP32), ("fp64", sdmm.FLAG_FP64_SUMS)):
+        opts = sdmm.default_opts(K, flags=flags)
+        t = fit_time(args, torch, off, smp, mix0, 1, K, opts, steps=max(3, args.steps // 4))
+        res[name] = {"updates_per_s": N * K / t, "ms_per_step": t * 1e3}
+    v = res["twosum"]
+    return {"metric": "EM sample x component updates/s, 1 cell of 2^24 samples K=32 (compensated FP32 E-step)",
+            "value": v["updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": max(3, args.steps // 4),
+            "warmup": 0, "ms_per_step": v["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "huge: 1 cell, 2^24 samples, K=32, weights lognormal(0,2.5), one E+M step "
+                                   "from the initial mixture per step"},
+            "variants": res}
+
+
 def fit_time(args, torch, off, smp, mix0, C, K, opts, steps=5):
     """Average wall time of one batched E+M step from fresh mixtures and state."""
     from paper_2111_13094_amd import sdmm
@@ -319,10 +446,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "single"])
+    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
+    ap.add_argument("--tune", type=int, default=1, help="1: let the autotuner pick the launch configuration")
+    ap.add_argument("--graph", type=int, default=1, help="1: replay the fit through the library's hipGraph cache")
     ap.add_argument("--sweep", default="", help="comma-separated schedule:items points, e.g. batched:256,fused:512")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -344,12 +473,17 @@ def main():
             sched, p = point.split(":")
             args.schedule, args.min_range, args.max_ranges = sched, int(p), 1 << 20
             args.no_plain = args.no_cpu = True
+            args.tune = 0
             print(json.dumps(bench_cells4k(args, torch)), flush=True)
         return
     if args.workload == "cells4k":
         out = bench_cells4k(args, torch)
     elif args.workload == "cells16k":
         out = bench_cells16k(args, torch)
+    elif args.workload == "grad":
+        out = bench_grad(args, torch)
+    elif args.workload == "huge":
+        out = bench_huge(args, torch)
     else:
         out = bench_single(args, torch)
     print(json.dumps(out))

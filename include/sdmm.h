@@ -87,7 +87,7 @@ typedef struct sdmm_fit_opts {
                             P = max(min_range, ceil(N / max_ranges)) samples and each
                             (cell, range) intersection is one wave's work item;
                             0 = 256. Results do not depend on it beyond FP rounding. */
-    int32_t max_ranges;  /* upper bound on the number of ranges, 0 = 4096, at most 2^20 */
+    int32_t max_ranges;  /* upper bound on the number of ranges, 0 = 65536, at most 2^20 */
     int32_t use_graph;   /* 1: capture the iteration sequence in a hipGraph, cached by
                             argument values, and replay it */
     double eta;          /* Robbins-Monro weight of a new batch for SDMM_ETA_CONSTANT */

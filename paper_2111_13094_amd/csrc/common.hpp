@@ -49,7 +49,10 @@ inline int group_for(int K)
 }
 
 
-constexpr int kDefaultWaves = 4096;   // 256 CUs x 4 SIMDs x 4 waves
+// E-step work items of 256 samples (about 47 us of one wave at 4 waves per SIMD for
+// K = 16): small enough that the launch tail is short, large enough that the per-item
+// record (21 G + 3 doubles) and the M-step's read of it stay cheap.
+constexpr int kDefaultWaves = 1 << 16;  // cap on the number of items; P grows beyond it
 constexpr int kDefaultMinSamplesPerWave = 256;
 
 inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o)
@@ -136,7 +139,7 @@ EstepFn adj64_function(int G);
 void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws,
                   const Layout& L, hipStream_t s);
 
-// E-step over the record slots [slot_lo, slot_hi) (slot = cell + sample range index)
+// E-step over the items in record slots [slot_lo, slot_hi), one wave per slot
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
                   int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s);
 

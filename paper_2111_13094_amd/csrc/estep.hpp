@@ -120,7 +120,8 @@ __device__ __forceinline__ void sum_cell_records(const double* __restrict__ reco
 
 // Mirror slots: 0-8 R, 9-11 mu_x, 12-26 scaled Linv, 27 shifted log2 constant, 28-29 twist
 // rates, 30 the cell's log2 shift, 31 unused, 32-40 R residue, 41-43 mu_x residue,
-// 44-58 scaled Linv residue, 59 residue of the shifted log2 constant, 60-63 unused.
+// 44-58 scaled Linv residue, 59 residue of the shifted log2 constant, 60-61 twist rate
+// residues, 62-63 unused.
 constexpr int kMirShift = 30;
 
 // Twist of the frame about mu when mu moves along its own tangent directions:
@@ -187,7 +188,9 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     for (int i = 0; i < 9; ++i) out[32 + i] = (float)(R[i] - (double)out[i]);
     for (int d = 0; d < 3; ++d) out[41 + d] = (float)(mux[d] - (double)out[9 + d]);
     for (int i = 0; i < 15; ++i) out[44 + i] = (float)(Li[i] * scale - (double)out[12 + i]);
-    for (int i = 59; i < kMirror; ++i) out[i] = 0.0f;
+    out[60] = (float)(phi[0] - (double)out[28]);
+    out[61] = (float)(phi[1] - (double)out[29]);
+    out[62] = out[63] = 0.0f;
     return true;
 }
 
@@ -546,7 +549,7 @@ __device__ void estep_segment_adj64(const float* __restrict__ smp, int64_t N, in
     for (int d = 0; d < 3; ++d) mx[d] = (double)P[9 + d] + (double)P[41 + d];
     for (int q = 0; q < 15; ++q) Li[q] = (double)P[12 + q] + (double)P[44 + q];
     const double c2 = comp < K ? (double)P[27] + (double)P[59] : -INFINITY;
-    const double ph0 = P[28], ph1 = P[29];
+    const double ph0 = (double)P[28] + (double)P[60], ph1 = (double)P[29] + (double)P[61];
 
     double acc[NS];
     for (int q = 0; q < NS; ++q) acc[q] = 0.0;

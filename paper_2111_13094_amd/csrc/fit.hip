@@ -111,26 +111,40 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------
-// E-step: one wave per record slot t in [slot_lo, slot_hi)
+// Work item of wave w of an E-step launch over the record slots [slot_lo, slot_hi):
+// slot t = slot_lo + w, its cell by the 64-ary search, its item index t - first. False
+// for a slot between two cells' items.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ bool wave_item(int64_t w, const int64_t* __restrict__ off, int64_t N, int C, int ps,
+                                          int64_t slot_lo, int64_t slot_hi, int& c, int64_t& t, int64_t& s0,
+                                          int64_t& s1, int64_t& n_items)
+{
+    t = slot_lo + w;
+    if (t >= slot_hi) return false;
+    c = find_slot_cell(off, C, ps, t);
+    int64_t first;
+    if (!cell_items(off, N, c, ps, first, n_items)) return false;
+    const int64_t j = t - first;
+    if (j < 0 || j >= n_items) return false;
+    s0 = off[c] + (j << ps);
+    s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    return true;
+}
+
+// ---------------------------------------------------------------------------------
+// E-step: one wave per work item (see wave_item)
 // ---------------------------------------------------------------------------------
 template <int G, int ACC, bool JAC, bool ADJ>
 __global__ __launch_bounds__(256) void estep_kernel(const float* __restrict__ smp, int64_t N,
-                                                    const int64_t* __restrict__ off, int C, int ps,
-                                                    int64_t slot_lo, int64_t slot_hi,
-                                                    const float* __restrict__ mirror, int K, int PS,
+                                                    const int64_t* __restrict__ off, int C, int ps, int64_t slot_lo,
+                                                    int64_t slot_hi, const float* __restrict__ mirror, int K, int PS,
                                                     double* __restrict__ records)
 {
-    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t >= slot_hi) return;
-    const int c = find_slot_cell(off, C, ps, t);
-    int64_t first, n_items;
-    if (!cell_items(off, N, c, ps, first, n_items)) return;
-    const int64_t j = t - first;
-    if (j < 0 || j >= n_items) return;  // a slot between two cells' items
-    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
-    estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
-                                    records + t * PS);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int c;
+    int64_t t, s0, s1, n_items;
+    if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
+    estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, records + t * PS);
 }
 
 // FP64 adjoint pass (verification mode), same work map as estep_kernel
@@ -141,15 +155,10 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
                                                           const float* __restrict__ mirror, int K, int PS,
                                                           double* __restrict__ records)
 {
-    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t >= slot_hi) return;
-    const int c = find_slot_cell(off, C, ps, t);
-    int64_t first, n_items;
-    if (!cell_items(off, N, c, ps, first, n_items)) return;
-    const int64_t j = t - first;
-    if (j < 0 || j >= n_items) return;
-    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int c;
+    int64_t t, s0, s1, n_items;
+    if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
     estep_segment_adj64<G>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, records + t * PS);
 }
 
@@ -328,19 +337,15 @@ __global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ sm
                                                     DevOpts o, float* __restrict__ mirror, int refresh_mirror,
                                                     int32_t* __restrict__ status)
 {
-    const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (t >= slot_hi) return;
     if (!*global_ok) {
-        if (t < C && lane == 0) status[t] = kBadInput;
+        if (w < C && lane == 0) status[w] = kBadInput;
         return;
     }
-    const int c = find_slot_cell(off, C, ps, t);
-    int64_t first, n_items;
-    if (!cell_items(off, N, c, ps, first, n_items)) return;
-    const int64_t j = t - first;
-    if (j < 0 || j >= n_items) return;
-    const int64_t s0 = off[c] + (j << ps), s1 = min(s0 + (int64_t(1) << ps), off[c + 1]);
+    int c;
+    int64_t t, s0, s1, n_items;
+    if (!wave_item(w, off, N, C, ps, 0, slot_hi, c, t, s0, s1, n_items)) return;
     estep_segment<G, ACC, JAC, false>(smp, N, s0, s1, mirror_in + (int64_t)c * K * kMirror, K, records + t * PS);
     __threadfence();
     int done = 0;
@@ -455,8 +460,9 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
                   int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s)
 {
-    if (slot_hi <= slot_lo) return;
-    const unsigned blocks = (unsigned)((slot_hi - slot_lo + 3) / 4);
+    const int64_t waves = slot_hi - slot_lo;
+    if (waves <= 0) return;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
     hipLaunchKernelGGL(est, dim3(blocks), dim3(256), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
                        reinterpret_cast<const float*>(ws + L.mirror), K, PS,
                        reinterpret_cast<double*>(ws + L.records));

@@ -149,9 +149,39 @@ __device__ __forceinline__ void draw_uniforms(const float* uniforms, int64_t n_d
     }
 }
 
-// One draw for the group's query: pick the component by the CDF of pi' (sequential sum
-// in component order, lowest index on ties), sample nu = m + L' z (Box-Muller), discard
-// at |nu| >= pi, map with the exp map, evaluate the conditioned pdf at the result.
+// inclusive prefix sum over the G lanes of a group (lane order = component order):
+// DPP row shifts inside a row of 16 lanes, shuffles across rows
+template <int G>
+__device__ __forceinline__ float group_inclusive_scan(float v)
+{
+    const int comp = (threadIdx.x & 63) % G;
+#define SDMM_SCAN_STEP(o)                                                                          \
+    if constexpr (G > o) {                                                                         \
+        const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + o, \
+                                                                   0xF, 0xF, true));               \
+        v += comp >= o ? t : 0.0f;                                                                 \
+    }
+    SDMM_SCAN_STEP(1)
+    SDMM_SCAN_STEP(2)
+    SDMM_SCAN_STEP(4)
+    SDMM_SCAN_STEP(8)
+#undef SDMM_SCAN_STEP
+    if constexpr (G > 16) {  // add the totals of the group's earlier rows
+        const int base = (threadIdx.x & 63) - comp, row = comp >> 4;
+        const float t0 = __shfl(v, base + 15);
+        float add = row >= 1 ? t0 : 0.0f;
+        if constexpr (G > 32) {
+            const float t1 = __shfl(v, base + 31), t2 = __shfl(v, base + 47);
+            add = row >= 2 ? (row >= 3 ? (t0 + t1) + t2 : t0 + t1) : add;
+        }
+        v += add;
+    }
+    return v;
+}
+
+// One draw for the group's query: pick the component by the CDF of pi' (prefix sum in
+// component order, lowest index on ties), sample nu = m + L' z (Box-Muller), discard at
+// |nu| >= pi, map with the exp map, evaluate the conditioned pdf at the result.
 template <int G>
 __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk, float m0, float m1, int K,
                                            float u0, float u1, float u2, float& ox, float& oy, float& oz,
@@ -159,12 +189,7 @@ __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk
 {
     const int lane = threadIdx.x & 63;
     const int comp = lane % G, base = lane - comp;
-    float cdf = 0.0f;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-        const float v = __shfl(wk, base + j);
-        if (j <= comp) cdf += v;
-    }
+    const float cdf = group_inclusive_scan<G>(wk);
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
     const uint64_t hit = __ballot(comp < K && usable && u0 < cdf) & gmask;
     const uint64_t pos = __ballot(comp < K && usable && wk > 0.0f) & gmask;
@@ -348,19 +373,26 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
         const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
         const float den = group_sum<G>(e);
         const float wk = den > 0.0f ? e / den : 0.0f;
-        for (int t = 0; t < ns; ++t) {
-            const int64_t d = qq * ns + t;
-            float u0, u1, u2;
-            draw_uniforms(uniforms, nd, d, seed, u0, u1, u2);
-            float ox, oy, oz, pdf;
-            int valid, sel;
-            sample_one<G>(T, usable, wk, m0, m1, K, u0, u1, u2, ox, oy, oz, pdf, valid, sel);
-            if (inq && comp == 0) {
-                dirs_out[d] = ox;
-                dirs_out[nd + d] = oy;
-                dirs_out[2 * nd + d] = oz;
-                pdf_out[d] = pdf;
-                valid_out[d] = (uint8_t)valid;
+        // the uniforms of up to G draws of this query at once, one draw per lane of the
+        // group, then broadcast draw by draw
+        for (int t0 = 0; t0 < ns; t0 += G) {
+            float ul0 = 0.0f, ul1 = 0.0f, ul2 = 0.0f;
+            if (t0 + comp < ns) draw_uniforms(uniforms, nd, qq * ns + t0 + comp, seed, ul0, ul1, ul2);
+            const int tn = min(G, ns - t0);
+            for (int tt = 0; tt < tn; ++tt) {
+                const int64_t d = qq * ns + t0 + tt;
+                const int src = slot * G + tt;
+                const float u0 = __shfl(ul0, src), u1 = __shfl(ul1, src), u2 = __shfl(ul2, src);
+                float ox, oy, oz, pdf;
+                int valid, sel;
+                sample_one<G>(T, usable, wk, m0, m1, K, u0, u1, u2, ox, oy, oz, pdf, valid, sel);
+                if (inq && comp == 0) {
+                    dirs_out[d] = ox;
+                    dirs_out[nd + d] = oy;
+                    dirs_out[2 * nd + d] = oz;
+                    pdf_out[d] = pdf;
+                    valid_out[d] = (uint8_t)valid;
+                }
             }
         }
     }

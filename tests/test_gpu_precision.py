@@ -9,7 +9,7 @@ the per-lane running sums are kept:
   fp64    FP32 block sums folded into an FP64 running sum
 
 and over how many samples a lane sums before the FP64 reduction across work items
-(the default work item of 4096 samples, or the whole cell as one item). Errors are the
+(the default work item of 256 samples, or the whole cell as one item). Errors are the
 parity metrics of tests/parity_utils.py (relative for pi, mu_pos and Sigma in the
 oracle covariance's metric, radians for mu_dir)."""
 import numpy as np
@@ -45,9 +45,9 @@ def test_precision_variants_on_the_huge_cell(dev, orc):
     off, smp = torch.from_numpy(b.offsets).cuda(), torch.from_numpy(b.samples).cuda()
     one_item = 1 << 24
     variants = {
-        "twosum, 4096-sample items": dict(),
-        "fp64, 4096-sample items": dict(flags=sdmm.FLAG_FP64_SUMS),
-        "plain, 4096-sample items": dict(flags=sdmm.FLAG_PLAIN_FP32),
+        "twosum, default items": dict(),
+        "fp64, default items": dict(flags=sdmm.FLAG_FP64_SUMS),
+        "plain, default items": dict(flags=sdmm.FLAG_PLAIN_FP32),
         "twosum, one item": dict(min_range=one_item),
         "plain, one item": dict(min_range=one_item, flags=sdmm.FLAG_PLAIN_FP32),
     }
@@ -64,7 +64,7 @@ def test_precision_variants_on_the_huge_cell(dev, orc):
 
     def worst(w):
         return max(w["pi"], w["mu_pos"], w["cov"], 10 * w["mu_dir"])
-    for name in ("twosum, 4096-sample items", "fp64, 4096-sample items", "twosum, one item"):
+    for name in ("twosum, default items", "fp64, default items", "twosum, one item"):
         assert worst(res[name]) < 1e-4, (name, res[name])
     # compensation is what keeps a lane's long sum exact: without it the one-item sums drift
     assert worst(res["plain, one item"]) > 3 * worst(res["twosum, one item"])
