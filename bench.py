@@ -38,7 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # launch configurations the headline run lets the autotuner choose from (schedule, items)
-TUNE_CANDIDATES = [{"schedule": 0, "min_range": p} for p in (128, 256, 512)] + [{"schedule": 2, "min_range": 256}]
+TUNE_CANDIDATES = ([{"schedule": 0, "min_range": p, "waves_per_block": w} for p in (128, 256, 512) for w in (1, 2, 4)]
+                   + [{"schedule": 2, "min_range": 256, "waves_per_block": 4}])
 
 FLOPS_PER_PAIR = 140.0       # algorithmic FP32 flops per (sample, component) per E+M pass
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (published)
@@ -130,12 +131,15 @@ def bench_cells4k(args, torch):
         opts.min_range = args.min_range
     if args.max_ranges:
         opts.max_ranges = args.max_ranges
+    if args.wpb:
+        opts.waves_per_block = args.wpb
     tuned = None
     if args.tune:  # the autotuner picks the launch configuration on the first batch (untimed)
         from paper_2111_13094_amd import tune
         m_t, s_t = fresh()
         opts = tune.tune_fit(offs[0], smps[0], m_t, s_t, opts, candidates=TUNE_CANDIDATES, reps=3)
-        tuned = {"schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched", "items": int(opts.min_range)}
+        tuned = {"schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched", "items": int(opts.min_range),
+                 "waves_per_block": int(opts.waves_per_block or 1)}
         del m_t, s_t
     status = torch.empty(C, dtype=torch.int32, device=dev)
     ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
@@ -180,6 +184,7 @@ def bench_cells4k(args, torch):
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
                    "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
                    "min_range": int(opts.min_range or 256), "max_ranges": int(opts.max_ranges or 65536),
+                   "waves_per_block": int(opts.waves_per_block or 1),
                    "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
@@ -207,6 +212,7 @@ def bench_cells4k(args, torch):
         out["hipgraph"] = {"value": gpairs / gw, "unit": "updates/s", "ms_per_step": gw * 1e3 / args.steps}
     if not args.no_plain:
         popts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_PER_CELL)
+        ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, popts) for n in N), dtype=torch.uint8, device=dev)
         pmix, pst = fresh()
         sdmm.fit_mixtures(offs[0], smps[0], pmix, pst, popts, status, ws)
         _sync(torch)
@@ -403,6 +409,9 @@ def fit_time(args, torch, off, smp, mix0, C, K, opts, steps=5):
     """Average wall time of one batched E+M step from fresh mixtures and state."""
     from paper_2111_13094_amd import sdmm
     dev = smp.device
+    m = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+    sdmm.fit_mixtures(off, smp, m, sdmm.new_state(C, K, dev), opts)  # warm-up (module load, first launch)
+    _sync(torch)
     tot = 0.0
     for _ in range(steps):
         m = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
@@ -450,9 +459,11 @@ def main():
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
+    ap.add_argument("--wpb", type=int, default=0, help="E-step waves per work group (0: library default)")
     ap.add_argument("--tune", type=int, default=1, help="1: let the autotuner pick the launch configuration")
     ap.add_argument("--graph", type=int, default=1, help="1: replay the fit through the library's hipGraph cache")
-    ap.add_argument("--sweep", default="", help="comma-separated schedule:items points, e.g. batched:256,fused:512")
+    ap.add_argument("--sweep", default="", help="comma-separated schedule:items[:waves_per_block] points, "
+                                                "e.g. batched:256:1,fused:512")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -470,8 +481,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:  # launch-configuration sweep on the cells4k workload, one line per point
         for point in args.sweep.split(","):
-            sched, p = point.split(":")
+            sched, p, *w = point.split(":")
             args.schedule, args.min_range, args.max_ranges = sched, int(p), 1 << 20
+            args.wpb = int(w[0]) if w else 0
             args.no_plain = args.no_cpu = True
             args.tune = 0
             print(json.dumps(bench_cells4k(args, torch)), flush=True)

@@ -90,6 +90,10 @@ typedef struct sdmm_fit_opts {
     int32_t max_ranges;  /* upper bound on the number of ranges, 0 = 65536, at most 2^20 */
     int32_t use_graph;   /* 1: capture the iteration sequence in a hipGraph, cached by
                             argument values, and replay it */
+    int32_t waves_per_block; /* E-step launch: 1, 2 or 4 waves (work items) per work
+                            group; 0 = 1. Single-wave groups let a compute unit start a
+                            new item as soon as any wave slot frees up. */
+    int32_t reserved;    /* must be 0 */
     double eta;          /* Robbins-Monro weight of a new batch for SDMM_ETA_CONSTANT */
     double rm_alpha, rm_beta; /* SDMM_ETA_PAPER schedule (paper: 0.5, 0.1) */
     double prior_scale;  /* beta for SDMM_PRIOR_FIXED */

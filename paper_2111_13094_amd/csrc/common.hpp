@@ -31,7 +31,8 @@ struct StatePtrs {
 // FP64 records of the E-step (one per record slot; C + W slots with W = ceil(N / P)).
 // Records are sized for the larger (adjoint) pass so one workspace serves every call.
 struct Layout {
-    size_t mirror, flags, arrive, global_ok, records, total;
+    int wpb;  // waves per work group of the E-step launch
+    size_t mirror, flags, arrive, global_ok, records, total;  // global_ok: int32[2] control words
     int64_t P;  // samples per E-step work item, 2^ps
     int ps;
     int W;
@@ -58,6 +59,7 @@ constexpr int kDefaultMinSamplesPerWave = 256;
 inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o)
 {
     Layout L{};
+    L.wpb = (o->waves_per_block == 2 || o->waves_per_block == 4) ? o->waves_per_block : 1;
     const int64_t wmax = o->max_ranges > 0 ? o->max_ranges : kDefaultWaves;
     const int64_t pmin = o->min_range > 0 ? o->min_range : kDefaultMinSamplesPerWave;
     int64_t P = (N + wmax - 1) / wmax;
@@ -78,7 +80,7 @@ inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o
     L.arrive = p;
     p = align256(p + (size_t)C * sizeof(int32_t));
     L.global_ok = p;
-    p = align256(p + sizeof(int32_t));
+    p = align256(p + 2 * sizeof(int32_t));
     L.records = p;
     p = align256(p + ((size_t)C + (size_t)L.W) * (size_t)L.ps_grad * sizeof(double));
     L.total = p;
@@ -138,6 +140,11 @@ EstepFn adj64_function(int G);
 // setup kernel: FP32 mirrors, status reset, per-cell flags and the offsets check
 void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws,
                   const Layout& L, hipStream_t s);
+
+// record tree levels after an E-step pass (all cells, or one cell when cell >= 0, whose
+// samples are [c0, c1))
+void launch_tree(bool adj, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
+                 int64_t c1, char* ws, hipStream_t s);
 
 // E-step over the items in record slots [slot_lo, slot_hi), one wave per slot
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,

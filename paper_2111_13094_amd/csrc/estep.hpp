@@ -79,34 +79,38 @@ struct ChunkLayout {
     static __host__ __device__ constexpr int record(int G) { return (kNStat * G + (kNRed - kNStat) + 1) & ~1; }
 };
 
-// Sums the records of one cell's items [first, first + n_items) in item order, one
-// column per lane (all 64 lanes of the wave, which must be uniform in first/n_items),
-// with the loads of four items in flight, then hands lane k < G its component's
-// statistics S[s] = column s * G + k and every lane the extras X[i] = column NS * G + i.
+// Sums the records of one cell's items 0, 2^stride_log2, 2 * 2^stride_log2, ... below
+// n_items (record slots from `first`) in item order, one column per lane (all 64 lanes
+// of the wave, which must be uniform in first/n_items), with the loads of four records
+// in flight, then hands lane k < G its component's statistics S[s] = column s * G + k and
+// every lane the extras X[i] = column NS * G + i. With stride 2^(4 L) the summed records
+// are the level-L leaders of the record tree (see tree_kernel).
 template <int G, int NS, int NX>
 __device__ __forceinline__ void sum_cell_records(const double* __restrict__ records, int64_t first, int64_t n_items,
-                                                 int PS, double (&S)[NS], double (&X)[NX])
+                                                 int PS, int stride_log2, double (&S)[NS], double (&X)[NX])
 {
     constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
     const int lane = threadIdx.x & 63;
+    const int64_t n = (n_items + (int64_t(1) << stride_log2) - 1) >> stride_log2;  // records to sum
+    const int64_t step = (int64_t)PS << stride_log2;                                 // doubles between them
     double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = 0.0;
     int64_t j = 0;
-    for (; j + 4 <= n_items; j += 4) {
-        const double* r0 = records + (first + j) * PS;
+    for (; j + 4 <= n; j += 4) {
+        const double* r0 = records + first * PS + j * step;
         double a[4][NQ];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) a[u][q] = (q * 64 + lane < NCOL) ? r0[u * PS + q * 64 + lane] : 0.0;
+            for (int q = 0; q < NQ; ++q) a[u][q] = (q * 64 + lane < NCOL) ? r0[u * step + q * 64 + lane] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) v[q] += a[u][q];
     }
-    for (; j < n_items; ++j) {
-        const double* r0 = records + (first + j) * PS;
+    for (; j < n; ++j) {
+        const double* r0 = records + first * PS + j * step;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q * 64 + lane < NCOL) v[q] += r0[q * 64 + lane];
@@ -295,6 +299,24 @@ __device__ __forceinline__ float group_max_negative(float v)
     if constexpr (G >= 32) k = min(k, __shfl_xor(k, 16));
     if constexpr (G >= 64) k = min(k, __shfl_xor(k, 32));
     return __int_as_float(k);
+}
+
+// largest c in [0, C) with c + off[c] / 2^ps <= t (0 if none), by a 64-ary search of the wave
+__device__ __forceinline__ int find_slot_cell(const int64_t* __restrict__ off, int C, int ps, int64_t t)
+{
+    const int lane = threadIdx.x & 63;
+    int a = 0, n = C;
+    while (n > 1) {
+        const int step = (n + 63) / 64;
+        const int idx = a + lane * step;
+        const bool le = idx < a + n && (int64_t)idx + (off[idx] >> ps) <= t;
+        const uint64_t m = __ballot(le);
+        const int j = m ? 63 - __builtin_clzll(m) : 0;
+        const int end = a + n;
+        a += j * step;
+        n = min(step, end - a);
+    }
+    return a;
 }
 
 // E-step work items of cell c: its samples [off[c], off[c+1]) cut from the cell's first
@@ -509,6 +531,65 @@ __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int
             for (int s = NS; s < NR; ++s) part[NS * G + (s - NS)] = v[s];
         }
     }
+}
+
+// ---------------------------------------------------------------------------------
+// Record tree for cells with many items. Level l >= 1 groups a cell's items in blocks of
+// 16^l; the level-l leader of a block (its first item's record) receives the sum, in
+// order, of the block's up to 16 level-(l-1) leaders. Level-l leaders are exactly the
+// items of size P * 16^l, so a wave finds its leader by the same slot search with the
+// shift ps + 4 l. Levels run while the largest cell would leave more than kTreeTop
+// leaders for the M-step; the M-step then sums at most kTreeTop leader records.
+// ---------------------------------------------------------------------------------
+constexpr int kTreeLog2R = 4;
+constexpr int kTreeTop = 128;
+
+__host__ __device__ inline int tree_levels(int64_t max_items)
+{
+    int L = 0;
+    while (max_items > kTreeTop) {
+        max_items = (max_items + (1 << kTreeLog2R) - 1) >> kTreeLog2R;
+        ++L;
+    }
+    return L;
+}
+
+// control[0]: offsets valid, control[1]: the largest item count of a cell (setup kernel)
+template <int G, int NS, int NX>
+__global__ __launch_bounds__(256) void tree_kernel(const int64_t* __restrict__ off, int64_t N, int C, int ps,
+                                                   int level, int64_t slot_lo, int64_t slot_hi,
+                                                   const int32_t* __restrict__ control, double* __restrict__ records,
+                                                   int PS)
+{
+    constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
+    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= slot_hi || !control[0] || level > tree_levels(control[1])) return;
+    const int psl = ps + kTreeLog2R * level;
+    const int c = find_slot_cell(off, C, psl, t);
+    int64_t first, n_items;
+    if (!cell_items(off, N, c, ps, first, n_items)) return;
+    const int64_t b = t - (c + (off[c] >> psl));
+    const int64_t leaders = (n_items + (int64_t(1) << (kTreeLog2R * level)) - 1) >> (kTreeLog2R * level);
+    if (b < 0 || b >= leaders) return;
+    const int64_t sub = int64_t(1) << (kTreeLog2R * (level - 1));
+    const int64_t base = b << (kTreeLog2R * level);
+    const int64_t count = min((int64_t)(1 << kTreeLog2R), (n_items - base + sub - 1) / sub);
+    if (count <= 1) return;
+    const int lane = threadIdx.x & 63;
+    double* r0 = records + (first + base) * PS;
+    const int64_t step = (int64_t)PS * sub;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = (q * 64 + lane < NCOL) ? r0[q * 64 + lane] : 0.0;
+    for (int64_t i = 1; i < count; ++i) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q * 64 + lane < NCOL) v[q] += r0[i * step + q * 64 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q * 64 + lane < NCOL) r0[q * 64 + lane] = v[q];
 }
 
 // ---------------------------------------------------------------------------------

@@ -48,44 +48,35 @@ __device__ __forceinline__ int group_or(int v, int GM)
     return v;
 }
 
-// largest c in [0, C) with c + off[c] / 2^ps <= t (0 if none), by a 64-ary search of the wave
-__device__ __forceinline__ int find_slot_cell(const int64_t* __restrict__ off, int C, int ps, int64_t t)
-{
-    const int lane = threadIdx.x & 63;
-    int a = 0, n = C;
-    while (n > 1) {
-        const int step = (n + 63) / 64;
-        const int idx = a + lane * step;
-        const bool le = idx < a + n && (int64_t)idx + (off[idx] >> ps) <= t;
-        const uint64_t m = __ballot(le);
-        const int j = m ? 63 - __builtin_clzll(m) : 0;
-        const int end = a + n;
-        a += j * step;
-        n = min(step, end - a);
-    }
-    return a;
-}
-
 // ---------------------------------------------------------------------------------
 // setup: FP32 mirrors with the per-cell shift, status reset, per-cell flags; the last
 // block checks that the offsets are non-decreasing within [0, N]
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ off, int64_t N, int C, int K,
-                                                    int GM, MixPtrs mix, float* __restrict__ mirror,
+                                                    int GM, int ps, MixPtrs mix, float* __restrict__ mirror,
                                                     int32_t* __restrict__ flags, int32_t* __restrict__ status,
-                                                    int32_t* __restrict__ arrive, int32_t* __restrict__ global_ok,
+                                                    int32_t* __restrict__ arrive, int32_t* __restrict__ control,
                                                     int n_cell_blocks)
 {
-    if ((int)blockIdx.x == n_cell_blocks) {
-        __shared__ int bad;
-        if (threadIdx.x == 0) bad = 0;
+    if ((int)blockIdx.x == n_cell_blocks) {  // control[0]: offsets valid; control[1]: most items in a cell
+        __shared__ int bad, most;
+        if (threadIdx.x == 0) bad = 0, most = 1;
         __syncthreads();
         int b = 0;
-        for (int c = threadIdx.x; c < C; c += blockDim.x) b |= off[c + 1] < off[c];
+        int64_t m = 1;
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            const int64_t c0 = off[c], c1 = off[c + 1];
+            b |= c1 < c0;
+            m = max(m, (c1 - c0 + (int64_t(1) << ps) - 1) >> ps);
+        }
         if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;
         if (b) atomicOr(&bad, 1);
+        atomicMax(&most, (int)min(m, (int64_t)INT32_MAX));
         __syncthreads();
-        if (threadIdx.x == 0) *global_ok = bad ? 0 : 1;
+        if (threadIdx.x == 0) {
+            control[0] = bad ? 0 : 1;
+            control[1] = most;
+        }
         return;
     }
     const int per_block = blockDim.x / GM;
@@ -170,7 +161,7 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
 // ---------------------------------------------------------------------------------
 template <int G>
 __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
-                                           const double* __restrict__ records, int PS,
+                                           bool tree, const double* __restrict__ records, int PS,
                                            const int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
                                            const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
                                            float* __restrict__ mirror, int refresh_mirror,
@@ -189,7 +180,9 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     double S[kStats], X[3];
     int64_t first = 0, n_items = 0;
     const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
-    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, S, X);
+    // after the record tree (batched and per-cell schedules) only the top leaders remain
+    const int lv = tree && *global_ok ? tree_levels(global_ok[1]) : 0;
+    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     const double W = X[0], Mc = X[1], negs = X[2];
     int fin = isfinite(W);
     for (int s = 0; s < kStats; ++s) fin &= isfinite(S[s]) ? 1 : 0;
@@ -315,8 +308,8 @@ __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ 
 {
     const int cl = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool cell_ok = cl < n_cells;
-    mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, records, PS, flags, global_ok, mix, st, o, mirror,
-                  refresh_mirror, status);
+    mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, true, records, PS, flags, global_ok, mix, st, o,
+                  mirror, refresh_mirror, status);
 }
 
 // ---------------------------------------------------------------------------------
@@ -352,7 +345,9 @@ __global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ sm
     if (lane == 0) done = atomicAdd(arrive + c, 1) == (int)n_items - 1;
     if (!__builtin_amdgcn_readfirstlane(done)) return;
     __threadfence();
-    mstep_cell<G>(off, N, c, true, ps, records, PS, flags, global_ok, mix, st, o, mirror, refresh_mirror, status);
+    // no record tree here: the completing wave sums all of the cell's records itself
+    mstep_cell<G>(off, N, c, true, ps, false, records, PS, flags, global_ok, mix, st, o, mirror, refresh_mirror,
+                  status);
     if (lane == 0) arrive[c] = 0;
 }
 
@@ -451,7 +446,7 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
     const int per_block = 256 / GM;
     const int blocks = (C + per_block - 1) / per_block;
     const MixPtrs mp{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov};
-    setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, mp, reinterpret_cast<float*>(ws + L.mirror),
+    setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, L.ps, mp, reinterpret_cast<float*>(ws + L.mirror),
                                             reinterpret_cast<int32_t*>(ws + L.flags), status,
                                             reinterpret_cast<int32_t*>(ws + L.arrive),
                                             reinterpret_cast<int32_t*>(ws + L.global_ok), blocks);
@@ -462,10 +457,44 @@ void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, 
 {
     const int64_t waves = slot_hi - slot_lo;
     if (waves <= 0) return;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL(est, dim3(blocks), dim3(256), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
+    const unsigned blocks = (unsigned)((waves + L.wpb - 1) / L.wpb);
+    hipLaunchKernelGGL(est, dim3(blocks), dim3(64 * L.wpb), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
                        reinterpret_cast<const float*>(ws + L.mirror), K, PS,
                        reinterpret_cast<double*>(ws + L.records));
+}
+
+typedef void (*TreeFn)(const int64_t*, int64_t, int, int, int, int64_t, int64_t, const int32_t*, double*, int);
+
+template <int NS, int NX>
+static TreeFn tree_function(int G)
+{
+    switch (G) {
+        case 4: return tree_kernel<4, NS, NX>;
+        case 8: return tree_kernel<8, NS, NX>;
+        case 16: return tree_kernel<16, NS, NX>;
+        case 32: return tree_kernel<32, NS, NX>;
+        case 64: return tree_kernel<64, NS, NX>;
+    }
+    return nullptr;
+}
+
+void launch_tree(bool adj, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
+                 int64_t c1, char* ws, hipStream_t s)
+{
+    const TreeFn fn = adj ? tree_function<kStats + 2, 4>(group_for(K)) : tree_function<kStats, 3>(group_for(K));
+    const int PS = adj ? L.ps_grad : L.ps_fit;
+    const int levels = tree_levels((N + L.P - 1) / L.P);  // bound: the device skips levels it does not need
+    for (int level = 1; level <= levels; ++level) {
+        const int psl = L.ps + kTreeLog2R * level;
+        int64_t lo = 0, hi = (int64_t)C + ((N + (int64_t(1) << psl) - 1) >> psl);
+        if (cell >= 0) {  // one cell's leaders only
+            lo = cell + (c0 >> psl);
+            hi = lo + (c1 > c0 ? (c1 - c0 + (int64_t(1) << psl) - 1) >> psl : 1);
+        }
+        hipLaunchKernelGGL(fn, dim3((unsigned)((hi - lo + 3) / 4)), dim3(256), 0, s, off, N, C, L.ps, level, lo, hi,
+                           reinterpret_cast<const int32_t*>(ws + L.global_ok),
+                           reinterpret_cast<double*>(ws + L.records), PS);
+    }
 }
 
 struct FitArgs {
@@ -508,6 +537,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
                     const int64_t c0 = (*host_off)[c], c1 = (*host_off)[c + 1];
                     const int64_t first = c + (c0 >> L.ps), n_items = c1 > c0 ? (c1 - c0 + L.P - 1) >> L.ps : 1;
                     launch_estep(est, a.smp, a.N, a.off, C, K, L, first, first + n_items, L.ps_fit, a.ws, s);
+                    launch_tree(false, a.off, a.N, C, K, L, c, c0, c1, a.ws, s);
                 }
                 hipLaunchKernelGGL(mstep, dim3(1), dim3(64), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok, mp, sp,
                                    dopt, mirror, refresh, a.status, c, 1);
@@ -517,6 +547,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
                 ScopedTimer tm(SDMM_TIMER_ESTEP, s);
                 launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s);
             }
+            launch_tree(false, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s);
             ScopedTimer tm(SDMM_TIMER_MSTEP, s);
             hipLaunchKernelGGL(mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok,
                                mp, sp, dopt, mirror, refresh, a.status, 0, C);
@@ -542,6 +573,8 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
     if (opts->iters < 1 || opts->min_samples < 0) return SDMM_EINVAL;
     if (!mix->weights || !mix->mean_dir || !mix->mean_pos || !mix->cov) return SDMM_EINVAL;
     if (opts->min_range < 0 || opts->max_ranges < 0 || opts->max_ranges > (1 << 20)) return SDMM_EINVAL;
+    if (opts->waves_per_block < 0 || opts->waves_per_block > 4 || opts->waves_per_block == 3 || opts->reserved != 0)
+        return SDMM_EINVAL;
     const Layout L = layout_for(mix->n_cells, opts->K, n_samples, opts);
     // lane offsets inside a segment are 32-bit byte offsets; record slots are int32
     if (L.P * 4 > (int64_t)INT32_MAX || (int64_t)mix->n_cells + L.W > INT32_MAX) return SDMM_EINVAL;

@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(const int64_t* __res
     double S[NS], X[4];
     int64_t first = 0, n_items = 0;
     const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
-    sum_cell_records<G, NS, 4>(records, first, have ? n_items : 0, PS, S, X);
+    const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;  // top leaders of the record tree
+    sum_cell_records<G, NS, 4>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     const double W = X[0], Mc = X[1], negs = X[2], LL = X[3];
     int fin = isfinite(W) && isfinite(LL);
     for (int s = 0; s < NS; ++s) fin &= isfinite(S[s]) ? 1 : 0;
@@ -173,6 +174,7 @@ extern "C" int sdmm_fit_grad(const int64_t* cell_offsets, const float* samples, 
         launch_estep(pass, samples, n_samples, cell_offsets, C,
                      K, L, 0, (int64_t)C + L.W, L.ps_grad, ws, s);
     }
+    launch_tree(true, cell_offsets, n_samples, C, K, L, -1, 0, 0, ws, s);
     const MixPtrs mp{mix->weights, mix->mean_dir, mix->mean_pos, mix->cov};
     auto asm_fn = grad_assemble_kernel<16>;
     switch (group_for(K)) {

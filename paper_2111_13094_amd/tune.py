@@ -1,13 +1,15 @@
 """Autotuner for the launch configuration of sdmm_fit_mixtures.
 
-The batched fit has two free launch parameters that change its speed but not what it
+The batched fit has three free launch parameters that change its speed but not what it
 computes beyond FP32 rounding:
 
   * the E-step work-item size P (min_range, with max_ranges large so that P = min_range
     rounded up to a power of two): small items balance the waves across the 256 compute
     units; large items cost fewer records and M-step reads;
   * the schedule: one E launch then one M launch (SCHED_BATCHED), or the fused launch in
-    which the last wave of each cell runs its M-step (SCHED_FUSED).
+    which the last wave of each cell runs its M-step (SCHED_FUSED);
+  * the waves per work group of the E-step launch (1, 2 or 4), which changes how soon a
+    compute unit can start new items when items end at different times.
 
 tune_fit times every candidate on the caller's own batch, with HIP events on the
 stream the library launches on, using copies of the mixtures and state, and returns
@@ -26,10 +28,9 @@ from . import sdmm
 _CACHE: dict = {}
 
 DEFAULT_CANDIDATES = [
-    {"schedule": sched, "min_range": P}
-    for sched in (sdmm.SCHED_BATCHED, sdmm.SCHED_FUSED)
-    for P in (128, 256, 512, 1024, 2048)
-]
+    {"schedule": sdmm.SCHED_BATCHED, "min_range": P, "waves_per_block": wpb}
+    for P in (128, 256, 512, 1024) for wpb in (1, 2, 4)
+] + [{"schedule": sdmm.SCHED_FUSED, "min_range": P, "waves_per_block": 4} for P in (256, 1024)]
 
 
 def _key(n_cells, K, N, opts):
@@ -41,6 +42,7 @@ def _apply(opts, cand):
     o.schedule = cand["schedule"]
     o.min_range = cand["min_range"]
     o.max_ranges = 1 << 20
+    o.waves_per_block = cand.get("waves_per_block", 0)
     return o
 
 

@@ -266,6 +266,38 @@ def test_work_split_does_not_change_results(dev, orc, split):
     assert_close(worst, what=f"split {split}")
 
 
+def test_record_tree_schedules(dev, orc):
+    """Cells with more than 128 work items have their records pre-summed in a 16-ary tree
+    (two levels here: a 120000-sample cell in 64-sample items, 1875 items, next to small
+    cells). The batched and per-cell schedules sum in the same order (bitwise equal);
+    the fused schedule sums a cell's records in one pass (equal to rounding); all match
+    the oracle."""
+    print("case: record tree, 120000-sample cell in 64-sample items + 7 small cells", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("single", seed=17)
+    counts = [120000, 300, 0, 5000, 64, 2000, 17, 900]
+    b = synth.make_batch(19, counts, np.tile(wl["box_lo"], (8, 1)), np.tile(wl["box_size"], (8, 1)), wl["lobes"])
+    C = len(counts)
+    lo, size = np.tile(wl["box_lo"], (C, 1)), np.tile(wl["box_size"], (C, 1))
+    mix0 = synth.initial_mixtures(lo, size, 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    s_o = orc.fit(_orc_opts(orc, iters=2), b.offsets, b.samples, om, ost)
+    runs = {}
+    for name, sched in (("batched", sdmm.SCHED_BATCHED), ("per_cell", sdmm.SCHED_PER_CELL),
+                        ("fused", sdmm.SCHED_FUSED)):
+        gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+        st = _gpu_fit(dev, b, gm, gst, iters=2, schedule=sched, min_range=64, max_ranges=1 << 20)
+        assert (st == s_o).all(), (name, st, s_o)
+        runs[name] = to_numpy(gm)
+    for k in runs["batched"]:
+        assert np.array_equal(runs["batched"][k], runs["per_cell"][k]), k
+    fitted = [c for c in range(C) if not s_o[c] & (1 | 2 | 4 | 32)]
+    for name, got in runs.items():
+        worst = compare_mixtures(got, om, 16, cells=fitted)
+        print(name, worst)
+        assert_close(worst, rtol=2e-4, ang_tol=2e-5, what=name)
+
+
 def test_unsorted_offsets_mark_every_cell_bad_input(dev, orc):
     """Offsets that decrease somewhere are rejected on the device: every cell reports
     BAD_INPUT and no parameter changes, as in the oracle."""

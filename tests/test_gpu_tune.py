@@ -36,7 +36,7 @@ def test_tuner_picks_a_candidate_and_keeps_parity(dev, orc):
     tuned = tune.tune_fit(off, smp, gm, gst, opts, candidates=cands, reps=2)
     for k in gm:
         assert torch.equal(gm[k], before[k])
-    chosen = {"schedule": tuned.schedule, "min_range": tuned.min_range}
+    chosen = {"schedule": tuned.schedule, "min_range": tuned.min_range, "waves_per_block": tuned.waves_per_block}
     assert chosen in cands
     cached = tune.tuned_config(C, 16, smp.shape[1], opts)
     assert cached is not None and cached["ms"] > 0
