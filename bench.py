@@ -133,6 +133,7 @@ def bench_cells4k(args, torch):
         opts.max_ranges = args.max_ranges
     if args.wpb:
         opts.waves_per_block = args.wpb
+    opts.flags = {"twosum": 0, "plain": sdmm.FLAG_PLAIN_FP32, "fp64": sdmm.FLAG_FP64_SUMS}[args.sums]
     tuned = None
     if args.tune:  # the autotuner picks the launch configuration on the first batch (untimed)
         from paper_2111_13094_amd import tune
@@ -185,7 +186,7 @@ def bench_cells4k(args, torch):
                    "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
                    "min_range": int(opts.min_range or 256), "max_ranges": int(opts.max_ranges or 65536),
                    "waves_per_block": int(opts.waves_per_block or 1),
-                   "autotuned": tuned},
+                   "running_sums": args.sums, "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": ("fused_kernel<16,TwoSum,false>" if opts.schedule == sdmm.SCHED_FUSED
@@ -460,6 +461,8 @@ def main():
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
     ap.add_argument("--wpb", type=int, default=0, help="E-step waves per work group (0: library default)")
+    ap.add_argument("--sums", default="twosum", choices=["twosum", "plain", "fp64"],
+                    help="E-step running sums: compensated FP32 (default), plain FP32, FP64 fold")
     ap.add_argument("--tune", type=int, default=1, help="1: let the autotuner pick the launch configuration")
     ap.add_argument("--graph", type=int, default=1, help="1: replay the fit through the library's hipGraph cache")
     ap.add_argument("--sweep", default="", help="comma-separated schedule:items[:waves_per_block] points, "
@@ -484,6 +487,7 @@ def main():
             sched, p, *w = point.split(":")
             args.schedule, args.min_range, args.max_ranges = sched, int(p), 1 << 20
             args.wpb = int(w[0]) if w else 0
+            args.sums = w[1] if len(w) > 1 else "twosum"
             args.no_plain = args.no_cpu = True
             args.tune = 0
             print(json.dumps(bench_cells4k(args, torch)), flush=True)

@@ -210,6 +210,14 @@ __device__ inline void set_mirror_shift(float* out, double c2, double shift)
     out[kMirShift] = (float)shift;
 }
 
+// stores a mirror built in registers with 16-byte stores
+__device__ __forceinline__ void store_mirror(float* __restrict__ dst, const float (&m)[kMirror])
+{
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int q = 0; q < kMirror / 4; ++q) d4[q] = make_float4(m[4 * q], m[4 * q + 1], m[4 * q + 2], m[4 * q + 3]);
+}
+
 struct SampleRegs {
     float ox, oy, oz, px, py, pz, w;
 };
@@ -554,17 +562,12 @@ __host__ __device__ inline int tree_levels(int64_t max_items)
     return L;
 }
 
-// control[0]: offsets valid, control[1]: the largest item count of a cell (setup kernel)
+// the level-`level` leader in level slot t, if any, sums its block (see tree_kernel)
 template <int G, int NS, int NX>
-__global__ __launch_bounds__(256) void tree_kernel(const int64_t* __restrict__ off, int64_t N, int C, int ps,
-                                                   int level, int64_t slot_lo, int64_t slot_hi,
-                                                   const int32_t* __restrict__ control, double* __restrict__ records,
-                                                   int PS)
+__device__ __forceinline__ void tree_leader(const int64_t* __restrict__ off, int64_t N, int C, int ps, int level,
+                                            int64_t t, double* __restrict__ records, int PS)
 {
     constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
-    const int64_t t = slot_lo + (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t >= slot_hi || !control[0] || level > tree_levels(control[1])) return;
     const int psl = ps + kTreeLog2R * level;
     const int c = find_slot_cell(off, C, psl, t);
     int64_t first, n_items;
@@ -590,6 +593,22 @@ __global__ __launch_bounds__(256) void tree_kernel(const int64_t* __restrict__ o
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         if (q * 64 + lane < NCOL) r0[q * 64 + lane] = v[q];
+}
+
+// control[0]: offsets valid, control[1]: the largest item count of a cell (setup kernel).
+// A fixed grid strides over the level slots, so a level that is not needed costs one
+// small dispatch.
+template <int G, int NS, int NX>
+__global__ __launch_bounds__(256) void tree_kernel(const int64_t* __restrict__ off, int64_t N, int C, int ps,
+                                                   int level, int64_t slot_lo, int64_t slot_hi,
+                                                   const int32_t* __restrict__ control, double* __restrict__ records,
+                                                   int PS)
+{
+    if (!control[0] || level > tree_levels(control[1])) return;  // a level this batch does not need
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t t = slot_lo + wave; t < slot_hi; t += nwaves)
+        tree_leader<G, NS, NX>(off, N, C, ps, level, t, records, PS);
 }
 
 // ---------------------------------------------------------------------------------

@@ -18,6 +18,7 @@
 // on its own samples and P, and items of at most P samples keep the waves balanced.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -62,12 +63,24 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
         __shared__ int bad, most;
         if (threadIdx.x == 0) bad = 0, most = 1;
         __syncthreads();
+        // each thread scans a contiguous run of offsets, eight independent loads at a time
         int b = 0;
         int64_t m = 1;
-        for (int c = threadIdx.x; c < C; c += blockDim.x) {
-            const int64_t c0 = off[c], c1 = off[c + 1];
-            b |= c1 < c0;
-            m = max(m, (c1 - c0 + (int64_t(1) << ps) - 1) >> ps);
+        const int per = (C + blockDim.x - 1) / blockDim.x;
+        const int lo = min(C, (int)threadIdx.x * per), hi = min(C, lo + per);
+        int64_t prev = lo < hi ? off[lo] : 0;
+        for (int c = lo; c < hi; c += 8) {
+            int64_t nx[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nx[u] = c + u < hi ? off[c + u + 1] : prev;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (c + u < hi) {
+                    b |= nx[u] < prev;
+                    m = max(m, (nx[u] - prev + (int64_t(1) << ps) - 1) >> ps);
+                    prev = nx[u];
+                }
+            }
         }
         if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;
         if (b) atomicOr(&bad, 1);
@@ -79,20 +92,24 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
         }
         return;
     }
-    const int per_block = blockDim.x / GM;
-    const int c = blockIdx.x * per_block + threadIdx.x / GM;
-    const int k = threadIdx.x % GM;
+    // one cell per wave (its FP64 chains are long: more waves in flight hide latency),
+    // lane k = component k
+    const int c = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    const int k = threadIdx.x & 63;
     const bool active = c < C && k < K;
     const int64_t g = (int64_t)c * K + k;
     double c2 = -INFINITY;
     bool ok = true;
-    float* out = mirror + g * kMirror;
-    if (active) ok = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    float m[kMirror];
+    if (active) ok = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, m, c2);
     const double cmax = group_max_d(active && ok ? c2 : -INFINITY, GM);
     const int bad = group_or(active && !ok ? 1 : 0, GM);
     // the shift is an FP32 value, so adding it back in FP64 is exact
     const float shift = isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f;
-    if (active) set_mirror_shift(out, c2, (double)shift);
+    if (active) {
+        set_mirror_shift(m, c2, (double)shift);
+        store_mirror(mirror + g * kMirror, m);
+    }
     if (c < C && k == 0) {
         status[c] = 0;
         arrive[c] = 0;
@@ -280,7 +297,7 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     if (refresh_mirror) {  // mirrors for the next iteration of this call
         double c2 = -INFINITY;
         bool okm = true;
-        float* out = mirror + g * kMirror;
+        float* out = mirror + g * kMirror;  // written in place (keeps the M-step's registers free)
         if (run && act) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
         const double cmax = group_max_d((run && act && okm) ? c2 : -INFINITY, GM);
         if (run && act) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f));
@@ -443,8 +460,7 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
 {
     const int C = mix.n_cells, K = mix.K;
     const int GM = group_pow2(K);
-    const int per_block = 256 / GM;
-    const int blocks = (C + per_block - 1) / per_block;
+    const int blocks = (C + 3) / 4;  // one cell per wave
     const MixPtrs mp{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov};
     setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, L.ps, mp, reinterpret_cast<float*>(ws + L.mirror),
                                             reinterpret_cast<int32_t*>(ws + L.flags), status,
@@ -491,7 +507,8 @@ void launch_tree(bool adj, const int64_t* off, int64_t N, int C, int K, const La
             lo = cell + (c0 >> psl);
             hi = lo + (c1 > c0 ? (c1 - c0 + (int64_t(1) << psl) - 1) >> psl : 1);
         }
-        hipLaunchKernelGGL(fn, dim3((unsigned)((hi - lo + 3) / 4)), dim3(256), 0, s, off, N, C, L.ps, level, lo, hi,
+        const int64_t blocks = std::min<int64_t>((hi - lo + 3) / 4, 256);  // grid-stride: at most 1024 waves
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, s, off, N, C, L.ps, level, lo, hi,
                            reinterpret_cast<const int32_t*>(ws + L.global_ok),
                            reinterpret_cast<double*>(ws + L.records), PS);
     }
