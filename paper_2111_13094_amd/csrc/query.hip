@@ -88,6 +88,19 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
 // per-lane pieces
 // ---------------------------------------------------------------------------------
 
+// FP32 exp map w = R^T (nu sinc r, cos r) with the hardware sine / cosine (which take
+// revolutions), square root and reciprocal
+__device__ __forceinline__ void exp_map_hw(const float* R, float n0, float n1, float w[3])
+{
+    const float r2 = fmaf(n0, n0, n1 * n1);
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float rev = r * 0.15915494309189535f;
+    const float sr = __builtin_amdgcn_sinf(rev), cr = __builtin_amdgcn_cosf(rev);
+    const float sc = r > 1e-4f ? sr * __builtin_amdgcn_rcpf(r) : 1.0f - r2 * (1.0f / 6.0f);
+    const float v0 = n0 * sc, v1 = n1 * sc;
+    for (int j = 0; j < 3; ++j) w[j] = fmaf(R[j], v0, fmaf(R[3 + j], v1, R[6 + j] * cr));
+}
+
 // conditional log2-weight and mean of component T at position x
 __device__ __forceinline__ float cond_component(const float* T, float x0, float x1, float x2, float& m0, float& m1)
 {
@@ -197,14 +210,16 @@ __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk
     if (hit) sel = __builtin_ctzll(hit) - base;
     else if (pos) sel = 63 - __builtin_clzll(pos) - base;
     // every lane forms its own component's candidate; the selected one is broadcast
-    const float rad = sqrtf(-2.0f * logf(1.0f - u1));
+    // hardware log2 / sqrt / sin / cos (the sine and cosine take revolutions: sin(2 pi u2))
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718056f * __builtin_amdgcn_logf(1.0f - u1));
     float sn, cs;
-    sincospif(2.0f * u2, &sn, &cs);
+    sn = __builtin_amdgcn_sinf(u2);
+    cs = __builtin_amdgcn_cosf(u2);
     const float z0 = rad * cs, z1 = rad * sn;
     const float n0 = fmaf(T[24], z0, m0);
     const float n1 = fmaf(T[25], z0, fmaf(T[26], z1, m1));
     float w[3];
-    exp_map_f32(T, n0, n1, w);
+    exp_map_hw(T, n0, n1, w);
     const int ok = fmaf(n0, n0, n1 * n1) < kPiSq;
     const int src = base + (sel < 0 ? 0 : sel);
     ox = __shfl(w[0], src);
