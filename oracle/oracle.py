@@ -37,7 +37,7 @@ class _Opts(C.Structure):
     _fields_ = [
         ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
         ("estep_jacobian", C.c_int32), ("euclidean", C.c_int32), ("min_samples", C.c_int32),
-        ("reserved", C.c_int32),
+        ("accurate_sigma", C.c_int32),
         ("eta", C.c_double), ("rm_alpha", C.c_double), ("rm_beta", C.c_double),
         ("prior_scale", C.c_double), ("prior_q", C.c_double), ("prior_a", C.c_double),
         ("prior_b", C.c_double * 5), ("dead_threshold", C.c_double),
@@ -63,6 +63,7 @@ class Opts:
     euclidean: int = 0
     min_samples: int = 16
     dead_threshold: float = 1e-12
+    accurate_sigma: int = 0    # 1: covariance from a second pass in the new tangent spaces (eta = 1)
 
     def to_c(self) -> _Opts:
         q = 1.0 / self.K if self.prior_q is None else self.prior_q
@@ -76,6 +77,7 @@ class Opts:
         for i in range(5):
             o.prior_b[i] = b[i]
         o.dead_threshold = self.dead_threshold
+        o.accurate_sigma = self.accurate_sigma
         return o
 
 

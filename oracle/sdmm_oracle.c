@@ -15,7 +15,9 @@
  *   - the M-step: weights, tangent-space mean update through the exp map, covariance
  *     computed in the old frame and carried to the new one by the first-order
  *     Jacobian (Sec. 3.2 mean update; Sec. 3.4 "Efficient tangent-space covariance
- *     update"; Appendix A);
+ *     update"; Appendix A); optionally the accurate covariance, from a second pass that
+ *     takes the second moment in the new mean's tangent space (Sec. 3.2, "Sufficient
+ *     statistics in tangent spaces");
  *   - Robbins-Monro averaging of the statistics and the normaliser across batches,
  *     and the MAP (Dirichlet / inverse-Wishart) updates (Sec. 4.3);
  *   - closed-form Gaussian conditioning on the position, the solid-angle pdf and
@@ -30,7 +32,8 @@
  * weights the new batch for every statistic; the prior strength is beta_j = eta_j / M_j
  * unless a fixed value is given; statistics are carried to the new frame after every
  * M-step with the first moment reset to zero; the prior is added after the transfer;
- * antipodal log-map input maps to (pi, 0).
+ * antipodal log-map input maps to (pi, 0); the accurate covariance pass keeps the
+ * responsibilities of the E-step and is defined for batch steps (eta = 1) only.
  *
  * Layouts (shared as an interface with the GPU library, written independently):
  *   samples   float32 structure-of-arrays [7][N]: dir x,y,z, pos x,y,z, weight
@@ -63,7 +66,7 @@ typedef struct {
     int32_t estep_jacobian; /* 1: responsibilities from solid-angle densities */
     int32_t euclidean;      /* 1: the two directional coordinates are plain R^2 */
     int32_t min_samples;    /* cells with fewer positive-weight samples are skipped */
-    int32_t reserved;
+    int32_t accurate_sigma; /* 1: second moment re-taken in the new mean's tangent space */
     double eta, rm_alpha, rm_beta, prior_scale;
     double prior_q, prior_a, prior_b[5];
     double dead_threshold;
@@ -530,6 +533,68 @@ static int gate(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i
     return 0;
 }
 
+/* Accurate covariance update (Sec. 3.2, "Sufficient statistics in tangent spaces"): once
+ * the new means are known, the second moment of the batch is taken again in each new
+ * mean's tangent space, S2^_k = sum_i w_i r_ik y^_ik y^_ik^T with
+ * y^_ik = (log_{mu^_k} w_i, p_i - mu^_x_k), and Sigma^_k = (beta B + S2^_k / W) /
+ * (beta a + S0_k / W). No mean is subtracted: the coordinates are already centred on the
+ * new mean. The responsibilities r_ik are those of the E-step (the current parameters);
+ * only the coordinates move. Defined for batch steps (eta = 1), where the carried
+ * statistics do not enter. Components the M-step left unchanged (dead) are skipped; a
+ * covariance that is not SPD keeps the previous one and flags the cell. */
+static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0,
+                               int64_t i1, const double *pi0, const double *mud0, const double *mux0,
+                               const double *cov0, const double *mud, const double *mux, double *cov,
+                               double *s2, const double *S0, double W, int64_t M)
+{
+    comp_t c_old[ORC_KMAX], c_new[ORC_KMAX];
+    double S2a[ORC_KMAX * 15];
+    int status = 0;
+    memset(S2a, 0, sizeof(S2a));
+    setup_components(K, pi0, mud0, mux0, cov0, c_old);
+    for (int k = 0; k < K; ++k) orc_frame(mud + 3 * k, c_new[k].R);
+    for (int64_t i = i0; i < i1; ++i) {
+        double w[3], p[3], wt, y[ORC_KMAX][5], l[ORC_KMAX];
+        load_sample(smp, N, i, w, p, &wt);
+        double lmax = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            tangent_coords(o, &c_old[k], mud0 + 3 * k, mux0 + 3 * k, w, p, y[k]);
+            l[k] = comp_log_density(o, &c_old[k], y[k]);
+            if (l[k] > lmax) lmax = l[k];
+        }
+        double den = 0.0;
+        for (int k = 0; k < K; ++k) den += exp(l[k] - lmax);
+        for (int k = 0; k < K; ++k) {
+            const double wr = wt * exp(l[k] - lmax) / den;
+            double yh[5];
+            tangent_coords(o, &c_new[k], mud + 3 * k, mux + 3 * k, w, p, yh);
+            for (int d = 0; d < 5; ++d)
+                for (int e = 0; e <= d; ++e) S2a[15 * k + TRI(d, e)] += wr * yh[d] * yh[e];
+        }
+    }
+    const double beta = (o->prior_mode == 0) ? 1.0 / (double)M : o->prior_scale;
+    for (int k = 0; k < K; ++k) {
+        const double bar0 = S0[k] / W;
+        if (!(bar0 > o->dead_threshold)) continue;
+        double Sig[15], Lt[15];
+        const double den = beta * o->prior_a + bar0;
+        for (int d = 0; d < 5; ++d)
+            for (int e = 0; e <= d; ++e) {
+                double v = S2a[15 * k + TRI(d, e)] / W;
+                if (d == e) v += beta * o->prior_b[d];
+                Sig[TRI(d, e)] = v / den;
+            }
+        if (chol_packed(5, Sig, Lt) == 0) {
+            memcpy(cov + 15 * k, Sig, sizeof(Sig));
+        } else {
+            memcpy(cov + 15 * k, cov0 + 15 * k, sizeof(Sig));
+            status |= ORC_CHOL_FAIL_KEPT_PREV;
+        }
+        memcpy(s2 + 15 * k, S2a + 15 * k, sizeof(Sig));
+    }
+    return status;
+}
+
 /* Fit: o->iters E+M iterations of every cell on the given batch. Parameters and the
  * averaged statistics are updated in place; status[c] receives the OR of the cell's
  * status bits over the iterations. */
@@ -539,7 +604,10 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
 {
     const int K = o->K;
     if (K < 1 || K > ORC_KMAX) return -1;
+    /* the accurate covariance update is defined for batch steps */
+    if (o->accurate_sigma && !(o->eta_mode == 0 && o->eta == 1.0)) return -2;
     double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
+    double pi0[ORC_KMAX], mud0[ORC_KMAX * 3], mux0[ORC_KMAX * 3], cov0[ORC_KMAX * 15];
     /* the offsets must partition a prefix of the sample array: non-decreasing, from >= 0
      * to <= N. An array that is not is rejected as a whole: every cell reports bad input
      * and nothing changes (a decreasing entry says the batch itself is malformed). */
@@ -575,8 +643,22 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
                 status[c] |= ORC_BAD_INPUT;
                 break;
             }
-            status[c] |= cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
-                                    cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
+            if (o->accurate_sigma) {
+                memcpy(pi0, pi + ck, sizeof(double) * K);
+                memcpy(mud0, mud + 3 * ck, sizeof(double) * 3 * K);
+                memcpy(mux0, mux + 3 * ck, sizeof(double) * 3 * K);
+                memcpy(cov0, cov + 15 * ck, sizeof(double) * 15 * K);
+            }
+            int ms = cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
+                                cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
+            if (o->accurate_sigma) {
+                /* the first-order covariance of the M-step is replaced by the second pass,
+                 * and so is its SPD verdict */
+                ms &= ~ORC_CHOL_FAIL_KEPT_PREV;
+                ms |= accurate_sigma_pass(o, K, smp, N, i0, i1, pi0, mud0, mux0, cov0, mud + 3 * ck,
+                                          mux + 3 * ck, cov + 15 * ck, s2 + 15 * ck, S0, W, M);
+            }
+            status[c] |= ms;
         }
     }
     return 0;

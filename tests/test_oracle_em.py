@@ -437,3 +437,116 @@ def test_malformed_offsets_reject_the_whole_batch(orc):
     o4[-1] = o4[-2]
     m, s, stat = _fit_copy(orc, orc.Opts(K=16), o4, b.samples, mix)
     assert stat[-1] == orc.SKIPPED_FEW and (stat[:-1] & orc.BAD_INPUT == 0).all()
+
+
+# --- P12 accurate covariance update (Sec. 3.2, second pass in the new tangent space) ---
+
+def _geodesic_coords(Wd, P, mu, mx, basis_seed):
+    """Tangent coordinates of unit directions about `mu` from their geodesic distance and
+    direction, in an orthonormal tangent basis chosen independently of the oracle's frame."""
+    cos = Wd @ mu
+    proj = Wd - cos[:, None] * mu
+    sin = np.linalg.norm(proj, axis=1)
+    th = np.arctan2(sin, cos)
+    e1 = _unit(np.cross(mu, np.random.default_rng(basis_seed).normal(size=3)))
+    e2 = np.cross(mu, e1)
+    nu = (th / sin)[:, None] * np.stack([proj @ e1, proj @ e2], 1)
+    return np.concatenate([nu, P - mx], 1)
+
+
+def _accurate_problem(n=3000, kappa=4.0, offset=0.7, K=1, seed=21):
+    rng = np.random.default_rng(seed)
+    lobes = [_unit(np.array([0.2, -0.7, 0.5])), _unit(np.array([-0.6, 0.1, 0.4])), _unit(np.array([0.3, 0.8, 0.2]))]
+    lab = rng.integers(0, K, n)
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = synth.sample_vmf(rng, np.stack([lobes[k] for k in lab]), np.full(n, kappa)).T
+    smp[3:6] = rng.random((3, n))
+    smp[3] += 0.8 * smp[0]  # direction-position coupling, so the cross block is not zero
+    smp[6] = synth.draw_weights(rng, n)
+    mix = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), K)
+    mud = mix["mu_dir"].reshape(K, 3)
+    for k in range(K):
+        ax = _unit(np.cross(lobes[k], [1.0, 0.0, 0.0]))
+        mud[k] = np.cos(offset) * lobes[k] + np.sin(offset) * ax
+    return smp, mix
+
+
+def test_accurate_sigma_single_component_is_the_scatter_about_the_new_mean(orc):
+    """K = 1: every responsibility is 1, so the accurate update is the weighted second
+    moment of the samples' geodesic tangent coordinates about the new mean, plus the
+    prior. Compared up to a rotation of the tangent basis (eigenvalues of the 5x5 matrix)
+    and exactly in the positional block. The first-order transfer is visibly off here
+    (the initial mean is 0.7 rad from the lobe)."""
+    smp, mix0 = _accurate_problem()
+    n = smp.shape[1]
+    beta = 0.01
+    gaps = {}
+    for acc in (1, 0):
+        mix = synth.copy_mix(mix0)
+        opts = orc.Opts(K=1, iters=1, prior_mode=1, prior_scale=beta, accurate_sigma=acc)
+        o = opts.to_c()
+        st = orc.new_state(1, 1)
+        assert orc.fit(opts, np.array([0, n]), smp, mix, st)[0] == 0
+        w = smp[6].astype(np.float64)
+        Y = _geodesic_coords(smp[0:3].T.astype(np.float64), smp[3:6].T.astype(np.float64), mix["mu_dir"],
+                             mix["mu_pos"], 5)
+        scatter = (w[:, None] * Y).T @ Y / w.sum()
+        S = _unpack(mix["cov"]) * (1.0 + beta * o.prior_a) - beta * np.diag(o.prior_b)
+        ev, ev_ref = np.linalg.eigvalsh(S), np.linalg.eigvalsh(scatter)
+        gaps[acc] = np.abs(ev - ev_ref).max() / ev_ref.max()
+        assert np.allclose(S[2:, 2:], scatter[2:, 2:], rtol=1e-12, atol=1e-15)
+    assert gaps[1] < 1e-12, gaps
+    assert gaps[0] > 1e-3, gaps
+
+
+def test_accurate_sigma_uses_the_e_step_responsibilities(orc):
+    """K = 3 on the sphere: each component's accurate second moment is the sum of
+    w r y^ y^^T with r the responsibilities under the parameters before the step and y^ the
+    geodesic coordinates about the new mean."""
+    K = 3
+    smp, mix0 = _accurate_problem(n=2400, kappa=10.0, offset=0.3, K=K, seed=8)
+    n = smp.shape[1]
+    beta = 0.02
+    opts = orc.Opts(K=K, iters=1, prior_mode=1, prior_scale=beta, accurate_sigma=1)
+    o = opts.to_c()
+    w = smp[6].astype(np.float64)
+    r = np.stack([orc.responsibilities(opts, smp[0:3, i].astype(np.float64), smp[3:6, i].astype(np.float64), mix0)
+                  for i in range(n)])
+    mix = synth.copy_mix(mix0)
+    st = orc.new_state(1, K)
+    assert orc.fit(opts, np.array([0, n]), smp, mix, st)[0] == 0
+    W = w.sum()
+    for k in range(K):
+        mu, mx = mix["mu_dir"].reshape(K, 3)[k], mix["mu_pos"].reshape(K, 3)[k]
+        Y = _geodesic_coords(smp[0:3].T.astype(np.float64), smp[3:6].T.astype(np.float64), mu, mx, k)
+        wr = w * r[:, k]
+        scatter = (wr[:, None] * Y).T @ Y / W
+        S = _unpack(mix["cov"].reshape(K, 15)[k]) * (beta * o.prior_a + wr.sum() / W) - beta * np.diag(o.prior_b)
+        ev, ev_ref = np.linalg.eigvalsh(S), np.linalg.eigvalsh(scatter)
+        assert np.abs(ev - ev_ref).max() < 1e-11 * ev_ref.max(), (k, ev, ev_ref)
+        assert np.allclose(S[2:, 2:], scatter[2:, 2:], rtol=1e-11, atol=1e-15)
+
+
+def test_accurate_sigma_is_the_textbook_update_in_euclidean_mode(orc):
+    """Euclidean coordinates: moving the frame is a translation, so the second pass gives
+    the textbook covariance about the new mean, as the first-order path does."""
+    smp, X, w, (pi, mu, Sig), mix = _euclid_problem(seed=13)
+    K = pi.size
+    beta = 0.3
+    opts = orc.Opts(K=K, iters=1, euclidean=1, prior_mode=1, prior_scale=beta, accurate_sigma=1)
+    o = opts.to_c()
+    st = orc.new_state(1, K)
+    for it in range(4):
+        pi, mu, Sig = _textbook_step(X, w, pi, mu, Sig, beta, o.prior_q, o.prior_a, np.array(o.prior_b))
+        assert orc.fit(opts, np.array([0, X.shape[0]]), smp, mix, st)[0] == 0
+        got_S = np.stack([_unpack(c) for c in mix["cov"].reshape(K, 15)])
+        assert np.allclose(mix["pi"], pi, rtol=1e-10, atol=1e-14)
+        assert np.allclose(got_S, Sig, rtol=1e-9, atol=1e-13)
+
+
+def test_accurate_sigma_needs_batch_steps(orc):
+    smp, mix = _accurate_problem(n=64)
+    st = orc.new_state(1, 1)
+    for kw in ({"eta": 0.5}, {"eta_mode": 1}):
+        with pytest.raises(ValueError):
+            orc.fit(orc.Opts(K=1, accurate_sigma=1, **kw), np.array([0, 64]), smp, synth.copy_mix(mix), st)
