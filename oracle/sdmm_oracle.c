@@ -32,8 +32,9 @@
  * weights the new batch for every statistic; the prior strength is beta_j = eta_j / M_j
  * unless a fixed value is given; statistics are carried to the new frame after every
  * M-step with the first moment reset to zero; the prior is added after the transfer;
- * antipodal log-map input maps to (pi, 0); the accurate covariance pass keeps the
- * responsibilities of the E-step and is defined for batch steps (eta = 1) only.
+ * antipodal log-map input maps to (pi, 0); the accurate covariance pass takes its
+ * responsibilities from the new weights and means with the previous covariances, its
+ * covariance from that pass's S0 and S2, and is defined for batch steps (eta = 1) only.
  *
  * Layouts (shared as an interface with the GPU library, written independently):
  *   samples   float32 structure-of-arrays [7][N]: dir x,y,z, pos x,y,z, weight
@@ -533,64 +534,51 @@ static int gate(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i
     return 0;
 }
 
-/* Accurate covariance update (Sec. 3.2, "Sufficient statistics in tangent spaces"): once
- * the new means are known, the second moment of the batch is taken again in each new
- * mean's tangent space, S2^_k = sum_i w_i r_ik y^_ik y^_ik^T with
- * y^_ik = (log_{mu^_k} w_i, p_i - mu^_x_k), and Sigma^_k = (beta B + S2^_k / W) /
- * (beta a + S0_k / W). No mean is subtracted: the coordinates are already centred on the
- * new mean. The responsibilities r_ik are those of the E-step (the current parameters);
- * only the coordinates move. Defined for batch steps (eta = 1), where the carried
- * statistics do not enter. Components the M-step left unchanged (dead) are skipped; a
- * covariance that is not SPD keeps the previous one and flags the cell. */
+/* Accurate covariance update (Sec. 3.2, "Sufficient statistics in tangent spaces"). The
+ * second moment that sets the new covariance is taken in the tangent space of the new
+ * mean, with responsibilities from the component densities in that tangent space. Once
+ * the M-step has produced the new weights and means, a second E-step runs under
+ * (pi^, mu^, Sigma), Sigma being the covariance before the step (the only one known),
+ * giving S0'_k = sum w r', S2'_k = sum w r' y^ y^^T with y^ = (log_{mu^} w, p - mu^_x),
+ * and Sigma^_k = (beta B + S2'_k / W) / (beta a + S0'_k / W): the covariance about the new
+ * mean, without a mean subtracted. Defined for batch steps (eta = 1), where no carried
+ * statistic needs moving. Components dead in the M-step keep what it left; a component
+ * whose S0'/W is at or below the dead threshold keeps its covariance and flags the cell
+ * as dead; a covariance that is not SPD keeps the previous one and flags the cell. The
+ * carried S0 and S2 become S0' and S2'. */
 static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0,
-                               int64_t i1, const double *pi0, const double *mud0, const double *mux0,
-                               const double *cov0, const double *mud, const double *mux, double *cov,
-                               double *s2, const double *S0, double W, int64_t M)
+                               int64_t i1, const double *S0, double W, int64_t M, const double *pi,
+                               const double *mud, const double *mux, const double *cov0, double *cov,
+                               double *s0, double *s2)
 {
-    comp_t c_old[ORC_KMAX], c_new[ORC_KMAX];
-    double S2a[ORC_KMAX * 15];
+    double T0[ORC_KMAX], T1[ORC_KMAX * 5], T2[ORC_KMAX * 15], W2, LL;
+    int64_t M2;
     int status = 0;
-    memset(S2a, 0, sizeof(S2a));
-    setup_components(K, pi0, mud0, mux0, cov0, c_old);
-    for (int k = 0; k < K; ++k) orc_frame(mud + 3 * k, c_new[k].R);
-    for (int64_t i = i0; i < i1; ++i) {
-        double w[3], p[3], wt, y[ORC_KMAX][5], l[ORC_KMAX];
-        load_sample(smp, N, i, w, p, &wt);
-        double lmax = -INFINITY;
-        for (int k = 0; k < K; ++k) {
-            tangent_coords(o, &c_old[k], mud0 + 3 * k, mux0 + 3 * k, w, p, y[k]);
-            l[k] = comp_log_density(o, &c_old[k], y[k]);
-            if (l[k] > lmax) lmax = l[k];
-        }
-        double den = 0.0;
-        for (int k = 0; k < K; ++k) den += exp(l[k] - lmax);
-        for (int k = 0; k < K; ++k) {
-            const double wr = wt * exp(l[k] - lmax) / den;
-            double yh[5];
-            tangent_coords(o, &c_new[k], mud + 3 * k, mux + 3 * k, w, p, yh);
-            for (int d = 0; d < 5; ++d)
-                for (int e = 0; e <= d; ++e) S2a[15 * k + TRI(d, e)] += wr * yh[d] * yh[e];
-        }
-    }
+    /* the E-step under the new weights and means and the previous covariances */
+    memcpy(cov, cov0, sizeof(double) * 15 * K);
+    if (orc_cell_stats(o, K, smp, N, i0, i1, pi, mud, mux, cov, T0, T1, T2, &W2, &M2, &LL)) return ORC_BAD_PARAMS;
     const double beta = (o->prior_mode == 0) ? 1.0 / (double)M : o->prior_scale;
     for (int k = 0; k < K; ++k) {
-        const double bar0 = S0[k] / W;
-        if (!(bar0 > o->dead_threshold)) continue;
+        if (!(S0[k] / W > o->dead_threshold)) continue; /* dead in the M-step */
+        const double bar0 = T0[k] / W2;
+        if (!(bar0 > o->dead_threshold)) {
+            status |= ORC_DEAD_COMPONENT;
+            continue;
+        }
         double Sig[15], Lt[15];
         const double den = beta * o->prior_a + bar0;
         for (int d = 0; d < 5; ++d)
             for (int e = 0; e <= d; ++e) {
-                double v = S2a[15 * k + TRI(d, e)] / W;
+                double v = T2[15 * k + TRI(d, e)] / W2;
                 if (d == e) v += beta * o->prior_b[d];
                 Sig[TRI(d, e)] = v / den;
             }
-        if (chol_packed(5, Sig, Lt) == 0) {
+        if (chol_packed(5, Sig, Lt) == 0)
             memcpy(cov + 15 * k, Sig, sizeof(Sig));
-        } else {
-            memcpy(cov + 15 * k, cov0 + 15 * k, sizeof(Sig));
+        else
             status |= ORC_CHOL_FAIL_KEPT_PREV;
-        }
-        memcpy(s2 + 15 * k, S2a + 15 * k, sizeof(Sig));
+        s0[k] = T0[k];
+        memcpy(s2 + 15 * k, T2 + 15 * k, sizeof(Sig));
     }
     return status;
 }
@@ -607,7 +595,7 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
     /* the accurate covariance update is defined for batch steps */
     if (o->accurate_sigma && !(o->eta_mode == 0 && o->eta == 1.0)) return -2;
     double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
-    double pi0[ORC_KMAX], mud0[ORC_KMAX * 3], mux0[ORC_KMAX * 3], cov0[ORC_KMAX * 15];
+    double cov0[ORC_KMAX * 15];
     /* the offsets must partition a prefix of the sample array: non-decreasing, from >= 0
      * to <= N. An array that is not is rejected as a whole: every cell reports bad input
      * and nothing changes (a decreasing entry says the batch itself is malformed). */
@@ -643,20 +631,15 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
                 status[c] |= ORC_BAD_INPUT;
                 break;
             }
-            if (o->accurate_sigma) {
-                memcpy(pi0, pi + ck, sizeof(double) * K);
-                memcpy(mud0, mud + 3 * ck, sizeof(double) * 3 * K);
-                memcpy(mux0, mux + 3 * ck, sizeof(double) * 3 * K);
-                memcpy(cov0, cov + 15 * ck, sizeof(double) * 15 * K);
-            }
+            if (o->accurate_sigma) memcpy(cov0, cov + 15 * ck, sizeof(double) * 15 * K);
             int ms = cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
                                 cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
             if (o->accurate_sigma) {
                 /* the first-order covariance of the M-step is replaced by the second pass,
                  * and so is its SPD verdict */
                 ms &= ~ORC_CHOL_FAIL_KEPT_PREV;
-                ms |= accurate_sigma_pass(o, K, smp, N, i0, i1, pi0, mud0, mux0, cov0, mud + 3 * ck,
-                                          mux + 3 * ck, cov + 15 * ck, s2 + 15 * ck, S0, W, M);
+                ms |= accurate_sigma_pass(o, K, smp, N, i0, i1, S0, W, M, pi + ck, mud + 3 * ck, mux + 3 * ck,
+                                          cov0, cov + 15 * ck, s0 + ck, s2 + 15 * ck);
             }
             status[c] |= ms;
         }

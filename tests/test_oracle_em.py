@@ -499,22 +499,24 @@ def test_accurate_sigma_single_component_is_the_scatter_about_the_new_mean(orc):
     assert gaps[0] > 1e-3, gaps
 
 
-def test_accurate_sigma_uses_the_e_step_responsibilities(orc):
-    """K = 3 on the sphere: each component's accurate second moment is the sum of
-    w r y^ y^^T with r the responsibilities under the parameters before the step and y^ the
-    geodesic coordinates about the new mean."""
+def test_accurate_sigma_responsibilities_come_from_the_new_means(orc):
+    """K = 3 on the sphere: each component's accurate covariance is the second moment of
+    the geodesic coordinates about its new mean, weighted by w r' with r' the
+    responsibilities under the new weights and means and the previous covariances, and
+    normalised by the same weights."""
     K = 3
     smp, mix0 = _accurate_problem(n=2400, kappa=10.0, offset=0.3, K=K, seed=8)
     n = smp.shape[1]
     beta = 0.02
     opts = orc.Opts(K=K, iters=1, prior_mode=1, prior_scale=beta, accurate_sigma=1)
     o = opts.to_c()
-    w = smp[6].astype(np.float64)
-    r = np.stack([orc.responsibilities(opts, smp[0:3, i].astype(np.float64), smp[3:6, i].astype(np.float64), mix0)
-                  for i in range(n)])
     mix = synth.copy_mix(mix0)
     st = orc.new_state(1, K)
     assert orc.fit(opts, np.array([0, n]), smp, mix, st)[0] == 0
+    mid = dict(mix, cov=mix0["cov"].copy())  # new weights and means, previous covariances
+    r = np.stack([orc.responsibilities(opts, smp[0:3, i].astype(np.float64), smp[3:6, i].astype(np.float64), mid)
+                  for i in range(n)])
+    w = smp[6].astype(np.float64)
     W = w.sum()
     for k in range(K):
         mu, mx = mix["mu_dir"].reshape(K, 3)[k], mix["mu_pos"].reshape(K, 3)[k]
@@ -525,11 +527,36 @@ def test_accurate_sigma_uses_the_e_step_responsibilities(orc):
         ev, ev_ref = np.linalg.eigvalsh(S), np.linalg.eigvalsh(scatter)
         assert np.abs(ev - ev_ref).max() < 1e-11 * ev_ref.max(), (k, ev, ev_ref)
         assert np.allclose(S[2:, 2:], scatter[2:, 2:], rtol=1e-11, atol=1e-15)
+        assert st["s0"][k] == pytest.approx(wr.sum(), rel=1e-12)
 
 
-def test_accurate_sigma_is_the_textbook_update_in_euclidean_mode(orc):
-    """Euclidean coordinates: moving the frame is a translation, so the second pass gives
-    the textbook covariance about the new mean, as the first-order path does."""
+def _textbook_ecm_step(X, w, pi, mu, Sig, beta, q, a, B):
+    """One cycle of multi-cycle ECM for a weighted MAP Gaussian mixture in R^5 (Meng and
+    Rubin 1993): E-step, weights and means, a second E-step under the new weights and
+    means, then the covariances about the new means with those responsibilities."""
+    K = pi.size
+
+    def resp(pi, mu, Sig):
+        logp = np.stack([np.log(pi[k]) + multivariate_normal(mu[k], Sig[k]).logpdf(X) for k in range(K)], 1)
+        r = np.exp(logp - logp.max(1, keepdims=True))
+        return r / r.sum(1, keepdims=True)
+
+    W = w.sum()
+    wr = w[:, None] * resp(pi, mu, Sig)
+    N0 = wr.sum(0) / W
+    mu_new = (wr.T @ X) / wr.sum(0)[:, None]
+    pi_new = (N0 + beta * q) / (N0.sum() + K * beta * q)
+    wr2 = w[:, None] * resp(pi_new, mu_new, Sig)
+    Sig_new = np.zeros_like(Sig)
+    for k in range(K):
+        D = X - mu_new[k]
+        Sig_new[k] = ((wr2[:, k, None] * D).T @ D / W + beta * np.diag(B)) / (wr2[:, k].sum() / W + beta * a)
+    return pi_new, mu_new, Sig_new
+
+
+def test_accurate_sigma_is_the_textbook_ecm_cycle_in_euclidean_mode(orc):
+    """Euclidean coordinates: moving the frame is a translation, so the accurate update is
+    one cycle of multi-cycle ECM, written here independently."""
     smp, X, w, (pi, mu, Sig), mix = _euclid_problem(seed=13)
     K = pi.size
     beta = 0.3
@@ -537,11 +564,30 @@ def test_accurate_sigma_is_the_textbook_update_in_euclidean_mode(orc):
     o = opts.to_c()
     st = orc.new_state(1, K)
     for it in range(4):
-        pi, mu, Sig = _textbook_step(X, w, pi, mu, Sig, beta, o.prior_q, o.prior_a, np.array(o.prior_b))
+        pi, mu, Sig = _textbook_ecm_step(X, w, pi, mu, Sig, beta, o.prior_q, o.prior_a, np.array(o.prior_b))
         assert orc.fit(opts, np.array([0, X.shape[0]]), smp, mix, st)[0] == 0
+        got_mu = np.concatenate([mix["mu_dir"].reshape(K, 3)[:, :2], mix["mu_pos"].reshape(K, 3)], 1)
         got_S = np.stack([_unpack(c) for c in mix["cov"].reshape(K, 15)])
         assert np.allclose(mix["pi"], pi, rtol=1e-10, atol=1e-14)
+        assert np.allclose(got_mu, mu, rtol=1e-10, atol=1e-12)
         assert np.allclose(got_S, Sig, rtol=1e-9, atol=1e-13)
+
+
+def test_accurate_sigma_objective_is_monotone_in_euclidean_mode(orc):
+    """Every ECM cycle maximises the penalised objective over a block of parameters with
+    the others fixed, so the objective never decreases."""
+    smp, X, w, _, mix = _euclid_problem(seed=12, n=1200, K=3)
+    beta = 0.05
+    opts = orc.Opts(K=3, iters=1, euclidean=1, prior_mode=1, prior_scale=beta, accurate_sigma=1)
+    st = orc.new_state(1, 3)
+    off = np.array([0, X.shape[0]])
+    F = [orc.objective(opts, smp, 0, X.shape[0], mix, beta)]
+    for it in range(200):
+        orc.fit(opts, off, smp, mix, st)
+        F.append(orc.objective(opts, smp, 0, X.shape[0], mix, beta))
+    F = np.array(F)
+    assert (np.diff(F) >= -1e-12 * np.abs(F[1:])).all(), np.diff(F).min()
+    assert F[-1] > F[0]
 
 
 def test_accurate_sigma_needs_batch_steps(orc):
