@@ -544,8 +544,8 @@ static int gate(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i
  * mean, without a mean subtracted. Defined for batch steps (eta = 1), where no carried
  * statistic needs moving. Components dead in the M-step keep what it left; a component
  * whose S0'/W is at or below the dead threshold keeps its covariance and flags the cell
- * as dead; a covariance that is not SPD keeps the previous one and flags the cell. The
- * carried S0 and S2 become S0' and S2'. */
+ * as dead; a covariance that is not SPD keeps the previous one and flags the cell. For
+ * every component not dead in the M-step the carried S0 and S2 become S0' and S2'. */
 static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0,
                                int64_t i1, const double *S0, double W, int64_t M, const double *pi,
                                const double *mud, const double *mux, const double *cov0, double *cov,
@@ -560,6 +560,8 @@ static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64
     const double beta = (o->prior_mode == 0) ? 1.0 / (double)M : o->prior_scale;
     for (int k = 0; k < K; ++k) {
         if (!(S0[k] / W > o->dead_threshold)) continue; /* dead in the M-step */
+        s0[k] = T0[k];
+        memcpy(s2 + 15 * k, T2 + 15 * k, sizeof(double) * 15);
         const double bar0 = T0[k] / W2;
         if (!(bar0 > o->dead_threshold)) {
             status |= ORC_DEAD_COMPONENT;
@@ -577,8 +579,6 @@ static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64
             memcpy(cov + 15 * k, Sig, sizeof(Sig));
         else
             status |= ORC_CHOL_FAIL_KEPT_PREV;
-        s0[k] = T0[k];
-        memcpy(s2 + 15 * k, T2 + 15 * k, sizeof(Sig));
     }
     return status;
 }

@@ -596,3 +596,42 @@ def test_accurate_sigma_needs_batch_steps(orc):
     for kw in ({"eta": 0.5}, {"eta_mode": 1}):
         with pytest.raises(ValueError):
             orc.fit(orc.Opts(K=1, accurate_sigma=1, **kw), np.array([0, 64]), smp, synth.copy_mix(mix), st)
+
+
+def test_covariance_updates_naive_first_order_accurate(orc):
+    """The comparison the paper draws for one component whose mean moves: reusing the
+    old-frame covariance unchanged (naive), carrying it by the first-order Jacobian, and
+    the accurate second pass. Against the accurate update (which the K = 1 pin ties to
+    the geodesic scatter), the first-order transfer is several times closer than the
+    naive update at every mean shift, and both errors grow with the shift."""
+    rng = np.random.default_rng(21)
+    n = 20000
+    lobe = _unit(np.array([0.2, -0.7, 0.5]))
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = synth.sample_vmf(rng, np.tile(lobe, (n, 1)), np.full(n, 16.0)).T
+    smp[3:6] = rng.random((3, n))
+    smp[3] += 0.8 * smp[0]
+    smp[6] = synth.draw_weights(rng, n)
+    beta = 0.01
+    o = orc.Opts(K=1, prior_mode=1, prior_scale=beta).to_c()
+    errs = []
+    for delta in (0.1, 0.4, 1.2):
+        mix0 = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), 1)
+        ax = _unit(np.cross(lobe, [1.0, 0.0, 0.0]))
+        mix0["mu_dir"][:] = np.cos(delta) * lobe + np.sin(delta) * ax
+        out = {}
+        for acc in (1, 0):
+            mix = synth.copy_mix(mix0)
+            orc.fit(orc.Opts(K=1, prior_mode=1, prior_scale=beta, accurate_sigma=acc), np.array([0, n]), smp, mix,
+                    orc.new_state(1, 1))
+            out[acc] = _unpack(mix["cov"])
+        st = orc.cell_stats(orc.Opts(K=1), smp, 0, n, mix0)
+        S0, S1, S2, W = st["S0"][0], st["S1"][0], _unpack(st["S2"][0]), st["W"]
+        naive = (beta * np.diag(o.prior_b) + (S2 - np.outer(S1, S1) / S0) / W) / (beta * o.prior_a + S0 / W)
+        A = out[1]
+        e_naive = np.linalg.norm(naive - A) / np.linalg.norm(A)
+        e_first = np.linalg.norm(out[0] - A) / np.linalg.norm(A)
+        print(f"shift {delta}: naive {e_naive:.2e}, first-order {e_first:.2e}")
+        assert e_first < e_naive / 5, (delta, e_first, e_naive)
+        errs.append((e_naive, e_first))
+    assert errs[0][0] < errs[1][0] < errs[2][0] and errs[0][1] < errs[1][1] < errs[2][1]
