@@ -81,9 +81,10 @@ def _gen_cells4k(n_batches):
     return _GEN_CACHE[n_batches]
 
 
-def cpu_baseline(wl, batch, target_s=12.0):
+def cpu_baseline(wl, batch, target_s=12.0, orc_kw=None):
     """The oracle (single thread, FP64) on a bounded sample of the workload: a subset of
     cells of one batch, one E+M step each, sized to about target_s seconds."""
+    orc_kw = {"eta": 0.1} if orc_kw is None else orc_kw
     from oracle import oracle as orc
     from paper_2111_13094_amd import synth
     C = wl["grid"].n_cells
@@ -99,7 +100,7 @@ def cpu_baseline(wl, batch, target_s=12.0):
             mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
             st = orc.new_state(1, 16)
             t0 = time.perf_counter()
-            orc.fit(orc.Opts(K=16, eta=0.1), np.array([0, i1 - i0]), sub, mc, st)
+            orc.fit(orc.Opts(K=16, **orc_kw), np.array([0, i1 - i0]), sub, mc, st)
             t += time.perf_counter() - t0
             pairs += (i1 - i0) * 16
         return pairs, t
@@ -244,6 +245,97 @@ def bench_cells4k(args, torch):
             dst.copy_(src)
         _sync(torch)
         out["copy_probe_bytes"] = src.numel() * 4
+    return out
+
+
+def bench_accurate(args, torch):
+    """Batch EM (eta = 1) with the accurate covariance update on the 4096-cell batches:
+    per step one E-step pass, the weight and mean update, a second E-step pass in the new
+    tangent spaces and the covariance update. The first-order update on the same steps is
+    timed beside it. The roofline is that of the E-step kernel over both of its launches."""
+    from paper_2111_13094_amd import sdmm, synth
+    import ctypes as C_
+    n_batches = 8
+    wl, batches = _gen_cells4k(n_batches)
+    C, K = wl["grid"].n_cells, 16
+    dev = torch.device("cuda", 0)
+    offs = [torch.from_numpy(b.offsets).to(dev) for b in batches]
+    smps = [torch.from_numpy(b.samples).to(dev) for b in batches]
+    N = [b.samples.shape[1] for b in batches]
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    status = torch.empty(C, dtype=torch.int32, device=dev)
+    L = sdmm.lib()
+
+    def run(flags):
+        opts = sdmm.default_opts(K, flags=flags)
+        ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
+        mix = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+        st = sdmm.new_state(C, K, dev)
+        for w in range(args.warmup):
+            sdmm.fit_mixtures(offs[w % n_batches], smps[w % n_batches], mix, st, opts, status, ws)
+        _sync(torch)
+        L.sdmm_timing_enable(1)
+        tot, cnt = C_.c_double(), C_.c_int64()
+        for cls in range(5):
+            L.sdmm_timing_read(cls, C_.byref(tot), C_.byref(cnt), 1)
+        _sync(torch)
+        t0 = time.perf_counter()
+        pairs = 0
+        for s_ in range(args.steps):
+            j = (args.warmup + s_) % n_batches
+            sdmm.fit_mixtures(offs[j], smps[j], mix, st, opts, status, ws)
+            pairs += N[j] * K
+        _sync(torch)
+        wall = time.perf_counter() - t0
+        ms, e_tot, e_cnt = {}, 0.0, 0
+        for cls, name in ((0, "estep"), (1, "mstep"), (4, "second_pass")):
+            L.sdmm_timing_read(cls, C_.byref(tot), C_.byref(cnt), 1)
+            ms[name] = tot.value / cnt.value if cnt.value else None
+            if cls in (0, 4):
+                e_tot, e_cnt = e_tot + tot.value, e_cnt + cnt.value
+        ms["estep_kernel_avg"] = e_tot / max(e_cnt, 1)
+        L.sdmm_timing_enable(0)
+        return pairs, wall, ms
+
+    pairs, wall, ms = run(sdmm.FLAG_ACCURATE_SIGMA)
+    fpairs, fwall, fms = run(0)
+    # how far the first-order covariance lands from the accurate one after one step from
+    # the initial mixtures (relative Frobenius distance per component)
+    covs = {}
+    for flags in (sdmm.FLAG_ACCURATE_SIGMA, 0):
+        mix = {k: torch.from_numpy(v).to(dev) for k, v in mix0.items()}
+        sdmm.fit_mixtures(offs[0], smps[0], mix, sdmm.new_state(C, K, dev), sdmm.default_opts(K, flags=flags), status)
+        covs[flags] = mix["cov"].reshape(-1, 15).double()
+    tri_w = torch.tensor([1.0 if d == e else 2.0 for d in range(5) for e in range(d + 1)], device=dev,
+                         dtype=torch.float64)
+    diff = ((covs[0] - covs[sdmm.FLAG_ACCURATE_SIGMA]) ** 2 * tri_w).sum(1).sqrt()
+    ref = ((covs[sdmm.FLAG_ACCURATE_SIGMA] ** 2) * tri_w).sum(1).sqrt()
+    rel = (diff / ref).cpu().numpy()
+    per_launch = pairs / args.steps
+    achieved = FLOPS_PER_PAIR * per_launch / (ms["estep_kernel_avg"] * 1e-3) / 1e12
+    out = {
+        "metric": "EM sample x component updates/s, 4096 cells K=16, batch EM with the accurate covariance update",
+        "value": pairs / wall, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "accurate: the 4096-cell batches (lognormal(6.45,1) counts clipped to "
+                               "[64,8192]), batch EM (eta=1) from the initial mixtures, one iteration per "
+                               "step with the second pass in the new tangent spaces",
+                   "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "estep_kernel<16,TwoSum,false,false>", "kernel_ms": ms["estep_kernel_avg"],
+                     "flops_per_launch": FLOPS_PER_PAIR * per_launch},
+        "kernel_ms": ms,
+        "first_order": {"value": fpairs / fwall, "unit": "updates/s", "ms_per_step": fwall * 1e3 / args.steps,
+                        "kernel_ms": fms,
+                        "cov_rel_distance_after_one_step": {"median": float(np.median(rel)),
+                                                            "p90": float(np.quantile(rel, 0.9)),
+                                                            "max": float(rel.max())}},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, batches[0], target_s=args.cpu_seconds,
+                                           orc_kw={"eta": 1.0, "accurate_sigma": 1})
     return out
 
 
@@ -462,7 +554,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single"])
+    ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single",
+                                                                    "accurate"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
@@ -506,6 +599,8 @@ def main():
         out = bench_grad(args, torch)
     elif args.workload == "huge":
         out = bench_huge(args, torch)
+    elif args.workload == "accurate":
+        out = bench_accurate(args, torch)
     else:
         out = bench_single(args, torch)
     print(json.dumps(out))

@@ -67,6 +67,16 @@ extern "C" {
                                       the tangent densities of the statistics equation */
 #define SDMM_FLAG_PLAIN_FP32 2     /* precision study: plain FP32 running sums */
 #define SDMM_FLAG_FP64_SUMS 4      /* precision study: FP64 running sums */
+#define SDMM_FLAG_ACCURATE_SIGMA 8 /* accurate covariance update (Sec. 3.2, statistics in the
+                                      new mean's tangent space): after the M-step has moved
+                                      the weights and means, a second E-step pass under
+                                      (new weights, new means, previous covariances) forms
+                                      S0' = sum w r' and S2' = sum w r' y^ y^^T with y^ the
+                                      coordinates about the new mean, and
+                                      Sigma = (beta B + S2' / W) / (beta a + S0' / W).
+                                      Batch steps only: needs eta_mode SDMM_ETA_CONSTANT with
+                                      eta = 1 and the batched or per-cell schedule (else
+                                      SDMM_EINVAL). Twice the E-step work. */
 
 #define SDMM_SCHED_BATCHED 0  /* per iteration one E launch for all cells, then one M
                                  launch for all cells */
@@ -141,6 +151,9 @@ size_t sdmm_fit_workspace_size(int32_t n_cells, int32_t K, int64_t n_samples,
  *     Jacobian of log_{mu_new} o exp_{mu} at m; Sigma = (beta_j B + T C T^T / W^) /
  *     (beta_j a + S0^ / W^); pi = (beta_j q + S0^/W^) / (K beta_j q + sum S0^/W^);
  *     the carried state becomes S0^ and T C T^T; step += 1.
+ *   With SDMM_FLAG_ACCURATE_SIGMA the covariance instead comes from the second pass
+ *     described at the flag, and the carried S0 and S2 are S0' and S2'. Other flag bits
+ *     are rejected.
  *
  * cell_offsets [device] int64[n_cells+1]; samples [device] float32[7][n_samples];
  * mix, state: device arrays updated in place; opts [host]; cell_status [device]
@@ -233,7 +246,8 @@ int sdmm_condition_sample_pdf(const float *table, int32_t n_cells, int32_t K, co
  * Precision: by default the pass forms tangent coordinates and products in FP32 with
  * compensated sums and the quadratic form in FP64. With SDMM_FLAG_FP64_SUMS in
  * opts->flags every per-sample quantity is FP64 (verification mode: about 4x slower).
- * SDMM_FLAG_ESTEP_JACOBIAN is rejected (SDMM_EINVAL).
+ * SDMM_FLAG_ESTEP_JACOBIAN is rejected (SDMM_EINVAL); SDMM_FLAG_ACCURATE_SIGMA, an
+ * M-step option, has no effect here.
  */
 int sdmm_fit_grad(const int64_t *cell_offsets, const float *samples, int64_t n_samples,
                   const sdmm_mixtures *mix, const sdmm_fit_opts *opts, double *F_out,
@@ -286,6 +300,7 @@ int sdmm_grad_to_params(int32_t n_cells, int32_t K, const double *L, const doubl
 #define SDMM_TIMER_MSTEP 1   /* the M-step pass of sdmm_fit_mixtures */
 #define SDMM_TIMER_QUERY 2   /* sdmm_condition_sample_pdf */
 #define SDMM_TIMER_GRAD 3    /* the adjoint pass of sdmm_fit_grad */
+#define SDMM_TIMER_ACCURATE 4 /* the second E-step pass of SDMM_FLAG_ACCURATE_SIGMA */
 
 /* Enables (1) or disables (0) HIP-event timing: while enabled, every eager launch of
  * the kernel classes above is bracketed by a pair of events recorded on its stream

@@ -142,8 +142,9 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
                   const Layout& L, hipStream_t s);
 
 // record tree levels after an E-step pass (all cells, or one cell when cell >= 0, whose
-// samples are [c0, c1))
-void launch_tree(bool adj, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
+// samples are [c0, c1)); the pass names the record layout
+enum TreePass { kTreeFit = 0, kTreeGrad = 1 };
+void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
                  int64_t c1, char* ws, hipStream_t s);
 
 // E-step over the items in record slots [slot_lo, slot_hi), one wave per slot

@@ -171,6 +171,22 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------------
+// Mirror of component g for the next iteration, written in place (keeps the M-step's
+// registers free), with the cell's shift from the group of GM lanes. `upd`: this lane's
+// component was updated; the others keep their mirrors.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t g, bool upd, float* __restrict__ mirror,
+                                                    int GM)
+{
+    double c2 = -INFINITY;
+    bool okm = true;
+    float* out = mirror + g * kMirror;
+    if (upd) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    const double cmax = group_max_d((upd && okm) ? c2 : -INFINITY, GM);
+    if (upd) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f));
+}
+
+// ---------------------------------------------------------------------------------
 // M-step of one cell by one wave: all 64 lanes sum the cell's records (in item order,
 // column-parallel), then lanes k < G (lane k = component k) gate, blend (Robbins-Monro)
 // and update in FP64, and optionally write the next iteration's mirrors. cell_ok must
@@ -179,7 +195,7 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
 template <int G>
 __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
                                            bool tree, const double* __restrict__ records, int PS,
-                                           const int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
+                                           int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
                                            const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
                                            float* __restrict__ mirror, int refresh_mirror,
                                            int32_t* __restrict__ status)
@@ -188,6 +204,10 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     const int K = o.K;
     const int lane = threadIdx.x & 63;
     const int k = lane;
+    // accurate covariance update: this M-step moves the weights and means only; the
+    // mirrors it writes (new weights and means, previous covariances) drive the second
+    // E-step pass, whose statistics accurate_mstep_kernel turns into the covariances
+    const bool accurate = (o.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
     const bool wave_ok = cell_ok;
     cell_ok = cell_ok && lane < G;
     const bool act = cell_ok && k < K;
@@ -204,9 +224,9 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     int fin = isfinite(W);
     for (int s = 0; s < kStats; ++s) fin &= isfinite(S[s]) ? 1 : 0;
     const int notfin = group_or(act && !fin ? 1 : 0, GM) | (!isfinite(W) ? 1 : 0);
-    int gate = 0;
+    int gate = 0, fl = 0;
     if (cell_ok) {
-        const int fl = flags[c];
+        fl = flags[c];
         if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !*global_ok) gate = kBadInput;
         else if (fl & kBadParams) gate = kBadParams;
         else if (Mc < (double)o.min_samples) gate = kSkippedFew;
@@ -245,64 +265,60 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
             exp_map64(Ro, m[0], m[1], mun);
             const double inn = 1.0 / sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
             for (int i = 0; i < 3; ++i) mun[i] *= inn;
-            frame64(mun, Rn);
-            double J[4];
-            transfer_jac64(Ro, Rn, m[0], m[1], J);
-            // scatter about the new mean in the old frame, then T C T^T with T = blkdiag(J, I3)
-            double Cm[5][5];
-            for (int d = 0; d < 5; ++d)
-                for (int e = 0; e <= d; ++e) {
-                    const double v = hS2[tri(d, e)] - hS1[d] * hS1[e] * inv0;
-                    Cm[d][e] = v;
-                    Cm[e][d] = v;
-                }
-            double Tt[5][5];
-            for (int b = 0; b < 5; ++b) {  // rows 0,1: J * C
-                const double r0 = J[0] * Cm[0][b] + J[1] * Cm[1][b];
-                const double r1 = J[2] * Cm[0][b] + J[3] * Cm[1][b];
-                Tt[0][b] = r0;
-                Tt[1][b] = r1;
-                for (int a = 2; a < 5; ++a) Tt[a][b] = Cm[a][b];
-            }
-            for (int a = 0; a < 5; ++a) {  // columns 0,1: (J C) J^T
-                const double c0 = Tt[a][0] * J[0] + Tt[a][1] * J[1];
-                const double c1 = Tt[a][0] * J[2] + Tt[a][1] * J[3];
-                Tt[a][0] = c0;
-                Tt[a][1] = c1;
-            }
-            double Sig[15], Lt[15];
-            const double iden = 1.0 / (beta * o.prior_a + bar0), ihW = 1.0 / hW;
-            for (int d = 0; d < 5; ++d)
-                for (int e = 0; e <= d; ++e) {
-                    double v = 0.5 * (Tt[d][e] + Tt[e][d]) * ihW;
-                    if (d == e) v += beta * o.prior_b[d];
-                    Sig[tri(d, e)] = v * iden;
-                }
             for (int i = 0; i < 3; ++i) {
                 mix.mud[3 * g + i] = mun[i];
                 mix.mux[3 * g + i] += m[2 + i];
             }
-            if (chol64<5>(Sig, Lt)) {
-                for (int q = 0; q < 15; ++q) mix.cov[g * 15 + q] = Sig[q];
-            } else {
-                cholfail = 1;
-            }
             st.s0[g] = hS0;
-            for (int d = 0; d < 5; ++d)
-                for (int e = 0; e <= d; ++e) st.s2[g * 15 + tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
+            if (!accurate) {  // with the accurate update the second pass forms the covariance
+                frame64(mun, Rn);
+                double J[4];
+                transfer_jac64(Ro, Rn, m[0], m[1], J);
+                // scatter about the new mean in the old frame, then T C T^T with T = blkdiag(J, I3)
+                double Cm[5][5];
+                for (int d = 0; d < 5; ++d)
+                    for (int e = 0; e <= d; ++e) {
+                        const double v = hS2[tri(d, e)] - hS1[d] * hS1[e] * inv0;
+                        Cm[d][e] = v;
+                        Cm[e][d] = v;
+                    }
+                double Tt[5][5];
+                for (int b = 0; b < 5; ++b) {  // rows 0,1: J * C
+                    const double r0 = J[0] * Cm[0][b] + J[1] * Cm[1][b];
+                    const double r1 = J[2] * Cm[0][b] + J[3] * Cm[1][b];
+                    Tt[0][b] = r0;
+                    Tt[1][b] = r1;
+                    for (int a = 2; a < 5; ++a) Tt[a][b] = Cm[a][b];
+                }
+                for (int a = 0; a < 5; ++a) {  // columns 0,1: (J C) J^T
+                    const double c0 = Tt[a][0] * J[0] + Tt[a][1] * J[1];
+                    const double c1 = Tt[a][0] * J[2] + Tt[a][1] * J[3];
+                    Tt[a][0] = c0;
+                    Tt[a][1] = c1;
+                }
+                double Sig[15], Lt[15];
+                const double iden = 1.0 / (beta * o.prior_a + bar0), ihW = 1.0 / hW;
+                for (int d = 0; d < 5; ++d)
+                    for (int e = 0; e <= d; ++e) {
+                        double v = 0.5 * (Tt[d][e] + Tt[e][d]) * ihW;
+                        if (d == e) v += beta * o.prior_b[d];
+                        Sig[tri(d, e)] = v * iden;
+                    }
+                if (chol64<5>(Sig, Lt)) {
+                    for (int q = 0; q < 15; ++q) mix.cov[g * 15 + q] = Sig[q];
+                } else {
+                    cholfail = 1;
+                }
+                for (int d = 0; d < 5; ++d)
+                    for (int e = 0; e <= d; ++e) st.s2[g * 15 + tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
+            }
         }
         mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
     const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
-    if (refresh_mirror) {  // mirrors for the next iteration of this call
-        double c2 = -INFINITY;
-        bool okm = true;
-        float* out = mirror + g * kMirror;  // written in place (keeps the M-step's registers free)
-        if (run && act) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
-        const double cmax = group_max_d((run && act && okm) ? c2 : -INFINITY, GM);
-        if (run && act) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f));
-    }
+    if (refresh_mirror) refresh_cell_mirror(mix, g, run && act, mirror, GM);  // for the next iteration
     if (cell_ok && k == 0) {
+        if (accurate) flags[c] = gate ? (fl & ~kFlagStepped) : (fl | kFlagStepped);
         if (gate) {
             status[c] |= gate;
         } else {
@@ -317,16 +333,80 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
 template <int G>
 __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
                                                     const double* __restrict__ records, int PS,
-                                                    const int32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ flags,
                                                     const int32_t* __restrict__ global_ok, MixPtrs mix,
                                                     StatePtrs st, DevOpts o, float* __restrict__ mirror,
-                                                    int refresh_mirror, int32_t* __restrict__ status, int cell_lo,
-                                                    int n_cells)
+                                                    int refresh_mirror, int32_t* __restrict__ status,
+                                                    int cell_lo, int n_cells)
 {
     const int cl = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool cell_ok = cl < n_cells;
     mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, true, records, PS, flags, global_ok, mix, st, o,
                   mirror, refresh_mirror, status);
+}
+
+// ---------------------------------------------------------------------------------
+// Accurate covariance update (Sec. 3.2: the second moment in the new mean's tangent
+// space, with responsibilities from the densities in that tangent space). Per iteration:
+// E-step, record tree, M-step for the weights and means only (it writes mirrors of the new
+// weights and means with the previous covariances and marks the cells it stepped), the
+// same E-step pass again on those mirrors (S0', S2' about the new means), its record tree,
+// then accurate_mstep_kernel, one wave per cell:
+//   Sigma = (beta B + S2' / W) / (beta a + S0' / W), beta = 1 / M unless fixed (eta = 1),
+// a Cholesky check (the previous covariance is kept if it fails), carried S0 = S0' and
+// S2 = S2', and the mirrors for the next iteration. Components dead in the first M-step
+// keep what it left; one whose S0' / W is at or below the dead threshold keeps its
+// covariance and flags the cell as dead. Cells the first M-step did not step are skipped.
+// ---------------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(256) void accurate_mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
+                                                             const double* __restrict__ records, int PS,
+                                                             const int32_t* __restrict__ flags,
+                                                             const int32_t* __restrict__ global_ok, MixPtrs mix,
+                                                             StatePtrs st, DevOpts o, float* __restrict__ mirror,
+                                                             int refresh_mirror, int32_t* __restrict__ status,
+                                                             int cell_lo, int n_cells)
+{
+    const int cl = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (cl >= n_cells) return;
+    const int c = cell_lo + cl;
+    const int K = o.K;
+    const int k = threadIdx.x & 63;
+    const bool stepped = (flags[c] & kFlagStepped) != 0;  // uniform over the wave
+    int64_t first = 0, n_items = 0;
+    const bool have = stepped && cell_items(off, N, c, ps, first, n_items);
+    const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;
+    double S[kStats], X[3];
+    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
+    const bool act = have && k < K;
+    const int64_t g = (int64_t)c * K + (k < K ? k : 0);
+    int dead = 0, cholfail = 0;
+    if (act && st.s0[g] / st.sw[c] > o.dead_threshold) {  // else dead in the first M-step
+        const double W = X[0], bar0 = S[0] / W;
+        st.s0[g] = S[0];
+        for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = S[6 + q];
+        if (!(bar0 > o.dead_threshold)) {
+            dead = 1;
+        } else {
+            const double beta = o.prior_mode == 0 ? 1.0 / fmax(X[1], 1.0) : o.prior_scale;
+            const double iden = 1.0 / (beta * o.prior_a + bar0), iW = 1.0 / W;
+            double Sig[15], Lt[15];
+            for (int d = 0; d < 5; ++d)
+                for (int e = 0; e <= d; ++e) {
+                    double v = S[6 + tri(d, e)] * iW;
+                    if (d == e) v += beta * o.prior_b[d];
+                    Sig[tri(d, e)] = v * iden;
+                }
+            if (chol64<5>(Sig, Lt)) {
+                for (int q = 0; q < 15; ++q) mix.cov[g * 15 + q] = Sig[q];
+            } else {
+                cholfail = 1;
+            }
+        }
+    }
+    const int any_dead = group_or(dead, G), any_chol = group_or(cholfail, G);
+    if (refresh_mirror) refresh_cell_mirror(mix, g, act, mirror, G);
+    if (have && k == 0) status[c] |= (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
 }
 
 // ---------------------------------------------------------------------------------
@@ -342,7 +422,7 @@ __global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ sm
                                                     const int64_t* __restrict__ off, int C, int ps,
                                                     int64_t slot_hi, const float* __restrict__ mirror_in, int K,
                                                     int PS, double* __restrict__ records,
-                                                    int32_t* __restrict__ arrive, const int32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ arrive, int32_t* __restrict__ flags,
                                                     const int32_t* __restrict__ global_ok, MixPtrs mix, StatePtrs st,
                                                     DevOpts o, float* __restrict__ mirror, int refresh_mirror,
                                                     int32_t* __restrict__ status)
@@ -389,10 +469,24 @@ static EstepFn estep_for_g(int acc, bool jac)
 }
 
 typedef void (*FusedFn)(const float*, int64_t, const int64_t*, int, int, int64_t, const float*, int, int,
-                        double*, int32_t*, const int32_t*, const int32_t*, MixPtrs, StatePtrs, DevOpts, float*, int,
+                        double*, int32_t*, int32_t*, const int32_t*, MixPtrs, StatePtrs, DevOpts, float*, int,
                         int32_t*);
-typedef void (*MstepFn)(const int64_t*, int64_t, int, const double*, int, const int32_t*, const int32_t*, MixPtrs,
+typedef void (*MstepFn)(const int64_t*, int64_t, int, const double*, int, int32_t*, const int32_t*, MixPtrs,
                         StatePtrs, DevOpts, float*, int, int32_t*, int, int);
+typedef void (*AccMstepFn)(const int64_t*, int64_t, int, const double*, int, const int32_t*, const int32_t*, MixPtrs,
+                           StatePtrs, DevOpts, float*, int, int32_t*, int, int);
+
+static AccMstepFn accurate_mstep_function(int G)
+{
+    switch (G) {
+        case 4: return accurate_mstep_kernel<4>;
+        case 8: return accurate_mstep_kernel<8>;
+        case 16: return accurate_mstep_kernel<16>;
+        case 32: return accurate_mstep_kernel<32>;
+        case 64: return accurate_mstep_kernel<64>;
+    }
+    return nullptr;
+}
 
 static MstepFn mstep_function(int G)
 {
@@ -494,11 +588,12 @@ static TreeFn tree_function(int G)
     return nullptr;
 }
 
-void launch_tree(bool adj, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
+void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
                  int64_t c1, char* ws, hipStream_t s)
 {
-    const TreeFn fn = adj ? tree_function<kStats + 2, 4>(group_for(K)) : tree_function<kStats, 3>(group_for(K));
-    const int PS = adj ? L.ps_grad : L.ps_fit;
+    const int G = group_for(K);
+    const TreeFn fn = pass == kTreeGrad ? tree_function<kStats + 2, 4>(G) : tree_function<kStats, 3>(G);
+    const int PS = pass == kTreeGrad ? L.ps_grad : L.ps_fit;
     const int levels = tree_levels((N + L.P - 1) / L.P);  // bound: the device skips levels it does not need
     for (int level = 1; level <= levels; ++level) {
         const int psl = L.ps + kTreeLog2R * level;
@@ -528,6 +623,7 @@ struct FitArgs {
 static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_t>* host_off)
 {
     const int C = a.mix.n_cells, K = a.opts.K;
+    const int G = group_for(K);
     const Layout L = layout_for(C, K, a.N, &a.opts);
     const MixPtrs mp{a.mix.weights, a.mix.mean_dir, a.mix.mean_pos, a.mix.cov};
     const StatePtrs sp{a.st.s0, a.st.s2, a.st.sw, a.st.step};
@@ -535,46 +631,75 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
     const int acc = (a.opts.flags & SDMM_FLAG_PLAIN_FP32) ? kAccPlain
                     : (a.opts.flags & SDMM_FLAG_FP64_SUMS) ? kAccFp64 : kAccTwoSum;
     const bool jac = (a.opts.flags & SDMM_FLAG_ESTEP_JACOBIAN) != 0;
-    EstepFn est = estep_function(group_for(K), acc, jac, false);
-    FusedFn fused = fused_function(group_for(K), acc, jac);
-    MstepFn mstep = mstep_function(group_for(K));
+    const bool accurate = (a.opts.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
+    EstepFn est = estep_function(G, acc, jac, false);
+    FusedFn fused = fused_function(G, acc, jac);
+    MstepFn mstep = mstep_function(G);
+    AccMstepFn acc_mstep = accurate ? accurate_mstep_function(G) : nullptr;
     float* mirror = reinterpret_cast<float*>(a.ws + L.mirror);
-    const int32_t* flags = reinterpret_cast<const int32_t*>(a.ws + L.flags);
+    int32_t* flags = reinterpret_cast<int32_t*>(a.ws + L.flags);
     const int32_t* gok = reinterpret_cast<const int32_t*>(a.ws + L.global_ok);
-    const double* rec = reinterpret_cast<const double*>(a.ws + L.records);
+    double* rec = reinterpret_cast<double*>(a.ws + L.records);
+
+    // second E-step pass of the accurate update over record slots [lo, hi) on the mirrors
+    // the first M-step wrote, then its record tree
+    auto second_pass = [&](int64_t lo, int64_t hi, int cell, int64_t c0, int64_t c1) {
+        {
+            ScopedTimer tm(SDMM_TIMER_ACCURATE, s);
+            launch_estep(est, a.smp, a.N, a.off, C, K, L, lo, hi, L.ps_fit, a.ws, s);
+        }
+        launch_tree(kTreeFit, a.off, a.N, C, K, L, cell, c0, c1, a.ws, s);
+    };
 
     launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s);
     for (int it = 0; it < a.opts.iters; ++it) {
         const int refresh = it + 1 < a.opts.iters;
+        // with the accurate update the first M-step always writes mirrors (for the second
+        // pass) and the accurate M-step those of the next iteration
+        const int refresh1 = accurate ? 1 : refresh;
         if (a.opts.schedule == SDMM_SCHED_PER_CELL) {
             // host_off is empty when the offsets failed the host check: the M-steps then
             // only report BAD_INPUT (the setup kernel's check agrees)
             for (int c = 0; c < C; ++c) {
+                int64_t c0 = 0, c1 = 0, first = 0, n_items = 0;
                 if (!host_off->empty()) {
-                    const int64_t c0 = (*host_off)[c], c1 = (*host_off)[c + 1];
-                    const int64_t first = c + (c0 >> L.ps), n_items = c1 > c0 ? (c1 - c0 + L.P - 1) >> L.ps : 1;
+                    c0 = (*host_off)[c];
+                    c1 = (*host_off)[c + 1];
+                    first = c + (c0 >> L.ps);
+                    n_items = c1 > c0 ? (c1 - c0 + L.P - 1) >> L.ps : 1;
                     launch_estep(est, a.smp, a.N, a.off, C, K, L, first, first + n_items, L.ps_fit, a.ws, s);
-                    launch_tree(false, a.off, a.N, C, K, L, c, c0, c1, a.ws, s);
+                    launch_tree(kTreeFit, a.off, a.N, C, K, L, c, c0, c1, a.ws, s);
                 }
                 hipLaunchKernelGGL(mstep, dim3(1), dim3(64), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok, mp, sp,
-                                   dopt, mirror, refresh, a.status, c, 1);
+                                   dopt, mirror, refresh1, a.status, c, 1);
+                if (accurate) {
+                    if (!host_off->empty()) second_pass(first, first + n_items, c, c0, c1);
+                    hipLaunchKernelGGL(acc_mstep, dim3(1), dim3(64), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok,
+                                       mp, sp, dopt, mirror, refresh, a.status, c, 1);
+                }
             }
         } else if (a.opts.schedule == SDMM_SCHED_BATCHED) {
             {
                 ScopedTimer tm(SDMM_TIMER_ESTEP, s);
                 launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s);
             }
-            launch_tree(false, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s);
-            ScopedTimer tm(SDMM_TIMER_MSTEP, s);
-            hipLaunchKernelGGL(mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok,
-                               mp, sp, dopt, mirror, refresh, a.status, 0, C);
+            launch_tree(kTreeFit, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s);
+            {
+                ScopedTimer tm(SDMM_TIMER_MSTEP, s);
+                hipLaunchKernelGGL(mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags,
+                                   gok, mp, sp, dopt, mirror, refresh1, a.status, 0, C);
+            }
+            if (accurate) {
+                second_pass(0, (int64_t)C + L.W, -1, 0, 0);
+                hipLaunchKernelGGL(acc_mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit,
+                                   flags, gok, mp, sp, dopt, mirror, refresh, a.status, 0, C);
+            }
         } else {
             ScopedTimer tm(SDMM_TIMER_ESTEP, s);
             const int64_t slots = (int64_t)C + L.W;
             hipLaunchKernelGGL(fused, dim3((unsigned)((slots + 3) / 4)), dim3(256), 0, s, a.smp, a.N, a.off, C, L.ps,
-                               slots, mirror, K, L.ps_fit, reinterpret_cast<double*>(a.ws + L.records),
-                               reinterpret_cast<int32_t*>(a.ws + L.arrive), flags, gok, mp, sp, dopt, mirror, refresh,
-                               a.status);
+                               slots, mirror, K, L.ps_fit, rec, reinterpret_cast<int32_t*>(a.ws + L.arrive), flags,
+                               gok, mp, sp, dopt, mirror, refresh, a.status);
         }
     }
     return check(hipGetLastError());
@@ -592,6 +717,9 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
     if (opts->min_range < 0 || opts->max_ranges < 0 || opts->max_ranges > (1 << 20)) return SDMM_EINVAL;
     if (opts->waves_per_block < 0 || opts->waves_per_block > 4 || opts->waves_per_block == 3 || opts->reserved != 0)
         return SDMM_EINVAL;
+    if (opts->flags & ~(SDMM_FLAG_ESTEP_JACOBIAN | SDMM_FLAG_PLAIN_FP32 | SDMM_FLAG_FP64_SUMS | SDMM_FLAG_ACCURATE_SIGMA))
+        return SDMM_EINVAL;
+
     const Layout L = layout_for(mix->n_cells, opts->K, n_samples, opts);
     // lane offsets inside a segment are 32-bit byte offsets; record slots are int32
     if (L.P * 4 > (int64_t)INT32_MAX || (int64_t)mix->n_cells + L.W > INT32_MAX) return SDMM_EINVAL;
@@ -628,6 +756,10 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
     if (!state || !state->s0 || !state->s2 || !state->sw || !state->step) return SDMM_EINVAL;
     if (opts->schedule != SDMM_SCHED_BATCHED && opts->schedule != SDMM_SCHED_PER_CELL &&
         opts->schedule != SDMM_SCHED_FUSED)
+        return SDMM_EINVAL;
+    // the accurate covariance update is defined for batch steps and has no fused form
+    if ((opts->flags & SDMM_FLAG_ACCURATE_SIGMA) &&
+        (opts->eta_mode != SDMM_ETA_CONSTANT || opts->eta != 1.0 || opts->schedule == SDMM_SCHED_FUSED))
         return SDMM_EINVAL;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

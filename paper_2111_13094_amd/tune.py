@@ -77,6 +77,8 @@ def tune_fit(cell_offsets, samples, mix: dict, state: dict, opts, candidates=Non
     if key in _CACHE:
         return _apply(opts, _CACHE[key])
     cands = candidates or DEFAULT_CANDIDATES
+    if opts.flags & sdmm.FLAG_ACCURATE_SIGMA:  # the accurate update has no fused schedule
+        cands = [c for c in cands if c["schedule"] != sdmm.SCHED_FUSED]
     nbytes = max(sdmm.workspace_bytes(n_cells, opts.K, N, _apply(opts, c)) for c in cands)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=samples.device)
     timings = []

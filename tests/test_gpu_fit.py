@@ -342,3 +342,121 @@ def test_full_size_cells4k_sampled_cells(dev, orc):
         gc = {k: v.reshape(C, -1)[c] for k, v in got.items()}
         worst = compare_mixtures(gc, mc, 16)
         assert_close(worst, rtol=2e-4, ang_tol=2e-5, what=f"cell {c} (n={i1 - i0})")
+
+
+# --- accurate covariance update (second pass in the new tangent spaces) ---------------
+
+def test_accurate_sigma_parity_ragged_cells(dev, orc):
+    """SDMM_FLAG_ACCURATE_SIGMA against the oracle's accurate update on the 64 ragged
+    cells (gated and bad cells included), two iterations per call so that the second
+    M-step's mirror refresh is used."""
+    print("case: accurate covariance update, 64 ragged cells, 2 iterations", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl, b, mix0 = _ragged_case()
+    C = wl["grid"].n_cells
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    s_o = orc.fit(_orc_opts(orc, iters=2, accurate_sigma=1), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    s_g = _gpu_fit(dev, b, gm, gst, iters=2, flags=sdmm.FLAG_ACCURATE_SIGMA)
+    assert (s_g == s_o).all(), np.nonzero(s_g != s_o)
+    got = to_numpy(gm)
+    m_pos = np.array([(b.samples[6, b.offsets[c]:b.offsets[c + 1]] > 0).sum() for c in range(C)])
+    for c in range(C):
+        if s_o[c] & (1 | 2 | 4 | 32):
+            for k in got:
+                assert np.array_equal(got[k].reshape(C, -1)[c], mix0[k].reshape(C, -1)[c], equal_nan=True)
+            continue
+        worst = compare_mixtures(got, om, 16, cells=[c])
+        # the same FP32 rounding argument as for the first-order update: cells with fewer
+        # than 64 samples have prior-dominated covariance directions
+        assert_close(worst, rtol=2e-3 if m_pos[c] < 64 else 2e-4, ang_tol=2e-5, what=f"accurate cell {c}")
+    g = to_numpy(gst)
+    fitted = [c for c in range(C) if not s_o[c] & (1 | 2 | 4 | 32)]
+    s2g, s2o = g["s2"].reshape(C, 16, 15)[fitted], ost["s2"].reshape(C, 16, 15)[fitted]
+    scale = np.abs(s2o).max(axis=2, keepdims=True) + 1e-300
+    assert (np.abs(s2g - s2o) / scale).max() < 2e-3
+
+
+def test_accurate_sigma_single_cell_and_first_order_gap(dev, orc):
+    """One cell of 16384 samples from the initial mixture: the GPU's accurate update
+    matches the oracle's to 2e-4, while the first-order update differs from it by far
+    more, so the test sees which update ran."""
+    print("case: accurate covariance update, single cell N=16384", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl, b = _single(seed=4321)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    orc.fit(_orc_opts(orc, accurate_sigma=1), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, gm, gst, flags=sdmm.FLAG_ACCURATE_SIGMA)
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print("accurate:", worst)
+    assert_close(worst, what="accurate single cell")
+    fm, fst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, fm, fst)
+    gap = compare_mixtures(to_numpy(fm), om, 16)
+    print("first-order vs accurate:", gap)
+    assert gap["cov"] > 20 * max(worst["cov"], 1e-6)
+
+
+def test_accurate_sigma_schedules_graph_and_record_tree(dev, orc):
+    """Batched, per-cell and graph-replayed accurate fits are bitwise equal, with a cell
+    large enough for two record-tree levels in 64-sample items; all match the oracle."""
+    print("case: accurate update, record tree, batched / per-cell / graph", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("single", seed=23)
+    counts = [120000, 300, 0, 5000, 64, 2000, 17, 900]
+    C = len(counts)
+    lo, size = np.tile(wl["box_lo"], (C, 1)), np.tile(wl["box_size"], (C, 1))
+    b = synth.make_batch(29, counts, lo, size, wl["lobes"])
+    mix0 = synth.initial_mixtures(lo, size, 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, 16)
+    s_o = orc.fit(_orc_opts(orc, iters=2, accurate_sigma=1), b.offsets, b.samples, om, ost)
+    runs = []
+    for sched, graph in ((sdmm.SCHED_BATCHED, 0), (sdmm.SCHED_PER_CELL, 0), (sdmm.SCHED_BATCHED, 1),
+                         (sdmm.SCHED_BATCHED, 1)):
+        gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+        s = _gpu_fit(dev, b, gm, gst, iters=2, schedule=sched, use_graph=graph, min_range=64,
+                     max_ranges=1 << 20, flags=sdmm.FLAG_ACCURATE_SIGMA)
+        assert (s == s_o).all(), (sched, graph, s, s_o)
+        runs.append((to_numpy(gm), to_numpy(gst)))
+    for m, st in runs[1:]:
+        for k in m:
+            assert np.array_equal(m[k], runs[0][0][k]), k
+        for k in st:
+            assert np.array_equal(st[k], runs[0][1][k]), k
+    fitted = [c for c in range(C) if not s_o[c] & (1 | 2 | 4 | 32)]
+    worst = compare_mixtures(runs[0][0], om, 16, cells=fitted)
+    print(worst)
+    assert_close(worst, rtol=2e-4, ang_tol=2e-5, what="accurate, record tree")
+
+
+def test_accurate_sigma_with_jacobian_responsibilities(dev, orc):
+    print("case: accurate update with solid-angle responsibilities", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl, b = _single(n=8192, seed=57)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    om, ost = synth.copy_mix(mix0), orc.new_state(1, 16)
+    orc.fit(_orc_opts(orc, iters=2, accurate_sigma=1, estep_jacobian=1), b.offsets, b.samples, om, ost)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    _gpu_fit(dev, b, gm, gst, iters=2, flags=sdmm.FLAG_ACCURATE_SIGMA | sdmm.FLAG_ESTEP_JACOBIAN)
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print(worst)
+    assert_close(worst, rtol=2e-4, ang_tol=3e-5, what="accurate + Jacobian")
+
+
+def test_accurate_sigma_argument_checks(dev, orc):
+    """The accurate update needs batch steps (eta = 1) and a non-fused schedule; unknown
+    flag bits are rejected."""
+    from paper_2111_13094_amd import sdmm
+    wl, b = _single(n=256, seed=3)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    for kw in (dict(eta=0.5), dict(eta_mode=sdmm.ETA_PAPER), dict(schedule=sdmm.SCHED_FUSED)):
+        gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+        with pytest.raises(RuntimeError, match="invalid argument"):
+            _gpu_fit(dev, b, gm, gst, flags=sdmm.FLAG_ACCURATE_SIGMA, **kw)
+        for k, v in to_numpy(gm).items():
+            assert np.array_equal(v, mix0[k])
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        _gpu_fit(dev, b, gm, gst, flags=16)
