@@ -281,6 +281,89 @@ def sample(K, mix, qpos, qcell, uniforms):
     return dirs, pdfv, comp, valid
 
 
+# --- product sampling with a conditioned BSDF mixture ----------------------------------
+
+def pair_transfer(mu1, mu2, m2):
+    """Centre a = log_mu1(exp_mu2(m2)) and Jacobian J (2x2) of log_mu1 o exp_mu2 at m2."""
+    L = lib()
+    L.orc_pair_transfer.argtypes = [C.c_void_p] * 5
+    a, J = np.zeros(2), np.zeros(4)
+    L.orc_pair_transfer(_p(_f64(mu1)), _p(_f64(mu2)), _p(_f64(m2)), _p(a), _p(J))
+    return a, J.reshape(2, 2)
+
+
+def rotate_component(F, mu, m, S):
+    """Component (mu, offset m, packed 2x2 covariance S) rotated by F (world = F local)."""
+    L = lib()
+    L.orc_rotate_component.argtypes = [C.c_void_p] * 7
+    muw, mw, Sw = np.zeros(3), np.zeros(2), np.zeros(3)
+    L.orc_rotate_component(_p(_f64(np.asarray(F).ravel())), _p(_f64(mu)), _p(_f64(m)), _p(_f64(S)), _p(muw),
+                           _p(mw), _p(Sw))
+    return muw, mw, Sw
+
+
+def _product_args(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, frames):
+    return (K, _p(_f64(mix["pi"])), _p(_f64(mix["mu_dir"])), _p(_f64(mix["mu_pos"])), _p(_f64(mix["cov"])),
+            Kb, _p(_f64(bmix["pi"])), _p(_f64(bmix["mu_dir"])), _p(_f64(bmix["mu_pos"])), _p(_f64(bmix["cov"])))
+
+
+def product_pairs(K, mix, cell, Kb, bmix, bcell, x, bx, F):
+    """The 2K pairs of one query: dict of arrays logw (2K), mu (2K, 3), c (2K, 2), C (2K, 3)
+    in pair order 2k + j."""
+    L = lib()
+    i32, vp = C.c_int32, C.c_void_p
+    L.orc_product_pairs.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    pi, mud, mux, cov = _cell_params(mix, cell, K)
+    bpi, bmud, bmux, bcov = _cell_params(bmix, bcell, Kb)
+    out = np.zeros((2 * K, 9))
+    rc = L.orc_product_pairs(K, _p(pi), _p(mud), _p(mux), _p(cov), _p(_f64(x)), Kb, _p(bpi), _p(bmud), _p(bmux),
+                             _p(bcov), _p(_f64(bx)), _p(_f64(np.asarray(F).ravel())), _p(out))
+    if rc:
+        raise ValueError("orc_product_pairs failed")
+    return {"logw": out[:, 0], "mu": out[:, 1:4], "c": out[:, 4:6], "C": out[:, 6:9]}
+
+
+def product_sample(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, frames, uniforms):
+    """Product sampling. qpos, bpar: (nq, 3); frames: (nq, 3, 3) local-to-world;
+    uniforms: (nq, ns, 3). Returns dirs (nq, ns, 3), pdf (nq, ns), pair, valid."""
+    L = lib()
+    i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+    L.orc_product_sample.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp,
+                                     vp, vp, vp, vp]
+    qpos, bpar, F = _f64(qpos), _f64(bpar), _f64(frames)
+    qcell = np.ascontiguousarray(qcell, dtype=np.int32)
+    bcell = np.ascontiguousarray(bcell, dtype=np.int32)
+    u = _f64(uniforms)
+    nq, ns = u.shape[0], u.shape[1]
+    dirs, pdfv = np.zeros((nq, ns, 3)), np.zeros((nq, ns))
+    pair = np.zeros((nq, ns), dtype=np.int32)
+    valid = np.zeros((nq, ns), dtype=np.uint8)
+    rc = L.orc_product_sample(*_product_args(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, F), nq, _p(qpos),
+                              _p(qcell), _p(bpar), _p(bcell), _p(F), ns, _p(u), _p(dirs), _p(pdfv), _p(pair),
+                              _p(valid))
+    if rc:
+        raise ValueError("orc_product_sample failed")
+    return dirs, pdfv, pair, valid
+
+
+def product_pdf(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, frames, dirs):
+    """The product density at dirs (nq, nd, 3); returns (nq, nd)."""
+    L = lib()
+    i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+    L.orc_product_pdf.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp, vp]
+    qpos, bpar, F = _f64(qpos), _f64(bpar), _f64(frames)
+    qcell = np.ascontiguousarray(qcell, dtype=np.int32)
+    bcell = np.ascontiguousarray(bcell, dtype=np.int32)
+    dirs = _f64(dirs)
+    nq, nd = dirs.shape[0], dirs.shape[1]
+    out = np.zeros((nq, nd))
+    rc = L.orc_product_pdf(*_product_args(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, F), nq, _p(qpos), _p(qcell),
+                           _p(bpar), _p(bcell), _p(F), nd, _p(dirs), _p(out))
+    if rc:
+        raise ValueError("orc_product_pdf failed")
+    return out
+
+
 # --- counter-based uniforms -------------------------------------------------------
 
 def philox4x32_10(ctr, key):

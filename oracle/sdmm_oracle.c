@@ -23,7 +23,10 @@
  *   - closed-form Gaussian conditioning on the position, the solid-angle pdf and
  *     sampling with the cut-locus discard (Sec. 3.1 density and sampling paragraphs,
  *     Sec. 3.2 first paragraph, Sec. 3.3);
- *   - the penalised log-likelihood that the MAP update maximises and its gradient.
+ *   - the penalised log-likelihood that the MAP update maximises and its gradient;
+ *   - product sampling of a conditioned radiance mixture with a conditioned BSDF mixture
+ *     pruned to its two heaviest components (Sec. 3.4; Sec. 4.1 "Pruning before product
+ *     sampling").
  *
  * Readings where the paper is silent or garbled (each one is listed with its reason
  * in the design notes): the frame R_mu is the branchless orthonormal basis of Duff et
@@ -34,7 +37,10 @@
  * M-step with the first moment reset to zero; the prior is added after the transfer;
  * antipodal log-map input maps to (pi, 0); the accurate covariance pass takes its
  * responsibilities from the new weights and means with the previous covariances, its
- * covariance from that pass's S0 and S2, and is defined for batch steps (eta = 1) only.
+ * covariance from that pass's S0 and S2, and is defined for batch steps (eta = 1) only;
+ * a BSDF component is rotated to world with its tangent basis carried along, its
+ * transfer Jacobian is taken at its conditioned offset, and the product pairs are
+ * ordered 2k + j (radiance component k, j-th heaviest BSDF component).
  *
  * Layouts (shared as an interface with the GPU library, written independently):
  *   samples   float32 structure-of-arrays [7][N]: dir x,y,z, pos x,y,z, weight
@@ -949,6 +955,286 @@ int orc_sample(int32_t K, const double *pi, const double *mud, const double *mux
             for (int d = 0; d < 3; ++d) dirs_out[3 * o + d] = w[d];
             pdf_out[o] = orc_pdf_conditioned(K, mud + 3 * ck, pic, m, Sc, w);
         }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* product sampling with a conditioned BSDF mixture (Sec. 3.4; the pruning of   */
+/* Sec. 4.1)                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Derivative of the log map with respect to the frame coordinates p = R w of a unit
+ * vector, a 2x3 matrix. With s = |(p_x, p_y)|, theta = atan2(s, p_z), f = theta / s and
+ * nu = f (p_x, p_y): on the unit sphere d f/d p_x = p_x g, d f/d p_y = p_y g with
+ * g = (p_z - f) / s^2, and d f/d p_z = -1. Near the mean g -> -2/3 - theta^2 / 5. */
+static void log_jac_local(const double p[3], double Jl[6])
+{
+    double s = hypot(p[0], p[1]);
+    double th = atan2(s, p[2]);
+    double f = (s > 0.0) ? th / s : 1.0;
+    double g = (s > 1e-3) ? (p[2] - f) / (s * s) : -2.0 / 3.0 - th * th / 5.0;
+    Jl[0] = f + p[0] * p[0] * g;
+    Jl[1] = p[0] * p[1] * g;
+    Jl[2] = -p[0];
+    Jl[3] = p[0] * p[1] * g;
+    Jl[4] = f + p[1] * p[1] * g;
+    Jl[5] = -p[1];
+}
+
+/* A component centred at offset m2 in the tangent space of mu2, seen from the tangent
+ * space of mu1 (Sec. 3.4): its centre a = log_{mu1}(exp_{mu2}(m2)) and the Jacobian J of
+ * log_{mu1} o exp_{mu2} at m2, the first-order map of its covariance (J Sigma J^T).
+ * The Jacobian is d log / d w at the centre times d exp / d nu at m2 (Appendix A). */
+void orc_pair_transfer(const double mu1[3], const double mu2[3], const double m2[2], double a[2], double J[4])
+{
+    double R1[9], R2[9], w[3], p[3], M[6], Jl[6];
+    orc_frame(mu1, R1);
+    orc_frame(mu2, R2);
+    orc_exp_map(R2, m2, w);
+    orc_log_map(R1, w, a);
+    for (int i = 0; i < 3; ++i) p[i] = R1[3 * i] * w[0] + R1[3 * i + 1] * w[1] + R1[3 * i + 2] * w[2];
+    log_jac_local(p, Jl);
+    exp_jac_local(m2, M);
+    /* d w / d nu = R2^T M (3x2); d p / d nu = R1 R2^T M */
+    double D[6];
+    for (int j = 0; j < 3; ++j)
+        for (int b = 0; b < 2; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += R2[3 * i + j] * M[2 * i + b];
+            D[2 * j + b] = s;
+        }
+    double P[6];
+    for (int i = 0; i < 3; ++i)
+        for (int b = 0; b < 2; ++b) P[2 * i + b] = R1[3 * i] * D[b] + R1[3 * i + 1] * D[2 + b] + R1[3 * i + 2] * D[4 + b];
+    for (int r = 0; r < 2; ++r)
+        for (int b = 0; b < 2; ++b) J[2 * r + b] = Jl[3 * r] * P[b] + Jl[3 * r + 1] * P[2 + b] + Jl[3 * r + 2] * P[4 + b];
+}
+
+/* A tangent-space component rotated by the local-to-world rotation F (world = F local):
+ * the mean becomes F mu; the frame of F mu differs from F applied to the frame of mu by
+ * a rotation Q inside the tangent plane, Q_ij = t_i(F mu) . F t_j(mu), so the offset and
+ * the covariance become Q m and Q S Q^T. Exact: exp_{F mu}(Q nu) = F exp_mu(nu). */
+void orc_rotate_component(const double F[9], const double mu[3], const double m[2], const double S[3],
+                          double muw[3], double mw[2], double Sw[3])
+{
+    double R[9], Rw[9], Ft[6], Q[4];
+    for (int i = 0; i < 3; ++i) muw[i] = F[3 * i] * mu[0] + F[3 * i + 1] * mu[1] + F[3 * i + 2] * mu[2];
+    orc_frame(mu, R);
+    orc_frame(muw, Rw);
+    for (int j = 0; j < 2; ++j) /* F t_j(mu) */
+        for (int i = 0; i < 3; ++i) Ft[3 * j + i] = F[3 * i] * R[3 * j] + F[3 * i + 1] * R[3 * j + 1] + F[3 * i + 2] * R[3 * j + 2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            Q[2 * i + j] = Rw[3 * i] * Ft[3 * j] + Rw[3 * i + 1] * Ft[3 * j + 1] + Rw[3 * i + 2] * Ft[3 * j + 2];
+    mw[0] = Q[0] * m[0] + Q[1] * m[1];
+    mw[1] = Q[2] * m[0] + Q[3] * m[1];
+    double Sf[4] = {S[0], S[1], S[1], S[2]}, T[4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) T[2 * i + j] = Q[2 * i] * Sf[j] + Q[2 * i + 1] * Sf[2 + j];
+    Sw[0] = T[0] * Q[0] + T[1] * Q[1];
+    Sw[1] = T[2] * Q[0] + T[3] * Q[1];
+    Sw[2] = T[2] * Q[2] + T[3] * Q[3];
+}
+
+/* one pair of the product mixture, in the tangent space of the radiance component */
+typedef struct {
+    double logw;  /* log of pi'_k w_b N(m_k; a, A + B) (-inf for an empty pair) */
+    double mu[3]; /* the radiance component's mean direction */
+    double c[2];  /* product mean */
+    double C[3];  /* product covariance, packed */
+} orc_pair;
+
+/* the two BSDF components of largest conditioned weight (lowest index on ties); sel[1]
+ * is -1 when there is only one component or the second weight is zero */
+static void top_two(int Kb, const double *w, int sel[2])
+{
+    sel[0] = sel[1] = -1;
+    for (int b = 0; b < Kb; ++b) {
+        if (!(w[b] > 0.0)) continue;
+        if (sel[0] < 0 || w[b] > w[sel[0]]) {
+            sel[1] = sel[0];
+            sel[0] = b;
+        } else if (sel[1] < 0 || w[b] > w[sel[1]]) {
+            sel[1] = b;
+        }
+    }
+}
+
+/* Product of the conditioned radiance mixture of one query with its conditioned,
+ * pruned and rotated BSDF mixture: pairs[2k + j] for radiance component k and the j-th
+ * kept BSDF component. For each pair the BSDF component is moved into the tangent space
+ * of mu_k (centre a, covariance B = J S_b J^T, orc_pair_transfer) and multiplied with
+ * N(m_k, A = Sigma'_k): N(nu; m_k, A) N(nu; a, B) = N(m_k; a, A + B) N(nu; c, C) with
+ * C = A (A + B)^-1 B and c = B (A + B)^-1 m_k + A (A + B)^-1 a. Returns -1 if a mixture
+ * cannot be conditioned. */
+int orc_product_pairs(int32_t K, const double *pi, const double *mud, const double *mux, const double *cov,
+                      const double x[3], int32_t Kb, const double *bpi, const double *bmud, const double *bmux,
+                      const double *bcov, const double bx[3], const double F[9], orc_pair *pairs)
+{
+    double pic[ORC_KMAX], m[2 * ORC_KMAX], Sc[3 * ORC_KMAX];
+    double bpic[ORC_KMAX], bm[2 * ORC_KMAX], bSc[3 * ORC_KMAX];
+    if (orc_condition(K, pi, mux, cov, x, pic, m, Sc)) return -1;
+    if (orc_condition(Kb, bpi, bmux, bcov, bx, bpic, bm, bSc)) return -1;
+    int sel[2];
+    top_two(Kb, bpic, sel);
+    for (int k = 0; k < K; ++k) {
+        for (int j = 0; j < 2; ++j) {
+            orc_pair *pr = pairs + 2 * k + j;
+            pr->logw = -INFINITY;
+            for (int i = 0; i < 3; ++i) pr->mu[i] = mud[3 * k + i];
+            pr->c[0] = pr->c[1] = 0.0;
+            pr->C[0] = pr->C[2] = 1.0;
+            pr->C[1] = 0.0;
+            const int b = sel[j];
+            if (b < 0 || !(pic[k] > 0.0)) continue;
+            double muw[3], mw[2], Sw[3], a[2], J[4];
+            orc_rotate_component(F, bmud + 3 * b, bm + 2 * b, bSc + 3 * b, muw, mw, Sw);
+            orc_pair_transfer(mud + 3 * k, muw, mw, a, J);
+            /* B = J Sw J^T */
+            double Sf[4] = {Sw[0], Sw[1], Sw[1], Sw[2]}, JS[4], B[4];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) JS[2 * r + c] = J[2 * r] * Sf[c] + J[2 * r + 1] * Sf[2 + c];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) B[2 * r + c] = JS[2 * r] * J[2 * c] + JS[2 * r + 1] * J[2 * c + 1];
+            const double A[4] = {Sc[3 * k], Sc[3 * k + 1], Sc[3 * k + 1], Sc[3 * k + 2]};
+            double S[4] = {A[0] + B[0], A[1] + B[1], A[2] + B[2], A[3] + B[3]};
+            const double det = S[0] * S[3] - S[1] * S[2];
+            if (!(det > 0.0)) continue;
+            const double Si[4] = {S[3] / det, -S[1] / det, -S[2] / det, S[0] / det};
+            const double d[2] = {m[2 * k] - a[0], m[2 * k + 1] - a[1]};
+            const double q = d[0] * (Si[0] * d[0] + Si[1] * d[1]) + d[1] * (Si[2] * d[0] + Si[3] * d[1]);
+            pr->logw = log(pic[k]) + log(bpic[b]) - 0.5 * q - 0.5 * log(det) - log(2.0 * ORC_PI);
+            double ASi[4], BSi[4], C[4];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                    ASi[2 * r + c] = A[2 * r] * Si[c] + A[2 * r + 1] * Si[2 + c];
+                    BSi[2 * r + c] = B[2 * r] * Si[c] + B[2 * r + 1] * Si[2 + c];
+                }
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) C[2 * r + c] = ASi[2 * r] * B[c] + ASi[2 * r + 1] * B[2 + c];
+            pr->C[0] = C[0];
+            pr->C[1] = 0.5 * (C[1] + C[2]);
+            pr->C[2] = C[3];
+            for (int r = 0; r < 2; ++r)
+                pr->c[r] = BSi[2 * r] * m[2 * k] + BSi[2 * r + 1] * m[2 * k + 1] + ASi[2 * r] * a[0] + ASi[2 * r + 1] * a[1];
+        }
+    }
+    return 0;
+}
+
+/* normalised pair probabilities; 0 if every pair is empty */
+static int pair_probs(int np, const orc_pair *pairs, double *P)
+{
+    double lmax = -INFINITY, den = 0.0;
+    for (int p = 0; p < np; ++p)
+        if (pairs[p].logw > lmax) lmax = pairs[p].logw;
+    if (lmax == -INFINITY) return 0;
+    for (int p = 0; p < np; ++p) den += exp(pairs[p].logw - lmax);
+    for (int p = 0; p < np; ++p) P[p] = exp(pairs[p].logw - lmax) / den;
+    return 1;
+}
+
+/* solid-angle density of the normalised product mixture at w: sum_p P_p N(log_{mu_p} w;
+ * c_p, C_p) / sinc|log_{mu_p} w|, a pair contributing 0 at or beyond the cut locus */
+static double product_density(int np, const orc_pair *pairs, const double *P, const double w[3])
+{
+    double pdf = 0.0;
+    for (int p = 0; p < np; ++p) {
+        if (!(P[p] > 0.0)) continue;
+        double R[9], nu[2], L[3], d[2], z[2];
+        orc_frame(pairs[p].mu, R);
+        orc_log_map(R, w, nu);
+        double r = hypot(nu[0], nu[1]);
+        if (r >= ORC_PI * (1.0 - 1e-6)) continue;
+        if (chol_packed(2, pairs[p].C, L) != 0) continue;
+        d[0] = nu[0] - pairs[p].c[0];
+        d[1] = nu[1] - pairs[p].c[1];
+        forward_solve(2, L, d, z);
+        double sinc = (r > 0.0) ? sin(r) / r : 1.0;
+        pdf += P[p] * exp(-0.5 * (z[0] * z[0] + z[1] * z[1])) / (2.0 * ORC_PI * L[0] * L[2]) / sinc;
+    }
+    return pdf;
+}
+
+/* Product sampling for nq queries: radiance cell qcell[q] conditioned on qpos[q], BSDF
+ * model bcell[q] conditioned on bpar[q], rotated by frames[9 q ...] (row-major F,
+ * world = F local). Per draw (uniforms[(q ns + t) 3 + {0,1,2}] in [0,1)): the pair by the
+ * CDF of the pair probabilities in order 2k + j (lowest index on ties), nu = c + chol(C) z
+ * with z by Box-Muller (u1 mapped to (0,1]), discarded at |nu| >= pi, w = exp_{mu_k}(nu),
+ * and the product density at w. Invalid draws give dir 0, pdf 0, valid 0, pair -1. */
+int orc_product_sample(int32_t K, const double *pi, const double *mud, const double *mux, const double *cov,
+                       int32_t Kb, const double *bpi, const double *bmud, const double *bmux, const double *bcov,
+                       int64_t nq, const double *qpos, const int32_t *qcell, const double *bpar,
+                       const int32_t *bcell, const double *frames, int32_t ns, const double *uniforms,
+                       double *dirs_out, double *pdf_out, int32_t *pair_out, uint8_t *valid_out)
+{
+    orc_pair pairs[2 * ORC_KMAX];
+    double P[2 * ORC_KMAX];
+    for (int64_t q = 0; q < nq; ++q) {
+        const int64_t ck = (int64_t)qcell[q] * K, cb = (int64_t)bcell[q] * Kb;
+        if (orc_product_pairs(K, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck, qpos + 3 * q, Kb, bpi + cb,
+                              bmud + 3 * cb, bmux + 3 * cb, bcov + 15 * cb, bpar + 3 * q, frames + 9 * q, pairs))
+            return -1;
+        const int np = 2 * K;
+        const int any = pair_probs(np, pairs, P);
+        for (int t = 0; t < ns; ++t) {
+            const double *u = uniforms + 3 * (q * ns + t);
+            const int64_t o = q * ns + t;
+            valid_out[o] = 0;
+            pdf_out[o] = 0.0;
+            pair_out[o] = -1;
+            dirs_out[3 * o] = dirs_out[3 * o + 1] = dirs_out[3 * o + 2] = 0.0;
+            if (!any) continue;
+            int sel = -1;
+            double cdf = 0.0;
+            for (int p = 0; p < np; ++p) {
+                cdf += P[p];
+                if (u[0] < cdf) {
+                    sel = p;
+                    break;
+                }
+            }
+            if (sel < 0)
+                for (int p = np - 1; p >= 0; --p)
+                    if (P[p] > 0.0) {
+                        sel = p;
+                        break;
+                    }
+            pair_out[o] = sel;
+            double L[3];
+            if (chol_packed(2, pairs[sel].C, L) != 0) continue;
+            const double rad = sqrt(-2.0 * log(1.0 - u[1]));
+            const double z0 = rad * cos(2.0 * ORC_PI * u[2]), z1 = rad * sin(2.0 * ORC_PI * u[2]);
+            const double nu[2] = {pairs[sel].c[0] + L[0] * z0, pairs[sel].c[1] + L[1] * z0 + L[2] * z1};
+            if (hypot(nu[0], nu[1]) >= ORC_PI) continue;
+            double R[9], w[3];
+            orc_frame(pairs[sel].mu, R);
+            orc_exp_map(R, nu, w);
+            valid_out[o] = 1;
+            for (int d = 0; d < 3; ++d) dirs_out[3 * o + d] = w[d];
+            pdf_out[o] = product_density(np, pairs, P, w);
+        }
+    }
+    return 0;
+}
+
+/* the product density for nd given directions per query (dirs[(q nd + t) 3 ...]) */
+int orc_product_pdf(int32_t K, const double *pi, const double *mud, const double *mux, const double *cov,
+                    int32_t Kb, const double *bpi, const double *bmud, const double *bmux, const double *bcov,
+                    int64_t nq, const double *qpos, const int32_t *qcell, const double *bpar, const int32_t *bcell,
+                    const double *frames, int32_t nd, const double *dirs, double *pdf_out)
+{
+    orc_pair pairs[2 * ORC_KMAX];
+    double P[2 * ORC_KMAX];
+    for (int64_t q = 0; q < nq; ++q) {
+        const int64_t ck = (int64_t)qcell[q] * K, cb = (int64_t)bcell[q] * Kb;
+        if (orc_product_pairs(K, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck, qpos + 3 * q, Kb, bpi + cb,
+                              bmud + 3 * cb, bmux + 3 * cb, bcov + 15 * cb, bpar + 3 * q, frames + 9 * q, pairs))
+            return -1;
+        const int any = pair_probs(2 * K, pairs, P);
+        for (int t = 0; t < nd; ++t)
+            pdf_out[q * nd + t] = any ? product_density(2 * K, pairs, P, dirs + 3 * (q * nd + t)) : 0.0;
     }
     return 0;
 }

@@ -255,3 +255,84 @@ def workload_batch(wl: dict, batch_index: int = 0, parallax: bool = True) -> Bat
     return make_batch(wl["seed"] + 1000 + batch_index, wl["counts"], wl["box_lo"], wl["box_size"],
                       wl["lobes"], parallax=parallax, weight_sigma=wl["weight_sigma"],
                       zero_frac=wl["zero_frac"])
+
+
+# --- BSDF models and product-sampling queries ----------------------------------------
+#
+# A BSDF model is a 5-D tangent-space mixture like the radiance mixtures, over (local
+# incident direction; outgoing polar angle, outgoing azimuth, roughness): the three
+# Euclidean coordinates take the place of the position. Queries carry those three
+# inputs and a local-to-world rotation (the shading frame).
+
+BSDF_PAR_LO = np.array([0.0, 0.0, 0.05])
+BSDF_PAR_HI = np.array([1.4, 2.0 * np.pi, 0.6])
+
+
+def random_rotations(rng, n):
+    """n rotation matrices (det +1), uniform over SO(3), shape (n, 3, 3)."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                  2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                  2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], 1)
+    return R.reshape(n, 3, 3)
+
+
+def bsdf_mixtures(seed: int, n_models: int, Kb: int, lobe_sd=(0.08, 0.35)) -> dict:
+    """Random BSDF models: means in the upper hemisphere, directional standard deviations
+    in lobe_sd, inputs spread over [BSDF_PAR_LO, BSDF_PAR_HI], correlated through a random
+    lower-triangular factor; Dirichlet(2) weights."""
+    rng = np.random.default_rng(seed)
+    n = n_models * Kb
+    d = rng.normal(size=(n, 3))
+    d[:, 2] = np.abs(d[:, 2]) + 0.6
+    mu_dir = _normalize(d)
+    mu_pos = BSDF_PAR_LO + rng.random((n, 3)) * (BSDF_PAR_HI - BSDF_PAR_LO)
+    sd_dir = lobe_sd[0] + rng.random(n) * (lobe_sd[1] - lobe_sd[0])
+    diag = np.stack([sd_dir, sd_dir * (0.6 + 0.8 * rng.random(n)), np.full(n, 0.25), np.full(n, 0.8),
+                     np.full(n, 0.1)], 1)
+    cov = np.zeros((n, 15))
+    for i in range(n):
+        Lm = np.diag(diag[i])
+        for a in range(5):
+            for b in range(a):
+                Lm[a, b] = 0.3 * rng.uniform(-1, 1) * np.sqrt(diag[i, a] * diag[i, b])
+        S = Lm @ Lm.T
+        cov[i] = [S[a, b] for a in range(5) for b in range(a + 1)]
+    pi = rng.dirichlet(np.full(Kb, 2.0), size=n_models).reshape(-1)
+    return {"pi": pi, "mu_dir": mu_dir.reshape(-1), "mu_pos": mu_pos.reshape(-1), "cov": cov.reshape(-1)}
+
+
+def bsdf_queries(seed: int, nq: int, n_models: int = 1):
+    """Per query: the BSDF inputs (float64 [nq, 3]), the model index and a shading frame
+    (local-to-world rotation, [nq, 3, 3])."""
+    rng = np.random.default_rng(seed)
+    bpar = BSDF_PAR_LO + rng.random((nq, 3)) * (BSDF_PAR_HI - BSDF_PAR_LO)
+    bcell = rng.integers(0, n_models, nq).astype(np.int32)
+    return bpar, bcell, random_rotations(rng, nq)
+
+
+def ggx_training_batch(seed: int, n: int) -> Batch:
+    """Training samples of a BSDF model for an isotropic GGX reflection lobe, drawn the
+    way the BSDF's own importance sampler would: outgoing polar angle, azimuth and
+    roughness uniform over the input box, a microfacet normal from the GGX distribution
+    of normals (D(h) cos(theta_h)), and the mirror of the outgoing direction about it.
+    Directions below the surface get weight 0. One cell, float32 [7][n]."""
+    rng = np.random.default_rng(seed)
+    par = BSDF_PAR_LO + rng.random((n, 3)) * (BSDF_PAR_HI - BSDF_PAR_LO)
+    th_o, ph_o, alpha = par.T
+    wo = np.stack([np.sin(th_o) * np.cos(ph_o), np.sin(th_o) * np.sin(ph_o), np.cos(th_o)], 1)
+    u1, u2 = rng.random(n), rng.random(n)
+    tan2 = alpha * alpha * u1 / (1.0 - u1)
+    cos_h = 1.0 / np.sqrt(1.0 + tan2)
+    sin_h = np.sqrt(np.maximum(0.0, 1.0 - cos_h * cos_h))
+    ph_h = 2.0 * np.pi * u2
+    h = np.stack([sin_h * np.cos(ph_h), sin_h * np.sin(ph_h), cos_h], 1)
+    wi = 2.0 * (wo * h).sum(1, keepdims=True) * h - wo
+    wi = _normalize(wi)
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = wi.T
+    smp[3:6] = par.T
+    smp[6] = (wi[:, 2] > 0.0).astype(np.float32)
+    return Batch(smp, np.array([0, n], dtype=np.int64), np.zeros(n, dtype=np.int32))
