@@ -409,6 +409,86 @@ def bench_cells16k(args, torch):
             "fit": {"value": smp.shape[1] * K / t_fit, "unit": "updates/s", "ms_per_step": t_fit * 1e3}}
 
 
+def product_flops(K, Kb, ns):
+    """Algorithmic FP32 flops of product sampling per query (an FMA counts 2): conditioning
+    of both mixtures, 31 per component; the two kept BSDF components rotated to world
+    and prepared, 171 each (mean 15, frame 12, in-plane rotation 50, offset and covariance
+    28, centre and exp-map Jacobian 66); per pair (2K of them) 217 (centre in the tangent
+    space 40, log-map Jacobian 13, transfer 50, J S J^T 21, weight 25, product mean and
+    covariance 51, Cholesky factor, inverse and normaliser 17) and 3 to normalise; per
+    draw the pair CDF (2K), one candidate (Box-Muller 6, nu 5, exp map 25, validity 3) and
+    the density, 71 per radiance component (rotation 15, log map 25, |nu|^2 3, two
+    quadratic forms with weight 26, 1/sinc and sum 2)."""
+    return 31 * K + 31 * Kb + 2 * 171 + 2 * K * (217 + 3) + ns * (2 * K + 39 + 71 * K)
+
+
+def bench_product(args, torch):
+    """Product sampling with a conditioned BSDF mixture on the 16384-cell workload: the
+    radiance mixtures after one batched E+M step (as cells16k), a BSDF model (16
+    components over incident direction, outgoing polar angle, azimuth and roughness)
+    fitted by the same EM to 2^20 GGX training samples, then 2^22 queries (positions
+    sorted by cell, random BSDF inputs and shading frames) x 4 draws with the device
+    Philox generator, timed."""
+    import ctypes as C_
+    from paper_2111_13094_amd import sdmm, synth
+    wl = synth.workload("cells16k")
+    b = synth.workload_batch(wl)
+    C, K, Kb, ns = wl["grid"].n_cells, 16, 16, 4
+    dev = torch.device("cuda", 0)
+    off, smp = torch.from_numpy(b.offsets).to(dev), torch.from_numpy(b.samples).to(dev)
+    mix = {k: torch.from_numpy(v).to(dev) for k, v in synth.initial_mixtures(wl["box_lo"], wl["box_size"], K).items()}
+    sdmm.fit_mixtures(off, smp, mix, sdmm.new_state(C, K, dev), sdmm.default_opts(K))
+    table = sdmm.condition_prepare(mix, C, K)
+    # the BSDF model, fitted like any cell
+    tb = synth.ggx_training_batch(17, 1 << 20)
+    lo, hi = synth.BSDF_PAR_LO[None], synth.BSDF_PAR_HI[None]
+    bmix = {k: torch.from_numpy(v).to(dev) for k, v in synth.initial_mixtures(lo, hi - lo, Kb).items()}
+    bst = sdmm.fit_mixtures(torch.from_numpy(tb.offsets).to(dev), torch.from_numpy(tb.samples).to(dev), bmix,
+                            sdmm.new_state(1, Kb, dev), sdmm.default_opts(Kb, iters=40))
+    btable = sdmm.condition_prepare(bmix, 1, Kb)
+    qpos, qcell = synth.make_queries(7, wl["box_lo"], wl["box_size"], 256)
+    nq = qcell.size
+    bpar, bcell, F = synth.bsdf_queries(8, nq, 1)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
+    qp, qc = t(qpos.T, np.float32), t(qcell, np.int32)
+    bp, bc, fr = t(bpar.T, np.float32), t(bcell, np.int32), t(F.reshape(nq, 9).T, np.float32)
+    out = (torch.empty(3, nq * ns, dtype=torch.float32, device=dev), torch.empty(nq * ns, dtype=torch.float32, device=dev),
+           torch.empty(nq * ns, dtype=torch.uint8, device=dev), None)
+    for w in range(args.warmup):
+        sdmm.product_sample(table, C, K, qp, qc, btable, 1, Kb, bp, bc, fr, ns, seed=w, out=out)
+    _sync(torch)
+    L = sdmm.lib()
+    L.sdmm_timing_enable(1)
+    tot, cnt = C_.c_double(), C_.c_int64()
+    L.sdmm_timing_read(5, C_.byref(tot), C_.byref(cnt), 1)
+    _sync(torch)
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        sdmm.product_sample(table, C, K, qp, qc, btable, 1, Kb, bp, bc, fr, ns, seed=1000 + s_, out=out)
+    _sync(torch)
+    wall = time.perf_counter() - t0
+    L.sdmm_timing_read(5, C_.byref(tot), C_.byref(cnt), 1)
+    L.sdmm_timing_enable(0)
+    k_ms = tot.value / max(cnt.value, 1)
+    fl = product_flops(K, Kb, ns) * nq
+    achieved = fl / (k_ms * 1e-3) / 1e12
+    return {"metric": "product-sampled draws/s (radiance x BSDF mixture), 16384 cells K=16, BSDF Kb=16, "
+                      "4 draws per query",
+            "value": nq * ns * args.steps / wall, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "product: the cells16k radiance mixtures after one E+M step; one BSDF model "
+                                   "(Kb=16) fitted by 40 EM iterations to 2^20 GGX training samples; 2^22 queries "
+                                   "(256 per cell) with uniform BSDF inputs and random shading frames, 4 draws each "
+                                   "(Philox4x32-10), pruned to 2 BSDF components",
+                       "n_cells": C, "K": K, "Kb": Kb, "queries": nq, "draws_per_query": ns,
+                       "valid_fraction": float(out[2].float().mean().item()),
+                       "bsdf_fit_status": int(bst.cpu().numpy()[0])},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "product_sample_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl}}
+
+
 def bench_grad(args, torch):
     """Adjoint on the 4096-cell workload: the state after 8 stepwise batches, then the
     FP32 gradient pass (value + gradient of the penalised log-likelihood per cell) timed
@@ -555,7 +635,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single",
-                                                                    "accurate"])
+                                                                    "accurate", "product"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
@@ -601,6 +681,8 @@ def main():
         out = bench_huge(args, torch)
     elif args.workload == "accurate":
         out = bench_accurate(args, torch)
+    elif args.workload == "product":
+        out = bench_product(args, torch)
     else:
         out = bench_single(args, torch)
     print(json.dumps(out))

@@ -227,6 +227,57 @@ int sdmm_condition_sample_pdf(const float *table, int32_t n_cells, int32_t K, co
                               uint64_t seed, float *dirs_out, float *pdf_out, uint8_t *valid_out,
                               void *stream);
 
+/* ---- product sampling with a conditioned BSDF mixture ---- */
+
+/*
+ * sdmm_product_sample -- ns draws per query from the product of the conditioned radiance
+ * mixture and a conditioned BSDF mixture (paper Sec. 3.4; pruning of Sec. 4.1).
+ * Per query q:
+ *   radiance: cell qcell[q] of `table` (sdmm_condition_prepare of the radiance mixtures,
+ *     n_cells x K) conditioned on qpos[q] as in sdmm_condition: pi'_k, m_k, Sigma'_k in
+ *     the tangent space of mu_k;
+ *   BSDF: model bcell[q] of `btable` (sdmm_condition_prepare of BSDF models: 5-D
+ *     mixtures over (local incident direction; three BSDF inputs such as the outgoing
+ *     polar angle, azimuth and roughness), n_bsdf x Kb) conditioned on bpar[q]; the two
+ *     components of largest conditioned weight are kept (lowest index on ties);
+ *   each kept BSDF component is rotated to world by the shading frame F (world = F local):
+ *     mean F mu_b, offset and covariance carried into the frame of F mu_b exactly;
+ *   pair (k, j), radiance component k and the j-th kept BSDF component: the BSDF
+ *     component in the tangent space of mu_k, centre a = log_{mu_k}(exp_{mu_b}(m_b)) and
+ *     covariance J Sigma'_b J^T with J the Jacobian of log_{mu_k} o exp_{mu_b} at m_b; the
+ *     product N(m_k, Sigma'_k) N(a, J Sigma'_b J^T) = lambda N(c, C) with
+ *     lambda = pi'_k w_b N(m_k; a, Sigma'_k + J Sigma'_b J^T);
+ *   draw: pair by the CDF of the normalised lambda in the order 2k + j (lowest index on
+ *     ties), nu = c + chol(C) z with z by Box-Muller from (u1, u2) (u1 mapped to (0, 1] as
+ *     1 - u1), discarded when |nu| >= pi, w = exp_{mu_k}(nu); and the solid-angle density
+ *     of the normalised product mixture at w (sum of P N(log_{mu_k} w; c, C) /
+ *     sinc|log_{mu_k} w|, a pair contributing 0 at |nu| >= pi (1 - 1e-6)).
+ * qpos, bpar [device] float32[3][nq] (SoA); qcell [device] int32[nq] in [0, n_cells);
+ * bcell [device] int32[nq] in [0, n_bsdf); frames [device] float32[9][nq] (SoA, entry
+ * (r, c) of F at row 3r + c); uniforms [device] float32[3][nq*ns] in [0, 1) or NULL for
+ * the device generator (as sdmm_sample). dirs_out [device] float32[3][nq*ns] (world);
+ * pdf_out [device] float32[nq*ns]; valid_out [device] uint8[nq*ns]; pair_out [device]
+ * int32[nq*ns] (2k + j, or -1) or NULL. A query whose cell or model index is out of range,
+ * or whose pairs are all empty, and every discarded draw, give valid 0, direction
+ * (0, 0, 0), pdf 0. K and Kb in 1..64; SDMM_EINVAL otherwise.
+ */
+int sdmm_product_sample(const float *table, int32_t n_cells, int32_t K, const float *qpos,
+                        const int32_t *qcell, const float *btable, int32_t n_bsdf, int32_t Kb,
+                        const float *bpar, const int32_t *bcell, const float *frames, int64_t nq,
+                        int32_t ns, const float *uniforms, uint64_t seed, float *dirs_out,
+                        float *pdf_out, uint8_t *valid_out, int32_t *pair_out, void *stream);
+
+/*
+ * sdmm_product_pdf -- the density of the normalised product mixture of
+ * sdmm_product_sample at nd given world directions per query (dirs [device]
+ * float32[3][nq*nd], direction t of query q at column q*nd+t; pdf_out [device]
+ * float32[nq*nd]); 0 for a query without pairs.
+ */
+int sdmm_product_pdf(const float *table, int32_t n_cells, int32_t K, const float *qpos,
+                     const int32_t *qcell, const float *btable, int32_t n_bsdf, int32_t Kb,
+                     const float *bpar, const int32_t *bcell, const float *frames, int64_t nq,
+                     int32_t nd, const float *dirs, float *pdf_out, void *stream);
+
 /* ---- adjoint ---- */
 
 /*
@@ -301,6 +352,7 @@ int sdmm_grad_to_params(int32_t n_cells, int32_t K, const double *L, const doubl
 #define SDMM_TIMER_QUERY 2   /* sdmm_condition_sample_pdf */
 #define SDMM_TIMER_GRAD 3    /* the adjoint pass of sdmm_fit_grad */
 #define SDMM_TIMER_ACCURATE 4 /* the second E-step pass of SDMM_FLAG_ACCURATE_SIGMA */
+#define SDMM_TIMER_PRODUCT 5  /* sdmm_product_sample */
 
 /* Enables (1) or disables (0) HIP-event timing: while enabled, every eager launch of
  * the kernel classes above is bracketed by a pair of events recorded on its stream

@@ -1,0 +1,468 @@
+// product.hip -- product sampling of a conditioned radiance mixture with a conditioned BSDF
+// mixture on gfx950 (Dodik et al., arXiv 2111.13094, Sec. 3.4; the pruning to the two
+// heaviest BSDF components of Sec. 4.1).
+//
+// Per query, in one group of G lanes (lane k = radiance component k, and lane b = BSDF
+// component b while the BSDF model is conditioned):
+//   1. both mixtures conditioned on their inputs (radiance: the position; BSDF: its three
+//      inputs), weights by a DPP log-sum-exp;
+//   2. the two BSDF components of largest weight (lowest index on ties) by two group
+//      maxima; every BSDF lane rotates its own component to world (mean F mu_b, offset and
+//      covariance carried into the frame of F mu_b by the in-plane rotation between the
+//      frames) and forms its centre exp(m) and exp-map Jacobian; the two kept ones are
+//      broadcast;
+//   3. lane k forms its two pairs: the BSDF component moved into the tangent space of
+//      mu_k (centre a = log_mu_k(centre), covariance J S J^T with J the log-map Jacobian
+//      at the centre times the exp-map Jacobian), and the product of the two 2-D
+//      Gaussians: log2-weight, mean c, Cholesky factor of C and its scaled inverse;
+//   4. draws: pair by a group prefix sum over lanes (pair order 2k + j), Box-Muller,
+//      nu = c + L_C z, cut-locus discard, exp map; the pdf of the normalised product
+//      mixture at the drawn direction (one log map per lane, two 2-D quadratic forms).
+#include "common.hpp"
+#include "query_common.hpp"
+#include "timing.hpp"
+
+namespace sdmm {
+
+constexpr float kLog2eF = 1.4426950408889634f;
+constexpr float kLog2TwoPi = 2.6514961294723187f;  // log2(2 pi)
+constexpr float kHalfLog2e = 0.72134752044448170f;
+
+// FP32 frame of a unit vector, rows (t1, t2, mu): the branchless basis the mixtures use
+__device__ __forceinline__ void frame_f32(float mx, float my, float mz, float R[9])
+{
+    const float sg = copysignf(1.0f, mz);
+    const float a = -1.0f / (sg + mz);
+    const float b = mx * my * a;
+    R[0] = fmaf(sg * mx * mx, a, 1.0f);
+    R[1] = sg * b;
+    R[2] = -sg * mx;
+    R[3] = b;
+    R[4] = fmaf(my * my, a, sg);
+    R[5] = -my;
+    R[6] = mx;
+    R[7] = my;
+    R[8] = mz;
+}
+
+// A BSDF component rotated to world and prepared for the pairs: its offset and
+// covariance in the frame of the rotated mean, its centre exp(m) and the world-space
+// exp-map Jacobian D = d exp / d nu at m (3 x 2), and its log2 weight.
+struct BsdfWorld {
+    float m0, m1, s00, s01, s11;
+    float cx, cy, cz;
+    float d[6];  // D row-major: d[2 i + c]
+    float lw;
+};
+
+// rotates the component of table row TB (conditioned offset bm0, bm1) by F (row-major,
+// world = F local) and prepares it
+__device__ __forceinline__ BsdfWorld rotate_bsdf(const float* TB, float bm0, float bm1, const float* F, float lw)
+{
+    BsdfWorld o;
+    const float mw0 = fmaf(F[0], TB[6], fmaf(F[1], TB[7], F[2] * TB[8]));
+    const float mw1 = fmaf(F[3], TB[6], fmaf(F[4], TB[7], F[5] * TB[8]));
+    const float mw2 = fmaf(F[6], TB[6], fmaf(F[7], TB[7], F[8] * TB[8]));
+    float Rw[9];
+    frame_f32(mw0, mw1, mw2, Rw);
+    // Q_ij = t_i(F mu) . F t_j(mu)
+    float Q[4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float f0 = fmaf(F[0], TB[3 * j], fmaf(F[1], TB[3 * j + 1], F[2] * TB[3 * j + 2]));
+        const float f1 = fmaf(F[3], TB[3 * j], fmaf(F[4], TB[3 * j + 1], F[5] * TB[3 * j + 2]));
+        const float f2 = fmaf(F[6], TB[3 * j], fmaf(F[7], TB[3 * j + 1], F[8] * TB[3 * j + 2]));
+        Q[j] = fmaf(Rw[0], f0, fmaf(Rw[1], f1, Rw[2] * f2));
+        Q[2 + j] = fmaf(Rw[3], f0, fmaf(Rw[4], f1, Rw[5] * f2));
+    }
+    o.m0 = fmaf(Q[0], bm0, Q[1] * bm1);
+    o.m1 = fmaf(Q[2], bm0, Q[3] * bm1);
+    // S = L' L'^T, then Q S Q^T
+    const float l0 = TB[24], l1 = TB[25], l2 = TB[26];
+    const float a00 = l0 * l0, a01 = l0 * l1, a11 = fmaf(l1, l1, l2 * l2);
+    const float t00 = fmaf(Q[0], a00, Q[1] * a01), t01 = fmaf(Q[0], a01, Q[1] * a11);
+    const float t10 = fmaf(Q[2], a00, Q[3] * a01), t11 = fmaf(Q[2], a01, Q[3] * a11);
+    o.s00 = fmaf(t00, Q[0], t01 * Q[1]);
+    o.s01 = fmaf(t10, Q[0], t11 * Q[1]);
+    o.s11 = fmaf(t10, Q[2], t11 * Q[3]);
+    // centre and exp-map Jacobian at m: w = Rw^T v, v = (nu sinc r, cos r),
+    // dv/dnu = [[s + n0^2 c, n0 n1 c], [n0 n1 c, s + n1^2 c], [-n0 s, -n1 s]]
+    const float r2 = fmaf(o.m0, o.m0, o.m1 * o.m1);
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float rev = r * 0.15915494309189535f;
+    const float sr = __builtin_amdgcn_sinf(rev), cr = __builtin_amdgcn_cosf(rev);
+    const bool small = r < 1e-2f;
+    const float sc = small ? fmaf(-r2, 1.0f / 6.0f, 1.0f) : sr * __builtin_amdgcn_rcpf(r);
+    const float c = small ? fmaf(r2, 1.0f / 30.0f, -1.0f / 3.0f) : (cr - sc) * __builtin_amdgcn_rcpf(r2);
+    const float v0 = o.m0 * sc, v1 = o.m1 * sc;
+    o.cx = fmaf(Rw[0], v0, fmaf(Rw[3], v1, Rw[6] * cr));
+    o.cy = fmaf(Rw[1], v0, fmaf(Rw[4], v1, Rw[7] * cr));
+    o.cz = fmaf(Rw[2], v0, fmaf(Rw[5], v1, Rw[8] * cr));
+    const float M00 = fmaf(o.m0 * o.m0, c, sc), M01 = o.m0 * o.m1 * c, M11 = fmaf(o.m1 * o.m1, c, sc);
+    const float M20 = -o.m0 * sc, M21 = -o.m1 * sc;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o.d[2 * i] = fmaf(Rw[i], M00, fmaf(Rw[3 + i], M01, Rw[6 + i] * M20));
+        o.d[2 * i + 1] = fmaf(Rw[i], M01, fmaf(Rw[3 + i], M11, Rw[6 + i] * M21));
+    }
+    o.lw = lw;
+    return o;
+}
+
+__device__ __forceinline__ BsdfWorld shfl_bsdf(const BsdfWorld& v, int src)
+{
+    BsdfWorld o;
+    o.m0 = __shfl(v.m0, src);
+    o.m1 = __shfl(v.m1, src);
+    o.s00 = __shfl(v.s00, src);
+    o.s01 = __shfl(v.s01, src);
+    o.s11 = __shfl(v.s11, src);
+    o.cx = __shfl(v.cx, src);
+    o.cy = __shfl(v.cy, src);
+    o.cz = __shfl(v.cz, src);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) o.d[i] = __shfl(v.d[i], src);
+    o.lw = __shfl(v.lw, src);
+    return o;
+}
+
+// one product pair in the tangent space of the radiance component (frame R, conditioned
+// offset m, covariance from the table's L')
+struct Pair {
+    float l;             // log2 weight (-inf: empty)
+    float c0, c1;        // mean
+    float L0, L1, L2;    // Cholesky factor of C
+    float i0, i1, i2;    // its inverse times sqrt(log2(e) / 2)
+    float nrm;           // -log2(2 pi det L_C)
+};
+
+__device__ __forceinline__ Pair make_pair(const float* R, float lwk, float m0, float m1, float a00, float a01,
+                                          float a11, const BsdfWorld& b)
+{
+    Pair p;
+    p.l = -INFINITY;
+    p.c0 = p.c1 = 0.0f;
+    p.L0 = p.L2 = 1.0f;
+    p.L1 = 0.0f;
+    p.i0 = p.i2 = 1.0f;
+    p.i1 = 0.0f;
+    p.nrm = 0.0f;
+    // centre in the frame of mu_k and the log-map Jacobian there:
+    // nu = f (x, y), d f / d x = x g, d f / d y = y g, d f / d z = -1, g = (z - f) / s^2
+    const float px = fmaf(R[0], b.cx, fmaf(R[1], b.cy, R[2] * b.cz));
+    const float py = fmaf(R[3], b.cx, fmaf(R[4], b.cy, R[5] * b.cz));
+    const float pz = fmaf(R[6], b.cx, fmaf(R[7], b.cy, R[8] * b.cz));
+    float a0, a1;
+    const float f = log_map_f32(px, py, pz, a0, a1);
+    const float s2 = fmaf(px, px, py * py);
+    const float g = s2 > 1e-6f ? (pz - f) * __builtin_amdgcn_rcpf(s2) : -2.0f / 3.0f;
+    const float J00 = fmaf(px * px, g, f), J01 = px * py * g, J02 = -px;
+    const float J11 = fmaf(py * py, g, f), J12 = -py;
+    // E = R D (3 x 2), then J = Jl E (2 x 2)
+    float E[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        E[2 * i] = fmaf(R[3 * i], b.d[0], fmaf(R[3 * i + 1], b.d[2], R[3 * i + 2] * b.d[4]));
+        E[2 * i + 1] = fmaf(R[3 * i], b.d[1], fmaf(R[3 * i + 1], b.d[3], R[3 * i + 2] * b.d[5]));
+    }
+    const float j00 = fmaf(J00, E[0], fmaf(J01, E[2], J02 * E[4]));
+    const float j01 = fmaf(J00, E[1], fmaf(J01, E[3], J02 * E[5]));
+    const float j10 = fmaf(J01, E[0], fmaf(J11, E[2], J12 * E[4]));
+    const float j11 = fmaf(J01, E[1], fmaf(J11, E[3], J12 * E[5]));
+    // B = J S J^T
+    const float u00 = fmaf(j00, b.s00, j01 * b.s01), u01 = fmaf(j00, b.s01, j01 * b.s11);
+    const float u10 = fmaf(j10, b.s00, j11 * b.s01), u11 = fmaf(j10, b.s01, j11 * b.s11);
+    const float b00 = fmaf(u00, j00, u01 * j01), b01 = fmaf(u10, j00, u11 * j01), b11 = fmaf(u10, j10, u11 * j11);
+    // S = A + B and the weight N(m; a, S)
+    const float S00 = a00 + b00, S01 = a01 + b01, S11 = a11 + b11;
+    const float det = fmaf(S00, S11, -S01 * S01);
+    const bool ok = det > 0.0f && isfinite(lwk) && isfinite(b.lw) && isfinite(det);
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float si00 = S11 * idet, si01 = -S01 * idet, si11 = S00 * idet;
+    const float d0 = m0 - a0, d1 = m1 - a1;
+    const float q = fmaf(d0, fmaf(si00, d0, si01 * d1), d1 * fmaf(si01, d0, si11 * d1));
+    // C = A S^-1 B, c = B S^-1 m + A S^-1 a
+    const float as00 = fmaf(a00, si00, a01 * si01), as01 = fmaf(a00, si01, a01 * si11);
+    const float as10 = fmaf(a01, si00, a11 * si01), as11 = fmaf(a01, si01, a11 * si11);
+    const float bs00 = fmaf(b00, si00, b01 * si01), bs01 = fmaf(b00, si01, b01 * si11);
+    const float bs10 = fmaf(b01, si00, b11 * si01), bs11 = fmaf(b01, si01, b11 * si11);
+    const float C00 = fmaf(as00, b00, as01 * b01);
+    const float C01 = 0.5f * (fmaf(as00, b01, as01 * b11) + fmaf(as10, b00, as11 * b01));
+    const float C11 = fmaf(as10, b01, as11 * b11);
+    const float L0s = C00, L2s = fmaf(-C01, C01 * __builtin_amdgcn_rcpf(C00), C11);
+    if (!(ok && L0s > 0.0f && L2s > 0.0f)) return p;
+    p.c0 = fmaf(bs00, m0, fmaf(bs01, m1, fmaf(as00, a0, as01 * a1)));
+    p.c1 = fmaf(bs10, m0, fmaf(bs11, m1, fmaf(as10, a0, as11 * a1)));
+    p.L0 = __builtin_amdgcn_sqrtf(L0s);
+    p.L1 = C01 * __builtin_amdgcn_rcpf(p.L0);
+    p.L2 = __builtin_amdgcn_sqrtf(L2s);
+    const float r0 = __builtin_amdgcn_rcpf(p.L0), r2i = __builtin_amdgcn_rcpf(p.L2);
+    constexpr float kap = 0.84932180028801904f;  // sqrt(log2(e) / 2)
+    p.i0 = r0 * kap;
+    p.i1 = -p.L1 * r0 * r2i * kap;
+    p.i2 = r2i * kap;
+    p.nrm = -kLog2TwoPi - __builtin_amdgcn_logf(p.L0 * p.L2);
+    p.l = lwk + b.lw - kHalfLog2e * q - kLog2TwoPi - 0.5f * __builtin_amdgcn_logf(det);
+    return p;
+}
+
+// P N(nu; c, C) at a lane's tangent coordinates
+__device__ __forceinline__ float pair_density(const Pair& p, float P, float n0, float n1)
+{
+    const float d0 = n0 - p.c0, d1 = n1 - p.c1;
+    const float z0 = p.i0 * d0, z1 = fmaf(p.i1, d0, p.i2 * d1);
+    return P * __builtin_amdgcn_exp2f(p.nrm - fmaf(z0, z0, z1 * z1));
+}
+
+// Per-query state after the set-up: lane k's frame and two pairs with probabilities.
+struct ProductQuery {
+    float R[9];
+    Pair p0, p1;
+    float P0, P1;
+    bool any;  // some pair has weight
+};
+
+// Set-up of one query (steps 1-3). Lanes of a group must all call it.
+template <int G>
+__device__ __forceinline__ void product_setup(const float* __restrict__ table, int C, int K,
+                                              const float* __restrict__ btable, int CB, int Kb, int qc, int bc,
+                                              bool inq, float x0, float x1, float x2, float y0, float y1, float y2,
+                                              const float* F, ProductQuery& Qy)
+{
+    const int lane = threadIdx.x & 63, comp = lane % G, base = lane - comp;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const bool usable = inq && qc >= 0 && qc < C && bc >= 0 && bc < CB;
+    // radiance conditioning
+    float T[kCond];
+    load_row(table_row(table, qc, K, comp, usable), T);
+    float m0, m1;
+    float lw = cond_component(T, x0, x1, x2, m0, m1);
+    if (comp >= K || !usable) lw = -INFINITY;
+    float lmax = group_max<G>(lw);
+    float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
+    float den = group_sum<G>(e);
+    const float lwk = (e > 0.0f && den > 0.0f) ? (lw - lmax) - __builtin_amdgcn_logf(den) : -INFINITY;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Qy.R[i] = T[i];
+    const float l0 = T[24], l1 = T[25], l2 = T[26];
+    const float a00 = l0 * l0, a01 = l0 * l1, a11 = fmaf(l1, l1, l2 * l2);
+    // BSDF conditioning (lane b = component b), its weights, and the two heaviest
+    float TB[kCond];
+    load_row(table_row(btable, bc, Kb, comp, usable), TB);
+    float bm0, bm1;
+    float lb = cond_component(TB, y0, y1, y2, bm0, bm1);
+    if (comp >= Kb || !usable) lb = -INFINITY;
+    lmax = group_max<G>(lb);
+    e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lb - lmax);
+    den = group_sum<G>(e);
+    const float wb = den > 0.0f ? e * __builtin_amdgcn_rcpf(den) : 0.0f;
+    const float lwb = (e > 0.0f && den > 0.0f) ? (lb - lmax) - __builtin_amdgcn_logf(den) : -INFINITY;
+    const float w1 = group_max<G>(wb);
+    const uint64_t h0 = __ballot(comp < Kb && wb > 0.0f && wb == w1) & gmask;
+    const int s0 = h0 ? __builtin_ctzll(h0) - base : -1;
+    const float wb2 = (comp == s0) ? -1.0f : wb;
+    const float w2 = group_max<G>(wb2);
+    const uint64_t h1 = __ballot(comp < Kb && wb2 > 0.0f && wb2 == w2) & gmask;
+    const int s1 = h1 ? __builtin_ctzll(h1) - base : -1;
+    const BsdfWorld mine = rotate_bsdf(TB, bm0, bm1, F, lwb);
+    BsdfWorld b0 = shfl_bsdf(mine, base + (s0 < 0 ? 0 : s0));
+    BsdfWorld b1 = shfl_bsdf(mine, base + (s1 < 0 ? 0 : s1));
+    if (s0 < 0) b0.lw = -INFINITY;
+    if (s1 < 0) b1.lw = -INFINITY;
+    // pairs and their probabilities
+    Qy.p0 = make_pair(Qy.R, lwk, m0, m1, a00, a01, a11, b0);
+    Qy.p1 = make_pair(Qy.R, lwk, m0, m1, a00, a01, a11, b1);
+    if (comp >= K) Qy.p0.l = Qy.p1.l = -INFINITY;
+    const float lm = group_max<G>(fmaxf(Qy.p0.l, Qy.p1.l));
+    Qy.any = lm != -INFINITY;
+    const float e0 = Qy.any ? __builtin_amdgcn_exp2f(Qy.p0.l - lm) : 0.0f;
+    const float e1 = Qy.any ? __builtin_amdgcn_exp2f(Qy.p1.l - lm) : 0.0f;
+    const float tot = group_sum<G>(e0 + e1);
+    const float itot = tot > 0.0f ? __builtin_amdgcn_rcpf(tot) : 0.0f;
+    Qy.P0 = e0 * itot;
+    Qy.P1 = e1 * itot;
+}
+
+// density of the normalised product mixture at a world direction (step 4, all lanes)
+template <int G>
+__device__ __forceinline__ float product_density(const ProductQuery& Qy, int K, float wx, float wy, float wz)
+{
+    const int comp = (threadIdx.x & 63) % G;
+    const float xr = fmaf(Qy.R[0], wx, fmaf(Qy.R[1], wy, Qy.R[2] * wz));
+    const float yr = fmaf(Qy.R[3], wx, fmaf(Qy.R[4], wy, Qy.R[5] * wz));
+    const float zr = fmaf(Qy.R[6], wx, fmaf(Qy.R[7], wy, Qy.R[8] * wz));
+    float n0, n1;
+    const float f = log_map_f32(xr, yr, zr, n0, n1);
+    const float r2 = fmaf(n0, n0, n1 * n1);
+    float v = pair_density(Qy.p0, Qy.P0, n0, n1) + pair_density(Qy.p1, Qy.P1, n0, n1);
+    v = (comp < K && r2 < kCutSq) ? v * f : 0.0f;
+    return group_sum<G>(v);
+}
+
+// one draw for the group's query (step 4)
+template <int G>
+__device__ __forceinline__ void product_draw(const ProductQuery& Qy, int K, float u0, float u1, float u2,
+                                             float& ox, float& oy, float& oz, float& pdf, int& valid, int& pair)
+{
+    const int lane = threadIdx.x & 63;
+    const int comp = lane % G, base = lane - comp;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const float s = Qy.P0 + Qy.P1;
+    const float cdf = group_inclusive_scan<G>(s);
+    const uint64_t hit = __ballot(comp < K && Qy.any && u0 < cdf) & gmask;
+    const uint64_t pos = __ballot(comp < K && Qy.any && s > 0.0f) & gmask;
+    int sel = -1, j = 0;
+    if (hit) {
+        sel = __builtin_ctzll(hit) - base;
+        j = __shfl((u0 < (cdf - s) + Qy.P0 && Qy.P0 > 0.0f) || !(Qy.P1 > 0.0f) ? 0 : 1, base + sel);
+    } else if (pos) {
+        sel = 63 - __builtin_clzll(pos) - base;
+        j = __shfl(Qy.P1 > 0.0f ? 1 : 0, base + sel);
+    }
+    // every lane forms a candidate from its own pair j; the selected lane's is broadcast
+    const Pair& p = j ? Qy.p1 : Qy.p0;
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718056f * __builtin_amdgcn_logf(1.0f - u1));
+    const float z0 = rad * __builtin_amdgcn_cosf(u2), z1 = rad * __builtin_amdgcn_sinf(u2);
+    const float n0 = fmaf(p.L0, z0, p.c0);
+    const float n1 = fmaf(p.L1, z0, fmaf(p.L2, z1, p.c1));
+    float w[3];
+    exp_map_hw(Qy.R, n0, n1, w);
+    const int ok = fmaf(n0, n0, n1 * n1) < kPiSq;
+    const int src = base + (sel < 0 ? 0 : sel);
+    ox = __shfl(w[0], src);
+    oy = __shfl(w[1], src);
+    oz = __shfl(w[2], src);
+    valid = sel >= 0 ? __shfl(ok, src) : 0;
+    pair = sel >= 0 ? 2 * sel + j : -1;
+    pdf = product_density<G>(Qy, K, ox, oy, oz);
+    if (!valid) {
+        ox = oy = oz = 0.0f;
+        pdf = 0.0f;
+    }
+}
+
+__device__ __forceinline__ void load_frame(const float* __restrict__ frames, int64_t nq, int64_t q, float F[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) F[i] = frames[i * nq + q];
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void product_sample_kernel(
+    const float* __restrict__ table, int C, int K, const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
+    const float* __restrict__ btable, int CB, int Kb, const float* __restrict__ bpar,
+    const int32_t* __restrict__ bcell, const float* __restrict__ frames, int64_t nq, int ns,
+    const float* __restrict__ uniforms, uint64_t seed, float* __restrict__ dirs_out, float* __restrict__ pdf_out,
+    uint8_t* __restrict__ valid_out, int32_t* __restrict__ pair_out)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = nq * ns;
+    for (int64_t q0 = wave * S; q0 < nq; q0 += nwaves * S) {
+        const int64_t q = q0 + slot;
+        const bool inq = q < nq;
+        const int64_t qq = inq ? q : 0;
+        float F[9];
+        load_frame(frames, nq, qq, F);
+        ProductQuery Qy;
+        product_setup<G>(table, C, K, btable, CB, Kb, qcell[qq], bcell[qq], inq, qpos[qq], qpos[nq + qq],
+                         qpos[2 * nq + qq], bpar[qq], bpar[nq + qq], bpar[2 * nq + qq], F, Qy);
+        for (int t0 = 0; t0 < ns; t0 += G) {
+            float ul0 = 0.0f, ul1 = 0.0f, ul2 = 0.0f;
+            if (t0 + comp < ns) draw_uniforms(uniforms, nd, qq * ns + t0 + comp, seed, ul0, ul1, ul2);
+            const int tn = min(G, ns - t0);
+            for (int tt = 0; tt < tn; ++tt) {
+                const int64_t d = qq * ns + t0 + tt;
+                const int src = slot * G + tt;
+                const float u0 = __shfl(ul0, src), u1 = __shfl(ul1, src), u2 = __shfl(ul2, src);
+                float ox, oy, oz, pdf;
+                int valid, pair;
+                product_draw<G>(Qy, K, u0, u1, u2, ox, oy, oz, pdf, valid, pair);
+                if (inq && comp == 0) {
+                    dirs_out[d] = ox;
+                    dirs_out[nd + d] = oy;
+                    dirs_out[2 * nd + d] = oz;
+                    pdf_out[d] = pdf;
+                    valid_out[d] = (uint8_t)valid;
+                    if (pair_out) pair_out[d] = pair;
+                }
+            }
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void product_pdf_kernel(
+    const float* __restrict__ table, int C, int K, const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
+    const float* __restrict__ btable, int CB, int Kb, const float* __restrict__ bpar,
+    const int32_t* __restrict__ bcell, const float* __restrict__ frames, int64_t nq, int nd,
+    const float* __restrict__ dirs, float* __restrict__ pdf_out)
+{
+    constexpr int S = 64 / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t np = nq * nd;
+    for (int64_t q0 = wave * S; q0 < nq; q0 += nwaves * S) {
+        const int64_t q = q0 + slot;
+        const bool inq = q < nq;
+        const int64_t qq = inq ? q : 0;
+        float F[9];
+        load_frame(frames, nq, qq, F);
+        ProductQuery Qy;
+        product_setup<G>(table, C, K, btable, CB, Kb, qcell[qq], bcell[qq], inq, qpos[qq], qpos[nq + qq],
+                         qpos[2 * nq + qq], bpar[qq], bpar[nq + qq], bpar[2 * nq + qq], F, Qy);
+        for (int t = 0; t < nd; ++t) {
+            const int64_t p = qq * nd + t;
+            const float v = product_density<G>(Qy, K, dirs[p], dirs[np + p], dirs[2 * np + p]);
+            if (inq && comp == 0) pdf_out[p] = Qy.any ? v : 0.0f;
+        }
+    }
+}
+
+static int product_args_ok(const float* table, int32_t n_cells, int32_t K, const float* btable, int32_t n_bsdf,
+                           int32_t Kb, int64_t nq, int32_t n)
+{
+    return table && btable && n_cells > 0 && n_bsdf > 0 && K >= 1 && K <= kMaxK && Kb >= 1 && Kb <= kMaxK &&
+           nq >= 0 && n >= 0;
+}
+
+}  // namespace sdmm
+
+using namespace sdmm;
+
+extern "C" int sdmm_product_sample(const float* table, int32_t n_cells, int32_t K, const float* qpos,
+                                   const int32_t* qcell, const float* btable, int32_t n_bsdf, int32_t Kb,
+                                   const float* bpar, const int32_t* bcell, const float* frames, int64_t nq,
+                                   int32_t ns, const float* uniforms, uint64_t seed, float* dirs_out,
+                                   float* pdf_out, uint8_t* valid_out, int32_t* pair_out, void* stream)
+{
+    if (!product_args_ok(table, n_cells, K, btable, n_bsdf, Kb, nq, ns)) return SDMM_EINVAL;
+    if (nq == 0 || ns == 0) return SDMM_OK;
+    if (!qpos || !qcell || !bpar || !bcell || !frames || !dirs_out || !pdf_out || !valid_out) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K > Kb ? K : Kb);
+    ScopedTimer tm(SDMM_TIMER_PRODUCT, s);
+    SDMM_DISPATCH_G(G, (product_sample_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
+                           table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq, ns, uniforms,
+                           seed, dirs_out, pdf_out, valid_out, pair_out)));
+    return check(hipGetLastError());
+}
+
+extern "C" int sdmm_product_pdf(const float* table, int32_t n_cells, int32_t K, const float* qpos,
+                                const int32_t* qcell, const float* btable, int32_t n_bsdf, int32_t Kb,
+                                const float* bpar, const int32_t* bcell, const float* frames, int64_t nq, int32_t nd,
+                                const float* dirs, float* pdf_out, void* stream)
+{
+    if (!product_args_ok(table, n_cells, K, btable, n_bsdf, Kb, nq, nd)) return SDMM_EINVAL;
+    if (nq == 0 || nd == 0) return SDMM_OK;
+    if (!qpos || !qcell || !bpar || !bcell || !frames || !dirs || !pdf_out) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = group_for(K > Kb ? K : Kb);
+    SDMM_DISPATCH_G(G, (product_pdf_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
+                           table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq, nd, dirs,
+                           pdf_out)));
+    return check(hipGetLastError());
+}

@@ -10,18 +10,10 @@
 // Lane mapping as in the E-step: a wave holds 64/G queries (or draws) x G component lanes;
 // normalisations and mixture sums are DPP all-reduces inside the G-lane group.
 #include "common.hpp"
+#include "query_common.hpp"
 #include "timing.hpp"
 
 namespace sdmm {
-
-// conditioning table, per component (FP32):
-//   0-8   R_mu rows (t1, t2, mu)           9-11  mu_x
-//   12-17 Lxx^-1 * sqrt(log2(e)/2), packed   18-23 A = Sigma_nx Sigma_xx^-1 (2x3, row-major)
-//   24-26 L' packed (chol of Sigma')         27-29 L'^-1 * sqrt(log2(e)/2), packed
-//   30    log2(pi) - log2 det Lxx - (3/2) log2(2 pi)      (-inf for an unusable component)
-//   31    -log2 det L' - log2(2 pi)
-constexpr float kCutSq = (3.14159265358979323846f * (1.0f - 1e-6f)) * (3.14159265358979323846f * (1.0f - 1e-6f));
-constexpr float kPiSq = 3.14159265358979323846f * 3.14159265358979323846f;
 
 __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi, const double* __restrict__ mud,
                                     const double* __restrict__ mux, const double* __restrict__ cov,
@@ -84,36 +76,6 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
     T[31] = (float)((-(log(Lp[0]) + log(Lp[2])) - kLn2Pi) * kLog2e);
 }
 
-// ---------------------------------------------------------------------------------
-// per-lane pieces
-// ---------------------------------------------------------------------------------
-
-// FP32 exp map w = R^T (nu sinc r, cos r) with the hardware sine / cosine (which take
-// revolutions), square root and reciprocal
-__device__ __forceinline__ void exp_map_hw(const float* R, float n0, float n1, float w[3])
-{
-    const float r2 = fmaf(n0, n0, n1 * n1);
-    const float r = __builtin_amdgcn_sqrtf(r2);
-    const float rev = r * 0.15915494309189535f;
-    const float sr = __builtin_amdgcn_sinf(rev), cr = __builtin_amdgcn_cosf(rev);
-    const float sc = r > 1e-4f ? sr * __builtin_amdgcn_rcpf(r) : 1.0f - r2 * (1.0f / 6.0f);
-    const float v0 = n0 * sc, v1 = n1 * sc;
-    for (int j = 0; j < 3; ++j) w[j] = fmaf(R[j], v0, fmaf(R[3 + j], v1, R[6 + j] * cr));
-}
-
-// conditional log2-weight and mean of component T at position x
-__device__ __forceinline__ float cond_component(const float* T, float x0, float x1, float x2, float& m0, float& m1)
-{
-    const float d0 = x0 - T[9], d1 = x1 - T[10], d2 = x2 - T[11];
-    const float u0 = T[12] * d0;
-    const float u1 = fmaf(T[13], d0, T[14] * d1);
-    const float u2 = fmaf(T[15], d0, fmaf(T[16], d1, T[17] * d2));
-    const float q = fmaf(u0, u0, fmaf(u1, u1, u2 * u2));
-    m0 = fmaf(T[18], d0, fmaf(T[19], d1, T[20] * d2));
-    m1 = fmaf(T[21], d0, fmaf(T[22], d1, T[23] * d2));
-    return T[30] - q;
-}
-
 // pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k| at direction w (0 at the cut locus)
 __device__ __forceinline__ float pdf_component(const float* T, float wk, float m0, float m1, float wx, float wy,
                                                float wz)
@@ -130,66 +92,6 @@ __device__ __forceinline__ float pdf_component(const float* T, float wk, float m
     const float q = fmaf(u0, u0, u1 * u1);
     const float p = wk * __builtin_amdgcn_exp2f(T[31] - q) * f;
     return (r2 < kCutSq && wk > 0.0f) ? p : 0.0f;
-}
-
-// Philox4x32-10 (Salmon et al. 2011)
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-__device__ __forceinline__ void draw_uniforms(const float* uniforms, int64_t n_draws, int64_t d, uint64_t seed,
-                                              float& u0, float& u1, float& u2)
-{
-    if (uniforms) {
-        u0 = uniforms[d];
-        u1 = uniforms[n_draws + d];
-        u2 = uniforms[2 * n_draws + d];
-    } else {
-        const uint4 r = philox4x32_10(make_uint4((uint32_t)d, (uint32_t)((uint64_t)d >> 32), 0u, 0u),
-                                      (uint32_t)seed, (uint32_t)(seed >> 32));
-        u0 = (float)(r.x >> 8) * 0x1.0p-24f;
-        u1 = (float)(r.y >> 8) * 0x1.0p-24f;
-        u2 = (float)(r.z >> 8) * 0x1.0p-24f;
-    }
-}
-
-// inclusive prefix sum over the G lanes of a group (lane order = component order):
-// DPP row shifts inside a row of 16 lanes, shuffles across rows
-template <int G>
-__device__ __forceinline__ float group_inclusive_scan(float v)
-{
-    const int comp = (threadIdx.x & 63) % G;
-#define SDMM_SCAN_STEP(o)                                                                          \
-    if constexpr (G > o) {                                                                         \
-        const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + o, \
-                                                                   0xF, 0xF, true));               \
-        v += comp >= o ? t : 0.0f;                                                                 \
-    }
-    SDMM_SCAN_STEP(1)
-    SDMM_SCAN_STEP(2)
-    SDMM_SCAN_STEP(4)
-    SDMM_SCAN_STEP(8)
-#undef SDMM_SCAN_STEP
-    if constexpr (G > 16) {  // add the totals of the group's earlier rows
-        const int base = (threadIdx.x & 63) - comp, row = comp >> 4;
-        const float t0 = __shfl(v, base + 15);
-        float add = row >= 1 ? t0 : 0.0f;
-        if constexpr (G > 32) {
-            const float t1 = __shfl(v, base + 31), t2 = __shfl(v, base + 47);
-            add = row >= 2 ? (row >= 3 ? (t0 + t1) + t2 : t0 + t1) : add;
-        }
-        v += add;
-    }
-    return v;
 }
 
 // One draw for the group's query: pick the component by the CDF of pi' (prefix sum in
@@ -232,25 +134,6 @@ __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk
     if (!valid) {
         ox = oy = oz = 0.0f;
         pdf = 0.0f;
-    }
-}
-
-__device__ __forceinline__ const float* table_row(const float* table, int qc, int K, int comp, bool usable)
-{
-    const int kk = comp < K ? comp : K - 1;
-    return table + ((int64_t)(usable ? qc : 0) * K + kk) * kCond;
-}
-
-__device__ __forceinline__ void load_row(const float* src, float* T)
-{
-    const float4* p = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int q = 0; q < kCond / 4; ++q) {
-        const float4 v = p[q];
-        T[4 * q] = v.x;
-        T[4 * q + 1] = v.y;
-        T[4 * q + 2] = v.z;
-        T[4 * q + 3] = v.w;
     }
 }
 
@@ -412,25 +295,6 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
         }
     }
 }
-
-// grid for a wave-strided loop over `items` work units of S per wave
-static unsigned grid_for(int64_t items, int S)
-{
-    const int64_t waves = (items + S - 1) / S;
-    int64_t blocks = (waves + 3) / 4;
-    const int64_t cap = 256 * 32;  // 256 CUs x 32 waves of 256-thread blocks
-    if (blocks > cap) blocks = cap;
-    return (unsigned)(blocks < 1 ? 1 : blocks);
-}
-
-#define SDMM_DISPATCH_G(G, CALL)         \
-    switch (G) {                         \
-        case 4: { constexpr int g = 4; CALL; } break;   \
-        case 8: { constexpr int g = 8; CALL; } break;   \
-        case 16: { constexpr int g = 16; CALL; } break; \
-        case 32: { constexpr int g = 32; CALL; } break; \
-        default: { constexpr int g = 64; CALL; } break; \
-    }
 
 }  // namespace sdmm
 

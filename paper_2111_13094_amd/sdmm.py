@@ -69,6 +69,9 @@ def lib():
         L.sdmm_pdf.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, vp, vp]
         L.sdmm_sample.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, u64, vp, vp, vp, vp, vp]
         L.sdmm_condition_sample_pdf.argtypes = [vp, i32, i32, vp, vp, i64, i32, vp, u64, vp, vp, vp, vp]
+        L.sdmm_product_sample.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, i64, i32, vp, u64, vp, vp,
+                                          vp, vp, vp]
+        L.sdmm_product_pdf.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, i64, i32, vp, vp, vp]
         L.sdmm_fit_grad.argtypes = [vp, vp, i64, P(Mixtures), P(FitOpts), vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.sdmm_mixture_from_params.argtypes = [i32, i32, vp, vp, vp, vp, vp, P(Mixtures), vp, vp]
         L.sdmm_grad_to_params.argtypes = [i32, i32, vp, vp, vp, vp, vp]
@@ -252,6 +255,39 @@ def condition_sample_pdf(table, n_cells, K, qpos, qcell, ns, uniforms=None, seed
                                            _ptr(dirs), _ptr(pdfv), _ptr(valid), _stream(stream)),
            "sdmm_condition_sample_pdf")
     return dirs, pdfv, valid
+
+
+def product_sample(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, ns, uniforms=None, seed=0,
+                   with_pair=False, out=None, stream=None):
+    """Product sampling with a conditioned BSDF mixture. qpos, bpar float32 [3, nq];
+    frames float32 [9, nq] (row-major local-to-world rotation per query). Returns
+    (dirs [3, nq*ns], pdf [nq*ns], valid uint8 [nq*ns], pair int32 or None)."""
+    nq = qcell.numel()
+    dev = qcell.device
+    n = nq * ns
+    if out is None:
+        out = (torch.empty(3, n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.uint8, device=dev),
+               torch.empty(n, dtype=torch.int32, device=dev) if with_pair else None)
+    dirs, pdfv, valid, pair = out
+    _check(lib().sdmm_product_sample(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
+                                     _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
+                                     _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
+                                     nq, ns, _ptr(uniforms, torch.float32), seed, _ptr(dirs), _ptr(pdfv), _ptr(valid),
+                                     _ptr(pair), _stream(stream)), "sdmm_product_sample")
+    return dirs, pdfv, valid, pair
+
+
+def product_pdf(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, dirs, stream=None):
+    """Product density at dirs float32 [3, nq*nd]. Returns pdf [nq*nd]."""
+    nq = qcell.numel()
+    nd = dirs.shape[1] // max(nq, 1)
+    out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
+    _check(lib().sdmm_product_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
+                                  _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
+                                  _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
+                                  nq, nd, _ptr(dirs, torch.float32), _ptr(out), _stream(stream)), "sdmm_product_pdf")
+    return out
 
 
 def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=None):
