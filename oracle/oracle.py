@@ -364,6 +364,84 @@ def product_pdf(K, mix, Kb, bmix, qpos, qcell, bpar, bcell, frames, dirs):
     return out
 
 
+# --- spatial kD-tree --------------------------------------------------------------------
+
+class _Tree(C.Structure):
+    _fields_ = [("max_nodes", C.c_int32), ("max_leaves", C.c_int32), ("counts", C.c_void_p),
+                ("axis", C.c_void_p), ("left", C.c_void_p), ("leaf", C.c_void_p), ("split", C.c_void_p),
+                ("leaf_node", C.c_void_p), ("lo", C.c_void_p), ("hi", C.c_void_p), ("init", C.c_void_p)]
+
+
+class Tree:
+    """numpy arrays of a kD-tree with room for max_leaves leaves (2 max_leaves - 1 nodes)."""
+
+    def __init__(self, max_leaves):
+        n = 2 * max_leaves - 1
+        self.counts = np.zeros(2, dtype=np.int32)
+        self.axis = np.full(n, -1, dtype=np.int32)
+        self.left = np.full(n, -1, dtype=np.int32)
+        self.leaf = np.full(n, -1, dtype=np.int32)
+        self.split = np.zeros(n)
+        self.leaf_node = np.full(max_leaves, -1, dtype=np.int32)
+        self.lo = np.zeros((max_leaves, 3))
+        self.hi = np.zeros((max_leaves, 3))
+        self.init = np.zeros(max_leaves, dtype=np.int32)
+        self.max_leaves, self.max_nodes = max_leaves, n
+
+    def c(self):
+        return _Tree(self.max_nodes, self.max_leaves, *[_p(a) for a in (
+            self.counts, self.axis, self.left, self.leaf, self.split, self.leaf_node, self.lo, self.hi, self.init)])
+
+    @property
+    def n_nodes(self):
+        return int(self.counts[0])
+
+    @property
+    def n_leaves(self):
+        return int(self.counts[1])
+
+
+def tree_init(max_leaves, depth, lo, hi) -> Tree:
+    L = lib()
+    L.orc_tree_init.argtypes = [C.POINTER(_Tree), C.c_int32, C.c_void_p, C.c_void_p]
+    t = Tree(max_leaves)
+    ct = t.c()
+    if L.orc_tree_init(C.byref(ct), depth, _p(_f64(lo)), _p(_f64(hi))):
+        raise ValueError("orc_tree_init failed")
+    return t
+
+
+def init_leaf(K, lo, hi):
+    """The initial mixture of a leaf box (pi, mu_dir, mu_pos, cov as flat arrays)."""
+    L = lib()
+    L.orc_init_leaf.argtypes = [C.c_int32] + [C.c_void_p] * 6
+    pi, mud, mux, cov = np.zeros(K), np.zeros(3 * K), np.zeros(3 * K), np.zeros(15 * K)
+    L.orc_init_leaf(K, _p(_f64(lo)), _p(_f64(hi)), _p(pi), _p(mud), _p(mux), _p(cov))
+    return {"pi": pi, "mu_dir": mud, "mu_pos": mux, "cov": cov}
+
+
+def tree_refine(t: Tree, samples, c, K, mix, state, min_init=16):
+    """Refines t in place with the samples, copies and initialises leaf mixtures in mix /
+    state (arrays sized for t.max_leaves cells). Returns (status, sorted samples, offsets
+    [n_leaves + 1])."""
+    L = lib()
+    i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+    L.orc_tree_refine.argtypes = [C.POINTER(_Tree), vp, i64, i32, i32, i32] + [vp] * 10
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    N = samples.shape[1]
+    sorted_ = np.zeros_like(samples)
+    offsets = np.zeros(t.max_leaves + 1, dtype=np.int64)
+    for key in ("pi", "mu_dir", "mu_pos", "cov"):
+        assert mix[key].dtype == np.float64 and mix[key].flags["C_CONTIGUOUS"]
+    ct = t.c()
+    st = L.orc_tree_refine(C.byref(ct), _p(samples), N, c, min_init, K, _p(mix["pi"]), _p(mix["mu_dir"]),
+                           _p(mix["mu_pos"]), _p(mix["cov"]), _p(state["s0"]), _p(state["s2"]), _p(state["sw"]),
+                           _p(state["step"]), _p(sorted_), _p(offsets))
+    if st < 0:
+        raise ValueError("orc_tree_refine failed")
+    return st, sorted_, offsets[:t.n_leaves + 1].copy()
+
+
 # --- counter-based uniforms -------------------------------------------------------
 
 def philox4x32_10(ctr, key):

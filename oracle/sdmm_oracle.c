@@ -26,7 +26,11 @@
  *   - the penalised log-likelihood that the MAP update maximises and its gradient;
  *   - product sampling of a conditioned radiance mixture with a conditioned BSDF mixture
  *     pruned to its two heaviest components (Sec. 3.4; Sec. 4.1 "Pruning before product
- *     sampling").
+ *     sampling");
+ *   - the spatial kD-tree: pre-subdivision, refinement of leaves with more than c
+ *     samples at the mean of the axis of largest variance, copies of the mixture into
+ *     new leaves, and initialisation of leaves that reached 16 samples (Sec. 4.2
+ *     "Refinement of the spatial kD-tree", Sec. 4.3 "Initialization").
  *
  * Readings where the paper is silent or garbled (each one is listed with its reason
  * in the design notes): the frame R_mu is the branchless orthonormal basis of Duff et
@@ -1237,6 +1241,276 @@ int orc_product_pdf(int32_t K, const double *pi, const double *mud, const double
             pdf_out[q * nd + t] = any ? product_density(2 * K, pairs, P, dirs + 3 * (q * nd + t)) : 0.0;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* spatial kD-tree: pre-subdivision, refinement, leaf initialisation          */
+/* (Sec. 4.2 "Refinement of the spatial kD-tree"; Sec. 4.3 "Initialization")  */
+/* ------------------------------------------------------------------------- */
+
+/* Tree arrays (caller-owned): per node axis (0..2, -1 for a leaf), split position,
+ * left child (the right child is left + 1) and leaf index (-1 for an inner node); per
+ * leaf its node, its box and whether its mixture is initialised; counts[0] = nodes,
+ * counts[1] = leaves. */
+typedef struct {
+    int32_t max_nodes, max_leaves;
+    int32_t *counts;
+    int32_t *axis, *left, *leaf;
+    double *split;
+    int32_t *leaf_node;
+    double *lo, *hi; /* [max_leaves][3] */
+    int32_t *init;
+} orc_tree;
+
+/* Pre-subdivision: `depth` rounds of splitting every leaf at the centre of x, then y,
+ * then z, giving 8^depth equal boxes. Nodes in breadth-first order (children of node n
+ * at 2n + 1, 2n + 2); leaves numbered left to right. No leaf is initialised. */
+int orc_tree_init(orc_tree *t, int32_t depth, const double lo[3], const double hi[3])
+{
+    const int levels = 3 * depth;
+    const int64_t n_leaves = (int64_t)1 << levels, n_nodes = 2 * n_leaves - 1;
+    if (depth < 0 || n_nodes > t->max_nodes || n_leaves > t->max_leaves) return -1;
+    double (*blo)[3] = malloc(sizeof(double[3]) * n_nodes), (*bhi)[3] = malloc(sizeof(double[3]) * n_nodes);
+    for (int d = 0; d < 3; ++d) {
+        blo[0][d] = lo[d];
+        bhi[0][d] = hi[d];
+    }
+    for (int64_t n = 0; n < n_nodes; ++n) {
+        int level = 0;
+        while (((int64_t)1 << (level + 1)) - 1 <= n) ++level;
+        if (level < levels) {
+            const int ax = level % 3;
+            const double mid = 0.5 * (blo[n][ax] + bhi[n][ax]);
+            t->axis[n] = ax;
+            t->split[n] = mid;
+            t->left[n] = (int32_t)(2 * n + 1);
+            t->leaf[n] = -1;
+            for (int c = 0; c < 2; ++c) {
+                const int64_t ch = 2 * n + 1 + c;
+                for (int d = 0; d < 3; ++d) {
+                    blo[ch][d] = blo[n][d];
+                    bhi[ch][d] = bhi[n][d];
+                }
+                if (c == 0) bhi[ch][ax] = mid;
+                else blo[ch][ax] = mid;
+            }
+        } else {
+            const int64_t l = n - (n_leaves - 1);
+            t->axis[n] = -1;
+            t->split[n] = 0.0;
+            t->left[n] = -1;
+            t->leaf[n] = (int32_t)l;
+            t->leaf_node[l] = (int32_t)n;
+            for (int d = 0; d < 3; ++d) {
+                t->lo[3 * l + d] = blo[n][d];
+                t->hi[3 * l + d] = bhi[n][d];
+            }
+            t->init[l] = 0;
+        }
+    }
+    t->counts[0] = (int32_t)n_nodes;
+    t->counts[1] = (int32_t)n_leaves;
+    free(blo);
+    free(bhi);
+    return 0;
+}
+
+/* the leaf containing position p: left where p[axis] < split, else right */
+static int32_t tree_locate(const orc_tree *t, const double p[3])
+{
+    int32_t n = 0;
+    while (t->axis[n] >= 0) n = (p[t->axis[n]] < t->split[n]) ? t->left[n] : t->left[n] + 1;
+    return t->leaf[n];
+}
+
+/* The initial mixture of a leaf from its box (the recipe of the synthetic inputs, which
+ * stands in for the k-means++ and surface-normal construction of the paper's App. B/C):
+ * n_dir = min(8, K) directions at the cube vertices (+-1, +-1, +-1)/sqrt(3) in the order
+ * x-sign, y-sign, z-sign (positive first), n_pos = ceil(K / n_dir) positions spread
+ * along the longest box side (two: centre -+ d/4; four: a 2x2 pattern at -+d/4 on the two
+ * longest sides; more: evenly at ((s + 1/2)/n_pos - 1/2) d), component k = s n_dir + v;
+ * directional variance 2 pi / 8, positional variance r^2 / chi2_3^-1(0.9) with
+ * r = 2 d / n_pos; weights 1/K. */
+void orc_init_leaf(int32_t K, const double lo[3], const double hi[3], double *pi, double *mud, double *mux,
+                   double *cov)
+{
+    const double chi2_3_inv_090 = 6.251388631170325;
+    const int n_dir = K < 8 ? K : 8;
+    const int n_pos = (K + n_dir - 1) / n_dir;
+    double size[3], centre[3], d = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        size[a] = hi[a] - lo[a];
+        centre[a] = lo[a] + 0.5 * size[a];
+        if (size[a] > d) d = size[a];
+    }
+    int order[3] = {0, 1, 2}; /* axes by decreasing size, stable */
+    for (int i = 1; i < 3; ++i)
+        for (int j = i; j > 0 && size[order[j]] > size[order[j - 1]]; --j) {
+            int tmp = order[j];
+            order[j] = order[j - 1];
+            order[j - 1] = tmp;
+        }
+    const double r = 2.0 * d / n_pos;
+    const double inv_sqrt3 = 1.0 / sqrt(3.0);
+    for (int k = 0; k < K; ++k) {
+        const int s = k / n_dir, v = k % n_dir;
+        double off[3] = {0.0, 0.0, 0.0};
+        if (n_pos == 2) {
+            off[order[0]] = (s == 0 ? -1.0 : 1.0) * d / 4.0;
+        } else if (n_pos == 4) {
+            off[order[0]] = (s % 2 == 0 ? -1.0 : 1.0) * d / 4.0;
+            off[order[1]] = (s / 2 == 0 ? -1.0 : 1.0) * d / 4.0;
+        } else if (n_pos > 1) {
+            off[order[0]] = ((s + 0.5) / n_pos - 0.5) * d;
+        }
+        for (int a = 0; a < 3; ++a) mux[3 * k + a] = centre[a] + off[a];
+        mud[3 * k + 0] = ((v >> 2) & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        mud[3 * k + 1] = ((v >> 1) & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        mud[3 * k + 2] = (v & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        for (int q = 0; q < 15; ++q) cov[15 * k + q] = 0.0;
+        cov[15 * k + TRI(0, 0)] = cov[15 * k + TRI(1, 1)] = 2.0 * ORC_PI / 8.0;
+        for (int a = 0; a < 3; ++a) cov[15 * k + TRI(2 + a, 2 + a)] = r * r / chi2_3_inv_090;
+        pi[k] = 1.0 / K;
+    }
+}
+
+/* Refinement with the samples of one rendering iteration (positions in rows 3..5 of the
+ * float32 [7][N] array), K-component mixtures and Robbins-Monro state per leaf:
+ *   rounds: every leaf (first round) or every leaf created in the previous round (later
+ *   rounds) with more than c samples is split along the axis of largest variance of its
+ *   sample positions (ties: lowest axis), at their mean along that axis, if that leaves
+ *   samples on both sides (some x < mean <= some other x); leaves split in increasing
+ *   leaf order; the left child keeps the parent's leaf index and the right child takes
+ *   the next new index; both get new nodes (left = the next free node); the parent's
+ *   mixture, Robbins-Monro state and initialisation flag are copied to the right child.
+ *   A split that would exceed the node or leaf capacity is not made (status bit 1).
+ *   Rounds repeat until no leaf splits.
+ *   Then every leaf with at least min_init samples whose mixture is not initialised gets
+ *   the initial mixture of its box and a zero Robbins-Monro state.
+ * Output: offsets[0..n_leaves] (samples per leaf, leaf order) and the samples reordered
+ * by leaf, stably (index order within a leaf). Means and variances are FP64 sums over
+ * the leaf's samples in index order. Returns the status bits, or -1 on bad arguments. */
+int orc_tree_refine(orc_tree *t, const float *smp, int64_t N, int32_t c, int32_t min_init, int32_t K, double *pi,
+                    double *mud, double *mux, double *cov, double *s0, double *s2, double *sw, int32_t *step,
+                    float *sorted, int64_t *offsets)
+{
+    if (c < 1 || K < 1 || K > ORC_KMAX) return -1;
+    int status = 0;
+    int32_t *leaf_of = malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+    int32_t *active = malloc(sizeof(int32_t) * t->max_leaves);
+    int32_t *next = malloc(sizeof(int32_t) * t->max_leaves);
+    int32_t n_active = t->counts[1];
+    for (int32_t l = 0; l < n_active; ++l) active[l] = l;
+    for (;;) {
+        for (int64_t i = 0; i < N; ++i) {
+            double p[3] = {smp[3 * N + i], smp[4 * N + i], smp[5 * N + i]};
+            leaf_of[i] = tree_locate(t, p);
+        }
+        int32_t n_next = 0;
+        for (int32_t a = 0; a < n_active; ++a) {
+            const int32_t l = active[a];
+            int64_t M = 0;
+            double s1[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, mn[3] = {INFINITY, INFINITY, INFINITY},
+                   mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t i = 0; i < N; ++i) {
+                if (leaf_of[i] != l) continue;
+                ++M;
+                for (int d = 0; d < 3; ++d) {
+                    const double x = smp[(3 + d) * N + i];
+                    s1[d] += x;
+                    sq[d] += x * x;
+                    if (x < mn[d]) mn[d] = x;
+                    if (x > mx[d]) mx[d] = x;
+                }
+            }
+            if (M <= c) continue;
+            int ax = 0;
+            double best = -1.0, var[3];
+            for (int d = 0; d < 3; ++d) {
+                const double mean = s1[d] / (double)M;
+                var[d] = sq[d] / (double)M - mean * mean;
+                if (var[d] > best) {
+                    best = var[d];
+                    ax = d;
+                }
+            }
+            const double split = s1[ax] / (double)M;
+            if (!(mn[ax] < split && split <= mx[ax])) continue; /* not splittable */
+            if (t->counts[0] + 2 > t->max_nodes || t->counts[1] + 1 > t->max_leaves) {
+                status |= 1;
+                continue;
+            }
+            const int32_t n = t->leaf_node[l];
+            const int32_t L = t->counts[0], r = t->counts[1];
+            t->axis[n] = ax;
+            t->split[n] = split;
+            t->left[n] = L;
+            t->leaf[n] = -1;
+            t->axis[L] = t->axis[L + 1] = -1;
+            t->left[L] = t->left[L + 1] = -1;
+            t->split[L] = t->split[L + 1] = 0.0;
+            t->leaf[L] = l;
+            t->leaf[L + 1] = r;
+            t->leaf_node[l] = L;
+            t->leaf_node[r] = L + 1;
+            for (int d = 0; d < 3; ++d) {
+                t->lo[3 * r + d] = t->lo[3 * l + d];
+                t->hi[3 * r + d] = t->hi[3 * l + d];
+            }
+            t->hi[3 * l + ax] = split;
+            t->lo[3 * r + ax] = split;
+            t->init[r] = t->init[l];
+            memcpy(pi + (int64_t)r * K, pi + (int64_t)l * K, sizeof(double) * K);
+            memcpy(mud + (int64_t)r * K * 3, mud + (int64_t)l * K * 3, sizeof(double) * 3 * K);
+            memcpy(mux + (int64_t)r * K * 3, mux + (int64_t)l * K * 3, sizeof(double) * 3 * K);
+            memcpy(cov + (int64_t)r * K * 15, cov + (int64_t)l * K * 15, sizeof(double) * 15 * K);
+            memcpy(s0 + (int64_t)r * K, s0 + (int64_t)l * K, sizeof(double) * K);
+            memcpy(s2 + (int64_t)r * K * 15, s2 + (int64_t)l * K * 15, sizeof(double) * 15 * K);
+            sw[r] = sw[l];
+            step[r] = step[l];
+            t->counts[0] += 2;
+            t->counts[1] += 1;
+            next[n_next++] = l;
+            next[n_next++] = r;
+        }
+        if (n_next == 0) break;
+        /* the next round looks at the children, in increasing leaf order */
+        for (int32_t i = 1; i < n_next; ++i)
+            for (int32_t j = i; j > 0 && next[j] < next[j - 1]; --j) {
+                int32_t tmp = next[j];
+                next[j] = next[j - 1];
+                next[j - 1] = tmp;
+            }
+        memcpy(active, next, sizeof(int32_t) * n_next);
+        n_active = n_next;
+    }
+    /* counts, offsets and the stable reordering */
+    const int32_t L = t->counts[1];
+    for (int32_t l = 0; l <= L; ++l) offsets[l] = 0;
+    for (int64_t i = 0; i < N; ++i) offsets[leaf_of[i] + 1] += 1;
+    for (int32_t l = 0; l < L; ++l) offsets[l + 1] += offsets[l];
+    int64_t *fill = malloc(sizeof(int64_t) * (L > 0 ? L : 1));
+    for (int32_t l = 0; l < L; ++l) fill[l] = offsets[l];
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t o = fill[leaf_of[i]]++;
+        for (int a = 0; a < 7; ++a) sorted[(int64_t)a * N + o] = smp[(int64_t)a * N + i];
+    }
+    /* initialisation of leaves that reached min_init samples */
+    for (int32_t l = 0; l < L; ++l) {
+        if (t->init[l] || offsets[l + 1] - offsets[l] < min_init) continue;
+        const int64_t g = (int64_t)l * K;
+        orc_init_leaf(K, t->lo + 3 * l, t->hi + 3 * l, pi + g, mud + 3 * g, mux + 3 * g, cov + 15 * g);
+        memset(s0 + g, 0, sizeof(double) * K);
+        memset(s2 + 15 * g, 0, sizeof(double) * 15 * K);
+        sw[l] = 0.0;
+        step[l] = 0;
+        t->init[l] = 1;
+    }
+    free(fill);
+    free(leaf_of);
+    free(active);
+    free(next);
+    return status;
 }
 
 /* ------------------------------------------------------------------------- */
