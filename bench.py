@@ -489,6 +489,69 @@ def bench_product(args, torch):
                          "kernel": "product_sample_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl}}
 
 
+def bench_tree(args, torch):
+    """One rendering iteration's tree work on the 16384-cell workload's samples (16.6M
+    positions): refine a depth-3 pre-subdivided tree (512 leaves) with the paper's
+    threshold c = 16000, initialise the leaves, reorder the samples by leaf; then one
+    batched E+M step on the leaves. Each timed step starts from a fresh pre-subdivided
+    tree (re-initialised before the step, outside the timed region)."""
+    from paper_2111_13094_amd import sdmm, synth
+    wl = synth.workload("cells16k")
+    smp_np = synth.workload_batch(wl).samples
+    dev = torch.device("cuda", 0)
+    smp = torch.from_numpy(smp_np).to(dev)
+    N, K, max_leaves, c = smp.shape[1], 16, 8192, 16000
+    t = sdmm.new_tree(max_leaves)
+    mix = {k: torch.zeros(max_leaves * K * n, dtype=torch.float64, device=dev)
+           for k, n in (("pi", 1), ("mu_dir", 3), ("mu_pos", 3), ("cov", 15))}
+    st = sdmm.new_state(max_leaves, K, dev)
+    ws = torch.empty(sdmm.lib().sdmm_tree_workspace_size(N, max_leaves), dtype=torch.uint8, device=dev)
+    opts = sdmm.default_opts(K)
+    import ctypes as C_
+    L_ = sdmm.lib()
+    tot, cnt = C_.c_double(), C_.c_int64()
+    refine_ms, fit_ms, leaves = [], [], 0
+    for s_ in range(args.warmup + args.steps):
+        if s_ == args.warmup:
+            L_.sdmm_timing_enable(1)
+            L_.sdmm_timing_read(6, C_.byref(tot), C_.byref(cnt), 1)
+        sdmm.tree_init(t, 3, [0, 0, 0], [1, 1, 1])
+        _sync(torch)
+        t0 = time.perf_counter()
+        srt, off, L, status = sdmm.tree_refine(t, smp, c, mix, st, K, workspace=ws)
+        _sync(torch)
+        t1 = time.perf_counter()
+        view = {k: v[:L * (v.numel() // max_leaves)] for k, v in mix.items()}
+        sview = {k: v[:L * (v.numel() // max_leaves)] for k, v in st.items()}
+        sdmm.fit_mixtures(off, srt, view, sview, opts)
+        _sync(torch)
+        t2 = time.perf_counter()
+        if s_ >= args.warmup:
+            refine_ms.append((t1 - t0) * 1e3)
+            fit_ms.append((t2 - t1) * 1e3)
+        leaves = L
+    L_.sdmm_timing_read(6, C_.byref(tot), C_.byref(cnt), 1)
+    L_.sdmm_timing_enable(0)
+    loc_ms = tot.value / max(cnt.value, 1)
+    # the first locate launch walks every sample from the root: it reads 12 B of position
+    # and writes the node and leaf index, 8 B, per sample
+    loc_bytes = 20.0 * N
+    achieved = loc_bytes / (loc_ms * 1e-3) / 1e9
+    r_ms, f_ms = float(np.mean(refine_ms)), float(np.mean(fit_ms))
+    return {"metric": "kD-tree refinement: samples/s (locate, split rounds, reorder by leaf, initialise), "
+                      "16.6M samples, c=16000",
+            "value": N / (r_ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r_ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "tree: the cells16k samples (32x32x16 grid counts, 16.6M) refined from a "
+                                   "depth-3 pre-subdivided tree (512 leaves) with c=16000, K=16; wall time of "
+                                   "the host call, which synchronises once per round",
+                       "samples": N, "leaves": leaves, "max_leaves": max_leaves, "fit_after_refine_ms": f_ms},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "locate_kernel (first round)",
+                         "kernel_ms": loc_ms, "bytes_per_launch": loc_bytes}}
+
+
 def bench_grad(args, torch):
     """Adjoint on the 4096-cell workload: the state after 8 stepwise batches, then the
     FP32 gradient pass (value + gradient of the penalised log-likelihood per cell) timed
@@ -635,7 +698,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single",
-                                                                    "accurate", "product"])
+                                                                    "accurate", "product", "tree"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
     ap.add_argument("--min-range", type=int, default=0, help="E-step item size floor (0: library default)")
     ap.add_argument("--max-ranges", type=int, default=0, help="E-step range count cap (0: library default)")
@@ -683,6 +746,8 @@ def main():
         out = bench_accurate(args, torch)
     elif args.workload == "product":
         out = bench_product(args, torch)
+    elif args.workload == "tree":
+        out = bench_tree(args, torch)
     else:
         out = bench_single(args, torch)
     print(json.dumps(out))

@@ -227,6 +227,68 @@ int sdmm_condition_sample_pdf(const float *table, int32_t n_cells, int32_t K, co
                               uint64_t seed, float *dirs_out, float *pdf_out, uint8_t *valid_out,
                               void *stream);
 
+/* ---- spatial kD-tree (Sec. 4.2 "Refinement of the spatial kD-tree"; Sec. 4.3
+ *      "Initialization") ---- */
+
+/* A kD-tree over positions whose leaves are the cells of the mixtures. Nodes: split axis
+ * (0..2) and position (a point with p[axis] < split goes left), left child (the right
+ * child is left + 1), and for a leaf node its leaf index. Leaves: their node, box and
+ * whether their mixture is initialised. All arrays [device], caller-owned; counts[0] is
+ * the number of nodes in use, counts[1] the number of leaves. */
+typedef struct sdmm_tree {
+    int32_t max_nodes;  /* capacity, at least 2 max_leaves - 1 */
+    int32_t max_leaves; /* capacity: the cells of the mixtures and state */
+    int32_t *counts;    /* int32[2] */
+    int32_t *axis;      /* int32[max_nodes]: split axis, -1 for a leaf */
+    int32_t *left;      /* int32[max_nodes]: left child, -1 for a leaf */
+    int32_t *leaf;      /* int32[max_nodes]: leaf index of a leaf node, -1 otherwise */
+    double *split;      /* float64[max_nodes]: split position */
+    int32_t *leaf_node; /* int32[max_leaves]: the node of each leaf */
+    double *lo, *hi;    /* float64[max_leaves][3]: leaf boxes */
+    int32_t *init;      /* int32[max_leaves]: 1 once the leaf's mixture is initialised */
+} sdmm_tree;
+
+/*
+ * sdmm_tree_init -- the pre-subdivision of Sec. 4.3: `depth` rounds (0..6) of splitting
+ * every leaf at the centre of x, then y, then z, giving 8^depth equal boxes of the box
+ * [lo, hi) (lo, hi [host] float64[3], lo < hi). Nodes are numbered breadth first
+ * (children of node n at 2n + 1 and 2n + 2), leaves left to right; no leaf is
+ * initialised. SDMM_EINVAL if the capacity is too small.
+ */
+int sdmm_tree_init(const sdmm_tree *tree, int32_t depth, const double *lo, const double *hi, void *stream);
+
+/* Bytes of device workspace sdmm_tree_refine needs. */
+size_t sdmm_tree_workspace_size(int64_t n_samples, int32_t max_leaves);
+
+/*
+ * sdmm_tree_refine -- adapts the tree to one iteration's samples and reorders them by
+ * leaf for sdmm_fit_mixtures (Sec. 4.2, 4.3):
+ *   rounds: every leaf (first round) or every leaf made in the previous round that holds
+ *   more than split_threshold samples (the paper's c = 16000) is split at the mean of its
+ *   sample positions along the axis of largest variance (lowest axis on ties), provided
+ *   samples fall on both sides; leaves split in increasing leaf order, the left child
+ *   keeping the parent's leaf index, the right child taking the next one; the new leaf
+ *   gets a copy of the parent's mixture, Robbins-Monro state and initialisation flag.
+ *   Splits beyond the node or leaf capacity are skipped (status bit 1). Rounds repeat
+ *   until none splits (at most 64).
+ *   Then every leaf with at least min_init samples (the paper's 16) whose mixture is not
+ *   initialised gets the initial mixture of its box: min(8, K) directions at the cube
+ *   vertices crossed with ceil(K / 8) positions along the longest sides, directional
+ *   variance 2 pi / 8, positional variance (2 d / n_pos)^2 / chi2_3^-1(0.9) with d the
+ *   longest side, weights 1/K; its Robbins-Monro state is zeroed.
+ * samples [device] float32[7][n_samples] (as sdmm_fit_mixtures; n_samples < 2^31);
+ * mix, state: [device] arrays for tree->max_leaves cells (mix->n_cells must equal it),
+ * updated in place; sorted_out [device] float32[7][n_samples]: the samples by leaf, in
+ * index order within a leaf; cell_offsets_out [device] int64[max_leaves + 1], of which
+ * the first n_leaves + 1 entries are written; n_leaves_out, status_out [host] int32
+ * (status_out may be NULL). The call synchronises the stream once per round. Means and
+ * variances are FP64 sums over each leaf's samples.
+ */
+int sdmm_tree_refine(const sdmm_tree *tree, const float *samples, int64_t n_samples, int32_t split_threshold,
+                     int32_t min_init, const sdmm_mixtures *mix, const sdmm_em_state *state,
+                     float *sorted_out, int64_t *cell_offsets_out, int32_t *n_leaves_out,
+                     int32_t *status_out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* ---- product sampling with a conditioned BSDF mixture ---- */
 
 /*
@@ -353,6 +415,8 @@ int sdmm_grad_to_params(int32_t n_cells, int32_t K, const double *L, const doubl
 #define SDMM_TIMER_GRAD 3    /* the adjoint pass of sdmm_fit_grad */
 #define SDMM_TIMER_ACCURATE 4 /* the second E-step pass of SDMM_FLAG_ACCURATE_SIGMA */
 #define SDMM_TIMER_PRODUCT 5  /* sdmm_product_sample */
+#define SDMM_TIMER_TREE 6     /* the first point-location launch of sdmm_tree_refine (every
+                                 sample walked from the root) */
 
 /* Enables (1) or disables (0) HIP-event timing: while enabled, every eager launch of
  * the kernel classes above is bracketed by a pair of events recorded on its stream

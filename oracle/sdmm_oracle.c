@@ -1399,6 +1399,9 @@ int orc_tree_refine(orc_tree *t, const float *smp, int64_t N, int32_t c, int32_t
     int32_t *leaf_of = malloc(sizeof(int32_t) * (N > 0 ? N : 1));
     int32_t *active = malloc(sizeof(int32_t) * t->max_leaves);
     int32_t *next = malloc(sizeof(int32_t) * t->max_leaves);
+    int64_t *cnt = malloc(sizeof(int64_t) * t->max_leaves);
+    double *s1a = malloc(sizeof(double) * 3 * t->max_leaves), *sqa = malloc(sizeof(double) * 3 * t->max_leaves);
+    double *mna = malloc(sizeof(double) * 3 * t->max_leaves), *mxa = malloc(sizeof(double) * 3 * t->max_leaves);
     int32_t n_active = t->counts[1];
     for (int32_t l = 0; l < n_active; ++l) active[l] = l;
     for (;;) {
@@ -1406,23 +1409,32 @@ int orc_tree_refine(orc_tree *t, const float *smp, int64_t N, int32_t c, int32_t
             double p[3] = {smp[3 * N + i], smp[4 * N + i], smp[5 * N + i]};
             leaf_of[i] = tree_locate(t, p);
         }
+        /* per-leaf count, sums, minima and maxima of the positions, in index order */
+        const int32_t L0 = t->counts[1];
+        for (int32_t l = 0; l < L0; ++l) {
+            cnt[l] = 0;
+            for (int d = 0; d < 3; ++d) {
+                s1a[3 * l + d] = sqa[3 * l + d] = 0.0;
+                mna[3 * l + d] = INFINITY;
+                mxa[3 * l + d] = -INFINITY;
+            }
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            const int32_t l = leaf_of[i];
+            cnt[l] += 1;
+            for (int d = 0; d < 3; ++d) {
+                const double x = smp[(3 + d) * N + i];
+                s1a[3 * l + d] += x;
+                sqa[3 * l + d] += x * x;
+                if (x < mna[3 * l + d]) mna[3 * l + d] = x;
+                if (x > mxa[3 * l + d]) mxa[3 * l + d] = x;
+            }
+        }
         int32_t n_next = 0;
         for (int32_t a = 0; a < n_active; ++a) {
             const int32_t l = active[a];
-            int64_t M = 0;
-            double s1[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, mn[3] = {INFINITY, INFINITY, INFINITY},
-                   mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int64_t i = 0; i < N; ++i) {
-                if (leaf_of[i] != l) continue;
-                ++M;
-                for (int d = 0; d < 3; ++d) {
-                    const double x = smp[(3 + d) * N + i];
-                    s1[d] += x;
-                    sq[d] += x * x;
-                    if (x < mn[d]) mn[d] = x;
-                    if (x > mx[d]) mx[d] = x;
-                }
-            }
+            const int64_t M = cnt[l];
+            const double *s1 = s1a + 3 * l, *sq = sqa + 3 * l, *mn = mna + 3 * l, *mx = mxa + 3 * l;
             if (M <= c) continue;
             int ax = 0;
             double best = -1.0, var[3];
@@ -1510,6 +1522,11 @@ int orc_tree_refine(orc_tree *t, const float *smp, int64_t N, int32_t c, int32_t
     free(leaf_of);
     free(active);
     free(next);
+    free(cnt);
+    free(s1a);
+    free(sqa);
+    free(mna);
+    free(mxa);
     return status;
 }
 

@@ -1,0 +1,699 @@
+// tree.hip -- the spatial kD-tree on gfx950: pre-subdivision, refinement of leaves with
+// many samples, copies of the parent mixture into new leaves, leaf initialisation, and
+// the reordering of the samples by leaf that the batched fit consumes (Dodik et al.,
+// arXiv 2111.13094, Sec. 4.2 "Refinement of the spatial kD-tree", Sec. 4.3
+// "Initialization").
+//
+// Refinement runs in rounds. Each round: every sample is located in the current tree
+// (one thread per sample); a stable LSD radix sort by leaf index gives a permutation
+// with each leaf's samples contiguous and in index order; each leaf of the round with
+// more than c samples gets its FP64 position sums, minima and maxima from one wave
+// (fixed reduction order); one work group decides the splits in leaf order (a block
+// prefix sum numbers the new nodes and leaves); new leaves get copies of their parent's
+// mixture and Robbins-Monro state. The host reads the number of splits after each round
+// and stops when a round makes none; the last round's sort is the final order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "timing.hpp"
+
+namespace sdmm {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;                       // keys per thread per block
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
+constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
+constexpr int kMaxRounds = 64;
+
+struct TreePtrs {
+    int32_t max_nodes, max_leaves;
+    int32_t *counts, *axis, *left, *leaf;
+    double* split;
+    int32_t* leaf_node;
+    double *lo, *hi;
+    int32_t* init;
+};
+
+// ---------------------------------------------------------------------------------
+// pre-subdivision: node n of the complete tree (children 2n + 1, 2n + 2); its path from
+// the root is the binary expansion of n + 1 after the leading one (0 = left)
+// ---------------------------------------------------------------------------------
+__global__ void tree_init_kernel(TreePtrs t, int levels, double lo0, double lo1, double lo2, double hi0, double hi1,
+                                 double hi2)
+{
+    const int64_t n_leaves = int64_t(1) << levels, n_nodes = 2 * n_leaves - 1;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    int level = 0;
+    while ((int64_t(1) << (level + 1)) - 1 <= n) ++level;
+    double blo[3] = {lo0, lo1, lo2}, bhi[3] = {hi0, hi1, hi2};
+    const uint64_t path = (uint64_t)(n + 1);
+    for (int l = 0; l < level; ++l) {  // walk down from the root
+        const int ax = l % 3;
+        const double mid = 0.5 * (blo[ax] + bhi[ax]);
+        const int right = (int)((path >> (level - 1 - l)) & 1);
+        if (right) blo[ax] = mid;
+        else bhi[ax] = mid;
+    }
+    if (level < levels) {
+        const int ax = level % 3;
+        t.axis[n] = ax;
+        t.split[n] = 0.5 * (blo[ax] + bhi[ax]);
+        t.left[n] = (int32_t)(2 * n + 1);
+        t.leaf[n] = -1;
+    } else {
+        const int64_t l = n - (n_leaves - 1);
+        t.axis[n] = -1;
+        t.split[n] = 0.0;
+        t.left[n] = -1;
+        t.leaf[n] = (int32_t)l;
+        t.leaf_node[l] = (int32_t)n;
+        for (int d = 0; d < 3; ++d) {
+            t.lo[3 * l + d] = blo[d];
+            t.hi[3 * l + d] = bhi[d];
+        }
+        t.init[l] = 0;
+    }
+    if (n == 0) {
+        t.counts[0] = (int32_t)n_nodes;
+        t.counts[1] = (int32_t)n_leaves;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// point location: left where p[axis] < split, else right; child indices exceed their
+// parent's, so the walk ends within max_nodes steps. After the first round a sample
+// resumes from the node it reached in the previous round (node_of), which is still its
+// leaf unless that leaf was split; its position is read only when it has to move.
+// ---------------------------------------------------------------------------------
+__global__ void locate_kernel(TreePtrs t, const float* __restrict__ smp, int64_t N, int from_root,
+                              int32_t* __restrict__ node_of, int32_t* __restrict__ leaf_of)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t n = from_root ? 0 : node_of[i];
+    if (t.axis[n] >= 0) {
+        const double p[3] = {(double)smp[3 * N + i], (double)smp[4 * N + i], (double)smp[5 * N + i]};
+        for (int32_t s = 0; s < t.max_nodes && t.axis[n] >= 0; ++s)
+            n = (p[t.axis[n]] < t.split[n]) ? t.left[n] : t.left[n] + 1;
+    }
+    node_of[i] = n;
+    leaf_of[i] = t.leaf[n];
+}
+
+// ---------------------------------------------------------------------------------
+// stable LSD radix sort of (leaf index, sample index) by leaf index, 8 bits per pass
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const int32_t* __restrict__ keys, int64_t N,
+                                                                  int shift, int32_t* __restrict__ hist, int B)
+{
+    __shared__ int32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    // lanes with equal digits (found by 8 ballots) add their count once: the keys of a
+    // tile are mostly equal when the samples arrive grouped, and LDS atomics on one
+    // address serialise
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = base + (int64_t)it * kSortThreads + threadIdx.x;
+        const bool valid = i < N;
+        const int digit = valid ? (keys[i] >> shift) & (kRadix - 1) : 0;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const uint64_t m = __ballot((digit >> b) & 1);
+            peers &= ((digit >> b) & 1) ? m : ~m;
+        }
+        if (valid && (peers & lt) == 0) atomicAdd(&h[digit], __popcll(peers));
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * B + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive prefix sum of n int32 counts in three launches: tile sums (kScanTile
+// entries per work group), an exclusive scan of the tile sums by one work group, and the
+// scan of each tile from its base.
+constexpr int kScanPer = 16;
+constexpr int kScanTile = 256 * kScanPer;
+
+__device__ __forceinline__ int32_t block_exclusive_scan_256(int32_t v, int32_t& total)
+{
+    __shared__ int32_t wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t before = 0;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void scan_tile_sums_kernel(const int32_t* __restrict__ v, int64_t n,
+                                                             int32_t* __restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q)
+        if (base + q < n) s += v[base + q];
+    int32_t total;
+    (void)block_exclusive_scan_256(s, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int32_t* __restrict__ v, int64_t n)
+{
+    __shared__ int64_t part[1024];
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a = min(n, (int64_t)threadIdx.x * chunk), b = min(n, a + chunk);
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += v[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan of the partial sums
+        const int64_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t c = v[i];
+        v[i] = (int32_t)run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(int32_t* __restrict__ v, int64_t n,
+                                                         const int32_t* __restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t x[kScanPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        x[q] = base + q < n ? v[base + q] : 0;
+        s += x[q];
+    }
+    int32_t total;
+    int32_t run = sums[blockIdx.x] + block_exclusive_scan_256(s, total);
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < n) v[base + q] = run;
+        run += x[q];
+    }
+}
+
+// Each block scatters its tile in index order: per 256-key step, a key's rank among the
+// equal digits of its wave comes from 8 ballots, the waves of the block are ordered by
+// per-wave digit counts in LDS, and a running base per digit carries over the steps.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const int32_t* __restrict__ kin,
+                                                                     const int32_t* __restrict__ vin, int64_t N,
+                                                                     int shift, const int32_t* __restrict__ hist,
+                                                                     int B, int32_t* __restrict__ kout,
+                                                                     int32_t* __restrict__ vout)
+{
+    constexpr int W = kSortThreads / 64;
+    __shared__ int32_t base[kRadix];
+    __shared__ int32_t wcount[W][kRadix];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base[tid] = hist[(int64_t)tid * B + blockIdx.x];
+    for (int q = 0; q < W; ++q) wcount[q][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + tid;
+        const bool valid = i < N;
+        const int32_t key = valid ? kin[i] : 0;
+        const int32_t val = valid ? (vin ? vin[i] : (int32_t)i) : 0;
+        const int digit = (key >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const uint64_t m = __ballot((digit >> b) & 1);
+            peers &= ((digit >> b) & 1) ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcount[w][digit] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int32_t before = base[digit];
+            for (int q = 0; q < w; ++q) before += wcount[q][digit];
+            const int64_t dst = (int64_t)before + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        int32_t tot = 0;
+        for (int q = 0; q < W; ++q) {
+            tot += wcount[q][tid];
+            wcount[q][tid] = 0;
+        }
+        base[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// off[l] = first sorted position of leaf l (off[L] = N), for leaves 0..L
+__global__ void segment_kernel(const int32_t* __restrict__ keys, int64_t N, int32_t L, int64_t* __restrict__ off)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (N == 0) {
+        if (i <= L) off[i] = 0;
+        return;
+    }
+    if (i >= N) return;
+    const int32_t k = keys[i], kp = i > 0 ? keys[i - 1] : -1;
+    for (int32_t l = kp + 1; l <= k; ++l) off[l] = i;
+    if (i == N - 1)
+        for (int32_t l = k + 1; l <= L; ++l) off[l] = N;
+}
+
+// ---------------------------------------------------------------------------------
+// split statistics: one work group of 256 threads per leaf of the round with more than c
+// samples; FP64 sums reduced in a fixed order (lanes by butterfly, then the four waves)
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void split_stats_kernel(const float* __restrict__ smp, int64_t N,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int64_t* __restrict__ off, int32_t L, int32_t c,
+                                                          const int32_t* __restrict__ act, int32_t* __restrict__ want,
+                                                          int32_t* __restrict__ sax, double* __restrict__ spos)
+{
+    __shared__ double ls1[4][3], lsq[4][3];
+    __shared__ float lmn[4][3], lmx[4][3];
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (l >= L) return;
+    const int64_t a = off[l], b = off[l + 1], M = b - a;
+    if (!act[l] || M <= c) {
+        if (threadIdx.x == 0) want[l] = 0;
+        return;
+    }
+    double s1[3] = {0, 0, 0}, sq[3] = {0, 0, 0};
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t j = a + threadIdx.x; j < b; j += 256) {
+        const int32_t i = perm[j];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float xf = smp[(3 + d) * N + i];
+            const double x = (double)xf;
+            s1[d] += x;
+            sq[d] += x * x;
+            mn[d] = fminf(mn[d], xf);
+            mx[d] = fmaxf(mx[d], xf);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s1[d] += __shfl_xor(s1[d], o);
+            sq[d] += __shfl_xor(sq[d], o);
+            mn[d] = fminf(mn[d], __shfl_xor(mn[d], o));
+            mx[d] = fmaxf(mx[d], __shfl_xor(mx[d], o));
+        }
+    }
+    if (lane == 0)
+        for (int d = 0; d < 3; ++d) {
+            ls1[w][d] = s1[d];
+            lsq[w][d] = sq[d];
+            lmn[w][d] = mn[d];
+            lmx[w][d] = mx[d];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) {
+            s1[d] = ((ls1[0][d] + ls1[1][d]) + ls1[2][d]) + ls1[3][d];
+            sq[d] = ((lsq[0][d] + lsq[1][d]) + lsq[2][d]) + lsq[3][d];
+            mn[d] = fminf(fminf(lmn[0][d], lmn[1][d]), fminf(lmn[2][d], lmn[3][d]));
+            mx[d] = fmaxf(fmaxf(lmx[0][d], lmx[1][d]), fmaxf(lmx[2][d], lmx[3][d]));
+        }
+        const double Md = (double)M;
+        int ax = 0;
+        double best = -1.0;
+        for (int d = 0; d < 3; ++d) {
+            const double mean = s1[d] / Md;
+            const double var = sq[d] / Md - mean * mean;
+            if (var > best) {
+                best = var;
+                ax = d;
+            }
+        }
+        const double split = s1[ax] / Md;
+        want[l] = ((double)mn[ax] < split && split <= (double)mx[ax]) ? 1 : 0;
+        sax[l] = ax;
+        spos[l] = split;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// split decisions in leaf order by one work group; ctl[0] = splits made, ctl[1] |= 1
+// when the capacity stopped some
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void split_decide_kernel(TreePtrs t, int32_t L, const int32_t* __restrict__ want,
+                                                            const int32_t* __restrict__ sax,
+                                                            const double* __restrict__ spos,
+                                                            int32_t* __restrict__ act,
+                                                            int32_t* __restrict__ parent_of, int32_t* __restrict__ ctl)
+{
+    __shared__ int32_t part[1024];
+    const int32_t nodes = t.counts[0], leaves = t.counts[1];
+    const int32_t chunk = (L + 1023) / 1024;
+    const int32_t a = min(L, (int32_t)threadIdx.x * chunk), b = min(L, a + chunk);
+    int32_t s = 0;
+    for (int32_t l = a; l < b; ++l) s += want[l];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int32_t total = part[1023];
+    const int32_t cap = min((t.max_nodes - nodes) / 2, t.max_leaves - leaves);
+    const int32_t n_split = min(total, max(cap, 0));
+    int32_t rank = part[threadIdx.x] - s;
+    for (int32_t l = a; l < b; ++l) {
+        const bool go = want[l] && rank < n_split;
+        if (want[l]) ++rank;
+        if (!go) {
+            act[l] = 0;
+            continue;
+        }
+        const int32_t rk = rank - 1;
+        const int32_t r = leaves + rk, Ln = nodes + 2 * rk;
+        const int32_t n = t.leaf_node[l];
+        const int ax = sax[l];
+        const double sp = spos[l];
+        t.axis[n] = ax;
+        t.split[n] = sp;
+        t.left[n] = Ln;
+        t.leaf[n] = -1;
+        for (int q = 0; q < 2; ++q) {
+            t.axis[Ln + q] = -1;
+            t.left[Ln + q] = -1;
+            t.split[Ln + q] = 0.0;
+        }
+        t.leaf[Ln] = l;
+        t.leaf[Ln + 1] = r;
+        t.leaf_node[l] = Ln;
+        t.leaf_node[r] = Ln + 1;
+        for (int d = 0; d < 3; ++d) {
+            t.lo[3 * r + d] = t.lo[3 * l + d];
+            t.hi[3 * r + d] = t.hi[3 * l + d];
+        }
+        t.hi[3 * l + ax] = sp;
+        t.lo[3 * r + ax] = sp;
+        t.init[r] = t.init[l];
+        parent_of[rk] = l;
+        act[l] = 1;
+        act[r] = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        t.counts[0] = nodes + 2 * n_split;
+        t.counts[1] = leaves + n_split;
+        ctl[0] = n_split;
+        ctl[1] |= total > n_split ? 1 : 0;
+    }
+}
+
+// the new leaf r = leaves_before + rank copies its parent's mixture and state
+__global__ void copy_leaves_kernel(int32_t leaves_before, int32_t n_split, const int32_t* __restrict__ parent_of,
+                                   int K, MixPtrs mix, StatePtrs st)
+{
+    const int rk = blockIdx.x;
+    if (rk >= n_split) return;
+    const int64_t r = leaves_before + rk, l = parent_of[rk];
+    for (int q = threadIdx.x; q < 38 * K + 2; q += blockDim.x) {
+        if (q < K) mix.pi[r * K + q] = mix.pi[l * K + q];
+        else if (q < 4 * K) mix.mud[r * 3 * K + q - K] = mix.mud[l * 3 * K + q - K];
+        else if (q < 7 * K) mix.mux[r * 3 * K + q - 4 * K] = mix.mux[l * 3 * K + q - 4 * K];
+        else if (q < 22 * K) mix.cov[r * 15 * K + q - 7 * K] = mix.cov[l * 15 * K + q - 7 * K];
+        else if (q < 23 * K) st.s0[r * K + q - 22 * K] = st.s0[l * K + q - 22 * K];
+        else if (q < 38 * K) st.s2[r * 15 * K + q - 23 * K] = st.s2[l * 15 * K + q - 23 * K];
+        else if (q == 38 * K) st.sw[r] = st.sw[l];
+        else st.step[r] = st.step[l];
+    }
+}
+
+__global__ void set_active_kernel(int32_t* __restrict__ act, int32_t L, int32_t* __restrict__ ctl)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L) act[l] = 1;
+    if (l == 0) ctl[0] = ctl[1] = 0;
+}
+
+__global__ void gather_kernel(const float* __restrict__ smp, int64_t N, const int32_t* __restrict__ perm,
+                              float* __restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int32_t i = perm[j];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) out[a * N + j] = smp[a * N + i];
+}
+
+// Initial mixture of an uninitialised leaf with at least min_init samples, one thread
+// per component: n_dir = min(8, K) directions at the cube vertices (signs of x, y, z,
+// positive first), n_pos = ceil(K / n_dir) positions along the longest sides (two:
+// centre -+ d/4; four: a 2x2 pattern; more: evenly), directional variance 2 pi / 8,
+// positional variance r^2 / chi2_3^-1(0.9) with r = 2 d / n_pos, weights 1/K; the
+// Robbins-Monro state starts at zero.
+__global__ void init_leaves_kernel(TreePtrs t, int32_t L, const int64_t* __restrict__ off, int32_t min_init, int K,
+                                   MixPtrs mix, StatePtrs st)
+{
+    const int l = blockIdx.x;
+    if (l >= L || t.init[l] || off[l + 1] - off[l] < min_init) return;
+    const double chi2_3_inv_090 = 6.251388631170325;
+    const int n_dir = K < 8 ? K : 8;
+    const int n_pos = (K + n_dir - 1) / n_dir;
+    double size[3], centre[3], d = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        size[a] = t.hi[3 * l + a] - t.lo[3 * l + a];
+        centre[a] = t.lo[3 * l + a] + 0.5 * size[a];
+        d = fmax(d, size[a]);
+    }
+    int order[3] = {0, 1, 2};
+    for (int i = 1; i < 3; ++i)
+        for (int j = i; j > 0 && size[order[j]] > size[order[j - 1]]; --j) {
+            const int tmp = order[j];
+            order[j] = order[j - 1];
+            order[j - 1] = tmp;
+        }
+    const double r = 2.0 * d / n_pos;
+    const double inv_sqrt3 = 1.0 / sqrt(3.0);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const int s = k / n_dir, v = k % n_dir;
+        double o[3] = {0.0, 0.0, 0.0};
+        if (n_pos == 2) {
+            o[order[0]] = (s == 0 ? -1.0 : 1.0) * d / 4.0;
+        } else if (n_pos == 4) {
+            o[order[0]] = (s % 2 == 0 ? -1.0 : 1.0) * d / 4.0;
+            o[order[1]] = (s / 2 == 0 ? -1.0 : 1.0) * d / 4.0;
+        } else if (n_pos > 1) {
+            o[order[0]] = ((s + 0.5) / n_pos - 0.5) * d;
+        }
+        const int64_t g = (int64_t)l * K + k;
+        for (int a = 0; a < 3; ++a) mix.mux[3 * g + a] = centre[a] + o[a];
+        mix.mud[3 * g + 0] = ((v >> 2) & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        mix.mud[3 * g + 1] = ((v >> 1) & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        mix.mud[3 * g + 2] = (v & 1 ? -1.0 : 1.0) * inv_sqrt3;
+        for (int q = 0; q < 15; ++q) mix.cov[15 * g + q] = 0.0;
+        mix.cov[15 * g + tri(0, 0)] = mix.cov[15 * g + tri(1, 1)] = 2.0 * kPi / 8.0;
+        for (int a = 0; a < 3; ++a) mix.cov[15 * g + tri(2 + a, 2 + a)] = r * r / chi2_3_inv_090;
+        mix.pi[g] = 1.0 / K;
+        st.s0[g] = 0.0;
+        for (int q = 0; q < 15; ++q) st.s2[15 * g + q] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st.sw[l] = 0.0;
+        st.step[l] = 0;
+        t.init[l] = 1;
+    }
+}
+
+// workspace of a refinement
+struct TreeLayout {
+    size_t nodeof, keys0, keys1, vals0, vals1, hist, tsum, off, act, want, sax, spos, parent, ctl, total;
+    int B;
+};
+
+inline TreeLayout tree_layout(int64_t N, int32_t max_leaves)
+{
+    TreeLayout L{};
+    const int64_t n = N > 0 ? N : 1;
+    L.B = (int)((n + kSortTile - 1) / kSortTile);
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p = align256(p + bytes);
+        return at;
+    };
+    L.nodeof = take(n * 4);
+    L.keys0 = take(n * 4);
+    L.keys1 = take(n * 4);
+    L.vals0 = take(n * 4);
+    L.vals1 = take(n * 4);
+    L.hist = take((size_t)kRadix * L.B * 4);
+    L.tsum = take(((size_t)kRadix * L.B + kScanTile - 1) / kScanTile * 4);
+    L.off = take(((size_t)max_leaves + 1) * 8);
+    L.act = take((size_t)max_leaves * 4);
+    L.want = take((size_t)max_leaves * 4);
+    L.sax = take((size_t)max_leaves * 4);
+    L.spos = take((size_t)max_leaves * 8);
+    L.parent = take((size_t)max_leaves * 4);
+    L.ctl = take(4 * 4);
+    L.total = p;
+    return L;
+}
+
+static TreePtrs tree_ptrs(const sdmm_tree* t)
+{
+    return TreePtrs{t->max_nodes, t->max_leaves, t->counts, t->axis, t->left, t->leaf, t->split,
+                    t->leaf_node, t->lo, t->hi, t->init};
+}
+
+static bool tree_ok(const sdmm_tree* t)
+{
+    return t && t->max_leaves >= 1 && t->max_nodes >= 2 * t->max_leaves - 1 && t->counts && t->axis && t->left &&
+           t->leaf && t->split && t->leaf_node && t->lo && t->hi && t->init;
+}
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+}  // namespace sdmm
+
+using namespace sdmm;
+
+extern "C" int sdmm_tree_init(const sdmm_tree* tree, int32_t depth, const double* lo, const double* hi, void* stream)
+{
+    if (!tree_ok(tree) || !lo || !hi || depth < 0 || depth > 6) return SDMM_EINVAL;
+    const int levels = 3 * depth;
+    const int64_t n_leaves = int64_t(1) << levels, n_nodes = 2 * n_leaves - 1;
+    if (n_leaves > tree->max_leaves || n_nodes > tree->max_nodes) return SDMM_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!(lo[d] < hi[d])) return SDMM_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    tree_init_kernel<<<blocks_for(n_nodes, 256), 256, 0, s>>>(tree_ptrs(tree), levels, lo[0], lo[1], lo[2], hi[0],
+                                                             hi[1], hi[2]);
+    return check(hipGetLastError());
+}
+
+extern "C" size_t sdmm_tree_workspace_size(int64_t n_samples, int32_t max_leaves)
+{
+    if (n_samples < 0 || max_leaves < 1) return 0;
+    return tree_layout(n_samples, max_leaves).total;
+}
+
+extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int64_t n_samples,
+                                int32_t split_threshold, int32_t min_init, const sdmm_mixtures* mix,
+                                const sdmm_em_state* state, float* sorted_out, int64_t* cell_offsets_out,
+                                int32_t* n_leaves_out, int32_t* status_out, void* workspace,
+                                size_t workspace_bytes, void* stream)
+{
+    if (!tree_ok(tree) || n_samples < 0 || (n_samples > 0 && (!samples || !sorted_out)) || split_threshold < 1 ||
+        min_init < 0 || !mix || !state || !cell_offsets_out || !n_leaves_out || !workspace)
+        return SDMM_EINVAL;
+    if (n_samples > INT32_MAX) return SDMM_EINVAL;  // sample indices are int32
+    if (mix->n_cells != tree->max_leaves || mix->K < 1 || mix->K > kMaxK || !mix->weights || !mix->mean_dir ||
+        !mix->mean_pos || !mix->cov || !state->s0 || !state->s2 || !state->sw || !state->step)
+        return SDMM_EINVAL;
+    const int64_t N = n_samples;
+    const TreeLayout TL = tree_layout(N, tree->max_leaves);
+    if (workspace_bytes < TL.total) return SDMM_ENOWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    int32_t* nodeof = reinterpret_cast<int32_t*>(ws + TL.nodeof);
+    int32_t* k0 = reinterpret_cast<int32_t*>(ws + TL.keys0);
+    int32_t* k1 = reinterpret_cast<int32_t*>(ws + TL.keys1);
+    int32_t* v0 = reinterpret_cast<int32_t*>(ws + TL.vals0);
+    int32_t* v1 = reinterpret_cast<int32_t*>(ws + TL.vals1);
+    int32_t* hist = reinterpret_cast<int32_t*>(ws + TL.hist);
+    int32_t* tsum = reinterpret_cast<int32_t*>(ws + TL.tsum);
+    int64_t* off = reinterpret_cast<int64_t*>(ws + TL.off);
+    int32_t* act = reinterpret_cast<int32_t*>(ws + TL.act);
+    int32_t* want = reinterpret_cast<int32_t*>(ws + TL.want);
+    int32_t* sax = reinterpret_cast<int32_t*>(ws + TL.sax);
+    double* spos = reinterpret_cast<double*>(ws + TL.spos);
+    int32_t* parent = reinterpret_cast<int32_t*>(ws + TL.parent);
+    int32_t* ctl = reinterpret_cast<int32_t*>(ws + TL.ctl);
+    const TreePtrs tp = tree_ptrs(tree);
+    const MixPtrs mp{mix->weights, mix->mean_dir, mix->mean_pos, mix->cov};
+    const StatePtrs sp{state->s0, state->s2, state->sw, state->step};
+    const int K = mix->K;
+    int rc;
+
+    int32_t counts[2];
+    if ((rc = check(hipMemcpyAsync(counts, tree->counts, sizeof(counts), hipMemcpyDeviceToHost, s)))) return rc;
+    if ((rc = check(hipStreamSynchronize(s)))) return rc;
+    int32_t L = counts[1];
+    if (L < 1 || L > tree->max_leaves || counts[0] > tree->max_nodes) return SDMM_EINVAL;
+    set_active_kernel<<<blocks_for(L, 256), 256, 0, s>>>(act, L, ctl);
+
+    const int32_t* sorted_vals = v0;
+    for (int round = 0;; ++round) {
+        // locate, sort by leaf, segments
+        if (round == 0) {  // the full location of every sample from the root is timed
+            ScopedTimer tm(SDMM_TIMER_TREE, s);
+            locate_kernel<<<blocks_for(N, 256), 256, 0, s>>>(tp, samples, N, 1, nodeof, k0);
+        } else {
+            locate_kernel<<<blocks_for(N, 256), 256, 0, s>>>(tp, samples, N, 0, nodeof, k0);
+        }
+        int bits = 1;
+        while ((int64_t(1) << bits) < L) ++bits;
+        const int passes = (bits + kRadixBits - 1) / kRadixBits;
+        const int32_t *kin = k0, *vin = nullptr;
+        int32_t *kout = k1, *vout = v1;
+        for (int p = 0; p < passes && N > 0; ++p) {
+            radix_hist_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, N, p * kRadixBits, hist, TL.B);
+            const int64_t nh = (int64_t)kRadix * TL.B;
+            const unsigned nt = (unsigned)((nh + kScanTile - 1) / kScanTile);
+            scan_tile_sums_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+            scan_sums_kernel<<<1, 1024, 0, s>>>(tsum, nt);
+            scan_apply_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+            radix_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, vin, N, p * kRadixBits, hist, TL.B, kout, vout);
+            kin = kout;
+            vin = vout;
+            kout = (kout == k1) ? k0 : k1;
+            vout = (vout == v1) ? v0 : v1;
+        }
+        sorted_vals = vin;
+        segment_kernel<<<blocks_for(std::max<int64_t>(N, (int64_t)L + 1), 256), 256, 0, s>>>(kin, N, L, off);
+        if (round == kMaxRounds) break;
+        // statistics and decisions
+        split_stats_kernel<<<L, 256, 0, s>>>(samples, N, vin, off, L, split_threshold, act, want, sax, spos);
+        split_decide_kernel<<<1, 1024, 0, s>>>(tp, L, want, sax, spos, act, parent, ctl);
+        int32_t c2[2];
+        if ((rc = check(hipMemcpyAsync(c2, ctl, sizeof(c2), hipMemcpyDeviceToHost, s)))) return rc;
+        if ((rc = check(hipStreamSynchronize(s)))) return rc;
+        if (c2[0] == 0) break;
+        copy_leaves_kernel<<<c2[0], 64, 0, s>>>(L, c2[0], parent, K, mp, sp);
+        L += c2[0];
+    }
+    if (N > 0) gather_kernel<<<blocks_for(N, 256), 256, 0, s>>>(samples, N, sorted_vals, sorted_out);
+    if ((rc = check(hipMemcpyAsync(cell_offsets_out, off, ((size_t)L + 1) * 8, hipMemcpyDeviceToDevice, s))))
+        return rc;
+    init_leaves_kernel<<<L, 64, 0, s>>>(tp, L, off, min_init, K, mp, sp);
+    int32_t c2[2];
+    if ((rc = check(hipMemcpyAsync(c2, ctl, sizeof(c2), hipMemcpyDeviceToHost, s)))) return rc;
+    if ((rc = check(hipStreamSynchronize(s)))) return rc;
+    *n_leaves_out = L;
+    if (status_out) *status_out = c2[1];
+    return check(hipGetLastError());
+}

@@ -27,6 +27,12 @@ SCHED_BATCHED, SCHED_PER_CELL, SCHED_FUSED = 0, 1, 2
 COND_TABLE_STRIDE = 32
 
 
+class Tree(C.Structure):
+    _fields_ = [("max_nodes", C.c_int32), ("max_leaves", C.c_int32), ("counts", C.c_void_p), ("axis", C.c_void_p),
+                ("left", C.c_void_p), ("leaf", C.c_void_p), ("split", C.c_void_p), ("leaf_node", C.c_void_p),
+                ("lo", C.c_void_p), ("hi", C.c_void_p), ("init", C.c_void_p)]
+
+
 class FitOpts(C.Structure):
     _fields_ = [
         ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
@@ -72,6 +78,11 @@ def lib():
         L.sdmm_product_sample.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, i64, i32, vp, u64, vp, vp,
                                           vp, vp, vp]
         L.sdmm_product_pdf.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, i64, i32, vp, vp, vp]
+        L.sdmm_tree_init.argtypes = [P(Tree), i32, vp, vp, vp]
+        L.sdmm_tree_workspace_size.argtypes = [i64, i32]
+        L.sdmm_tree_workspace_size.restype = sz
+        L.sdmm_tree_refine.argtypes = [P(Tree), vp, i64, i32, i32, P(Mixtures), P(EmState), vp, vp, vp, vp, vp, sz,
+                                       vp]
         L.sdmm_fit_grad.argtypes = [vp, vp, i64, P(Mixtures), P(FitOpts), vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.sdmm_mixture_from_params.argtypes = [i32, i32, vp, vp, vp, vp, vp, P(Mixtures), vp, vp]
         L.sdmm_grad_to_params.argtypes = [i32, i32, vp, vp, vp, vp, vp]
@@ -288,6 +299,56 @@ def product_pdf(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell,
                                   _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
                                   nq, nd, _ptr(dirs, torch.float32), _ptr(out), _stream(stream)), "sdmm_product_pdf")
     return out
+
+
+def new_tree(max_leaves, device="cuda"):
+    """Device arrays of a kD-tree with room for max_leaves leaves (a dict of tensors)."""
+    n = 2 * max_leaves - 1
+    i32 = dict(dtype=torch.int32, device=device)
+    f64 = dict(dtype=torch.float64, device=device)
+    return {"counts": torch.zeros(2, **i32), "axis": torch.full((n,), -1, **i32), "left": torch.full((n,), -1, **i32),
+            "leaf": torch.full((n,), -1, **i32), "split": torch.zeros(n, **f64),
+            "leaf_node": torch.full((max_leaves,), -1, **i32), "lo": torch.zeros(max_leaves, 3, **f64),
+            "hi": torch.zeros(max_leaves, 3, **f64), "init": torch.zeros(max_leaves, **i32),
+            "max_leaves": max_leaves, "max_nodes": n}
+
+
+def _tree(t: dict) -> Tree:
+    return Tree(t["max_nodes"], t["max_leaves"], _ptr(t["counts"], torch.int32), _ptr(t["axis"], torch.int32),
+                _ptr(t["left"], torch.int32), _ptr(t["leaf"], torch.int32), _ptr(t["split"], torch.float64),
+                _ptr(t["leaf_node"], torch.int32), _ptr(t["lo"], torch.float64), _ptr(t["hi"], torch.float64),
+                _ptr(t["init"], torch.int32))
+
+
+def tree_init(t: dict, depth, lo, hi, stream=None):
+    lo_ = (C.c_double * 3)(*[float(v) for v in lo])
+    hi_ = (C.c_double * 3)(*[float(v) for v in hi])
+    tt = _tree(t)
+    _check(lib().sdmm_tree_init(C.byref(tt), depth, lo_, hi_, _stream(stream)), "sdmm_tree_init")
+
+
+def tree_refine(t: dict, samples, split_threshold, mix: dict, state: dict, K, min_init=16, workspace=None,
+                stream=None):
+    """Refines the tree with samples float32 [7, N]; mix / state hold max_leaves cells.
+    Returns (sorted samples [7, N], cell offsets int64 [n_leaves + 1], n_leaves, status)."""
+    N = samples.shape[1]
+    dev = samples.device
+    sorted_ = torch.empty_like(samples)
+    offsets = torch.empty(t["max_leaves"] + 1, dtype=torch.int64, device=dev)
+    nbytes = lib().sdmm_tree_workspace_size(N, t["max_leaves"])
+    if workspace is None:
+        workspace = _workspace(nbytes, dev)
+    m = _mixtures(mix, t["max_leaves"], K)
+    st = EmState()
+    st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
+    st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
+    nl, status = C.c_int32(0), C.c_int32(0)
+    tt = _tree(t)
+    _check(lib().sdmm_tree_refine(C.byref(tt), _ptr(samples, torch.float32), N, split_threshold, min_init, C.byref(m),
+                                  C.byref(st), _ptr(sorted_), _ptr(offsets, torch.int64), C.byref(nl),
+                                  C.byref(status), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "sdmm_tree_refine")
+    return sorted_, offsets[:nl.value + 1], nl.value, status.value
 
 
 def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=None):

@@ -77,16 +77,18 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [("sdmm_fit_opts", f) for f, _ in sdmm.FitOpts._fields_] + \
              [("sdmm_mixtures", f) for f, _ in sdmm.Mixtures._fields_] + \
-             [("sdmm_em_state", f) for f, _ in sdmm.EmState._fields_]
+             [("sdmm_em_state", f) for f, _ in sdmm.EmState._fields_] + \
+             [("sdmm_tree", f) for f, _ in sdmm.Tree._fields_]
     body = "".join(f'printf("%s.%s %zu\\n", offsetof({t}, {f}));\n'.replace("%s.%s", f"{t}.{f}") for t, f in fields)
-    body += "".join(f'printf("{t} %zu\\n", sizeof({t}));\n' for t in ("sdmm_fit_opts", "sdmm_mixtures", "sdmm_em_state"))
+    body += "".join(f'printf("{t} %zu\\n", sizeof({t}));\n' for t in ("sdmm_fit_opts", "sdmm_mixtures", "sdmm_em_state",
+                                                                     "sdmm_tree"))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sdmm.h"\nint main(void) {\n' + body + "return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
                                                        text=True).stdout.splitlines())
     for cls, name in ((sdmm.FitOpts, "sdmm_fit_opts"), (sdmm.Mixtures, "sdmm_mixtures"),
-                      (sdmm.EmState, "sdmm_em_state")):
+                      (sdmm.EmState, "sdmm_em_state"), (sdmm.Tree, "sdmm_tree")):
         assert int(got[name]) == C.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
