@@ -183,6 +183,23 @@ def fit(opts: Opts, offsets, samples, mix: dict, state: dict) -> np.ndarray:
     return status
 
 
+def fit_stepwise(opts: Opts, offsets, samples, mix: dict, state: dict) -> np.ndarray:
+    """Stepwise (per-sample) EM on one batch; arguments as fit()."""
+    L = lib()
+    L.orc_fit_stepwise.argtypes = L.orc_fit.argtypes
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    samples = np.ascontiguousarray(samples, dtype=np.float32)
+    n_cells = offsets.shape[0] - 1
+    status = np.zeros(n_cells, dtype=np.int32)
+    o = opts.to_c()
+    rc = L.orc_fit_stepwise(C.byref(o), n_cells, _p(offsets), _p(samples), samples.shape[1],
+                            _p(mix["pi"]), _p(mix["mu_dir"]), _p(mix["mu_pos"]), _p(mix["cov"]),
+                            _p(state["s0"]), _p(state["s2"]), _p(state["sw"]), _p(state["step"]), _p(status))
+    if rc != 0:
+        raise ValueError("orc_fit_stepwise failed (%d)" % rc)
+    return status
+
+
 def _cell_params(mix, c, K):
     s = slice(c * K, (c + 1) * K)
     return (_f64(mix["pi"][s]), _f64(mix["mu_dir"].reshape(-1, 3)[s]), _f64(mix["mu_pos"].reshape(-1, 3)[s]),

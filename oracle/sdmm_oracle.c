@@ -593,6 +593,59 @@ static int accurate_sigma_pass(const orc_opts *o, int K, const float *smp, int64
     return status;
 }
 
+/* One E+M step of one cell on its samples [i0, i1): gate, statistics, M-step (and the
+ * accurate covariance pass when asked for). Returns the status bits; stops the cell
+ * (*stop = 1) when it is gated or its statistics are not finite. */
+static int cell_batch_step(const orc_opts *o, int K, const float *smp, int64_t N, int64_t i0, int64_t i1,
+                           double *pi, double *mud, double *mux, double *cov, double *s0, double *s2, double *sw,
+                           int32_t *step, int *stop)
+{
+    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
+    double cov0[ORC_KMAX * 15];
+    int64_t M;
+    double W, LL;
+    *stop = 0;
+    int g = gate(o, K, smp, N, i0, i1, pi, mud, mux, cov, &M, &W);
+    if (g) {
+        *stop = 1;
+        return g;
+    }
+    orc_cell_stats(o, K, smp, N, i0, i1, pi, mud, mux, cov, S0, S1, S2, &W, &M, &LL);
+    /* statistics that are not finite (e.g. every component has zero weight) leave the cell
+     * untouched and are reported like bad input */
+    int finite = isfinite(W);
+    for (int t = 0; t < K && finite; ++t) {
+        finite = isfinite(S0[t]);
+        for (int d = 0; d < 5; ++d) finite = finite && isfinite(S1[5 * t + d]);
+        for (int d = 0; d < 15; ++d) finite = finite && isfinite(S2[15 * t + d]);
+    }
+    if (!finite) {
+        *stop = 1;
+        return ORC_BAD_INPUT;
+    }
+    if (o->accurate_sigma) memcpy(cov0, cov, sizeof(double) * 15 * K);
+    int ms = cell_mstep(o, K, M, W, S0, S1, S2, pi, mud, mux, cov, s0, s2, sw, step);
+    if (o->accurate_sigma) {
+        /* the first-order covariance of the M-step is replaced by the second pass, and so
+         * is its SPD verdict */
+        ms &= ~ORC_CHOL_FAIL_KEPT_PREV;
+        ms |= accurate_sigma_pass(o, K, smp, N, i0, i1, S0, W, M, pi, mud, mux, cov0, cov, s0, s2);
+    }
+    return ms;
+}
+
+/* the offsets must partition a prefix of the sample array: non-decreasing, from >= 0 to
+ * <= N. An array that is not is rejected as a whole: every cell reports bad input and
+ * nothing changes (a decreasing entry says the batch itself is malformed). */
+static int offsets_valid(int32_t n_cells, const int64_t *offsets, int64_t N, int32_t *status)
+{
+    int ok = n_cells == 0 || (offsets[0] >= 0 && offsets[n_cells] <= N);
+    for (int32_t c = 0; c < n_cells && ok; ++c) ok = offsets[c + 1] >= offsets[c];
+    if (!ok)
+        for (int32_t c = 0; c < n_cells; ++c) status[c] = ORC_BAD_INPUT;
+    return ok;
+}
+
 /* Fit: o->iters E+M iterations of every cell on the given batch. Parameters and the
  * averaged statistics are updated in place; status[c] receives the OR of the cell's
  * status bits over the iterations. */
@@ -604,54 +657,77 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
     if (K < 1 || K > ORC_KMAX) return -1;
     /* the accurate covariance update is defined for batch steps */
     if (o->accurate_sigma && !(o->eta_mode == 0 && o->eta == 1.0)) return -2;
-    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
-    double cov0[ORC_KMAX * 15];
-    /* the offsets must partition a prefix of the sample array: non-decreasing, from >= 0
-     * to <= N. An array that is not is rejected as a whole: every cell reports bad input
-     * and nothing changes (a decreasing entry says the batch itself is malformed). */
-    int offsets_ok = n_cells == 0 || (offsets[0] >= 0 && offsets[n_cells] <= N);
-    for (int32_t c = 0; c < n_cells && offsets_ok; ++c) offsets_ok = offsets[c + 1] >= offsets[c];
-    if (!offsets_ok) {
-        for (int32_t c = 0; c < n_cells; ++c) status[c] = ORC_BAD_INPUT;
-        return 0;
-    }
+    if (!offsets_valid(n_cells, offsets, N, status)) return 0;
     for (int32_t c = 0; c < n_cells; ++c) {
-        const int64_t i0 = offsets[c], i1 = offsets[c + 1];
         const int64_t ck = (int64_t)c * K;
         status[c] = 0;
         for (int it = 0; it < o->iters; ++it) {
+            int stop;
+            status[c] |= cell_batch_step(o, K, smp, N, offsets[c], offsets[c + 1], pi + ck, mud + 3 * ck,
+                                         mux + 3 * ck, cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c,
+                                         &stop);
+            if (stop) break;
+        }
+    }
+    return 0;
+}
+
+/* Stepwise EM, the per-sample alternative of Sec. 6 ("Mini-batch EM versus stepwise EM";
+ * Cappe and Moulines 2009, weighted as in Vorba et al. 2014): each sample with positive
+ * weight, in index order, is a mini-batch of one. Its statistics are taken under the
+ * current parameters, blended with eta_j for the cell's sample counter j, and the MAP
+ * M-step follows with M = 1 (so beta_j = eta_j unless fixed), including the first-order
+ * transport of the carried second moment into the new frame. A cell whose state is fresh
+ * (step 0) first takes one mini-batch step over its samples: the blend needs statistics
+ * to start from. The cell gate applies to the whole batch before each pass; o->iters
+ * passes over the samples. The accurate covariance update is not defined here (-2). */
+int orc_fit_stepwise(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const float *smp, int64_t N,
+                     double *pi, double *mud, double *mux, double *cov, double *s0, double *s2, double *sw,
+                     int32_t *step, int32_t *status)
+{
+    const int K = o->K;
+    if (K < 1 || K > ORC_KMAX) return -1;
+    if (o->accurate_sigma) return -2;
+    if (!offsets_valid(n_cells, offsets, N, status)) return 0;
+    double S0[ORC_KMAX], S1[ORC_KMAX * 5], S2[ORC_KMAX * 15];
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const int64_t i0 = offsets[c], i1 = offsets[c + 1];
+        const int64_t ck = (int64_t)c * K;
+        double *P = pi + ck, *D = mud + 3 * ck, *X = mux + 3 * ck, *V = cov + 15 * ck;
+        status[c] = 0;
+        for (int it = 0; it < o->iters; ++it) {
+            int stop = 0;
+            if (step[c] == 0) {
+                status[c] |= cell_batch_step(o, K, smp, N, i0, i1, P, D, X, V, s0 + ck, s2 + 15 * ck, sw + c,
+                                             step + c, &stop);
+                if (stop) break;
+                continue;
+            }
             int64_t M;
             double W, LL;
-            int g = gate(o, K, smp, N, i0, i1, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck, &M, &W);
+            int g = gate(o, K, smp, N, i0, i1, P, D, X, V, &M, &W);
             if (g) {
                 status[c] |= g;
                 break;
             }
-            orc_cell_stats(o, K, smp, N, i0, i1, pi + ck, mud + 3 * ck, mux + 3 * ck, cov + 15 * ck,
-                           S0, S1, S2, &W, &M, &LL);
-            /* statistics that are not finite (e.g. every component has zero weight) leave
-             * the cell untouched and are reported like bad input */
-            int finite = isfinite(W);
-            for (int t = 0; t < K && finite; ++t) {
-                finite = isfinite(S0[t]);
-                for (int d = 0; d < 5; ++d) finite = finite && isfinite(S1[5 * t + d]);
-                for (int d = 0; d < 15; ++d) finite = finite && isfinite(S2[15 * t + d]);
+            for (int64_t i = i0; i < i1 && !stop; ++i) {
+                if (!(smp[6 * N + i] > 0.0f)) continue;
+                orc_cell_stats(o, K, smp, N, i, i + 1, P, D, X, V, S0, S1, S2, &W, &M, &LL);
+                int finite = isfinite(W);
+                for (int t = 0; t < K && finite; ++t) {
+                    finite = isfinite(S0[t]);
+                    for (int d = 0; d < 5; ++d) finite = finite && isfinite(S1[5 * t + d]);
+                    for (int d = 0; d < 15; ++d) finite = finite && isfinite(S2[15 * t + d]);
+                }
+                if (!finite) {
+                    status[c] |= ORC_BAD_INPUT;
+                    stop = 1;
+                    break;
+                }
+                status[c] |= cell_mstep(o, K, 1, W, S0, S1, S2, P, D, X, V, s0 + ck, s2 + 15 * ck, sw + c,
+                                        step + c);
             }
-            if (!finite) {
-                status[c] |= ORC_BAD_INPUT;
-                break;
-            }
-            if (o->accurate_sigma) memcpy(cov0, cov + 15 * ck, sizeof(double) * 15 * K);
-            int ms = cell_mstep(o, K, M, W, S0, S1, S2, pi + ck, mud + 3 * ck, mux + 3 * ck,
-                                cov + 15 * ck, s0 + ck, s2 + 15 * ck, sw + c, step + c);
-            if (o->accurate_sigma) {
-                /* the first-order covariance of the M-step is replaced by the second pass,
-                 * and so is its SPD verdict */
-                ms &= ~ORC_CHOL_FAIL_KEPT_PREV;
-                ms |= accurate_sigma_pass(o, K, smp, N, i0, i1, S0, W, M, pi + ck, mud + 3 * ck, mux + 3 * ck,
-                                          cov0, cov + 15 * ck, s0 + ck, s2 + 15 * ck);
-            }
-            status[c] |= ms;
+            if (stop) break;
         }
     }
     return 0;

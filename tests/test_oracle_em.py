@@ -635,3 +635,78 @@ def test_covariance_updates_naive_first_order_accurate(orc):
         assert e_first < e_naive / 5, (delta, e_first, e_naive)
         errs.append((e_naive, e_first))
     assert errs[0][0] < errs[1][0] < errs[2][0] and errs[0][1] < errs[1][1] < errs[2][1]
+
+
+# --- P13 stepwise (per-sample) EM --------------------------------------------------------
+
+def test_stepwise_single_component_is_the_exponentially_weighted_estimate(orc):
+    """K = 1 in Euclidean coordinates with a constant eta: after the warm-start batch step
+    the per-sample recursion must equal the exponentially weighted mean and covariance
+    written out directly: the batch samples weigh (1 - eta)^j w_i, and the sample taken
+    at step i weighs eta (1 - eta)^(j - i) w_i; Sigma = (beta B + C / W^) / (beta a + 1)
+    with beta = eta (a mini-batch of one) and W^ the same weights' total."""
+    rng = np.random.default_rng(31)
+    n, eta = 300, 0.05
+    X = rng.normal(size=(n, 5)) * np.array([0.3, 0.2, 1.0, 0.5, 0.7]) + 1.0
+    w = np.exp(rng.normal(size=n)).astype(np.float32).astype(np.float64)
+    w[rng.random(n) < 0.1] = 0.0
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:2] = X[:, 0:2].T
+    smp[3:6] = X[:, 2:5].T
+    smp[6] = w
+    X = np.concatenate([smp[0:2].T, smp[3:6].T], 1).astype(np.float64)
+    mix = {"pi": np.ones(1), "mu_dir": np.array([0.0, 0.0, 0.0]), "mu_pos": np.zeros(3),
+           "cov": _pack(np.eye(5))}
+    opts = orc.Opts(K=1, eta=eta, euclidean=1, min_samples=1)
+    o = opts.to_c()
+    st = orc.new_state(1, 1)
+    assert orc.fit_stepwise(opts, np.array([0, n]), smp, mix, st)[0] == 0  # warm start: a batch step
+    assert st["step"][0] == 1
+    assert orc.fit_stepwise(opts, np.array([0, n]), smp, mix, st)[0] == 0  # one per-sample pass
+    pos = np.nonzero(w > 0)[0]
+    j = pos.size
+    assert st["step"][0] == 1 + j
+    lam = np.concatenate([w * (1 - eta) ** j, w[pos] * eta * (1 - eta) ** (j - 1 - np.arange(j))])
+    Y = np.concatenate([X, X[pos]])
+    mean = (lam[:, None] * Y).sum(0) / lam.sum()
+    D = Y - mean
+    Cw = (lam[:, None] * D).T @ D / lam.sum()
+    Sig = (eta * np.diag(o.prior_b) + Cw) / (eta * o.prior_a + 1.0)
+    got_mu = np.concatenate([mix["mu_dir"][:2], mix["mu_pos"]])
+    assert np.allclose(got_mu, mean, rtol=1e-11, atol=1e-12)
+    assert np.allclose(_unpack(mix["cov"]), Sig, rtol=1e-9, atol=1e-14)
+    assert st["sw"][0] == pytest.approx(lam.sum(), rel=1e-12)
+
+
+def test_stepwise_fresh_cells_take_a_batch_step(orc):
+    b, mix = _single_cell(1024)
+    opts = orc.Opts(K=16, eta=0.1)
+    m1, s1, st1 = _fit_copy(orc, opts, b.offsets, b.samples, mix)
+    m2 = synth.copy_mix(mix)
+    s2 = orc.new_state(1, 16)
+    st2 = orc.fit_stepwise(opts, b.offsets, b.samples, m2, s2)
+    assert np.array_equal(st1, st2)
+    for k in m1:
+        assert np.array_equal(m1[k], m2[k]), k
+
+
+def test_stepwise_skips_zero_weight_samples(orc):
+    b, mix = _single_cell(512, zero_frac=0.3)
+    opts = orc.Opts(K=16, eta_mode=1)
+    m1, s1 = synth.copy_mix(mix), orc.new_state(1, 16)
+    orc.fit_stepwise(opts, b.offsets, b.samples, m1, s1)
+    orc.fit_stepwise(opts, b.offsets, b.samples, m1, s1)
+    keep = b.samples[6] > 0
+    smp = np.ascontiguousarray(b.samples[:, keep])
+    m2, s2 = synth.copy_mix(mix), orc.new_state(1, 16)
+    orc.fit_stepwise(opts, np.array([0, smp.shape[1]]), smp, m2, s2)
+    orc.fit_stepwise(opts, np.array([0, smp.shape[1]]), smp, m2, s2)
+    for k in m1:
+        assert np.array_equal(m1[k], m2[k]), k
+    assert s1["step"][0] == s2["step"][0] == 1 + keep.sum()
+
+
+def test_stepwise_rejects_the_accurate_update(orc):
+    b, mix = _single_cell(64)
+    with pytest.raises(ValueError):
+        orc.fit_stepwise(orc.Opts(K=16, accurate_sigma=1), b.offsets, b.samples, mix, orc.new_state(1, 16))
