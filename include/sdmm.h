@@ -84,6 +84,13 @@ extern "C" {
                                  cell_offsets to the host and synchronises the stream */
 #define SDMM_SCHED_FUSED 2    /* one E+M launch per iteration: the last wave to finish a
                                  cell's E-step items runs that cell's M-step */
+#define SDMM_SCHED_STEPWISE 3 /* stepwise EM (Sec. 6, "Mini-batch EM versus stepwise EM"):
+                                 each sample with positive weight, in index order, is a
+                                 mini-batch of one (blend with eta_j for the cell's sample
+                                 counter j, MAP M-step with M = 1, transport of the carried
+                                 S2); a fresh cell (step 0) first takes one batch step over
+                                 its samples. One wave per cell, FP64 throughout (the
+                                 precision flags have no effect); iters passes. */
 
 typedef struct sdmm_fit_opts {
     int32_t K;           /* components per cell, 1..64 */
@@ -417,6 +424,7 @@ int sdmm_grad_to_params(int32_t n_cells, int32_t K, const double *L, const doubl
 #define SDMM_TIMER_PRODUCT 5  /* sdmm_product_sample */
 #define SDMM_TIMER_TREE 6     /* the first point-location launch of sdmm_tree_refine (every
                                  sample walked from the root) */
+#define SDMM_TIMER_STEPWISE 7 /* the stepwise-EM kernel of SDMM_SCHED_STEPWISE */
 
 /* Enables (1) or disables (0) HIP-event timing: while enabled, every eager launch of
  * the kernel classes above is bracketed by a pair of events recorded on its stream

@@ -147,6 +147,11 @@ enum TreePass { kTreeFit = 0, kTreeGrad = 1 };
 void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
                  int64_t c1, char* ws, hipStream_t s);
 
+// stepwise EM of every cell (one wave per cell), after launch_setup
+void launch_stepwise(const int64_t* off, const float* smp, int64_t N, const sdmm_mixtures& mix,
+                     const sdmm_em_state& st, const sdmm_fit_opts& opts, int32_t* status, const Layout& L, char* ws,
+                     hipStream_t s);
+
 // E-step over the items in record slots [slot_lo, slot_hi), one wave per slot
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
                   int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s);

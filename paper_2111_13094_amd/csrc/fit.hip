@@ -26,6 +26,7 @@
 
 #include "common.hpp"
 #include "estep.hpp"
+#include "mstep_math.hpp"
 #include "timing.hpp"
 
 namespace sdmm {
@@ -235,7 +236,7 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     const bool run = cell_ok && !gate;
 
     const int j = run ? st.step[c] : 0;
-    const double eta = j == 0 ? 1.0 : (o.eta_mode == 0 ? o.eta : pow(o.rm_beta * j + 1.0, -o.rm_alpha));
+    const double eta = rm_eta(o, j);
     const double beta = o.prior_mode == 0 ? eta / fmax(Mc, 1.0) : o.prior_scale;
     const double hW = j == 0 ? W : (1.0 - eta) * (run ? st.sw[c] : 0.0) + eta * W;
     const int64_t g = (int64_t)c * K + kk;
@@ -251,68 +252,9 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
 
     int dead = 0, cholfail = 0;
     if (run && act) {
-        const double mu[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
-        if (!(bar0 > o.dead_threshold)) {
-            dead = 1;
-            st.s0[g] = hS0;
-            for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = hS2[q];
-        } else {
-            double m[5];
-            const double inv0 = 1.0 / hS0;
-            for (int d = 0; d < 5; ++d) m[d] = hS1[d] * inv0;
-            double Ro[9], Rn[9], mun[3];
-            frame64(mu, Ro);
-            exp_map64(Ro, m[0], m[1], mun);
-            const double inn = 1.0 / sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
-            for (int i = 0; i < 3; ++i) mun[i] *= inn;
-            for (int i = 0; i < 3; ++i) {
-                mix.mud[3 * g + i] = mun[i];
-                mix.mux[3 * g + i] += m[2 + i];
-            }
-            st.s0[g] = hS0;
-            if (!accurate) {  // with the accurate update the second pass forms the covariance
-                frame64(mun, Rn);
-                double J[4];
-                transfer_jac64(Ro, Rn, m[0], m[1], J);
-                // scatter about the new mean in the old frame, then T C T^T with T = blkdiag(J, I3)
-                double Cm[5][5];
-                for (int d = 0; d < 5; ++d)
-                    for (int e = 0; e <= d; ++e) {
-                        const double v = hS2[tri(d, e)] - hS1[d] * hS1[e] * inv0;
-                        Cm[d][e] = v;
-                        Cm[e][d] = v;
-                    }
-                double Tt[5][5];
-                for (int b = 0; b < 5; ++b) {  // rows 0,1: J * C
-                    const double r0 = J[0] * Cm[0][b] + J[1] * Cm[1][b];
-                    const double r1 = J[2] * Cm[0][b] + J[3] * Cm[1][b];
-                    Tt[0][b] = r0;
-                    Tt[1][b] = r1;
-                    for (int a = 2; a < 5; ++a) Tt[a][b] = Cm[a][b];
-                }
-                for (int a = 0; a < 5; ++a) {  // columns 0,1: (J C) J^T
-                    const double c0 = Tt[a][0] * J[0] + Tt[a][1] * J[1];
-                    const double c1 = Tt[a][0] * J[2] + Tt[a][1] * J[3];
-                    Tt[a][0] = c0;
-                    Tt[a][1] = c1;
-                }
-                double Sig[15], Lt[15];
-                const double iden = 1.0 / (beta * o.prior_a + bar0), ihW = 1.0 / hW;
-                for (int d = 0; d < 5; ++d)
-                    for (int e = 0; e <= d; ++e) {
-                        double v = 0.5 * (Tt[d][e] + Tt[e][d]) * ihW;
-                        if (d == e) v += beta * o.prior_b[d];
-                        Sig[tri(d, e)] = v * iden;
-                    }
-                if (chol64<5>(Sig, Lt)) {
-                    for (int q = 0; q < 15; ++q) mix.cov[g * 15 + q] = Sig[q];
-                } else {
-                    cholfail = 1;
-                }
-                for (int d = 0; d < 5; ++d)
-                    for (int e = 0; e <= d; ++e) st.s2[g * 15 + tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
-            }
-        }
+        // with the accurate update the second pass forms the covariance
+        component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, mix.mud + 3 * g, mix.mux + 3 * g,
+                             mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
         mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
     const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
@@ -652,6 +594,10 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
     };
 
     launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s);
+    if (a.opts.schedule == SDMM_SCHED_STEPWISE) {
+        launch_stepwise(a.off, a.smp, a.N, a.mix, a.st, a.opts, a.status, L, a.ws, s);
+        return check(hipGetLastError());
+    }
     for (int it = 0; it < a.opts.iters; ++it) {
         const int refresh = it + 1 < a.opts.iters;
         // with the accurate update the first M-step always writes mirrors (for the second
@@ -755,11 +701,13 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
     if (rc) return rc;
     if (!state || !state->s0 || !state->s2 || !state->sw || !state->step) return SDMM_EINVAL;
     if (opts->schedule != SDMM_SCHED_BATCHED && opts->schedule != SDMM_SCHED_PER_CELL &&
-        opts->schedule != SDMM_SCHED_FUSED)
+        opts->schedule != SDMM_SCHED_FUSED && opts->schedule != SDMM_SCHED_STEPWISE)
         return SDMM_EINVAL;
-    // the accurate covariance update is defined for batch steps and has no fused form
+    // the accurate covariance update is defined for batch steps and has no fused or
+    // stepwise form
     if ((opts->flags & SDMM_FLAG_ACCURATE_SIGMA) &&
-        (opts->eta_mode != SDMM_ETA_CONSTANT || opts->eta != 1.0 || opts->schedule == SDMM_SCHED_FUSED))
+        (opts->eta_mode != SDMM_ETA_CONSTANT || opts->eta != 1.0 || opts->schedule == SDMM_SCHED_FUSED ||
+         opts->schedule == SDMM_SCHED_STEPWISE))
         return SDMM_EINVAL;
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

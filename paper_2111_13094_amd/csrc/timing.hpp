@@ -5,7 +5,7 @@
 
 namespace sdmm {
 
-constexpr int kTimerClasses = 7;  // SDMM_TIMER_* in sdmm.h
+constexpr int kTimerClasses = 8;  // SDMM_TIMER_* in sdmm.h
 
 bool timing_enabled();
 void timing_begin(int cls, hipStream_t s, void** token);

@@ -23,7 +23,7 @@ SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD
 ETA_CONSTANT, ETA_PAPER = 0, 1
 PRIOR_ETA_OVER_M, PRIOR_FIXED = 0, 1
 FLAG_ESTEP_JACOBIAN, FLAG_PLAIN_FP32, FLAG_FP64_SUMS, FLAG_ACCURATE_SIGMA = 1, 2, 4, 8
-SCHED_BATCHED, SCHED_PER_CELL, SCHED_FUSED = 0, 1, 2
+SCHED_BATCHED, SCHED_PER_CELL, SCHED_FUSED, SCHED_STEPWISE = 0, 1, 2, 3
 COND_TABLE_STRIDE = 32
 
 

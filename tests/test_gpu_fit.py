@@ -460,3 +460,99 @@ def test_accurate_sigma_argument_checks(dev, orc):
     gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
     with pytest.raises(RuntimeError, match="invalid argument"):
         _gpu_fit(dev, b, gm, gst, flags=16)
+
+
+# --- stepwise (per-sample) EM ---------------------------------------------------------
+
+def _stepwise_pair(dev, orc, b, mix0, C, K=16, calls=2, gopt=None, oopt=None):
+    """calls x (GPU stepwise, oracle stepwise) on the same batch from the same start."""
+    from paper_2111_13094_amd import sdmm
+    gopt = dict(gopt or {})
+    oopt = dict(oopt or {})
+    om, ost = synth.copy_mix(mix0), orc.new_state(C, K)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, K))
+    for _ in range(calls):
+        s_o = orc.fit_stepwise(_orc_opts(orc, K=K, **oopt), b.offsets, b.samples, om, ost)
+        s_g = _gpu_fit(dev, b, gm, gst, K=K, schedule=sdmm.SCHED_STEPWISE, **gopt)
+        assert (s_g == s_o).all(), (np.nonzero(s_g != s_o), s_g[s_g != s_o], s_o[s_g != s_o])
+    return gm, gst, om, ost, s_o
+
+
+def test_stepwise_parity_single_cell(dev, orc):
+    """A batch step (fresh cell) and then one per-sample pass over 4096 samples, FP64 on
+    both sides in the same sample order: the chain stays within 1e-10 (measured 3e-15;
+    the sides differ only in the order of the lane reductions and in FP64 contraction)."""
+    print("case: stepwise EM, one cell, 4096 samples, batch step then per-sample pass", flush=True)
+    wl, b = _single(n=4096, seed=71)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    gm, gst, om, ost, _ = _stepwise_pair(dev, orc, b, mix0, 1, gopt=dict(eta_mode=1), oopt=dict(eta_mode=1))
+    worst = compare_mixtures(to_numpy(gm), om, 16)
+    print(worst)
+    assert_close(worst, rtol=1e-10, ang_tol=1e-10, what="stepwise")
+    g = to_numpy(gst)
+    assert g["step"][0] == ost["step"][0] == 1 + (b.samples[6] > 0).sum()
+    assert abs(g["sw"][0] - ost["sw"][0]) <= 1e-10 * ost["sw"][0]
+
+
+@pytest.mark.parametrize("variant", ["ragged", "jacobian", "constant_eta"])
+def test_stepwise_variants(dev, orc, variant):
+    print(f"case: stepwise EM, {variant}", flush=True)
+    if variant == "ragged":
+        wl, b, mix0 = _ragged_case()
+        C = wl["grid"].n_cells
+        gopt, oopt = dict(eta_mode=1), dict(eta_mode=1)
+    else:
+        wl, b = _single(n=2048, seed=72)
+        mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+        C = 1
+        if variant == "jacobian":
+            from paper_2111_13094_amd import sdmm
+            gopt, oopt = dict(eta_mode=1, flags=sdmm.FLAG_ESTEP_JACOBIAN), dict(eta_mode=1, estep_jacobian=1)
+        else:
+            gopt, oopt = dict(eta=0.02), dict(eta=0.02)
+    gm, gst, om, ost, s_o = _stepwise_pair(dev, orc, b, mix0, C, gopt=gopt, oopt=oopt)
+    got = to_numpy(gm)
+    fitted = [c for c in range(C) if not s_o[c] & (1 | 2 | 4 | 32)]
+    for c in range(C):
+        if c not in fitted:
+            for k in got:
+                assert np.array_equal(got[k].reshape(C, -1)[c], mix0[k].reshape(C, -1)[c], equal_nan=True)
+    worst = compare_mixtures(got, om, 16, cells=fitted)
+    print(worst)
+    # measured up to 9e-11 (the constant-eta chain forgets slowest)
+    assert_close(worst, rtol=1e-9, ang_tol=1e-9, what=f"stepwise {variant}")
+
+
+def test_stepwise_rejects_the_accurate_update(dev, orc):
+    from paper_2111_13094_amd import sdmm
+    wl, b = _single(n=256, seed=3)
+    gm, gst = to_torch(synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)), state_to_torch(orc.new_state(1, 16))
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        _gpu_fit(dev, b, gm, gst, schedule=sdmm.SCHED_STEPWISE, flags=sdmm.FLAG_ACCURATE_SIGMA)
+
+
+def test_stepwise_full_size_sampled_cells(dev, orc):
+    """The 4096-cell batch in the launch configuration the stepwise benchmark times (a
+    batch step, then a per-sample pass over the next batch); 8 sampled cells recomputed by
+    the oracle one by one."""
+    print("case: stepwise EM at full size, 8 sampled cells", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("cells4k")
+    b0, b1 = synth.workload_batch(wl, 0), synth.workload_batch(wl, 1)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    _gpu_fit(dev, b0, gm, gst, schedule=sdmm.SCHED_STEPWISE, eta_mode=1)
+    s_g = _gpu_fit(dev, b1, gm, gst, schedule=sdmm.SCHED_STEPWISE, eta_mode=1)
+    got = to_numpy(gm)
+    order = np.argsort(wl["counts"])
+    for c in sorted(set(order[np.linspace(0, C - 1, 8).astype(int)].tolist())):
+        mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
+        st = orc.new_state(1, 16)
+        for bb in (b0, b1):
+            i0, i1 = bb.offsets[c], bb.offsets[c + 1]
+            s_o = orc.fit_stepwise(_orc_opts(orc, eta_mode=1), np.array([0, i1 - i0]),
+                                   np.ascontiguousarray(bb.samples[:, i0:i1]), mc, st)
+        assert s_o[0] == s_g[c]
+        worst = compare_mixtures({k: v.reshape(C, -1)[c] for k, v in got.items()}, mc, 16)
+        assert_close(worst, rtol=1e-9, ang_tol=1e-9, what=f"stepwise cell {c}")
