@@ -53,15 +53,18 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic_record():
+def _traffic_record(items, waves_per_block):
     """HBM bytes per launch of the E-step kernel from the committed counter summary, if
-    it was taken on the current kernel source; else None."""
+    it was taken on the current kernel source in the launch configuration timed here
+    (work-item size, waves per work group); else None."""
     path = os.path.join(ROOT, "profiles", "estep_cells4k_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("source_hash") != _kernel_source_hash():
+        return None
+    if rec.get("items") != items or rec.get("waves_per_block") != waves_per_block:
         return None
     return rec.get("bytes_per_launch")
 
@@ -180,7 +183,7 @@ def bench_cells4k(args, torch):
     value = pairs / wall
     flops_per_launch = FLOPS_PER_PAIR * (pairs / args.steps)
     achieved = flops_per_launch / (est_ms * 1e-3) / 1e12
-    traffic = _traffic_record()
+    traffic = _traffic_record(int(opts.min_range or 256), int(opts.waves_per_block or 1))
     out = {
         "metric": "EM sample x component updates/s, 4096 cells K=16 (batched)",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

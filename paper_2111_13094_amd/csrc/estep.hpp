@@ -435,13 +435,28 @@ __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int
         if constexpr (JAC) l += __log2f(f);  // solid-angle density: times f (may be > 0)
 
         // responsibilities: log-sum-exp across the component lanes of this sample
-        float lmax;
-        if constexpr (JAC) lmax = group_max<G>(l);
-        else lmax = group_max_negative<G>(l);
-        float e;
-        if constexpr (ADJ) e = __builtin_amdgcn_exp2f((float)(ld - (double)lmax));
-        else e = __builtin_amdgcn_exp2f(l - lmax);
-        const float den = group_sum<G>(e);
+        float lmax = 0.0f, e, den;
+        if constexpr (JAC || ADJ) {
+            if constexpr (JAC) lmax = group_max<G>(l);
+            else lmax = group_max_negative<G>(l);
+            if constexpr (ADJ) e = __builtin_amdgcn_exp2f((float)(ld - (double)lmax));
+            else e = __builtin_amdgcn_exp2f(l - lmax);
+            den = group_sum<G>(e);
+        } else {
+            // every l is at most -1 (the per-cell shift), so exp2(l) needs no maximum unless
+            // the sample's whole sum is tiny; such a group (rare: far from every component)
+            // takes the max-shifted form, the others keep their values
+            e = __builtin_amdgcn_exp2f(l);
+            den = group_sum<G>(e);
+            if (__ballot(den < 0x1p-100f)) {
+                const float m = group_max_negative<G>(l);
+                const float e2 = __builtin_amdgcn_exp2f(l - m);
+                const float den2 = group_sum<G>(e2);
+                const bool redo = den < 0x1p-100f;
+                e = redo ? e2 : e;
+                den = redo ? den2 : den;
+            }
+        }
         const float wr = w * (e * __builtin_amdgcn_rcpf(den));
 
         const float t0 = wr * y0, t1 = wr * y1, t2 = wr * y2, t3 = wr * y3, t4 = wr * y4;
@@ -503,7 +518,7 @@ __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int
     SampleRegs a{}, b{};
     if (n > 0) a = load_sample(ch, min(i, last));
     for (; it + 2 <= full; it += 2) {
-        b = load_sample(ch, min(i + S, last));
+        b = load_sample(ch, i + S);  // step it + 1 < full: in range
         body(a, true);
         a = load_sample(ch, min(i + 2 * S, last));
         body(b, true);
