@@ -17,30 +17,27 @@ namespace sdmm {
 enum { kAccTwoSum = 0, kAccPlain = 1, kAccFp64 = 2 };
 constexpr int kFoldEvery = 32;  // steps between folds of the FP32 block sums
 
-// running sums: FP32 block sums over kFoldEvery steps, folded into an FP32 TwoSum pair
-// (compensated), kept as one plain FP32 sum, or folded into FP64 (precision variants)
+// running sums: FP32 block sums over kFoldEvery steps, folded by TwoSum into an FP32
+// running total whose rounding error opens the next block (compensated), kept as one
+// plain FP32 sum, or folded into FP64 (precision variants)
 template <int ACC>
 struct RunSum;
 
 template <>
 struct RunSum<kAccTwoSum> {
-    float blk = 0.0f, hi = 0.0f, lo = 0.0f;
+    float blk = 0.0f, hi = 0.0f;
     __device__ __forceinline__ void add(float v) { blk += v; }
     __device__ __forceinline__ void fma_add(float a, float b) { blk = fmaf(a, b, blk); }
+    // hi + blk = s + err exactly (Knuth's TwoSum); s becomes the total and err the start
+    // of the next block, so hi + blk always equals the folded sum exactly
     __device__ __forceinline__ void fold()
     {
         const float s = hi + blk;
         const float bb = s - hi;
-        const float err = (hi - (s - bb)) + (blk - bb);
+        blk = (hi - (s - bb)) + (blk - bb);
         hi = s;
-        lo += err;
-        blk = 0.0f;
     }
-    __device__ __forceinline__ double total()
-    {
-        fold();
-        return (double)hi + (double)lo;
-    }
+    __device__ __forceinline__ double total() { return (double)hi + (double)blk; }
 };
 
 template <>
@@ -63,11 +60,7 @@ struct RunSum<kAccFp64> {
         hi += (double)blk;
         blk = 0.0f;
     }
-    __device__ __forceinline__ double total()
-    {
-        fold();
-        return hi;
-    }
+    __device__ __forceinline__ double total() { return hi + (double)blk; }
 };
 
 // statistics per component and the per-item record layout: statistic s of component k
@@ -227,6 +220,19 @@ struct SampleRegs {
 __device__ __forceinline__ float ld_off(const float* base, uint32_t byte_off)
 {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+__device__ __forceinline__ SampleRegs load_sample_at(const float* const* ch, uint32_t b)
+{
+    SampleRegs r;
+    r.ox = ld_off(ch[0], b);
+    r.oy = ld_off(ch[1], b);
+    r.oz = ld_off(ch[2], b);
+    r.px = ld_off(ch[3], b);
+    r.py = ld_off(ch[4], b);
+    r.pz = ld_off(ch[5], b);
+    r.w = ld_off(ch[6], b);
+    return r;
 }
 
 __device__ __forceinline__ SampleRegs load_sample(const float* const* ch, uint32_t ii)
@@ -511,19 +517,33 @@ __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int
     };
 
     // full steps (every slot valid) two at a time with alternating prefetch registers,
-    // then at most three tail steps with the validity test
+    // then at most two tail steps with the validity test. Inside the loop both loads of an
+    // iteration are full steps, so they need no clamp and take byte offsets that advance
+    // by one add each; the last pair of full steps clamps its prefetch and leaves its open
+    // blocks to total().
     const uint32_t full = n / S, steps = (n + S - 1) / S;  // wave-uniform
     uint32_t i = (uint32_t)slot;
     uint32_t it = 0;
     SampleRegs a{}, b{};
     if (n > 0) a = load_sample(ch, min(i, last));
-    for (; it + 2 <= full; it += 2) {
-        b = load_sample(ch, i + S);  // step it + 1 < full: in range
+    uint32_t ob = (i + S) * 4u, oa = (i + 2 * S) * 4u;
+    for (; it + 2 < full; it += 2) {
+        b = load_sample_at(ch, ob);  // step it + 1
+        body(a, true);
+        a = load_sample_at(ch, oa);  // step it + 2 < full
+        body(b, true);
+        ob += 8u * S;
+        oa += 8u * S;
+        i += 2 * S;
+        if (((it + 2) % kFoldEvery) == 0) fold_all();
+    }
+    if (it + 2 == full) {
+        b = load_sample(ch, i + S);
         body(a, true);
         a = load_sample(ch, min(i + 2 * S, last));
         body(b, true);
         i += 2 * S;
-        if (((it + 2) % kFoldEvery) == 0) fold_all();
+        it += 2;
     }
     for (; it < steps; ++it) {  // at most one full and one partial step
         body(a, i <= last);
