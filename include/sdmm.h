@@ -185,7 +185,8 @@ int sdmm_fit_mixtures(const int64_t *cell_offsets, const float *samples, int64_t
  * the frame R_mu, mu_x, the Cholesky factor of Sigma_xx (inverted), the regression
  * A = Sigma_nx Sigma_xx^-1, the Cholesky factor L' of the conditional covariance
  * Sigma' = Sigma_nn - A Sigma_xn (and its inverse), and the log normalisers.
- * table [device] float32[n_cells*K*SDMM_COND_TABLE_STRIDE], written.
+ * table [device] float32[n_cells*K*SDMM_COND_TABLE_STRIDE], written; the order of the
+ * entries inside it is the library's own (only the size is part of the interface).
  */
 int sdmm_condition_prepare(const sdmm_mixtures *mix, float *table, void *stream);
 

@@ -234,7 +234,7 @@ __device__ __forceinline__ void product_setup(const float* __restrict__ table, i
     const bool usable = inq && qc >= 0 && qc < C && bc >= 0 && bc < CB;
     // radiance conditioning
     float T[kCond];
-    load_row(table_row(table, qc, K, comp, usable), T);
+    load_row(table_row(table, qc, K, comp, usable), K, T);
     float m0, m1;
     float lw = cond_component(T, x0, x1, x2, m0, m1);
     if (comp >= K || !usable) lw = -INFINITY;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void product_setup(const float* __restrict__ table, i
     const float a00 = l0 * l0, a01 = l0 * l1, a11 = fmaf(l1, l1, l2 * l2);
     // BSDF conditioning (lane b = component b), its weights, and the two heaviest
     float TB[kCond];
-    load_row(table_row(btable, bc, Kb, comp, usable), TB);
+    load_row(table_row(btable, bc, Kb, comp, usable), Kb, TB);
     float bm0, bm1;
     float lb = cond_component(TB, y0, y1, y2, bm0, bm1);
     if (comp >= Kb || !usable) lb = -INFINITY;
@@ -299,54 +299,17 @@ __device__ __forceinline__ float product_density(const ProductQuery& Qy, int K, 
     return group_sum<G>(v);
 }
 
-// one draw for the group's query (step 4)
-template <int G>
-__device__ __forceinline__ void product_draw(const ProductQuery& Qy, int K, float u0, float u1, float u2,
-                                             float& ox, float& oy, float& oz, float& pdf, int& valid, int& pair)
-{
-    const int lane = threadIdx.x & 63;
-    const int comp = lane % G, base = lane - comp;
-    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
-    const float s = Qy.P0 + Qy.P1;
-    const float cdf = group_inclusive_scan<G>(s);
-    const uint64_t hit = __ballot(comp < K && Qy.any && u0 < cdf) & gmask;
-    const uint64_t pos = __ballot(comp < K && Qy.any && s > 0.0f) & gmask;
-    int sel = -1, j = 0;
-    if (hit) {
-        sel = __builtin_ctzll(hit) - base;
-        j = __shfl((u0 < (cdf - s) + Qy.P0 && Qy.P0 > 0.0f) || !(Qy.P1 > 0.0f) ? 0 : 1, base + sel);
-    } else if (pos) {
-        sel = 63 - __builtin_clzll(pos) - base;
-        j = __shfl(Qy.P1 > 0.0f ? 1 : 0, base + sel);
-    }
-    // every lane forms a candidate from its own pair j; the selected lane's is broadcast
-    const Pair& p = j ? Qy.p1 : Qy.p0;
-    const float rad = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718056f * __builtin_amdgcn_logf(1.0f - u1));
-    const float z0 = rad * __builtin_amdgcn_cosf(u2), z1 = rad * __builtin_amdgcn_sinf(u2);
-    const float n0 = fmaf(p.L0, z0, p.c0);
-    const float n1 = fmaf(p.L1, z0, fmaf(p.L2, z1, p.c1));
-    float w[3];
-    exp_map_hw(Qy.R, n0, n1, w);
-    const int ok = fmaf(n0, n0, n1 * n1) < kPiSq;
-    const int src = base + (sel < 0 ? 0 : sel);
-    ox = __shfl(w[0], src);
-    oy = __shfl(w[1], src);
-    oz = __shfl(w[2], src);
-    valid = sel >= 0 ? __shfl(ok, src) : 0;
-    pair = sel >= 0 ? 2 * sel + j : -1;
-    pdf = product_density<G>(Qy, K, ox, oy, oz);
-    if (!valid) {
-        ox = oy = oz = 0.0f;
-        pdf = 0.0f;
-    }
-}
-
 __device__ __forceinline__ void load_frame(const float* __restrict__ frames, int64_t nq, int64_t q, float F[9])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) F[i] = frames[i * nq + q];
 }
 
+// Draws (step 4), G at a time, draw t0 + c by lane c of the query's group: the group picks
+// every draw's pair against the query's pair CDF (one group prefix sum per query; pair
+// 2k + j, lowest index on ties), lane c gathers its pair (the radiance frame and the
+// pair's mean and factor) from the lane that holds it and forms the candidate, and the
+// group then evaluates the normalised product density at each draw's direction.
 template <int G>
 __global__ __launch_bounds__(256) void product_sample_kernel(
     const float* __restrict__ table, int C, int K, const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
@@ -356,7 +319,8 @@ __global__ __launch_bounds__(256) void product_sample_kernel(
     uint8_t* __restrict__ valid_out, int32_t* __restrict__ pair_out)
 {
     constexpr int S = 64 / G;
-    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G, base = lane - comp;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nd = nq * ns;
@@ -369,25 +333,65 @@ __global__ __launch_bounds__(256) void product_sample_kernel(
         ProductQuery Qy;
         product_setup<G>(table, C, K, btable, CB, Kb, qcell[qq], bcell[qq], inq, qpos[qq], qpos[nq + qq],
                          qpos[2 * nq + qq], bpar[qq], bpar[nq + qq], bpar[2 * nq + qq], F, Qy);
+        const float s = Qy.P0 + Qy.P1;
+        const float cdf = group_inclusive_scan<G>(s);
+        const bool cand = comp < K && Qy.any;
+        const uint64_t pos = __ballot(cand && s > 0.0f) & gmask;
+        const int last_pos = pos ? 63 - __builtin_clzll(pos) - base : -1;
+        const int j_last = __shfl(Qy.P1 > 0.0f ? 1 : 0, base + (last_pos < 0 ? 0 : last_pos));
         for (int t0 = 0; t0 < ns; t0 += G) {
             float ul0 = 0.0f, ul1 = 0.0f, ul2 = 0.0f;
             if (t0 + comp < ns) draw_uniforms(uniforms, nd, qq * ns + t0 + comp, seed, ul0, ul1, ul2);
-            const int tn = min(G, ns - t0);
-            for (int tt = 0; tt < tn; ++tt) {
-                const int64_t d = qq * ns + t0 + tt;
-                const int src = slot * G + tt;
-                const float u0 = __shfl(ul0, src), u1 = __shfl(ul1, src), u2 = __shfl(ul2, src);
-                float ox, oy, oz, pdf;
-                int valid, pair;
-                product_draw<G>(Qy, K, u0, u1, u2, ox, oy, oz, pdf, valid, pair);
-                if (inq && comp == 0) {
-                    dirs_out[d] = ox;
-                    dirs_out[nd + d] = oy;
-                    dirs_out[2 * nd + d] = oz;
-                    pdf_out[d] = pdf;
-                    valid_out[d] = (uint8_t)valid;
-                    if (pair_out) pair_out[d] = pair;
+            const int tn = min(G, ns - t0);  // wave-uniform
+            // pair of every draw of the batch, four at a time (a draw past tn repeats the
+            // last one and is not kept); lane c keeps the one of draw t0 + c
+            int sel = -1, j = 0;
+            for (int tt = 0; tt < tn; tt += 4) {
+                float u0[4];
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) u0[k4] = __shfl(ul0, base + min(tt + k4, tn - 1));
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const uint64_t hit = __ballot(cand && u0[k4] < cdf) & gmask;
+                    const int s_hit = hit ? __builtin_ctzll(hit) - base : 0;
+                    const int jh = (u0[k4] < (cdf - s) + Qy.P0 && Qy.P0 > 0.0f) || !(Qy.P1 > 0.0f) ? 0 : 1;
+                    const int j_hit = __shfl(jh, base + s_hit);
+                    const bool mine = comp == tt + k4;
+                    sel = mine ? (hit ? s_hit : last_pos) : sel;
+                    j = mine ? (hit ? j_hit : j_last) : j;
                 }
+            }
+            const int src = base + (sel < 0 ? 0 : sel);
+            float R[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) R[i] = __shfl(Qy.R[i], src);
+            const float a0 = __shfl(Qy.p0.L0, src), a1 = __shfl(Qy.p0.L1, src), a2 = __shfl(Qy.p0.L2, src);
+            const float ac0 = __shfl(Qy.p0.c0, src), ac1 = __shfl(Qy.p0.c1, src);
+            const float b0 = __shfl(Qy.p1.L0, src), b1 = __shfl(Qy.p1.L1, src), b2 = __shfl(Qy.p1.L2, src);
+            const float bc0 = __shfl(Qy.p1.c0, src), bc1 = __shfl(Qy.p1.c1, src);
+            float w[3];
+            const int ok = draw_candidate(R, j ? b0 : a0, j ? b1 : a1, j ? b2 : a2, j ? bc0 : ac0, j ? bc1 : ac1,
+                                          ul1, ul2, w);
+            const int valid = sel >= 0 && ok;
+            float pdf = 0.0f;
+            for (int tt = 0; tt < tn; tt += 4) {
+                float v[4];
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const int from = base + min(tt + k4, tn - 1);
+                    v[k4] = product_density<G>(Qy, K, __shfl(w[0], from), __shfl(w[1], from), __shfl(w[2], from));
+                }
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) pdf = comp == tt + k4 ? v[k4] : pdf;
+            }
+            if (inq && comp < tn) {
+                const int64_t d = qq * ns + t0 + comp;
+                dirs_out[d] = valid ? w[0] : 0.0f;
+                dirs_out[nd + d] = valid ? w[1] : 0.0f;
+                dirs_out[2 * nd + d] = valid ? w[2] : 0.0f;
+                pdf_out[d] = valid ? pdf : 0.0f;
+                valid_out[d] = (uint8_t)valid;
+                if (pair_out) pair_out[d] = sel >= 0 ? 2 * sel + j : -1;
             }
         }
     }

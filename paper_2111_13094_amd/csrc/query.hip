@@ -22,7 +22,14 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)C * K) return;
     const double* S = cov + 15 * g;
-    float* T = table + g * kCond;
+    float T[kCond];
+    // chunk q of component k of cell c at ((c * 8 + q) * K + k) * 4 floats
+    float4* dst = reinterpret_cast<float4*>(table + (g / K) * K * kCond + (g % K) * 4);
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < kCond / 4; ++q)
+            dst[(int64_t)q * K] = make_float4(T[4 * q], T[4 * q + 1], T[4 * q + 2], T[4 * q + 3]);
+    };
     bool ok = isfinite(pi[g]) && pi[g] >= 0.0;
     for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[3 * g + d]) && isfinite(mux[3 * g + d]);
     double Sxx[6], Lxx[6], Lxi[6], Sp[3], Lp[3], Lpi[3];
@@ -63,6 +70,7 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
         T[12] = T[14] = T[17] = 1.0f;
         T[24] = T[26] = T[27] = T[29] = 1.0f;
         T[30] = -INFINITY;
+        store();
         return;
     }
     for (int i = 0; i < 9; ++i) T[i] = (float)R[i];
@@ -74,6 +82,7 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
     const double ldx = log(Lxx[0]) + log(Lxx[2]) + log(Lxx[5]);
     T[30] = (float)((log(pi[g]) - ldx - 1.5 * kLn2Pi) * kLog2e);
     T[31] = (float)((-(log(Lp[0]) + log(Lp[2])) - kLn2Pi) * kLog2e);
+    store();
 }
 
 // pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k| at direction w (0 at the cut locus)
@@ -112,17 +121,8 @@ __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk
     if (hit) sel = __builtin_ctzll(hit) - base;
     else if (pos) sel = 63 - __builtin_clzll(pos) - base;
     // every lane forms its own component's candidate; the selected one is broadcast
-    // hardware log2 / sqrt / sin / cos (the sine and cosine take revolutions: sin(2 pi u2))
-    const float rad = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718056f * __builtin_amdgcn_logf(1.0f - u1));
-    float sn, cs;
-    sn = __builtin_amdgcn_sinf(u2);
-    cs = __builtin_amdgcn_cosf(u2);
-    const float z0 = rad * cs, z1 = rad * sn;
-    const float n0 = fmaf(T[24], z0, m0);
-    const float n1 = fmaf(T[25], z0, fmaf(T[26], z1, m1));
     float w[3];
-    exp_map_hw(T, n0, n1, w);
-    const int ok = fmaf(n0, n0, n1 * n1) < kPiSq;
+    const int ok = draw_candidate(T, T[24], T[25], T[26], m0, m1, u1, u2, w);
     const int src = base + (sel < 0 ? 0 : sel);
     ox = __shfl(w[0], src);
     oy = __shfl(w[1], src);
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void condition_kernel(const float* __restrict_
         const int qc = inq ? qcell[q] : 0;
         const bool usable = inq && qc >= 0 && qc < C;
         float T[kCond];
-        load_row(table_row(table, qc, K, comp, usable), T);
+        load_row(table_row(table, qc, K, comp, usable), K, T);
         const int64_t qq = inq ? q : 0;
         float m0, m1;
         float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void pdf_kernel(const float* __restrict__ tabl
         const int qc = qcell[q];
         const bool usable = inp && qc >= 0 && qc < C && comp < K;
         float T[kCond];
-        load_row(table_row(table, qc, K, comp, usable), T);
+        load_row(table_row(table, qc, K, comp, usable), K, T);
         const int kk = comp < K ? comp : K - 1;
         const float wk = usable ? cw[q * K + kk] : 0.0f;
         const float m0 = cm[(q * K + kk) * 2], m1 = cm[(q * K + kk) * 2 + 1];
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void sample_kernel(const float* __restrict__ t
         const int qc = qcell[q];
         const bool usable = ind && qc >= 0 && qc < C;
         float T[kCond];
-        load_row(table_row(table, qc, K, comp, usable), T);
+        load_row(table_row(table, qc, K, comp, usable), K, T);
         const int kk = comp < K ? comp : K - 1;
         const float wk = (usable && comp < K) ? cw[q * K + kk] : 0.0f;
         const float m0 = cm[(q * K + kk) * 2], m1 = cm[(q * K + kk) * 2 + 1];
@@ -242,7 +242,13 @@ __global__ __launch_bounds__(256) void sample_kernel(const float* __restrict__ t
     }
 }
 
-// conditioning + ns draws + pdf per query, pi' and m kept in registers
+// conditioning + ns draws + pdf per query, pi' and m kept in registers. The draws of a
+// query are taken G at a time, draw t0 + c by lane c of the query's group: the group
+// picks every draw's component against the query's CDF (one scan per query), lane c
+// gathers its draw's component row (frame, conditional factor and mean) from the lane
+// that holds it and forms the candidate, and the group then evaluates the pdf of each
+// draw's direction over all components. The arithmetic of every value is the one of
+// sample_one, so both paths give the same draws.
 template <int G>
 __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __restrict__ table, int C, int K,
                                                               const float* __restrict__ qpos,
@@ -252,7 +258,8 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
                                                               uint8_t* __restrict__ valid_out)
 {
     constexpr int S = 64 / G;
-    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G;
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G, base = lane - comp;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nd = nq * ns;
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
         const int qc = qcell[qq];
         const bool usable = inq && qc >= 0 && qc < C;
         float T[kCond];
-        load_row(table_row(table, qc, K, comp, usable), T);
+        load_row(table_row(table, qc, K, comp, usable), K, T);
         float m0, m1;
         float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
         if (comp >= K || !usable) lw = -INFINITY;
@@ -271,26 +278,57 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
         const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
         const float den = group_sum<G>(e);
         const float wk = den > 0.0f ? e / den : 0.0f;
-        // the uniforms of up to G draws of this query at once, one draw per lane of the
-        // group, then broadcast draw by draw
+        const float cdf = group_inclusive_scan<G>(wk);
+        const bool cand = comp < K && usable;
+        const uint64_t pos = __ballot(cand && wk > 0.0f) & gmask;
+        const int last_pos = pos ? 63 - __builtin_clzll(pos) - base : -1;
         for (int t0 = 0; t0 < ns; t0 += G) {
             float ul0 = 0.0f, ul1 = 0.0f, ul2 = 0.0f;
             if (t0 + comp < ns) draw_uniforms(uniforms, nd, qq * ns + t0 + comp, seed, ul0, ul1, ul2);
-            const int tn = min(G, ns - t0);
-            for (int tt = 0; tt < tn; ++tt) {
-                const int64_t d = qq * ns + t0 + tt;
-                const int src = slot * G + tt;
-                const float u0 = __shfl(ul0, src), u1 = __shfl(ul1, src), u2 = __shfl(ul2, src);
-                float ox, oy, oz, pdf;
-                int valid, sel;
-                sample_one<G>(T, usable, wk, m0, m1, K, u0, u1, u2, ox, oy, oz, pdf, valid, sel);
-                if (inq && comp == 0) {
-                    dirs_out[d] = ox;
-                    dirs_out[nd + d] = oy;
-                    dirs_out[2 * nd + d] = oz;
-                    pdf_out[d] = pdf;
-                    valid_out[d] = (uint8_t)valid;
+            const int tn = min(G, ns - t0);  // wave-uniform
+            // four draws at a time, so that their independent chains interleave (a draw
+            // past tn repeats the last one and is not kept)
+            int sel = -1;
+            for (int tt = 0; tt < tn; tt += 4) {
+                float u0[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u0[j] = __shfl(ul0, base + min(tt + j, tn - 1));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t hit = __ballot(cand && u0[j] < cdf) & gmask;
+                    const int s_tt = hit ? __builtin_ctzll(hit) - base : last_pos;
+                    sel = comp == tt + j ? s_tt : sel;
                 }
+            }
+            const int src = base + (sel < 0 ? 0 : sel);
+            float R[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) R[i] = __shfl(T[i], src);
+            const float l0 = __shfl(T[24], src), l1 = __shfl(T[25], src), l2 = __shfl(T[26], src);
+            float w[3];
+            const int ok = draw_candidate(R, l0, l1, l2, __shfl(m0, src), __shfl(m1, src), ul1, ul2, w);
+            const int valid = sel >= 0 && ok;
+            float pdf = 0.0f;
+            for (int tt = 0; tt < tn; tt += 4) {
+                float c[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int from = base + min(tt + j, tn - 1);
+                    c[j] = pdf_component(T, wk, m0, m1, __shfl(w[0], from), __shfl(w[1], from), __shfl(w[2], from));
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float p = group_sum<G>(comp < K ? c[j] : 0.0f);
+                    pdf = comp == tt + j ? p : pdf;
+                }
+            }
+            if (inq && comp < tn) {
+                const int64_t d = qq * ns + t0 + comp;
+                dirs_out[d] = valid ? w[0] : 0.0f;
+                dirs_out[nd + d] = valid ? w[1] : 0.0f;
+                dirs_out[2 * nd + d] = valid ? w[2] : 0.0f;
+                pdf_out[d] = valid ? pdf : 0.0f;
+                valid_out[d] = (uint8_t)valid;
             }
         }
     }

@@ -8,7 +8,10 @@
 
 namespace sdmm {
 
-// conditioning table, per component (FP32):
+// conditioning table: per cell, the eight 16-byte chunks of its K components stored chunk
+// by chunk ([cell][chunk][component][4 floats]), so that the lanes of a group, one
+// component each, read one chunk of every component from contiguous memory. Per
+// component (FP32):
 //   0-8   R_mu rows (t1, t2, mu)           9-11  mu_x
 //   12-17 Lxx^-1 * sqrt(log2(e)/2), packed   18-23 A = Sigma_nx Sigma_xx^-1 (2x3, row-major)
 //   24-26 L' packed (chol of Sigma')         27-29 L'^-1 * sqrt(log2(e)/2), packed
@@ -32,6 +35,22 @@ __device__ __forceinline__ void exp_map_hw(const float* R, float n0, float n1, f
     const float sc = r > 1e-4f ? sr * __builtin_amdgcn_rcpf(r) : 1.0f - r2 * (1.0f / 6.0f);
     const float v0 = n0 * sc, v1 = n1 * sc;
     for (int j = 0; j < 3; ++j) w[j] = fmaf(R[j], v0, fmaf(R[3 + j], v1, R[6 + j] * cr));
+}
+
+// The tangent candidate of one draw from a Gaussian on the tangent plane of frame R with
+// factor L = (l0; l1 l2) and mean m: Box-Muller with the hardware log2 / sqrt /
+// sin / cos (the sine and cosine take revolutions: sin(2 pi u2)), nu = m + L z, the exp
+// map. Returns whether |nu| < pi (a draw at or beyond the cut locus is discarded).
+__device__ __forceinline__ int draw_candidate(const float* R, float l0, float l1, float l2, float m0, float m1,
+                                              float u1, float u2, float w[3])
+{
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718056f * __builtin_amdgcn_logf(1.0f - u1));
+    const float sn = __builtin_amdgcn_sinf(u2), cs = __builtin_amdgcn_cosf(u2);
+    const float z0 = rad * cs, z1 = rad * sn;
+    const float n0 = fmaf(l0, z0, m0);
+    const float n1 = fmaf(l1, z0, fmaf(l2, z1, m1));
+    exp_map_hw(R, n0, n1, w);
+    return fmaf(n0, n0, n1 * n1) < kPiSq;
 }
 
 // conditional log2-weight and mean of component T at position x
@@ -107,18 +126,20 @@ __device__ __forceinline__ float group_inclusive_scan(float v)
     return v;
 }
 
+// first chunk of component comp (clamped to K - 1) of cell qc (cell 0 when unusable)
 __device__ __forceinline__ const float* table_row(const float* table, int qc, int K, int comp, bool usable)
 {
     const int kk = comp < K ? comp : K - 1;
-    return table + ((int64_t)(usable ? qc : 0) * K + kk) * kCond;
+    return table + (int64_t)(usable ? qc : 0) * K * kCond + (int64_t)kk * 4;
 }
 
-__device__ __forceinline__ void load_row(const float* src, float* T)
+// the kCond floats of one component, chunk q at q * K chunks from the first
+__device__ __forceinline__ void load_row(const float* src, int K, float* T)
 {
     const float4* p = reinterpret_cast<const float4*>(src);
 #pragma unroll
     for (int q = 0; q < kCond / 4; ++q) {
-        const float4 v = p[q];
+        const float4 v = p[(int64_t)q * K];
         T[4 * q] = v.x;
         T[4 * q + 1] = v.y;
         T[4 * q + 2] = v.z;
