@@ -87,7 +87,10 @@ __global__ void tree_init_kernel(TreePtrs t, int levels, double lo0, double lo1,
 // point location: left where p[axis] < split, else right; child indices exceed their
 // parent's, so the walk ends within max_nodes steps. After the first round a sample
 // resumes from the node it reached in the previous round (node_of), which is still its
-// leaf unless that leaf was split; its position is read only when it has to move.
+// leaf unless that leaf was split; its position is read only when it has to move. The
+// axis, split, left child and leaf index of a node are loaded together (with the
+// position, when every sample starts at the root): one memory round trip per level, the
+// entries that turn out not to be needed simply not used.
 // ---------------------------------------------------------------------------------
 __global__ void locate_kernel(TreePtrs t, const float* __restrict__ smp, int64_t N, int from_root,
                               int32_t* __restrict__ node_of, int32_t* __restrict__ leaf_of)
@@ -95,13 +98,36 @@ __global__ void locate_kernel(TreePtrs t, const float* __restrict__ smp, int64_t
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int32_t n = from_root ? 0 : node_of[i];
-    if (t.axis[n] >= 0) {
-        const double p[3] = {(double)smp[3 * N + i], (double)smp[4 * N + i], (double)smp[5 * N + i]};
-        for (int32_t s = 0; s < t.max_nodes && t.axis[n] >= 0; ++s)
-            n = (p[t.axis[n]] < t.split[n]) ? t.left[n] : t.left[n] + 1;
+    int32_t ax = t.axis[n], lf = t.left[n], leaf = t.leaf[n];
+    double sp = t.split[n];
+    float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
+    if (from_root) {  // every sample moves: its position comes with the root's entries
+        q0 = smp[3 * N + i];
+        q1 = smp[4 * N + i];
+        q2 = smp[5 * N + i];
+    }
+    // the loads above and in the loop complete together at these empty statements (the
+    // compiler would otherwise issue the later ones only after the axis came back)
+    asm volatile("" ::"v"(ax), "v"(lf), "v"(sp), "v"(leaf), "v"(q0), "v"(q1), "v"(q2));
+    if (ax >= 0) {
+        if (!from_root) {
+            q0 = smp[3 * N + i];
+            q1 = smp[4 * N + i];
+            q2 = smp[5 * N + i];
+        }
+        const double p0 = (double)q0, p1 = (double)q1, p2 = (double)q2;
+        for (int32_t s = 0; s < t.max_nodes && ax >= 0; ++s) {
+            const double pa = ax == 0 ? p0 : (ax == 1 ? p1 : p2);
+            n = pa < sp ? lf : lf + 1;
+            ax = t.axis[n];
+            lf = t.left[n];
+            sp = t.split[n];
+            leaf = t.leaf[n];
+            asm volatile("" ::"v"(ax), "v"(lf), "v"(sp), "v"(leaf));
+        }
     }
     node_of[i] = n;
-    leaf_of[i] = t.leaf[n];
+    leaf_of[i] = leaf;
 }
 
 // ---------------------------------------------------------------------------------
