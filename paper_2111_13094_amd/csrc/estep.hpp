@@ -74,41 +74,49 @@ struct ChunkLayout {
 
 // Sums the records of one cell's items 0, 2^stride_log2, 2 * 2^stride_log2, ... below
 // n_items (record slots from `first`) in item order, one column per lane (all 64 lanes
-// of the wave, which must be uniform in first/n_items), with the loads of four records
-// in flight, then hands lane k < G its component's statistics S[s] = column s * G + k and
-// every lane the extras X[i] = column NS * G + i. With stride 2^(4 L) the summed records
-// are the level-L leaders of the record tree (see tree_kernel).
-template <int G, int NS, int NX>
-__device__ __forceinline__ void sum_cell_records(const double* __restrict__ records, int64_t first, int64_t n_items,
-                                                 int PS, int stride_log2, double (&S)[NS], double (&X)[NX])
+// of the wave, which must be uniform in first/n_items), with the loads of several records
+// in flight: column q * 64 + lane of the record (statistic s of component k at s * G + k,
+// then the extras) ends in v[q]. With stride 2^(4 L) the summed records are the level-L
+// leaders of the record tree (see tree_kernel). RB0 records per round trip by default
+// (fewer when a record spans many registers).
+template <int G, int NS, int NX, int RB0 = 4>
+__device__ __forceinline__ void sum_cell_columns(const double* __restrict__ records, int64_t first, int64_t n_items,
+                                                 int PS, int stride_log2, double (&v)[(NS * G + NX + 63) / 64])
 {
     constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
     const int lane = threadIdx.x & 63;
     const int64_t n = (n_items + (int64_t(1) << stride_log2) - 1) >> stride_log2;  // records to sum
     const int64_t step = (int64_t)PS << stride_log2;                                 // doubles between them
-    double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-    int64_t j = 0;
-    for (; j + 4 <= n; j += 4) {
+    // RB records per round trip; past the last record the loads are skipped and add an
+    // exact zero, so the sum is the same as record by record
+    constexpr int RB = NQ > 6 ? 2 : RB0;
+    for (int64_t j = 0; j < n; j += RB) {
         const double* r0 = records + first * PS + j * step;
-        double a[4][NQ];
+        double a[RB][NQ];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < RB; ++u)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) a[u][q] = (q * 64 + lane < NCOL) ? r0[u * step + q * 64 + lane] : 0.0;
+            for (int q = 0; q < NQ; ++q)
+                a[u][q] = (j + u < n && q * 64 + lane < NCOL) ? r0[u * step + q * 64 + lane] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < RB; ++u)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) v[q] += a[u][q];
     }
-    for (; j < n; ++j) {
-        const double* r0 = records + first * PS + j * step;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (q * 64 + lane < NCOL) v[q] += r0[q * 64 + lane];
-    }
-    const int k = lane % G;
+}
+
+// The same sums handed to lane k < G as its component's statistics S[s] = column
+// s * G + k, and to every lane as the extras X[i] = column NS * G + i.
+template <int G, int NS, int NX>
+__device__ __forceinline__ void sum_cell_records(const double* __restrict__ records, int64_t first, int64_t n_items,
+                                                 int PS, int stride_log2, double (&S)[NS], double (&X)[NX])
+{
+    constexpr int NQ = (NS * G + NX + 63) / 64;
+    double v[NQ];
+    sum_cell_columns<G, NS, NX>(records, first, n_items, PS, stride_log2, v);
+    const int k = (threadIdx.x & 63) % G;
 #pragma unroll
     for (int s = 0; s < NS; ++s) S[s] = __shfl(v[(s * G) / 64], (s * G) % 64 + k);
 #pragma unroll

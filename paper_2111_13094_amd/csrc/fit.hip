@@ -93,10 +93,11 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
         }
         return;
     }
-    // one cell per wave (its FP64 chains are long: more waves in flight hide latency),
-    // lane k = component k
-    const int c = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
-    const int k = threadIdx.x & 63;
+    // one cell per group of GM lanes (64 / GM cells per wave), lane k % GM = component k:
+    // the FP64 mirror construction then issues once for up to 64 components
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(t / GM);
+    const int k = (int)(t % GM);
     const bool active = c < C && k < K;
     const int64_t g = (int64_t)c * K + k;
     double c2 = -INFINITY;
@@ -188,39 +189,30 @@ __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t 
 }
 
 // ---------------------------------------------------------------------------------
-// M-step of one cell by one wave: all 64 lanes sum the cell's records (in item order,
-// column-parallel), then lanes k < G (lane k = component k) gate, blend (Robbins-Monro)
-// and update in FP64, and optionally write the next iteration's mirrors. cell_ok must
-// be uniform over the wave.
+// M-step of one component (lane): from its cell's summed statistics (S: the component's,
+// X: the cell's W, M and count of negative weights) it gates the cell, blends
+// (Robbins-Monro) and updates in FP64, and optionally writes the next iteration's
+// mirrors. Each group of G consecutive lanes holds the components of one cell (lane
+// k % G = component k); every lane of the wave takes part (group reductions). c must be
+// a valid cell index even where cell_ok is false.
 // ---------------------------------------------------------------------------------
 template <int G>
-__device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
-                                           bool tree, const double* __restrict__ records, int PS,
-                                           int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
-                                           const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
-                                           float* __restrict__ mirror, int refresh_mirror,
-                                           int32_t* __restrict__ status)
+__device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const double (&S)[kStats],
+                                             const double (&X)[3], int32_t* __restrict__ flags,
+                                             const int32_t* __restrict__ global_ok, const MixPtrs& mix,
+                                             const StatePtrs& st, const DevOpts& o, float* __restrict__ mirror,
+                                             int refresh_mirror, int32_t* __restrict__ status)
 {
     constexpr int GM = G;
     const int K = o.K;
-    const int lane = threadIdx.x & 63;
-    const int k = lane;
     // accurate covariance update: this M-step moves the weights and means only; the
     // mirrors it writes (new weights and means, previous covariances) drive the second
     // E-step pass, whose statistics accurate_mstep_kernel turns into the covariances
     const bool accurate = (o.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
-    const bool wave_ok = cell_ok;
-    cell_ok = cell_ok && lane < G;
     const bool act = cell_ok && k < K;
     const int kk = k < K ? k : 0;
+    const int64_t g = (int64_t)c * K + kk;
 
-    // sum of the cell's records
-    double S[kStats], X[3];
-    int64_t first = 0, n_items = 0;
-    const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
-    // after the record tree (batched and per-cell schedules) only the top leaders remain
-    const int lv = tree && *global_ok ? tree_levels(global_ok[1]) : 0;
-    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     const double W = X[0], Mc = X[1], negs = X[2];
     int fin = isfinite(W);
     for (int s = 0; s < kStats; ++s) fin &= isfinite(S[s]) ? 1 : 0;
@@ -239,7 +231,6 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     const double eta = rm_eta(o, j);
     const double beta = o.prior_mode == 0 ? eta / fmax(Mc, 1.0) : o.prior_scale;
     const double hW = j == 0 ? W : (1.0 - eta) * (run ? st.sw[c] : 0.0) + eta * W;
-    const int64_t g = (int64_t)c * K + kk;
 
     double hS0 = 0.0, hS1[5], hS2[15];
     if (run && act) {
@@ -253,8 +244,10 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     int dead = 0, cholfail = 0;
     if (run && act) {
         // with the accurate update the second pass forms the covariance
-        component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, mix.mud + 3 * g, mix.mux + 3 * g,
-                             mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
+        const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
+        const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
+        component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, mu_in, mux_in, mix.mud + 3 * g,
+                             mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
         mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
     const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
@@ -271,6 +264,27 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     }
 }
 
+// M-step of one cell by one wave: all 64 lanes sum the cell's records (in item order,
+// column-parallel), then lanes k < G (lane k = component k) update. cell_ok must be
+// uniform over the wave.
+template <int G>
+__device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
+                                           bool tree, const double* __restrict__ records, int PS,
+                                           int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
+                                           const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
+                                           float* __restrict__ mirror, int refresh_mirror,
+                                           int32_t* __restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    double S[kStats], X[3];
+    int64_t first = 0, n_items = 0;
+    const bool have = cell_ok && cell_items(off, N, c, ps, first, n_items);
+    // after the record tree (batched and per-cell schedules) only the top leaders remain
+    const int lv = tree && *global_ok ? tree_levels(global_ok[1]) : 0;
+    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
+    mstep_update<G>(c, lane, cell_ok && lane < G, S, X, flags, global_ok, mix, st, o, mirror, refresh_mirror, status);
+}
+
 // M-step of cells [cell_lo, cell_lo + n_cells), one cell per wave
 template <int G>
 __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
@@ -285,6 +299,51 @@ __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ 
     const bool cell_ok = cl < n_cells;
     mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, true, records, PS, flags, global_ok, mix, st, o,
                   mirror, refresh_mirror, status);
+}
+
+// M-step of cells [cell_lo, cell_lo + n_cells) after the record tree, 64 / G cells per
+// work group of 64 / G waves. Wave w sums the records of the group's cell w over all 64
+// lanes into LDS; then one wave updates every component of the group's cells, lane
+// w * G + k = component k of cell w. The FP64 update, which needs one lane per
+// component, then issues once for 64 components instead of once per cell. The sums and
+// the update are those of mstep_kernel, so both give the same results.
+template <int G>
+__global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_kernel(
+    const int64_t* __restrict__ off, int64_t N, int ps, const double* __restrict__ records, int PS,
+    int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok, MixPtrs mix, StatePtrs st, DevOpts o,
+    float* __restrict__ mirror, int refresh_mirror, int32_t* __restrict__ status, int cell_lo, int n_cells)
+{
+    constexpr int NCW = 64 / G, NCOL = kStats * G + 3, NQ = (NCOL + 63) / 64;
+    __shared__ double cols[NCW][NCOL];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int cb = blockIdx.x * NCW;
+    {
+        const int cl = cb + w;
+        const bool ok = cl < n_cells;
+        const int c = cell_lo + (ok ? cl : 0);
+        int64_t first = 0, n_items = 0;
+        const bool have = ok && cell_items(off, N, c, ps, first, n_items);
+        const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;
+        double v[NQ];
+        // this phase holds few other registers: eight records per round trip
+        sum_cell_columns<G, kStats, 3, 8>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, v);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q * 64 + lane < NCOL) cols[w][q * 64 + lane] = v[q];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    const int slot = lane / G, k = lane % G;
+    const int cl = cb + slot;
+    const bool ok = cl < n_cells;
+    double S[kStats], X[3];
+#pragma unroll
+    for (int s = 0; s < kStats; ++s) S[s] = cols[slot][s * G + k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[i] = cols[slot][kStats * G + i];
+    mstep_update<G>(cell_lo + (ok ? cl : 0), k, ok, S, X, flags, global_ok, mix, st, o, mirror, refresh_mirror,
+                    status);
 }
 
 // ---------------------------------------------------------------------------------
@@ -430,6 +489,18 @@ static AccMstepFn accurate_mstep_function(int G)
     return nullptr;
 }
 
+static MstepFn mstep_packed_function(int G)
+{
+    switch (G) {
+        case 4: return mstep_packed_kernel<4>;
+        case 8: return mstep_packed_kernel<8>;
+        case 16: return mstep_packed_kernel<16>;
+        case 32: return mstep_packed_kernel<32>;
+        case 64: return mstep_packed_kernel<64>;
+    }
+    return nullptr;
+}
+
 static MstepFn mstep_function(int G)
 {
     switch (G) {
@@ -496,7 +567,7 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
 {
     const int C = mix.n_cells, K = mix.K;
     const int GM = group_pow2(K);
-    const int blocks = (C + 3) / 4;  // one cell per wave
+    const int blocks = (int)(((int64_t)C * GM + 255) / 256);  // one cell per GM lanes
     const MixPtrs mp{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov};
     setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, L.ps, mp, reinterpret_cast<float*>(ws + L.mirror),
                                             reinterpret_cast<int32_t*>(ws + L.flags), status,
@@ -576,7 +647,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
     const bool accurate = (a.opts.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
     EstepFn est = estep_function(G, acc, jac, false);
     FusedFn fused = fused_function(G, acc, jac);
-    MstepFn mstep = mstep_function(G);
+    MstepFn mstep = mstep_function(G), mstep_packed = mstep_packed_function(G);
     AccMstepFn acc_mstep = accurate ? accurate_mstep_function(G) : nullptr;
     float* mirror = reinterpret_cast<float*>(a.ws + L.mirror);
     int32_t* flags = reinterpret_cast<int32_t*>(a.ws + L.flags);
@@ -632,8 +703,9 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
             launch_tree(kTreeFit, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s);
             {
                 ScopedTimer tm(SDMM_TIMER_MSTEP, s);
-                hipLaunchKernelGGL(mstep, dim3((C + 3) / 4), dim3(256), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags,
-                                   gok, mp, sp, dopt, mirror, refresh1, a.status, 0, C);
+                const int ncw = 64 / G;  // cells per work group
+                hipLaunchKernelGGL(mstep_packed, dim3((C + ncw - 1) / ncw), dim3(64 * ncw), 0, s, a.off, a.N, L.ps,
+                                   rec, L.ps_fit, flags, gok, mp, sp, dopt, mirror, refresh1, a.status, 0, C);
             }
             if (accurate) {
                 second_pass(0, (int64_t)C + L.W, -1, 0, 0);

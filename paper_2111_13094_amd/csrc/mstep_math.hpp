@@ -15,8 +15,9 @@ __device__ __forceinline__ double rm_eta(const DevOpts& o, int j)
 }
 
 // Updates one component (arrays of the component: mud[3], mux[3], cov[15], s0[1],
-// s2[15]) from the blended statistics hS0, hS1, hS2 and normaliser hW with prior strength
-// beta; bar0 = hS0 / hW. A dead component (bar0 at or below the threshold) keeps its
+// s2[15]; its current means mu_in, mux_in passed by value, so that the caller can load
+// them early) from the blended statistics hS0, hS1, hS2 and normaliser hW with prior
+// strength beta; bar0 = hS0 / hW. A dead component (bar0 at or below the threshold) keeps its
 // mean and covariance and stores the blended statistics. Otherwise the mean moves by
 // m = hS1 / hS0 (direction through the exp map of the old frame, position by
 // translation) and, with cov_update, the scatter about the new mean is carried into the
@@ -25,8 +26,9 @@ __device__ __forceinline__ double rm_eta(const DevOpts& o, int j)
 // hS0 and T C T^T. The weight is left to the caller (it needs the cell's sum of bar0).
 __device__ inline void component_map_update(double hS0, const double* hS1, const double* hS2, double hW,
                                             double beta, double bar0, const DevOpts& o, bool cov_update,
-                                            double* mud, double* mux, double* cov, double* s0, double* s2,
-                                            int& dead, int& cholfail)
+                                            const double mu_in[3], const double mux_in[3], double* mud,
+                                            double* mux, double* cov, double* s0, double* s2, int& dead,
+                                            int& cholfail)
 {
     if (!(bar0 > o.dead_threshold)) {
         dead = 1;
@@ -34,7 +36,7 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
         for (int q = 0; q < 15; ++q) s2[q] = hS2[q];
         return;
     }
-    const double mu[3] = {mud[0], mud[1], mud[2]};
+    const double mu[3] = {mu_in[0], mu_in[1], mu_in[2]};
     double m[5];
     const double inv0 = 1.0 / hS0;
     for (int d = 0; d < 5; ++d) m[d] = hS1[d] * inv0;
@@ -45,7 +47,7 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
     for (int i = 0; i < 3; ++i) mun[i] *= inn;
     for (int i = 0; i < 3; ++i) {
         mud[i] = mun[i];
-        mux[i] += m[2 + i];
+        mux[i] = mux_in[i] + m[2 + i];
     }
     *s0 = hS0;
     if (!cov_update) return;

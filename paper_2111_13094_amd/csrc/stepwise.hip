@@ -209,8 +209,10 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             const double sum0 = wave_sum_d(bar0);
             int dead = 0, cholfail = 0;
             if (act) {
-                component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, true, mix.mud + 3 * g, mix.mux + 3 * g,
-                                     mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
+                const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
+                const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
+                component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, true, mu_in, mux_in, mix.mud + 3 * g,
+                                     mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
             }
@@ -231,8 +233,10 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             const double sum0 = wave_sum_d(bar0);
             int dead = 0, cholfail = 0;
             if (act) {
-                component_map_update(S[0], S + 1, S + 6, Wb, beta, bar0, o, true, mix.mud + 3 * g, mix.mux + 3 * g,
-                                     mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
+                const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
+                const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
+                component_map_update(S[0], S + 1, S + 6, Wb, beta, bar0, o, true, mu_in, mux_in, mix.mud + 3 * g,
+                                     mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
             }
