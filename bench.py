@@ -138,6 +138,11 @@ def bench_cells4k(args, torch):
     if args.wpb:
         opts.waves_per_block = args.wpb
     opts.flags = {"twosum": 0, "plain": sdmm.FLAG_PLAIN_FP32, "fp64": sdmm.FLAG_FP64_SUMS}[args.sums]
+    # the caller's bound on samples per cell (the largest cell of its batches, from the
+    # host-side offsets): with at most 8192 samples no cell needs the record tree, so
+    # its launches are left out
+    max_cell = max(int(np.diff(b.offsets).max()) for b in batches)
+    opts.max_cell_samples = max_cell
     tuned = None
     if args.tune:
         # the autotuner's pick on the first batch (untimed), reported beside the timed run;
@@ -196,7 +201,7 @@ def bench_cells4k(args, torch):
                    "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
                    "min_range": int(opts.min_range or 256), "max_ranges": int(opts.max_ranges or 65536),
                    "waves_per_block": int(opts.waves_per_block or 1),
-                   "running_sums": args.sums, "autotuned": tuned},
+                   "running_sums": args.sums, "max_cell_samples": max_cell, "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": ("fused_kernel<16,TwoSum,false>" if opts.schedule == sdmm.SCHED_FUSED

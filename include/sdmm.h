@@ -110,7 +110,12 @@ typedef struct sdmm_fit_opts {
     int32_t waves_per_block; /* E-step launch: 1, 2 or 4 waves (work items) per work
                             group; 0 = 1. Single-wave groups let a compute unit start a
                             new item as soon as any wave slot frees up. */
-    int32_t reserved;    /* must be 0 */
+    int32_t max_cell_samples; /* hint: no cell of the batch holds more samples than this
+                            (for cells that are kD-tree leaves, the split threshold);
+                            0 = no bound, negative is rejected. It only bounds how many
+                            record-tree levels are launched (each a kernel launch): a cell
+                            above it is still fitted, its M-step then sums more records,
+                            in a different order (FP64 rounding). */
     double eta;          /* Robbins-Monro weight of a new batch for SDMM_ETA_CONSTANT */
     double rm_alpha, rm_beta; /* SDMM_ETA_PAPER schedule (paper: 0.5, 0.1) */
     double prior_scale;  /* beta for SDMM_PRIOR_FIXED */

@@ -32,11 +32,12 @@ struct StatePtrs {
 // Records are sized for the larger (adjoint) pass so one workspace serves every call.
 struct Layout {
     int wpb;  // waves per work group of the E-step launch
-    size_t mirror, flags, arrive, global_ok, records, total;  // global_ok: int32[2] control words
+    size_t mirror, flags, arrive, global_ok, records, total;  // global_ok: int32[3] control words
     int64_t P;  // samples per E-step work item, 2^ps
     int ps;
     int W;
     int ps_fit, ps_grad;
+    int32_t max_cell;  // the caller's bound on samples per cell (0: none)
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -69,6 +70,7 @@ inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o
     P = int64_t(1) << L.ps;
     L.P = P;
     L.W = N > 0 ? (int)((N + P - 1) / P) : 0;
+    L.max_cell = o->max_cell_samples;
     const int G = group_for(K);  // records keep statistic s of component k at s * G + k
     L.ps_fit = (kStats * G + 3 + 1) & ~1;
     L.ps_grad = ((kStats + 2) * G + 4 + 1) & ~1;
@@ -80,7 +82,7 @@ inline Layout layout_for(int32_t C, int32_t K, int64_t N, const sdmm_fit_opts* o
     L.arrive = p;
     p = align256(p + (size_t)C * sizeof(int32_t));
     L.global_ok = p;
-    p = align256(p + 2 * sizeof(int32_t));
+    p = align256(p + 3 * sizeof(int32_t));
     L.records = p;
     p = align256(p + ((size_t)C + (size_t)L.W) * (size_t)L.ps_grad * sizeof(double));
     L.total = p;

@@ -605,6 +605,22 @@ __host__ __device__ inline int tree_levels(int64_t max_items)
     return L;
 }
 
+// record-tree levels to launch for N samples in items of P when no cell holds more than
+// max_cell samples (max_cell <= 0: no bound); a cell above the bound needs more levels
+// than launched, and the M-step then sums the leaders of the highest launched level
+inline int tree_levels_launched(int64_t N, int64_t P, int32_t max_cell)
+{
+    const int64_t cap = (max_cell > 0 && max_cell < N) ? max_cell : N;
+    return tree_levels((cap + P - 1) / P);
+}
+
+// record-tree level whose leaders the M-step sums: the levels the largest cell needs,
+// at most those launched (control words: [1] most items in a cell, [2] levels launched)
+__device__ __forceinline__ int tree_levels_done(const int32_t* __restrict__ control)
+{
+    return min(tree_levels(control[1]), control[2]);
+}
+
 // the level-`level` leader in level slot t, if any, sums its block (see tree_kernel)
 template <int G, int NS, int NX>
 __device__ __forceinline__ void tree_leader(const int64_t* __restrict__ off, int64_t N, int C, int ps, int level,

@@ -58,9 +58,11 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
                                                     int GM, int ps, MixPtrs mix, float* __restrict__ mirror,
                                                     int32_t* __restrict__ flags, int32_t* __restrict__ status,
                                                     int32_t* __restrict__ arrive, int32_t* __restrict__ control,
-                                                    int n_cell_blocks)
+                                                    int n_cell_blocks, int tree_max)
 {
-    if ((int)blockIdx.x == n_cell_blocks) {  // control[0]: offsets valid; control[1]: most items in a cell
+    // control[0]: offsets valid; control[1]: most items in a cell; control[2]: record-tree
+    // levels launched
+    if ((int)blockIdx.x == n_cell_blocks) {
         __shared__ int bad, most;
         if (threadIdx.x == 0) bad = 0, most = 1;
         __syncthreads();
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
         if (threadIdx.x == 0) {
             control[0] = bad ? 0 : 1;
             control[1] = most;
+            control[2] = tree_max;
         }
         return;
     }
@@ -280,7 +283,7 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
     int64_t first = 0, n_items = 0;
     const bool have = cell_ok && cell_items(off, N, c, ps, first, n_items);
     // after the record tree (batched and per-cell schedules) only the top leaders remain
-    const int lv = tree && *global_ok ? tree_levels(global_ok[1]) : 0;
+    const int lv = tree && *global_ok ? tree_levels_done(global_ok) : 0;
     sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     mstep_update<G>(c, lane, cell_ok && lane < G, S, X, flags, global_ok, mix, st, o, mirror, refresh_mirror, status);
 }
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
         const int c = cell_lo + (ok ? cl : 0);
         int64_t first = 0, n_items = 0;
         const bool have = ok && cell_items(off, N, c, ps, first, n_items);
-        const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;
+        const int lv = *global_ok ? tree_levels_done(global_ok) : 0;
         double v[NQ];
         // this phase holds few other registers: eight records per round trip
         sum_cell_columns<G, kStats, 3, 8>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, v);
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(256) void accurate_mstep_kernel(const int64_t* __re
     const bool stepped = (flags[c] & kFlagStepped) != 0;  // uniform over the wave
     int64_t first = 0, n_items = 0;
     const bool have = stepped && cell_items(off, N, c, ps, first, n_items);
-    const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;
+    const int lv = *global_ok ? tree_levels_done(global_ok) : 0;
     double S[kStats], X[3];
     sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     const bool act = have && k < K;
@@ -572,7 +575,8 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
     setup_kernel<<<blocks + 1, 256, 0, s>>>(off, N, C, K, GM, L.ps, mp, reinterpret_cast<float*>(ws + L.mirror),
                                             reinterpret_cast<int32_t*>(ws + L.flags), status,
                                             reinterpret_cast<int32_t*>(ws + L.arrive),
-                                            reinterpret_cast<int32_t*>(ws + L.global_ok), blocks);
+                                            reinterpret_cast<int32_t*>(ws + L.global_ok), blocks,
+                                            tree_levels_launched(N, L.P, L.max_cell));
 }
 
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
@@ -607,7 +611,9 @@ void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, con
     const int G = group_for(K);
     const TreeFn fn = pass == kTreeGrad ? tree_function<kStats + 2, 4>(G) : tree_function<kStats, 3>(G);
     const int PS = pass == kTreeGrad ? L.ps_grad : L.ps_fit;
-    const int levels = tree_levels((N + L.P - 1) / L.P);  // bound: the device skips levels it does not need
+    // a bound from the caller's largest cell (else all samples in one cell); the device
+    // skips levels no cell needs
+    const int levels = tree_levels_launched(N, L.P, L.max_cell);
     for (int level = 1; level <= levels; ++level) {
         const int psl = L.ps + kTreeLog2R * level;
         int64_t lo = 0, hi = (int64_t)C + ((N + (int64_t(1) << psl) - 1) >> psl);
@@ -733,7 +739,8 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
     if (opts->iters < 1 || opts->min_samples < 0) return SDMM_EINVAL;
     if (!mix->weights || !mix->mean_dir || !mix->mean_pos || !mix->cov) return SDMM_EINVAL;
     if (opts->min_range < 0 || opts->max_ranges < 0 || opts->max_ranges > (1 << 20)) return SDMM_EINVAL;
-    if (opts->waves_per_block < 0 || opts->waves_per_block > 4 || opts->waves_per_block == 3 || opts->reserved != 0)
+    if (opts->waves_per_block < 0 || opts->waves_per_block > 4 || opts->waves_per_block == 3 ||
+        opts->max_cell_samples < 0)
         return SDMM_EINVAL;
     if (opts->flags & ~(SDMM_FLAG_ESTEP_JACOBIAN | SDMM_FLAG_PLAIN_FP32 | SDMM_FLAG_FP64_SUMS | SDMM_FLAG_ACCURATE_SIGMA))
         return SDMM_EINVAL;

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(const int64_t* __res
     double S[NS], X[4];
     int64_t first = 0, n_items = 0;
     const bool have = wave_ok && cell_items(off, N, c, ps, first, n_items);
-    const int lv = *global_ok ? tree_levels(global_ok[1]) : 0;  // top leaders of the record tree
+    const int lv = *global_ok ? tree_levels_done(global_ok) : 0;  // top leaders of the record tree
     sum_cell_records<G, NS, 4>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
     const double W = X[0], Mc = X[1], negs = X[2], LL = X[3];
     int fin = isfinite(W) && isfinite(LL);

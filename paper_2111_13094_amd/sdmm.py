@@ -38,7 +38,7 @@ class FitOpts(C.Structure):
         ("K", C.c_int32), ("iters", C.c_int32), ("eta_mode", C.c_int32), ("prior_mode", C.c_int32),
         ("flags", C.c_int32), ("min_samples", C.c_int32), ("schedule", C.c_int32), ("min_range", C.c_int32),
         ("max_ranges", C.c_int32), ("use_graph", C.c_int32), ("waves_per_block", C.c_int32),
-        ("reserved", C.c_int32),
+        ("max_cell_samples", C.c_int32),
         ("eta", C.c_double), ("rm_alpha", C.c_double), ("rm_beta", C.c_double), ("prior_scale", C.c_double),
         ("prior_q", C.c_double), ("prior_a", C.c_double), ("prior_b", C.c_double * 5),
         ("dead_threshold", C.c_double),

@@ -298,6 +298,42 @@ def test_record_tree_schedules(dev, orc):
         assert_close(worst, rtol=2e-4, ang_tol=2e-5, what=name)
 
 
+def test_max_cell_samples_hint(dev, orc):
+    """The caller's bound on samples per cell only sets how many record-tree levels are
+    launched. An exact bound gives the same bits as no bound; a bound below the largest
+    cell launches too few levels, and the M-step then sums more records: the same
+    result up to FP64 rounding of the different summation order."""
+    print("case: max_cell_samples hint, 120000-sample cell in 64-sample items", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("single", seed=17)
+    counts = [120000, 300, 0, 5000, 64, 2000, 17, 900]
+    b = synth.make_batch(19, counts, np.tile(wl["box_lo"], (8, 1)), np.tile(wl["box_size"], (8, 1)), wl["lobes"])
+    C = len(counts)
+    lo, size = np.tile(wl["box_lo"], (C, 1)), np.tile(wl["box_size"], (C, 1))
+    mix0 = synth.initial_mixtures(lo, size, 16)
+    runs, stats = {}, {}
+    # 1875 items of 64 samples in the big cell need one level; a bound of 200000 launches
+    # two (the second does nothing), one of 1000 launches none
+    for name, hint in (("none", 0), ("exact", 120000), ("above", 200000), ("below", 1000)):
+        for sched in (sdmm.SCHED_BATCHED, sdmm.SCHED_PER_CELL):
+            gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+            stats[(name, sched)] = _gpu_fit(dev, b, gm, gst, iters=2, schedule=sched, min_range=64,
+                                            max_ranges=1 << 20, max_cell_samples=hint)
+            runs[(name, sched)] = to_numpy(gm)
+    ref = runs[("none", sdmm.SCHED_BATCHED)]
+    for key, got in runs.items():
+        assert (stats[key] == stats[("none", sdmm.SCHED_BATCHED)]).all(), key
+        for k in ref:
+            if key[0] != "below":
+                assert np.array_equal(got[k], ref[k]), (key, k)
+            else:
+                assert np.allclose(got[k], ref[k], rtol=1e-10, atol=1e-13), (key, k)
+    o = sdmm.default_opts(16, max_cell_samples=-1)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
+    with pytest.raises(RuntimeError):
+        sdmm.fit_mixtures(dev.from_numpy(b.offsets).cuda(), dev.from_numpy(b.samples).cuda(), gm, gst, o)
+
+
 def test_unsorted_offsets_mark_every_cell_bad_input(dev, orc):
     """Offsets that decrease somewhere are rejected on the device: every cell reports
     BAD_INPUT and no parameter changes, as in the oracle."""
