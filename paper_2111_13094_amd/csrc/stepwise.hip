@@ -2,15 +2,16 @@
 // the paper weighs in Sec. 6 ("Mini-batch EM versus stepwise EM"; Cappe and Moulines 2009,
 // weighted as in Vorba et al. 2014).
 //
-// One wave per cell, lane k = component k, FP64 throughout, samples in index order. Per
-// sample with positive weight: the responsibilities under the current parameters (log
-// map, quadratic form through the Cholesky factor, a log-sum-exp over the lanes), the
-// Robbins-Monro blend for the cell's sample counter, and the MAP update of
-// component_map_update with a mini-batch of one (beta = eta unless fixed); then the
-// component's frame, factor and log constant are rebuilt for the next sample. A fresh
-// cell (step 0) first accumulates the statistics of its whole batch in the same sample
-// order and takes one batch step. The chain is sequential within a cell; cells run in
-// parallel.
+// One wave per cell, lane k = component k (the first G = K rounded up to a power of two
+// lanes), FP64 throughout, samples in index order. Per sample with positive weight: the
+// responsibilities under the current parameters (log map, quadratic form through the
+// Cholesky factor, a log-sum-exp over the component lanes), the Robbins-Monro blend for
+// the cell's sample counter, and the MAP update of component_map_update with a
+// mini-batch of one (beta = eta unless fixed); then the component's frame, factor and log
+// constant are rebuilt for the next sample. A fresh cell (step 0) first accumulates the
+// statistics of its whole batch in the same sample order and takes one batch step. The chain is sequential within a cell; cells run in parallel, so
+// the pass lasts as long as its largest cell: the per-sample reductions run within the
+// component lanes (DPP) and every flag is a ballot.
 #include "common.hpp"
 #include "mstep_math.hpp"
 #include "timing.hpp"
@@ -23,18 +24,43 @@ __device__ __forceinline__ double wave_sum_d(double v)
     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
     return v;
 }
-__device__ __forceinline__ double wave_max_d(double v)
+
+// an FP64 value of the lane given by a DPP pattern of the row (both halves moved)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true));
+}
+
+// sum / maximum over each group of G consecutive lanes (every lane of a group gets it):
+// DPP inside rows of 16 lanes, shuffles across rows
+template <int G>
+__device__ __forceinline__ double group_sum_fp64(double v)
+{
+    if constexpr (G >= 2) v += dpp_d<kDppXor1>(v);
+    if constexpr (G >= 4) v += dpp_d<kDppXor2>(v);
+    if constexpr (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_d<kDppMirror>(v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32);
     return v;
 }
-__device__ __forceinline__ int wave_or(int v)
+template <int G>
+__device__ __forceinline__ double group_max_fp64(double v)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v |= __shfl_xor(v, o);
+    if constexpr (G >= 2) v = fmax(v, dpp_d<kDppXor1>(v));
+    if constexpr (G >= 4) v = fmax(v, dpp_d<kDppXor2>(v));
+    if constexpr (G >= 8) v = fmax(v, dpp_d<kDppHalfMirror>(v));
+    if constexpr (G >= 16) v = fmax(v, dpp_d<kDppMirror>(v));
+    if constexpr (G >= 32) v = fmax(v, __shfl_xor(v, 16));
+    if constexpr (G >= 64) v = fmax(v, __shfl_xor(v, 32));
     return v;
 }
+
+// any lane of the wave
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
 // a component prepared for the E-step: frame, positional mean, Cholesky factor with its
 // reciprocal diagonal, log pi - log det L - (5/2) log 2 pi
@@ -42,6 +68,23 @@ struct Comp64 {
     double R[9], mx[3], L[15], rd[5], logc;
     bool ok;
 };
+
+__device__ inline void make_inert(Comp64& c)
+{
+    c.ok = false;
+    c.logc = -INFINITY;
+    for (int i = 0; i < 9; ++i) c.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int i = 0; i < 15; ++i) c.L[i] = 0.0;
+    for (int d = 0; d < 5; ++d) c.L[tri(d, d)] = c.rd[d] = 1.0;
+}
+
+// the log constant from the weight and the factor
+__device__ __forceinline__ void set_log_constant(Comp64& c, double pi)
+{
+    double ld = 0.0;
+    for (int d = 0; d < 5; ++d) ld += log(c.L[tri(d, d)]);
+    c.logc = log(pi) - ld - 2.5 * kLn2Pi;
+}
 
 __device__ inline void load_comp(const MixPtrs& mix, int64_t g, Comp64& c)
 {
@@ -56,19 +99,12 @@ __device__ inline void load_comp(const MixPtrs& mix, int64_t g, Comp64& c)
     ok = ok && chol64<5>(mix.cov + 15 * g, c.L);
     c.ok = ok;
     if (!ok) {
-        c.logc = -INFINITY;
-        for (int i = 0; i < 9; ++i) c.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
-        for (int i = 0; i < 15; ++i) c.L[i] = 0.0;
-        for (int d = 0; d < 5; ++d) c.L[tri(d, d)] = c.rd[d] = 1.0;
+        make_inert(c);
         return;
     }
     frame64(mu, c.R);
-    double ld = 0.0;
-    for (int d = 0; d < 5; ++d) {
-        c.rd[d] = 1.0 / c.L[tri(d, d)];
-        ld += log(c.L[tri(d, d)]);
-    }
-    c.logc = log(pi) - ld - 2.5 * kLn2Pi;
+    for (int d = 0; d < 5; ++d) c.rd[d] = 1.0 / c.L[tri(d, d)];
+    set_log_constant(c, pi);
 }
 
 // tangent coordinates of a sample and the component's log density there
@@ -103,6 +139,7 @@ __device__ inline double comp_log_density(const Comp64& c, const double w[3], co
     return l;
 }
 
+template <int G>
 __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict__ off, int64_t N,
                                                        const float* __restrict__ smp, int C, MixPtrs mix,
                                                        StatePtrs st, DevOpts o, int iters,
@@ -125,25 +162,25 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
     Comp64 cp;
     load_comp(mix, g, cp);
     for (int it = 0; it < iters; ++it) {
-        // the cell gate over the whole batch
-        int bad = !range_ok;
+        // the cell gate over the whole batch, all 64 lanes
+        bool bad = !range_ok;
         double Wt = 0.0, Mt = 0.0;
         if (range_ok) {
             for (int64_t i = i0 + k; i < i1; i += 64) {
                 const float wi = smp[6 * N + i];
                 bool b = wi < 0.0f;
                 for (int a = 0; a < 7; ++a) b = b || !isfinite(smp[a * N + i]);
-                bad |= b ? 1 : 0;
+                bad = bad || b;
                 Wt += (double)wi;
                 Mt += wi > 0.0f ? 1.0 : 0.0;
             }
         }
-        bad = wave_or(bad);
+        const bool any_bad = wave_any(bad);
         Wt = wave_sum_d(Wt);
         Mt = wave_sum_d(Mt);
-        const int badp = wave_or(act && !cp.ok ? 1 : 0);
+        const bool badp = wave_any(act && !cp.ok);
         int gate = 0;
-        if (bad) gate = kBadInput;
+        if (any_bad) gate = kBadInput;
         else if (badp) gate = kBadParams;
         else if (Mt < (double)o.min_samples) gate = kSkippedFew;
         else if (!(Wt > 0.0)) gate = kSkippedZeroW;
@@ -155,7 +192,7 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
         double S[21];
         double Wb = 0.0, Mb = 0.0;
         for (int q = 0; q < 21; ++q) S[q] = 0.0;
-        int stop = 0;
+        bool stop = false;
         for (int64_t i = i0; i < i1 && !stop; ++i) {
             const double wi = (double)smp[6 * N + i];
             if (fresh) {
@@ -169,10 +206,12 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             double y[5];
             double l = comp_log_density(cp, w, p, jac, y);
             if (!act) l = -INFINITY;
-            const double lmax = wave_max_d(l);
+            // the log-sum-exp over the component lanes (the first G lanes hold the cell's
+            // components; the other groups of G lanes hold only inactive lanes)
+            const double lmax = group_max_fp64<G>(l);
             const double e = act ? exp(l - lmax) : 0.0;
-            const double den = wave_sum_d(e);
-            const double wr = wi * (e / den);
+            const double den = group_sum_fp64<G>(e);
+            const double wr = act ? wi * (e / den) : 0.0;
             if (fresh) {
                 S[0] += wr;
                 for (int d = 0; d < 5; ++d) {
@@ -191,9 +230,9 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             Mb = 1.0;
             bool fin = isfinite(Wb);
             for (int q = 0; q < 21; ++q) fin = fin && isfinite(S[q]);
-            if (wave_or(act && !fin ? 1 : 0)) {
+            if (wave_any(act && !fin)) {
                 st_bits |= kBadInput;
-                stop = 1;
+                stop = true;
                 break;
             }
             const double eta = rm_eta(o, j);
@@ -206,7 +245,7 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
                 for (int q = 0; q < 15; ++q) hS2[q] = (1.0 - eta) * st.s2[g * 15 + q] + eta * S[6 + q];
             }
             const double bar0 = act ? hS0 / hW : 0.0;
-            const double sum0 = wave_sum_d(bar0);
+            const double sum0 = group_sum_fp64<G>(bar0);
             int dead = 0, cholfail = 0;
             if (act) {
                 const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
@@ -216,7 +255,7 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
             }
-            st_bits |= (wave_or(dead) ? kDeadComponent : 0) | (wave_or(cholfail) ? kCholFailKeptPrev : 0);
+            st_bits |= (wave_any(dead) ? kDeadComponent : 0) | (wave_any(cholfail) ? kCholFailKeptPrev : 0);
             sw = hW;
             ++j;
         }
@@ -224,13 +263,13 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
         if (fresh) {  // one batch step with the accumulated statistics
             bool fin = isfinite(Wb);
             for (int q = 0; q < 21; ++q) fin = fin && isfinite(S[q]);
-            if (wave_or(act && !fin ? 1 : 0)) {
+            if (wave_any(act && !fin)) {
                 st_bits |= kBadInput;
                 break;
             }
             const double beta = o.prior_mode == 0 ? 1.0 / fmax(Mb, 1.0) : o.prior_scale;
             const double bar0 = act ? S[0] / Wb : 0.0;
-            const double sum0 = wave_sum_d(bar0);
+            const double sum0 = group_sum_fp64<G>(bar0);
             int dead = 0, cholfail = 0;
             if (act) {
                 const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
@@ -240,7 +279,7 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
             }
-            st_bits |= (wave_or(dead) ? kDeadComponent : 0) | (wave_or(cholfail) ? kCholFailKeptPrev : 0);
+            st_bits |= (wave_any(dead) ? kDeadComponent : 0) | (wave_any(cholfail) ? kCholFailKeptPrev : 0);
             sw = Wb;
             j = 1;
         }
@@ -260,9 +299,23 @@ void launch_stepwise(const int64_t* off, const float* smp, int64_t N, const sdmm
     const MixPtrs mp{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov};
     const StatePtrs sp{st.s0, st.s2, st.sw, st.step};
     ScopedTimer tm(SDMM_TIMER_STEPWISE, s);
-    stepwise_kernel<<<(C + 3) / 4, 256, 0, s>>>(off, N, smp, C, mp, sp, dev_opts(&opts), opts.iters,
-                                                reinterpret_cast<const int32_t*>(ws + L.flags),
-                                                reinterpret_cast<const int32_t*>(ws + L.global_ok), status);
+    const int32_t* fl = reinterpret_cast<const int32_t*>(ws + L.flags);
+    const int32_t* ctl = reinterpret_cast<const int32_t*>(ws + L.global_ok);
+    const DevOpts d = dev_opts(&opts);
+    const unsigned blocks = (unsigned)((C + 3) / 4);
+    switch (group_for(opts.K)) {
+        case 4: stepwise_kernel<4><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
+        case 8: stepwise_kernel<8><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
+        case 16:
+            stepwise_kernel<16><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            break;
+        case 32:
+            stepwise_kernel<32><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            break;
+        default:
+            stepwise_kernel<64><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            break;
+    }
 }
 
 }  // namespace sdmm
