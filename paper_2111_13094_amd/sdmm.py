@@ -106,6 +106,22 @@ def _ptr(t: torch.Tensor | None, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(t: torch.Tensor | None, n: int, what: str):
+    """Size check before a launch: the C ABI takes bare pointers, so a tensor smaller than
+    its documented layout would let a kernel access memory past its end."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {n}")
+
+
+def _state_ptrs(state: dict, n_cells: int, K: int):
+    for key, n in (("s0", n_cells * K), ("s2", n_cells * K * 15), ("sw", n_cells), ("step", n_cells)):
+        _need(state[key], n, f"state[{key!r}]")
+    st = EmState()
+    st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
+    st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
+    return st
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
@@ -192,13 +208,12 @@ def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, s
     N = samples.shape[1]
     if status is None:
         status = torch.empty(n_cells, dtype=torch.int32, device=samples.device)
+    _need(status, n_cells, "status")
     nbytes = workspace_bytes(n_cells, K, N, opts)
     if workspace is None:
         workspace = _workspace(nbytes, samples.device)
     m = _mixtures(mix, n_cells, K)
-    st = EmState()
-    st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
-    st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
+    st = _state_ptrs(state, n_cells, K)
     rc = lib().sdmm_fit_mixtures(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N, C.byref(m),
                                  C.byref(st), C.byref(opts), _ptr(status, torch.int32), _ptr(workspace),
                                  workspace.numel(), _stream(stream))
@@ -209,6 +224,7 @@ def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, s
 def condition_prepare(mix: dict, n_cells: int, K: int, table: torch.Tensor | None = None, stream=None):
     if table is None:
         table = torch.empty(n_cells * K * COND_TABLE_STRIDE, dtype=torch.float32, device=mix["pi"].device)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
     m = _mixtures(mix, n_cells, K)
     _check(lib().sdmm_condition_prepare(C.byref(m), _ptr(table, torch.float32), _stream(stream)),
            "sdmm_condition_prepare")
@@ -218,6 +234,8 @@ def condition_prepare(mix: dict, n_cells: int, K: int, table: torch.Tensor | Non
 def condition(table, n_cells, K, qpos, qcell, stream=None):
     """qpos float32 [3, nq]; qcell int32 [nq]. Returns (cond_w [nq, K], cond_m [nq, K, 2])."""
     nq = qcell.numel()
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
+    _need(qpos, 3 * nq, "qpos")
     cw = torch.empty(nq, K, dtype=torch.float32, device=qcell.device)
     cm = torch.empty(nq, K, 2, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_condition(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
@@ -228,6 +246,10 @@ def condition(table, n_cells, K, qpos, qcell, stream=None):
 def pdf(table, n_cells, K, qcell, cond_w, cond_m, dirs, nd, stream=None):
     """dirs float32 [3, nq*nd]. Returns pdf float32 [nq*nd]."""
     nq = qcell.numel()
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
+    _need(cond_w, nq * K, "cond_w")
+    _need(cond_m, nq * K * 2, "cond_m")
+    _need(dirs, 3 * nq * nd, "dirs")
     out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qcell, torch.int32), nq,
                           _ptr(cond_w, torch.float32), _ptr(cond_m, torch.float32), nd, _ptr(dirs, torch.float32),
@@ -241,6 +263,10 @@ def sample(table, n_cells, K, qcell, cond_w, cond_m, ns, uniforms=None, seed=0, 
     nq = qcell.numel()
     dev = qcell.device
     n = nq * ns
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
+    _need(cond_w, nq * K, "cond_w")
+    _need(cond_m, nq * K * 2, "cond_m")
+    _need(uniforms, 3 * n, "uniforms")
     dirs = torch.empty(3, n, dtype=torch.float32, device=dev)
     pdfv = torch.empty(n, dtype=torch.float32, device=dev)
     valid = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -261,11 +287,25 @@ def condition_sample_pdf(table, n_cells, K, qpos, qcell, ns, uniforms=None, seed
         out = (torch.empty(3, n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.uint8, device=dev))
     dirs, pdfv, valid = out
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
+    _need(qpos, 3 * nq, "qpos")
+    _need(uniforms, 3 * n, "uniforms")
+    for t, m, what in ((dirs, 3 * n, "dirs"), (pdfv, n, "pdf"), (valid, n, "valid")):
+        _need(t, m, what)
     _check(lib().sdmm_condition_sample_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                            _ptr(qcell, torch.int32), nq, ns, _ptr(uniforms, torch.float32), seed,
                                            _ptr(dirs), _ptr(pdfv), _ptr(valid), _stream(stream)),
            "sdmm_condition_sample_pdf")
     return dirs, pdfv, valid
+
+
+def _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq):
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
+    _need(btable, n_bsdf * Kb * COND_TABLE_STRIDE, "btable")
+    _need(qpos, 3 * nq, "qpos")
+    _need(bpar, 3 * nq, "bpar")
+    _need(bcell, nq, "bcell")
+    _need(frames, 9 * nq, "frames")
 
 
 def product_sample(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, ns, uniforms=None, seed=0,
@@ -281,6 +321,10 @@ def product_sample(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bce
                torch.empty(n, dtype=torch.uint8, device=dev),
                torch.empty(n, dtype=torch.int32, device=dev) if with_pair else None)
     dirs, pdfv, valid, pair = out
+    _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
+    _need(uniforms, 3 * n, "uniforms")
+    for t, m, what in ((dirs, 3 * n, "dirs"), (pdfv, n, "pdf"), (valid, n, "valid"), (pair, n, "pair")):
+        _need(t, m, what)
     _check(lib().sdmm_product_sample(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                      _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
                                      _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
@@ -293,6 +337,8 @@ def product_pdf(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell,
     """Product density at dirs float32 [3, nq*nd]. Returns pdf [nq*nd]."""
     nq = qcell.numel()
     nd = dirs.shape[1] // max(nq, 1)
+    _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
+    _need(dirs, 3 * nq * nd, "dirs")
     out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_product_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                   _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
@@ -331,6 +377,8 @@ def tree_refine(t: dict, samples, split_threshold, mix: dict, state: dict, K, mi
                 stream=None):
     """Refines the tree with samples float32 [7, N]; mix / state hold max_leaves cells.
     Returns (sorted samples [7, N], cell offsets int64 [n_leaves + 1], n_leaves, status)."""
+    if samples.dim() != 2 or samples.shape[0] != 7:
+        raise ValueError("samples must be [7, N]")
     N = samples.shape[1]
     dev = samples.device
     sorted_ = torch.empty_like(samples)
@@ -339,9 +387,7 @@ def tree_refine(t: dict, samples, split_threshold, mix: dict, state: dict, K, mi
     if workspace is None:
         workspace = _workspace(nbytes, dev)
     m = _mixtures(mix, t["max_leaves"], K)
-    st = EmState()
-    st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
-    st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
+    st = _state_ptrs(state, t["max_leaves"], K)
     nl, status = C.c_int32(0), C.c_int32(0)
     tt = _tree(t)
     _check(lib().sdmm_tree_refine(C.byref(tt), _ptr(samples, torch.float32), N, split_threshold, min_init, C.byref(m),
@@ -355,6 +401,8 @@ def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=N
     """F and its gradient per cell (sdmm_fit_grad). Returns a dict of device tensors."""
     n_cells = cell_offsets.numel() - 1
     K = opts.K
+    if samples.dim() != 2 or samples.shape[0] != 7:
+        raise ValueError("samples must be [7, N]")
     N = samples.shape[1]
     dev = samples.device
     out = {"F": torch.empty(n_cells, dtype=torch.float64, device=dev),
@@ -380,6 +428,10 @@ def mixture_from_params(alpha, mu_dir0, delta, mu_pos, L, out=None, with_jac=Tru
     (sdmm_mixture_from_params); returns (mixture dict, 2x2 Jacobians or None)."""
     n_cells, K = alpha.shape[0], alpha.shape[1]
     dev = alpha.device
+    for t, m, what in ((alpha, n_cells * K, "alpha"), (mu_dir0, n_cells * K * 3, "mu_dir0"),
+                       (delta, n_cells * K * 2, "delta"), (mu_pos, n_cells * K * 3, "mu_pos"),
+                       (L, n_cells * K * 15, "L")):
+        _need(t, m, what)
     if out is None:
         out = {"pi": torch.empty(n_cells * K, dtype=torch.float64, device=dev),
                "mu_dir": torch.empty(n_cells * K * 3, dtype=torch.float64, device=dev),
@@ -397,6 +449,9 @@ def mixture_from_params(alpha, mu_dir0, delta, mu_pos, L, out=None, with_jac=Tru
 def grad_to_params(L, jac, g_delta, g_L, stream=None):
     """In-place pull-back of sdmm_fit_grad's delta and L gradients (sdmm_grad_to_params)."""
     n_cells, K = L.shape[0], L.shape[1]
+    for t, m, what in ((L, n_cells * K * 15, "L"), (jac, n_cells * K * 4, "jac"), (g_delta, n_cells * K * 2, "g_delta"),
+                       (g_L, n_cells * K * 15, "g_L")):
+        _need(t, m, what)
     rc = lib().sdmm_grad_to_params(n_cells, K, _ptr(L), _ptr(jac), _ptr(g_delta), _ptr(g_L), _stream(stream))
     _check(rc, "sdmm_grad_to_params")
 

@@ -92,3 +92,27 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == C.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_binding_rejects_undersized_tensors():
+    """The C ABI sees bare pointers, so the binding checks every tensor against the size
+    its layout needs before anything reaches the library."""
+    import torch
+    from paper_2111_13094_amd import sdmm
+    K, n_cells, nq = 16, 4, 8
+    full = n_cells * K * sdmm.COND_TABLE_STRIDE
+    qcell = torch.zeros(nq, dtype=torch.int32)
+    with pytest.raises(ValueError, match="table"):
+        sdmm.condition(torch.zeros(full - 1), n_cells, K, torch.zeros(3, nq), qcell)
+    with pytest.raises(ValueError, match="qpos"):
+        sdmm.condition(torch.zeros(full), n_cells, K, torch.zeros(3, nq - 1), qcell)
+    cw, cm = torch.zeros(nq, K), torch.zeros(nq, K, 2)
+    with pytest.raises(ValueError, match="dirs"):
+        sdmm.pdf(torch.zeros(full), n_cells, K, qcell, cw, cm, torch.zeros(3, nq * 2 - 1), 2)
+    with pytest.raises(ValueError, match="cond_m"):
+        sdmm.pdf(torch.zeros(full), n_cells, K, qcell, cw, cm[:-1], torch.zeros(3, nq * 2), 2)
+    with pytest.raises(ValueError, match="uniforms"):
+        sdmm.sample(torch.zeros(full), n_cells, K, qcell, cw, cm, 4, uniforms=torch.zeros(3, nq * 4 - 1))
+    off = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int64)
+    with pytest.raises(ValueError, match="status"):
+        sdmm.fit_mixtures(off, torch.zeros(7, 4), {}, {}, sdmm.default_opts(K), status=torch.zeros(3, dtype=torch.int32))
