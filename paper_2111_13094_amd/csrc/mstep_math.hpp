@@ -24,11 +24,12 @@ __device__ __forceinline__ double rm_eta(const DevOpts& o, int j)
 // new frame by T = blkdiag(J, I3) and Sigma = (beta B + T C T^T / hW) / (beta a + bar0)
 // replaces the covariance if it is SPD (else cholfail); the carried statistics become
 // hS0 and T C T^T. The weight is left to the caller (it needs the cell's sum of bar0).
+// When fac is given, the Cholesky factor of a replacing covariance is written there too.
 __device__ inline void component_map_update(double hS0, const double* hS1, const double* hS2, double hW,
                                             double beta, double bar0, const DevOpts& o, bool cov_update,
                                             const double mu_in[3], const double mux_in[3], double* mud,
                                             double* mux, double* cov, double* s0, double* s2, int& dead,
-                                            int& cholfail)
+                                            int& cholfail, double* fac = nullptr)
 {
     if (!(bar0 > o.dead_threshold)) {
         dead = 1;
@@ -86,6 +87,8 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
         }
     if (chol64<5>(Sig, Lt)) {
         for (int q = 0; q < 15; ++q) cov[q] = Sig[q];
+        if (fac)
+            for (int q = 0; q < 15; ++q) fac[q] = Lt[q];
     } else {
         cholfail = 1;
     }

@@ -139,18 +139,87 @@ __device__ inline double comp_log_density(const Comp64& c, const double w[3], co
     return l;
 }
 
-template <int G>
-__global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict__ off, int64_t N,
-                                                       const float* __restrict__ smp, int C, MixPtrs mix,
-                                                       StatePtrs st, DevOpts o, int iters,
-                                                       const int32_t* __restrict__ flags,
-                                                       const int32_t* __restrict__ control,
-                                                       int32_t* __restrict__ status)
+// Samples reach the chain through LDS, 64 at a time: lane l loads sample base + l of
+// every channel (coalesced; lanes past the end reload the last sample), the loads of the
+// next 64 are in flight while the current ones are used, and each step reads its sample
+// from LDS by broadcast. No global load is left on the per-sample chain.
+__device__ __forceinline__ void stage_fetch(const float* smp, int64_t N, int64_t i, int64_t last, float pre[7])
 {
-    const int c = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int64_t ii = i < last ? i : last;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) pre[a] = smp[a * N + ii];
+}
+
+__device__ __forceinline__ void stage_store(float4 (*stage)[2], int lane, const float pre[7])
+{
+    __syncthreads();  // the wave is done reading the previous 64
+    stage[lane][0] = make_float4(pre[0], pre[1], pre[2], pre[3]);
+    stage[lane][1] = make_float4(pre[4], pre[5], pre[6], 0.0f);
+    __syncthreads();
+}
+
+// Each lane keeps its component in E-step form and its carried statistics in LDS, slot
+// by slot with the 64 lanes of a slot contiguous (conflict-free), the factor as one row
+// of 15 per lane (the update writes a new factor there itself): the E-step copies the
+// component into registers for its own span only, and the update, which needs many
+// registers of its own, runs without it.
+constexpr int kSlotR = 0, kSlotMx = 9, kSlotRd = 12, kSlotLogc = 17, kCompSlots = 18;
+
+__device__ __forceinline__ void comp_put(double (*cs)[64], double* Ls, int lane, const Comp64& c, bool with_L)
+{
+    for (int q = 0; q < 9; ++q) cs[kSlotR + q][lane] = c.R[q];
+    for (int d = 0; d < 3; ++d) cs[kSlotMx + d][lane] = c.mx[d];
+    if (with_L)
+        for (int q = 0; q < 15; ++q) Ls[q] = c.L[q];
+    for (int d = 0; d < 5; ++d) cs[kSlotRd + d][lane] = c.rd[d];
+    cs[kSlotLogc][lane] = c.logc;
+}
+
+__device__ __forceinline__ void comp_get(double (*cs)[64], const double* Ls, int lane, bool ok, Comp64& c)
+{
+    for (int q = 0; q < 9; ++q) c.R[q] = cs[kSlotR + q][lane];
+    for (int d = 0; d < 3; ++d) c.mx[d] = cs[kSlotMx + d][lane];
+    for (int q = 0; q < 15; ++q) c.L[q] = Ls[q];
+    for (int d = 0; d < 5; ++d) c.rd[d] = cs[kSlotRd + d][lane];
+    c.logc = cs[kSlotLogc][lane];
+    c.ok = ok;
+}
+
+// The component in E-step form after an update that replaced the covariance of a usable
+// component, from what the update produced: the new mean's frame, the new positional
+// mean, the diagonal of the update's own factor of the new covariance (the whole factor
+// is already in LDS) and the new weight. This equals load_comp of the stored values:
+// from finite statistics the new direction is a unit vector, the positional mean moves
+// by a finite weighted mean, and the weight's denominator is at least this component's
+// bar0, above the dead threshold, so load_comp's finiteness checks would pass.
+__device__ __forceinline__ void refresh_comp(Comp64& c, const double mu[3], const double mx[3], const double* L,
+                                             double pi)
+{
+    c.ok = true;
+    frame64(mu, c.R);
+    for (int d = 0; d < 3; ++d) c.mx[d] = mx[d];
+    for (int d = 0; d < 5; ++d) c.L[tri(d, d)] = L[tri(d, d)];
+    for (int d = 0; d < 5; ++d) c.rd[d] = 1.0 / c.L[tri(d, d)];
+    set_log_constant(c, pi);
+}
+
+// One wave (= one work group) per cell.
+template <int G>
+__global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict__ off, int64_t N,
+                                                      const float* __restrict__ smp, int C, MixPtrs mix,
+                                                      StatePtrs st, DevOpts o, int iters,
+                                                      const int32_t* __restrict__ flags,
+                                                      const int32_t* __restrict__ control,
+                                                      int32_t* __restrict__ status)
+{
+    __shared__ float4 stage[64][2];
+    __shared__ double comp[kCompSlots][64];
+    __shared__ double stat[16][64];  // s0, then s2
+    __shared__ double Lsh[64][15];
+    const int c = blockIdx.x;
     if (c >= C) return;
     const int K = o.K;
-    const int k = threadIdx.x & 63;
+    const int k = threadIdx.x;
     const bool act = k < K;
     const int64_t g = (int64_t)c * K + (act ? k : 0);
     const bool jac = (o.flags & SDMM_FLAG_ESTEP_JACOBIAN) != 0;
@@ -159,8 +228,14 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
     const bool range_ok = control[0] && !(flags[c] & kFlagBadRange);
     int j = st.step[c];
     double sw = st.sw[c];
-    Comp64 cp;
-    load_comp(mix, g, cp);
+    for (int q = 0; q < 16; ++q) stat[q][k] = q == 0 ? st.s0[g] : st.s2[g * 15 + q - 1];
+    bool cok;
+    {
+        Comp64 cp;
+        load_comp(mix, g, cp);
+        comp_put(comp, Lsh[k], k, cp, true);
+        cok = cp.ok;
+    }
     for (int it = 0; it < iters; ++it) {
         // the cell gate over the whole batch, all 64 lanes
         bool bad = !range_ok;
@@ -178,7 +253,7 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
         const bool any_bad = wave_any(bad);
         Wt = wave_sum_d(Wt);
         Mt = wave_sum_d(Mt);
-        const bool badp = wave_any(act && !cp.ok);
+        const bool badp = wave_any(act && !cok);
         int gate = 0;
         if (any_bad) gate = kBadInput;
         else if (badp) gate = kBadParams;
@@ -188,79 +263,42 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             st_bits |= gate;
             break;
         }
-        const bool fresh = j == 0;
-        double S[21];
-        double Wb = 0.0, Mb = 0.0;
-        for (int q = 0; q < 21; ++q) S[q] = 0.0;
-        bool stop = false;
-        for (int64_t i = i0; i < i1 && !stop; ++i) {
-            const double wi = (double)smp[6 * N + i];
-            if (fresh) {
-                Wb += wi;
-                Mb += wi > 0.0 ? 1.0 : 0.0;
-            } else if (!(wi > 0.0)) {
-                continue;
-            }
-            const double w[3] = {(double)smp[i], (double)smp[N + i], (double)smp[2 * N + i]};
-            const double p[3] = {(double)smp[3 * N + i], (double)smp[4 * N + i], (double)smp[5 * N + i]};
-            double y[5];
-            double l = comp_log_density(cp, w, p, jac, y);
-            if (!act) l = -INFINITY;
-            // the log-sum-exp over the component lanes (the first G lanes hold the cell's
-            // components; the other groups of G lanes hold only inactive lanes)
-            const double lmax = group_max_fp64<G>(l);
-            const double e = act ? exp(l - lmax) : 0.0;
-            const double den = group_sum_fp64<G>(e);
-            const double wr = act ? wi * (e / den) : 0.0;
-            if (fresh) {
-                S[0] += wr;
-                for (int d = 0; d < 5; ++d) {
-                    S[1 + d] += wr * y[d];
-                    for (int f = 0; f <= d; ++f) S[6 + tri(d, f)] += wr * y[d] * y[f];
+        // (the gate passed, so i0 < i1 <= N)
+        float pre[7];
+        stage_fetch(smp, N, i0 + k, i1 - 1, pre);
+        if (j == 0) {
+            // a fresh cell: the statistics of the whole batch in sample order, then one
+            // batch step
+            double S[21];
+            double Wb = 0.0, Mb = 0.0;
+            for (int q = 0; q < 21; ++q) S[q] = 0.0;
+            Comp64 cp;
+            comp_get(comp, Lsh[k], k, cok, cp);
+            for (int64_t base = i0; base < i1; base += 64) {
+                stage_store(stage, k, pre);
+                if (base + 64 < i1) stage_fetch(smp, N, base + 64 + k, i1 - 1, pre);
+                const int n = (int)(i1 - base < 64 ? i1 - base : 64);
+                for (int t = 0; t < n; ++t) {
+                    const float4 a = stage[t][0], b = stage[t][1];
+                    const double wi = (double)b.z;
+                    Wb += wi;
+                    Mb += wi > 0.0 ? 1.0 : 0.0;
+                    const double w[3] = {(double)a.x, (double)a.y, (double)a.z};
+                    const double p[3] = {(double)a.w, (double)b.x, (double)b.y};
+                    double y[5];
+                    double l = comp_log_density(cp, w, p, jac, y);
+                    if (!act) l = -INFINITY;
+                    const double lmax = group_max_fp64<G>(l);
+                    const double e = act ? exp(l - lmax) : 0.0;
+                    const double den = group_sum_fp64<G>(e);
+                    const double wr = act ? wi * (e / den) : 0.0;
+                    S[0] += wr;
+                    for (int d = 0; d < 5; ++d) {
+                        S[1 + d] += wr * y[d];
+                        for (int f = 0; f <= d; ++f) S[6 + tri(d, f)] += wr * y[d] * y[f];
+                    }
                 }
-                continue;
             }
-            // a mini-batch of one
-            S[0] = wr;
-            for (int d = 0; d < 5; ++d) {
-                S[1 + d] = wr * y[d];
-                for (int f = 0; f <= d; ++f) S[6 + tri(d, f)] = wr * y[d] * y[f];
-            }
-            Wb = wi;
-            Mb = 1.0;
-            bool fin = isfinite(Wb);
-            for (int q = 0; q < 21; ++q) fin = fin && isfinite(S[q]);
-            if (wave_any(act && !fin)) {
-                st_bits |= kBadInput;
-                stop = true;
-                break;
-            }
-            const double eta = rm_eta(o, j);
-            const double beta = o.prior_mode == 0 ? eta / fmax(Mb, 1.0) : o.prior_scale;
-            const double hW = (1.0 - eta) * sw + eta * Wb;
-            double hS0 = 0.0, hS1[5], hS2[15];
-            if (act) {
-                hS0 = (1.0 - eta) * st.s0[g] + eta * S[0];
-                for (int d = 0; d < 5; ++d) hS1[d] = eta * S[1 + d];
-                for (int q = 0; q < 15; ++q) hS2[q] = (1.0 - eta) * st.s2[g * 15 + q] + eta * S[6 + q];
-            }
-            const double bar0 = act ? hS0 / hW : 0.0;
-            const double sum0 = group_sum_fp64<G>(bar0);
-            int dead = 0, cholfail = 0;
-            if (act) {
-                const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
-                const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
-                component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, true, mu_in, mux_in, mix.mud + 3 * g,
-                                     mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
-                mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
-                load_comp(mix, g, cp);
-            }
-            st_bits |= (wave_any(dead) ? kDeadComponent : 0) | (wave_any(cholfail) ? kCholFailKeptPrev : 0);
-            sw = hW;
-            ++j;
-        }
-        if (stop) break;
-        if (fresh) {  // one batch step with the accumulated statistics
             bool fin = isfinite(Wb);
             for (int q = 0; q < 21; ++q) fin = fin && isfinite(S[q]);
             if (wave_any(act && !fin)) {
@@ -274,15 +312,113 @@ __global__ __launch_bounds__(256) void stepwise_kernel(const int64_t* __restrict
             if (act) {
                 const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
                 const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
+                double s0n, s2n[15];
                 component_map_update(S[0], S + 1, S + 6, Wb, beta, bar0, o, true, mu_in, mux_in, mix.mud + 3 * g,
-                                     mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
+                                     mix.mux + 3 * g, mix.cov + 15 * g, &s0n, s2n, dead, cholfail);
+                stat[0][k] = s0n;
+                for (int q = 0; q < 15; ++q) stat[1 + q][k] = s2n[q];
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
+                comp_put(comp, Lsh[k], k, cp, true);
+                cok = cp.ok;
             }
             st_bits |= (wave_any(dead) ? kDeadComponent : 0) | (wave_any(cholfail) ? kCholFailKeptPrev : 0);
             sw = Wb;
             j = 1;
+            continue;
         }
+        // every sample with positive weight is a mini-batch of one
+        bool stop = false;
+        for (int64_t base = i0; base < i1 && !stop; base += 64) {
+            stage_store(stage, k, pre);
+            if (base + 64 < i1) stage_fetch(smp, N, base + 64 + k, i1 - 1, pre);
+            const int n = (int)(i1 - base < 64 ? i1 - base : 64);
+            for (int t = 0; t < n; ++t) {
+                const float4 a = stage[t][0], b = stage[t][1];
+                const double wi = (double)b.z;
+                if (!(wi > 0.0)) continue;
+                const double eta = rm_eta(o, j);
+                double y[5], l, mu[3], mx[3];
+                {
+                    Comp64 cp;
+                    comp_get(comp, Lsh[k], k, cok, cp);
+                    const double w[3] = {(double)a.x, (double)a.y, (double)a.z};
+                    const double p[3] = {(double)a.w, (double)b.x, (double)b.y};
+                    l = comp_log_density(cp, w, p, jac, y);
+                    // the current means of a usable component (its frame's last row is its mean)
+                    for (int d = 0; d < 3; ++d) {
+                        mu[d] = cp.R[6 + d];
+                        mx[d] = cp.mx[d];
+                    }
+                }
+                if (!act) l = -INFINITY;
+                // the log-sum-exp over the component lanes (the first G lanes hold the
+                // cell's components; the other groups of G lanes hold only inactive lanes)
+                const double lmax = group_max_fp64<G>(l);
+                const double e = act ? exp(l - lmax) : 0.0;
+                const double den = group_sum_fp64<G>(e);
+                const double wr = act ? wi * (e / den) : 0.0;
+                double S[21];
+                S[0] = wr;
+                for (int d = 0; d < 5; ++d) {
+                    S[1 + d] = wr * y[d];
+                    for (int f = 0; f <= d; ++f) S[6 + tri(d, f)] = wr * y[d] * y[f];
+                }
+                bool fin = isfinite(wi);
+                for (int q = 0; q < 21; ++q) fin = fin && isfinite(S[q]);
+                if (wave_any(act && !fin)) {
+                    st_bits |= kBadInput;
+                    stop = true;
+                    break;
+                }
+                const double beta = o.prior_mode == 0 ? eta : o.prior_scale;
+                const double hW = (1.0 - eta) * sw + eta * wi;
+                double hS0 = 0.0, hS1[5], hS2[15];
+                if (act) {
+                    hS0 = (1.0 - eta) * stat[0][k] + eta * S[0];
+                    for (int d = 0; d < 5; ++d) hS1[d] = eta * S[1 + d];
+                    for (int q = 0; q < 15; ++q) hS2[q] = (1.0 - eta) * stat[1 + q][k] + eta * S[6 + q];
+                }
+                const double bar0 = act ? hS0 / hW : 0.0;
+                const double sum0 = group_sum_fp64<G>(bar0);
+                int dead = 0, cholfail = 0;
+                if (act) {
+                    if (!cok)  // an unusable component's means come from memory
+                        for (int d = 0; d < 3; ++d) {
+                            mu[d] = mix.mud[3 * g + d];
+                            mx[d] = mix.mux[3 * g + d];
+                        }
+                    const double mu_in[3] = {mu[0], mu[1], mu[2]};
+                    const double mux_in[3] = {mx[0], mx[1], mx[2]};
+                    double s0n, s2n[15];
+                    component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, true, mu_in, mux_in, mu, mx,
+                                         mix.cov + 15 * g, &s0n, s2n, dead, cholfail, Lsh[k]);
+                    stat[0][k] = s0n;
+                    for (int q = 0; q < 15; ++q) stat[1 + q][k] = s2n[q];
+                    const double pin = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
+                    mix.pi[g] = pin;
+                    for (int d = 0; d < 3; ++d) {
+                        mix.mud[3 * g + d] = mu[d];
+                        mix.mux[3 * g + d] = mx[d];
+                    }
+                    // a dead component, a kept covariance or an unusable one reloads
+                    Comp64 cn;
+                    const bool rebuilt = cok && !dead && !cholfail;
+                    if (rebuilt) refresh_comp(cn, mu, mx, Lsh[k], pin);
+                    else load_comp(mix, g, cn);
+                    comp_put(comp, Lsh[k], k, cn, !rebuilt);
+                    cok = cn.ok;
+                }
+                st_bits |= (wave_any(dead) ? kDeadComponent : 0) | (wave_any(cholfail) ? kCholFailKeptPrev : 0);
+                sw = hW;
+                ++j;
+            }
+        }
+        if (stop) break;
+    }
+    if (act) {
+        st.s0[g] = stat[0][k];
+        for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = stat[1 + q][k];
     }
     if (k == 0) {
         status[c] = st_bits;
@@ -302,18 +438,18 @@ void launch_stepwise(const int64_t* off, const float* smp, int64_t N, const sdmm
     const int32_t* fl = reinterpret_cast<const int32_t*>(ws + L.flags);
     const int32_t* ctl = reinterpret_cast<const int32_t*>(ws + L.global_ok);
     const DevOpts d = dev_opts(&opts);
-    const unsigned blocks = (unsigned)((C + 3) / 4);
+    const unsigned blocks = (unsigned)C;
     switch (group_for(opts.K)) {
-        case 4: stepwise_kernel<4><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
-        case 8: stepwise_kernel<8><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
+        case 4: stepwise_kernel<4><<<blocks, 64, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
+        case 8: stepwise_kernel<8><<<blocks, 64, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status); break;
         case 16:
-            stepwise_kernel<16><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            stepwise_kernel<16><<<blocks, 64, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
             break;
         case 32:
-            stepwise_kernel<32><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            stepwise_kernel<32><<<blocks, 64, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
             break;
         default:
-            stepwise_kernel<64><<<blocks, 256, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
+            stepwise_kernel<64><<<blocks, 64, 0, s>>>(off, N, smp, C, mp, sp, d, opts.iters, fl, ctl, status);
             break;
     }
 }
