@@ -24,7 +24,8 @@ __device__ __forceinline__ double rm_eta(const DevOpts& o, int j)
 // new frame by T = blkdiag(J, I3) and Sigma = (beta B + T C T^T / hW) / (beta a + bar0)
 // replaces the covariance if it is SPD (else cholfail); the carried statistics become
 // hS0 and T C T^T. The weight is left to the caller (it needs the cell's sum of bar0).
-// When fac is given, the Cholesky factor of a replacing covariance is written there too.
+// When fac is given, the Cholesky factor of a replacing covariance (15 packed values) and
+// the reciprocals of its diagonal (5) are written there too.
 __device__ inline void component_map_update(double hS0, const double* hS1, const double* hS2, double hW,
                                             double beta, double bar0, const DevOpts& o, bool cov_update,
                                             const double mu_in[3], const double mux_in[3], double* mud,
@@ -43,7 +44,8 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
     for (int d = 0; d < 5; ++d) m[d] = hS1[d] * inv0;
     double Ro[9], Rn[9], mun[3];
     frame64(mu, Ro);
-    exp_map64(Ro, m[0], m[1], mun);
+    const TangentRadius64 tr = tangent_radius64(m[0], m[1]);
+    exp_map64(Ro, m[0], m[1], tr, mun);
     const double inn = 1.0 / sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
     for (int i = 0; i < 3; ++i) mun[i] *= inn;
     for (int i = 0; i < 3; ++i) {
@@ -54,7 +56,7 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
     if (!cov_update) return;
     frame64(mun, Rn);
     double J[4];
-    transfer_jac64(Ro, Rn, m[0], m[1], J);
+    transfer_jac64(Ro, Rn, m[0], m[1], tr, J);
     // scatter about the new mean in the old frame, then T C T^T with T = blkdiag(J, I3)
     double Cm[5][5];
     for (int d = 0; d < 5; ++d)
@@ -85,10 +87,13 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
             if (d == e) v += beta * o.prior_b[d];
             Sig[tri(d, e)] = v * iden;
         }
-    if (chol64<5>(Sig, Lt)) {
+    double Lti[5];
+    if (chol64<5>(Sig, Lt, Lti)) {
         for (int q = 0; q < 15; ++q) cov[q] = Sig[q];
-        if (fac)
+        if (fac) {
             for (int q = 0; q < 15; ++q) fac[q] = Lt[q];
+            for (int d = 0; d < 5; ++d) fac[15 + d] = Lti[d];
+        }
     } else {
         cholfail = 1;
     }

@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void mixture_from_params_kernel(int C, int K, 
     double Ro[9], Rn[9], w[3];
     frame64(m0, Ro);
     const double d0 = delta[2 * g], d1 = delta[2 * g + 1];
-    exp_map64(Ro, d0, d1, w);
+    const TangentRadius64 tr = tangent_radius64(d0, d1);
+    exp_map64(Ro, d0, d1, tr, w);
     const double nw = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     for (int j = 0; j < 3; ++j) {
         w[j] *= nw;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(256) void mixture_from_params_kernel(int C, int K, 
     if (jac) {
         frame64(w, Rn);
         double J[4];
-        transfer_jac64(Ro, Rn, d0, d1, J);
+        transfer_jac64(Ro, Rn, d0, d1, tr, J);
         for (int q = 0; q < 4; ++q) jac[4 * g + q] = J[q];
     }
     const double* l = L + 15 * g;

@@ -81,9 +81,9 @@ __device__ inline void make_inert(Comp64& c)
 // the log constant from the weight and the factor
 __device__ __forceinline__ void set_log_constant(Comp64& c, double pi)
 {
-    double ld = 0.0;
-    for (int d = 0; d < 5; ++d) ld += log(c.L[tri(d, d)]);
-    c.logc = log(pi) - ld - 2.5 * kLn2Pi;
+    double det = c.L[0];  // det L, the product of the diagonal (far inside FP64 range for
+    for (int d = 1; d < 5; ++d) det *= c.L[tri(d, d)];  // any factor of a usable covariance)
+    c.logc = log(pi) - log(det) - 2.5 * kLn2Pi;
 }
 
 __device__ inline void load_comp(const MixPtrs& mix, int64_t g, Comp64& c)
@@ -114,7 +114,7 @@ __device__ inline double comp_log_density(const Comp64& c, const double w[3], co
     const double x = c.R[0] * w[0] + c.R[1] * w[1] + c.R[2] * w[2];
     const double yy = c.R[3] * w[0] + c.R[4] * w[1] + c.R[5] * w[2];
     const double z = c.R[6] * w[0] + c.R[7] * w[1] + c.R[8] * w[2];
-    const double s = hypot(x, yy);
+    const double s = sqrt(x * x + yy * yy);  // (x, yy, z) is a unit vector: no overflow
     if (s > 0.0) {
         const double f = atan2(s, z) / s;
         y[0] = f * x;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void stage_store(float4 (*stage)[2], int lane, const 
 
 // Each lane keeps its component in E-step form and its carried statistics in LDS, slot
 // by slot with the 64 lanes of a slot contiguous (conflict-free), the factor as one row
-// of 15 per lane (the update writes a new factor there itself): the E-step copies the
+// per lane (the update writes a new factor there itself): the E-step copies the
 // component into registers for its own span only, and the update, which needs many
 // registers of its own, runs without it.
 constexpr int kSlotR = 0, kSlotMx = 9, kSlotRd = 12, kSlotLogc = 17, kCompSlots = 18;
@@ -187,8 +187,8 @@ __device__ __forceinline__ void comp_get(double (*cs)[64], const double* Ls, int
 
 // The component in E-step form after an update that replaced the covariance of a usable
 // component, from what the update produced: the new mean's frame, the new positional
-// mean, the diagonal of the update's own factor of the new covariance (the whole factor
-// is already in LDS) and the new weight. This equals load_comp of the stored values:
+// mean, the diagonal of the update's own factor of the new covariance and its
+// reciprocals (the update wrote both to LDS; the factor stays there) and the new weight. This equals load_comp of the stored values:
 // from finite statistics the new direction is a unit vector, the positional mean moves
 // by a finite weighted mean, and the weight's denominator is at least this component's
 // bar0, above the dead threshold, so load_comp's finiteness checks would pass.
@@ -198,8 +198,10 @@ __device__ __forceinline__ void refresh_comp(Comp64& c, const double mu[3], cons
     c.ok = true;
     frame64(mu, c.R);
     for (int d = 0; d < 3; ++d) c.mx[d] = mx[d];
-    for (int d = 0; d < 5; ++d) c.L[tri(d, d)] = L[tri(d, d)];
-    for (int d = 0; d < 5; ++d) c.rd[d] = 1.0 / c.L[tri(d, d)];
+    for (int d = 0; d < 5; ++d) {
+        c.L[tri(d, d)] = L[tri(d, d)];
+        c.rd[d] = L[15 + d];
+    }
     set_log_constant(c, pi);
 }
 
@@ -215,7 +217,8 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
     __shared__ float4 stage[64][2];
     __shared__ double comp[kCompSlots][64];
     __shared__ double stat[16][64];  // s0, then s2
-    __shared__ double Lsh[64][15];
+    __shared__ double Lsh[64][21];  // factor, reciprocals of its diagonal, one pad (row stride
+                                    // of 42 dwords: the 64 lanes start on 32 distinct banks)
     const int c = blockIdx.x;
     if (c >= C) return;
     const int K = o.K;
