@@ -196,3 +196,36 @@ def test_condition_and_pdf_other_K(dev, orc, K):
     for q in range(ref.shape[0]):
         big = ref[q] > 1e-6 * ref[q].max()
         assert (np.abs(got[q][big] - ref[q][big]) / ref[q][big]).max() < 1e-4
+
+
+@pytest.mark.parametrize("K,ns", [(16, 3), (16, 5), (16, 12), (8, 2), (32, 4), (32, 20)])
+def test_fused_path_matches_the_separate_calls(dev, orc, K, ns):
+    """The fused condition + sample + pdf call batches the draws of several rounds of
+    queries when a query has at most half a lane group of draws, and runs one round
+    otherwise; both must give the draws of the separate condition, sample and pdf calls
+    on the same caller uniforms (43 queries: a ragged last pass)."""
+    print(f"case: fused vs separate, K={K}, ns={ns}", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("single", seed=6)
+    b = synth.make_batch(13, [4096], wl["box_lo"], wl["box_size"], wl["lobes"])
+    mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    orc.fit(orc.Opts(K=K, iters=3), b.offsets, b.samples, mix, orc.new_state(1, K))
+    qpos, qcell = synth.make_queries(5, wl["box_lo"], wl["box_size"], 43)
+    qcell = qcell.copy()
+    qcell[[3, 17]] = -1  # unusable queries give no draws on either path
+    table, qp, qc, cw, cm = _gpu_cond(dev, mix, 1, K, qpos, qcell)
+    nq = qcell.size
+    u = synth.make_uniforms(23, nq * ns)
+    gu = dev.from_numpy(np.ascontiguousarray(u.T)).cuda()
+    dirs, pdfv, valid, _ = sdmm.sample(table, 1, K, qc, cw, cm, ns, uniforms=gu)
+    fd, fp, fv = sdmm.condition_sample_pdf(table, 1, K, qp, qc, ns, uniforms=gu)
+    assert dev.equal(fv, valid)
+    assert int(valid.sum()) >= (nq - 2) * ns // 2
+    assert not valid.view(nq, ns)[[3, 17]].any()
+    assert np.allclose(fd.cpu().numpy(), dirs.cpu().numpy(), rtol=0, atol=1e-6)
+    assert np.allclose(fp.cpu().numpy(), pdfv.cpu().numpy(), rtol=1e-6, atol=0)
+    # the device generator: the same draws through both paths
+    d1, p1, v1, _ = sdmm.sample(table, 1, K, qc, cw, cm, ns, uniforms=None, seed=77)
+    f1, q1, w1 = sdmm.condition_sample_pdf(table, 1, K, qp, qc, ns, uniforms=None, seed=77)
+    assert dev.equal(w1, v1)
+    assert np.allclose(f1.cpu().numpy(), d1.cpu().numpy(), rtol=0, atol=1e-6)
