@@ -164,8 +164,8 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
 {
     bool ok = isfinite(pi) && pi >= 0.0;
     for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[d]) && isfinite(mux[d]);
-    double L[15], Li[15];
-    ok = ok && chol64<5>(cov, L);
+    double L[15], Li[15], Ld[5];
+    ok = ok && chol64<5>(cov, L, Ld);
     if (!ok) {
         for (int i = 0; i < kMirror; ++i) out[i] = 0.0f;
         out[0] = out[4] = out[8] = 1.0f;
@@ -176,9 +176,8 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     }
     double R[9];
     frame64(mud, R);
-    tri_inv64<5>(L, Li);
-    double logdet = 0.0;
-    for (int d = 0; d < 5; ++d) logdet += log(L[tri(d, d)]);
+    tri_inv64<5>(L, Li, Ld);
+    const double logdet = log_det5(L);
     const double scale = sqrt(0.5 * kLog2e);
     for (int i = 0; i < 9; ++i) out[i] = (float)R[i];
     for (int d = 0; d < 3; ++d) out[9 + d] = (float)mux[d];

@@ -81,9 +81,7 @@ __device__ inline void make_inert(Comp64& c)
 // the log constant from the weight and the factor
 __device__ __forceinline__ void set_log_constant(Comp64& c, double pi)
 {
-    double det = c.L[0];  // det L, the product of the diagonal (far inside FP64 range for
-    for (int d = 1; d < 5; ++d) det *= c.L[tri(d, d)];  // any factor of a usable covariance)
-    c.logc = log(pi) - log(det) - 2.5 * kLn2Pi;
+    c.logc = log(pi) - log_det5(c.L) - 2.5 * kLn2Pi;
 }
 
 __device__ inline void load_comp(const MixPtrs& mix, int64_t g, Comp64& c)
