@@ -145,10 +145,17 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const int32_t*
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    int32_t kv[kSortItems];  // the thread's keys, loaded together
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = base + (int64_t)it * kSortThreads + threadIdx.x;
+        kv[it] = i < N ? keys[i] : 0;
+    }
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = base + (int64_t)it * kSortThreads + threadIdx.x;
         const bool valid = i < N;
-        const int digit = valid ? (keys[i] >> shift) & (kRadix - 1) : 0;
+        const int digit = valid ? (kv[it] >> shift) & (kRadix - 1) : 0;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -243,7 +250,8 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(int32_t* __restrict__ v
 }
 
 // Each block scatters its tile in index order: per 256-key step, a key's rank among the
-// equal digits of its wave comes from 8 ballots, the waves of the block are ordered by
+// equal digits of its wave comes from 8 ballots (the tile's keys and values are loaded up
+// front), the waves of the block are ordered by
 // per-wave digit counts in LDS, and a running base per digit carries over the steps.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const int32_t* __restrict__ kin,
                                                                      const int32_t* __restrict__ vin, int64_t N,
@@ -260,11 +268,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const int32
     __syncthreads();
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    // the thread's keys and values, loaded together before the barriers of the steps
+    int32_t kv[kSortItems], vv[kSortItems];
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = tile + (int64_t)it * kSortThreads + tid;
         const bool valid = i < N;
-        const int32_t key = valid ? kin[i] : 0;
-        const int32_t val = valid ? (vin ? vin[i] : (int32_t)i) : 0;
+        kv[it] = valid ? kin[i] : 0;
+        vv[it] = valid ? (vin ? vin[i] : (int32_t)i) : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + tid;
+        const bool valid = i < N;
+        const int32_t key = kv[it];
+        const int32_t val = vv[it];
         const int digit = (key >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -330,16 +348,34 @@ __global__ __launch_bounds__(256) void split_stats_kernel(const float* __restric
     }
     double s1[3] = {0, 0, 0}, sq[3] = {0, 0, 0};
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t j = a + threadIdx.x; j < b; j += 256) {
-        const int32_t i = perm[j];
+    // the positions are gathered through the sort's permutation: four of a thread's
+    // samples are loaded together (indices clamped into the leaf, so every load is in
+    // bounds) and then added in the thread's sample order
+    constexpr int U = 4;
+    for (int64_t j0 = a + threadIdx.x; j0 < b; j0 += U * 256) {
+        int32_t idx[U];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float xf = smp[(3 + d) * N + i];
-            const double x = (double)xf;
-            s1[d] += x;
-            sq[d] += x * x;
-            mn[d] = fminf(mn[d], xf);
-            mx[d] = fmaxf(mx[d], xf);
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + u * 256;
+            idx[u] = perm[j < b ? j : b - 1];
+        }
+        float xs[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xs[u][d] = smp[(3 + d) * N + idx[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (j0 + u * 256 >= b) break;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const float xf = xs[u][d];
+                const double x = (double)xf;
+                s1[d] += x;
+                sq[d] += x * x;
+                mn[d] = fminf(mn[d], xf);
+                mx[d] = fmaxf(mx[d], xf);
+            }
         }
     }
 #pragma unroll
