@@ -79,6 +79,10 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
         Tt[a][0] = c0;
         Tt[a][1] = c1;
     }
+    // the carried scatter first, so that it need not stay in registers through the
+    // factorisation
+    for (int d = 0; d < 5; ++d)
+        for (int e = 0; e <= d; ++e) s2[tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
     double Sig[15], Lt[15];
     const double iden = 1.0 / (beta * o.prior_a + bar0), ihW = 1.0 / hW;
     for (int d = 0; d < 5; ++d)
@@ -97,8 +101,6 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
     } else {
         cholfail = 1;
     }
-    for (int d = 0; d < 5; ++d)
-        for (int e = 0; e <= d; ++e) s2[tri(d, e)] = 0.5 * (Tt[d][e] + Tt[e][d]);
 }
 
 }  // namespace sdmm

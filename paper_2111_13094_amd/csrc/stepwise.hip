@@ -156,9 +156,9 @@ __device__ __forceinline__ void stage_store(float4 (*stage)[2], int lane, const 
     __syncthreads();
 }
 
-// Each lane keeps its component in E-step form and its carried statistics in LDS, slot
-// by slot with the 64 lanes of a slot contiguous (conflict-free), the factor as one row
-// per lane (the update writes a new factor there itself): the E-step copies the
+// Each lane keeps its component in E-step form in LDS, slot by slot with the 64 lanes of
+// a slot contiguous (conflict-free), and its factor and carried statistics as rows of
+// its own (the update writes a new factor and the new statistics there itself): the E-step copies the
 // component into registers for its own span only, and the update, which needs many
 // registers of its own, runs without it.
 constexpr int kSlotR = 0, kSlotMx = 9, kSlotRd = 12, kSlotLogc = 17, kCompSlots = 18;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
 {
     __shared__ float4 stage[64][2];
     __shared__ double comp[kCompSlots][64];
-    __shared__ double stat[16][64];  // s0, then s2
+    __shared__ double stat[64][17];  // per lane s0, then s2, one pad (row stride of 34 dwords)
     __shared__ double Lsh[64][21];  // factor, reciprocals of its diagonal, one pad (row stride
                                     // of 42 dwords: the 64 lanes start on 32 distinct banks)
     const int c = blockIdx.x;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
     const bool range_ok = control[0] && !(flags[c] & kFlagBadRange);
     int j = st.step[c];
     double sw = st.sw[c];
-    for (int q = 0; q < 16; ++q) stat[q][k] = q == 0 ? st.s0[g] : st.s2[g * 15 + q - 1];
+    for (int q = 0; q < 16; ++q) stat[k][q] = q == 0 ? st.s0[g] : st.s2[g * 15 + q - 1];
     bool cok;
     {
         Comp64 cp;
@@ -313,11 +313,8 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
             if (act) {
                 const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
                 const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
-                double s0n, s2n[15];
                 component_map_update(S[0], S + 1, S + 6, Wb, beta, bar0, o, true, mu_in, mux_in, mix.mud + 3 * g,
-                                     mix.mux + 3 * g, mix.cov + 15 * g, &s0n, s2n, dead, cholfail);
-                stat[0][k] = s0n;
-                for (int q = 0; q < 15; ++q) stat[1 + q][k] = s2n[q];
+                                     mix.mux + 3 * g, mix.cov + 15 * g, &stat[k][0], &stat[k][1], dead, cholfail);
                 mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                 load_comp(mix, g, cp);
                 comp_put(comp, Lsh[k], k, cp, true);
@@ -376,9 +373,9 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
                 const double hW = (1.0 - eta) * sw + eta * wi;
                 double hS0 = 0.0, hS1[5], hS2[15];
                 if (act) {
-                    hS0 = (1.0 - eta) * stat[0][k] + eta * S[0];
+                    hS0 = (1.0 - eta) * stat[k][0] + eta * S[0];
                     for (int d = 0; d < 5; ++d) hS1[d] = eta * S[1 + d];
-                    for (int q = 0; q < 15; ++q) hS2[q] = (1.0 - eta) * stat[1 + q][k] + eta * S[6 + q];
+                    for (int q = 0; q < 15; ++q) hS2[q] = (1.0 - eta) * stat[k][1 + q] + eta * S[6 + q];
                 }
                 const double bar0 = act ? hS0 / hW : 0.0;
                 const double sum0 = group_sum_fp64<G>(bar0);
@@ -391,11 +388,8 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
                         }
                     const double mu_in[3] = {mu[0], mu[1], mu[2]};
                     const double mux_in[3] = {mx[0], mx[1], mx[2]};
-                    double s0n, s2n[15];
                     component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, true, mu_in, mux_in, mu, mx,
-                                         mix.cov + 15 * g, &s0n, s2n, dead, cholfail, Lsh[k]);
-                    stat[0][k] = s0n;
-                    for (int q = 0; q < 15; ++q) stat[1 + q][k] = s2n[q];
+                                         mix.cov + 15 * g, &stat[k][0], &stat[k][1], dead, cholfail, Lsh[k]);
                     const double pin = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
                     mix.pi[g] = pin;
                     for (int d = 0; d < 3; ++d) {
@@ -418,8 +412,8 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
         if (stop) break;
     }
     if (act) {
-        st.s0[g] = stat[0][k];
-        for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = stat[1 + q][k];
+        st.s0[g] = stat[k][0];
+        for (int q = 0; q < 15; ++q) st.s2[g * 15 + q] = stat[k][1 + q];
     }
     if (k == 0) {
         status[c] = st_bits;
