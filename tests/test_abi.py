@@ -116,3 +116,30 @@ def test_binding_rejects_undersized_tensors():
     off = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int64)
     with pytest.raises(ValueError, match="status"):
         sdmm.fit_mixtures(off, torch.zeros(7, 4), {}, {}, sdmm.default_opts(K), status=torch.zeros(3, dtype=torch.int32))
+
+
+def test_binding_rejects_undersized_product_and_parameter_tensors():
+    import torch
+    from paper_2111_13094_amd import sdmm
+    K, Kb, n_cells, n_bsdf, nq, ns = 16, 16, 2, 3, 5, 4
+    st = sdmm.COND_TABLE_STRIDE
+    table, btable = torch.zeros(n_cells * K * st), torch.zeros(n_bsdf * Kb * st)
+    qpos, bpar, frames = torch.zeros(3, nq), torch.zeros(3, nq), torch.zeros(9, nq)
+    qcell, bcell = torch.zeros(nq, dtype=torch.int32), torch.zeros(nq, dtype=torch.int32)
+    args = dict(table=table, n_cells=n_cells, K=K, qpos=qpos, qcell=qcell, btable=btable, n_bsdf=n_bsdf, Kb=Kb,
+                bpar=bpar, bcell=bcell, frames=frames)
+    for key, bad in (("btable", btable[:-1]), ("frames", frames[:, :-1]), ("bpar", bpar[:, :-1]),
+                     ("bcell", bcell[:-1]), ("table", table[:-1])):
+        with pytest.raises(ValueError, match=key):
+            sdmm.product_sample(**{**args, key: bad}, ns=ns)
+    with pytest.raises(ValueError, match="uniforms"):
+        sdmm.product_sample(**args, ns=ns, uniforms=torch.zeros(3, nq * ns - 1))
+    with pytest.raises(ValueError, match="btable"):  # (the draw count is taken from dirs' shape)
+        sdmm.product_pdf(**{**args, "btable": btable[:-1]}, dirs=torch.zeros(3, nq * 2))
+    n = n_cells * K
+    with pytest.raises(ValueError, match="jac"):
+        sdmm.grad_to_params(torch.zeros(n_cells, K, 15), torch.zeros(n * 4 - 1), torch.zeros(n * 2),
+                            torch.zeros(n * 15))
+    with pytest.raises(ValueError, match="delta"):
+        sdmm.mixture_from_params(torch.zeros(n_cells, K), torch.zeros(n * 3), torch.zeros(n * 2 - 1),
+                                 torch.zeros(n * 3), torch.zeros(n * 15))
