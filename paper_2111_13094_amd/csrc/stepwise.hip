@@ -215,6 +215,7 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
     __shared__ float4 stage[64][2];
     __shared__ double comp[kCompSlots][64];
     __shared__ double stat[64][17];  // per lane s0, then s2, one pad (row stride of 34 dwords)
+    __shared__ double eta_s[64];    // step sizes of the next 64 sample counters
     __shared__ double Lsh[64][21];  // factor, reciprocals of its diagonal, one pad (row stride
                                     // of 42 dwords: the 64 lanes start on 32 distinct banks)
     const int c = blockIdx.x;
@@ -328,14 +329,21 @@ __global__ __launch_bounds__(64) void stepwise_kernel(const int64_t* __restrict_
         // every sample with positive weight is a mini-batch of one
         bool stop = false;
         for (int64_t base = i0; base < i1 && !stop; base += 64) {
-            stage_store(stage, k, pre);
+            // the 64 samples, and the Robbins-Monro step sizes of the sample counters they
+            // can reach (the counter rises by at most one per sample): one per lane
+            const int jb = j;
+            __syncthreads();
+            stage[k][0] = make_float4(pre[0], pre[1], pre[2], pre[3]);
+            stage[k][1] = make_float4(pre[4], pre[5], pre[6], 0.0f);
+            eta_s[k] = rm_eta(o, jb + k);
+            __syncthreads();
             if (base + 64 < i1) stage_fetch(smp, N, base + 64 + k, i1 - 1, pre);
             const int n = (int)(i1 - base < 64 ? i1 - base : 64);
             for (int t = 0; t < n; ++t) {
                 const float4 a = stage[t][0], b = stage[t][1];
                 const double wi = (double)b.z;
                 if (!(wi > 0.0)) continue;
-                const double eta = rm_eta(o, j);
+                const double eta = eta_s[j - jb];
                 double y[5], l, mu[3], mx[3];
                 {
                     Comp64 cp;
