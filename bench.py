@@ -113,7 +113,48 @@ def cpu_baseline(wl, batch, target_s=12.0, orc_kw=None):
     p1, t1 = run(order[16:16 + n])
     pairs, t = p0 + p1, t0 + t1
     return {"value": pairs / t, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{16 + n} of {C} cells of one batch, one E+M step each, FP64, single thread, {t:.1f} s"}
+            "sample": f"{16 + n} of {C} cells of one batch, one E+M step each, FP64, single thread, {t:.1f} s",
+            "host": host_description()}
+
+
+def host_description():
+    """nproc, the CPUs this process may run on, and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline_all_cores(wl, batches, target_s=12.0, orc_kw=None):
+    """The same oracle source built with OpenMP over cells, on every CPU this process
+    may use (capped by OMP_NUM_THREADS when set): whole batches, one E+M step each from
+    the initial mixtures, repeated over the resident batches until about target_s
+    seconds of wall time have passed."""
+    orc_kw = {"eta": 0.1} if orc_kw is None else orc_kw
+    from oracle import oracle as orc
+    from paper_2111_13094_amd import synth
+    C = wl["grid"].n_cells
+    want = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        want = min(want, int(os.environ["OMP_NUM_THREADS"]))
+    threads = orc.threads_in_use(want)
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    pairs, t, nb = 0, 0.0, 0
+    while t < target_s and nb < 4 * len(batches):
+        b = batches[nb % len(batches)]
+        mix, st = synth.copy_mix(mix0), orc.new_state(C, 16)
+        t0 = time.perf_counter()
+        orc.fit(orc.Opts(K=16, **orc_kw), b.offsets, b.samples, mix, st, threads=threads)
+        t += time.perf_counter() - t0
+        pairs += b.samples.shape[1] * 16
+        nb += 1
+    return {"value": pairs / t, "unit": "updates/s", "cores": threads, "kind": "oracle (OpenMP over cells)",
+            "sample": f"{nb} whole batches of {C} cells, one E+M step each, FP64, {threads} threads, {t:.1f} s"}
 
 
 def bench_cells4k(args, torch):
@@ -245,6 +286,7 @@ def bench_cells4k(args, torch):
                         "speedup_batched_over_plain": value / (ppairs / pt)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, batches[0], target_s=args.cpu_seconds)
+        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(wl, batches, target_s=args.cpu_seconds)
     if args.copy_probe:
         # a plain device copy of known size, to scale the HBM byte counters of a profiler run
         src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)

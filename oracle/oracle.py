@@ -19,18 +19,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sdmm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")  # the same source with OpenMP over cells
 
 SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD_PARAMS = (
     1, 2, 4, 8, 16, 32)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc: -O2, no fast-math, FP64 throughout."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, FP64 throughout. omp=True builds the
+    same source with OpenMP, whose fit spreads independent cells over threads (the
+    all-cores CPU baseline); the single-threaded library is the reference."""
+    out = LIB_OMP if omp else LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        flags = ["-fopenmp"] if omp else []
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *flags, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Opts(C.Structure):
@@ -82,6 +87,19 @@ class Opts:
 
 
 _lib = None
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP build (fit over cells on all threads), for the all-cores baseline."""
+    global _lib_omp
+    if _lib_omp is None:
+        L = C.CDLL(build(omp=True))
+        L.orc_fit.argtypes = [C.POINTER(_Opts), C.c_int32] + [C.c_void_p] * 2 + [C.c_int64] + [C.c_void_p] * 9
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
+        _lib_omp = L
+    return _lib_omp
 
 
 def lib():
@@ -164,9 +182,11 @@ def new_state(n_cells: int, K: int) -> dict:
             "sw": np.zeros(n_cells), "step": np.zeros(n_cells, dtype=np.int32)}
 
 
-def fit(opts: Opts, offsets, samples, mix: dict, state: dict) -> np.ndarray:
+def fit(opts: Opts, offsets, samples, mix: dict, state: dict, threads: int = 0) -> np.ndarray:
     """``opts.iters`` E+M iterations on one batch; ``mix`` (pi, mu_dir, mu_pos, cov) and
-    ``state`` (s0, s2, sw, step) are updated in place. Returns per-cell status bits."""
+    ``state`` (s0, s2, sw, step) are updated in place. Returns per-cell status bits.
+    threads > 0 runs the OpenMP build of the same source with that many threads (cells
+    spread over them; every cell's result is the same as with one thread)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     samples = np.ascontiguousarray(samples, dtype=np.float32)
     n_cells = offsets.shape[0] - 1
@@ -174,7 +194,11 @@ def fit(opts: Opts, offsets, samples, mix: dict, state: dict) -> np.ndarray:
     for key in ("pi", "mu_dir", "mu_pos", "cov"):
         assert mix[key].dtype == np.float64 and mix[key].flags["C_CONTIGUOUS"]
     o = opts.to_c()
-    rc = lib().orc_fit(C.byref(o), n_cells, _p(offsets), _p(samples), samples.shape[1],
+    L = lib()
+    if threads > 0:
+        L = lib_omp()
+        L.orc_set_threads(int(threads))
+    rc = L.orc_fit(C.byref(o), n_cells, _p(offsets), _p(samples), samples.shape[1],
                        _p(mix["pi"]), _p(mix["mu_dir"]), _p(mix["mu_pos"]), _p(mix["cov"]),
                        _p(state["s0"]), _p(state["s2"]), _p(state["sw"]), _p(state["step"]),
                        _p(status))
@@ -478,3 +502,8 @@ def draw_uniforms(seed: int, n: int):
     u = np.zeros((n, 3))
     L.orc_draw_uniforms(seed, n, _p(u))
     return u
+
+
+def threads_in_use(threads: int) -> int:
+    """The thread count the OpenMP build runs with after asking for `threads`."""
+    return int(lib_omp().orc_set_threads(int(threads)))

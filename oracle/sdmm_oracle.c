@@ -658,6 +658,11 @@ int orc_fit(const orc_opts *o, int32_t n_cells, const int64_t *offsets, const fl
     /* the accurate covariance update is defined for batch steps */
     if (o->accurate_sigma && !(o->eta_mode == 0 && o->eta == 1.0)) return -2;
     if (!offsets_valid(n_cells, offsets, N, status)) return 0;
+    /* cells are independent (Sec. 4.2); a build with OpenMP (the all-cores CPU baseline)
+     * spreads them over threads, each cell's arithmetic unchanged */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
     for (int32_t c = 0; c < n_cells; ++c) {
         const int64_t ck = (int64_t)c * K;
         status[c] = 0;
@@ -1642,4 +1647,20 @@ void orc_draw_uniforms(uint64_t seed, int64_t n, double *u /* [n][3] */)
         orc_philox4x32_10(c, k, o);
         for (int j = 0; j < 3; ++j) u[3 * d + j] = (double)(o[j] >> 8) * (1.0 / 16777216.0);
     }
+}
+
+/* Threads of the OpenMP build (the all-cores CPU baseline); returns the count in use.
+ * The single-threaded build ignores the request and returns 1. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

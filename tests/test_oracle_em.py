@@ -710,3 +710,190 @@ def test_stepwise_rejects_the_accurate_update(orc):
     b, mix = _single_cell(64)
     with pytest.raises(ValueError):
         orc.fit_stepwise(orc.Opts(K=16, accurate_sigma=1), b.offsets, b.samples, mix, orc.new_state(1, 16))
+
+
+# --- default prior strength and solid-angle responsibilities (pins of two oracle branches)
+
+def _k1_cell(rng, n, zero_frac, lo, size):
+    """One cell of n samples for K = 1: a vMF lobe, positions uniform in the box, weights
+    lognormal(0, 1.5) with a fraction set exactly to zero."""
+    lobe = _unit(np.array([0.3, -0.5, 0.8]))
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = synth.sample_vmf(rng, np.tile(lobe, (n, 1)), np.full(n, 6.0)).T
+    smp[3:6] = (lo[:, None] + size[:, None] * rng.random((3, n))).astype(np.float32)
+    w = np.exp(1.5 * rng.normal(size=n))
+    w[rng.random(n) < zero_frac] = 0.0
+    smp[6] = w.astype(np.float32)
+    return smp
+
+
+def test_default_prior_strength_is_eta_over_positive_count(orc):
+    """Sec. 4.3 (MAP update with the prior strength of reading A12): with the default
+    prior mode, beta_j = eta_j / M_j where M_j counts the batch's samples of positive
+    weight. K = 1 makes every responsibility 1, so the positional block of the covariance
+    has a closed form over two batches: after the first (eta = 1)
+        Sigma_xx = (beta_0 B_xx + scatter_0) / (beta_0 a + 1),
+    and after the second (eta = 0.1, statistics averaged and normalised by the averaged
+    weight sum, the carried second moment taken about the first batch's mean)
+        Sigma_xx = (beta_1 B_xx + C_xx / W^) / (beta_1 a + 1).
+    A large prior B and a small cell make beta matter; a third of the weights are zero,
+    so counting them in M, or dropping eta from beta, or normalising by N instead of W^,
+    fails this test."""
+    rng = np.random.default_rng(404)
+    lo, size = np.array([0.25, 0.5, 0.0]), np.array([0.0625, 0.0625, 0.0625])
+    b = np.array([0.5, 0.5, 2e-4, 3e-4, 4e-4])
+    a = 0.8
+    opts = orc.Opts(K=1, iters=1, eta=0.1, prior_a=a, prior_b=tuple(b), min_samples=16)
+    mix = synth.initial_mixtures(lo[None, :], size[None, :], 1)
+    st = orc.new_state(1, 1)
+    batches = [_k1_cell(rng, 300, 0.33, lo, size), _k1_cell(rng, 220, 0.33, lo, size)]
+
+    P0 = batches[0][3:6].T.astype(np.float64)
+    w0 = batches[0][6].astype(np.float64)
+    M0, W0 = int((w0 > 0).sum()), w0.sum()
+    assert M0 < w0.size
+    assert orc.fit(opts, np.array([0, w0.size]), batches[0], mix, st)[0] == 0
+    mean0 = (w0[:, None] * P0).sum(0) / W0
+    D0 = P0 - mean0
+    scatter0 = (w0[:, None] * D0).T @ D0  # unnormalised
+    beta0 = 1.0 / M0
+    Sxx0 = (beta0 * np.diag(b[2:]) + scatter0 / W0) / (beta0 * a + 1.0)
+    assert mix["pi"][0] == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(mix["mu_pos"], mean0, rtol=1e-13)
+    assert np.allclose(_unpack(mix["cov"])[2:, 2:], Sxx0, rtol=1e-11, atol=0)
+    assert st["sw"][0] == pytest.approx(W0, rel=1e-14) and st["step"][0] == 1
+
+    eta = 0.1
+    P1 = batches[1][3:6].T.astype(np.float64)
+    w1 = batches[1][6].astype(np.float64)
+    M1, W1 = int((w1 > 0).sum()), w1.sum()
+    assert orc.fit(opts, np.array([0, w1.size]), batches[1], mix, st)[0] == 0
+    D1 = P1 - mean0                       # about the mean the first batch produced
+    hW = (1.0 - eta) * W0 + eta * W1
+    hS0 = hW                              # K = 1: S0 = W in each batch
+    hS1 = eta * (w1[:, None] * D1).sum(0)
+    hS2 = (1.0 - eta) * scatter0 + eta * (w1[:, None] * D1).T @ D1
+    C = hS2 - np.outer(hS1, hS1) / hS0
+    beta1 = eta / M1
+    Sxx1 = (beta1 * np.diag(b[2:]) + C / hW) / (beta1 * a + hS0 / hW)
+    assert np.allclose(mix["mu_pos"], mean0 + hS1 / hS0, rtol=1e-13)
+    assert np.allclose(_unpack(mix["cov"])[2:, 2:], Sxx1, rtol=1e-11, atol=0)
+    assert st["sw"][0] == pytest.approx(hW, rel=1e-14) and st["step"][0] == 2
+    # the same batch with beta from a wrong count would be visibly different
+    wrong = (eta / w1.size * np.diag(b[2:]) + C / hW) / (eta / w1.size * a + 1.0)
+    assert np.abs(wrong - Sxx1).max() > 1e-6 * np.abs(Sxx1).max()
+
+
+def test_accurate_sigma_default_prior_is_one_over_positive_count(orc):
+    """The accurate covariance update (Sec. 3.2) with the default prior strength: with
+    eta = 1, beta = 1 / M, M the count of positive weights. For K = 1 the positional block
+    is (B_xx / M + scatter about the new mean) / (a / M + 1) exactly."""
+    rng = np.random.default_rng(405)
+    lo, size = np.array([0.5, 0.0, 0.25]), np.array([0.0625, 0.0625, 0.0625])
+    b = np.array([0.5, 0.5, 2e-4, 3e-4, 4e-4])
+    a = 0.8
+    smp = _k1_cell(rng, 260, 0.3, lo, size)
+    mix = synth.initial_mixtures(lo[None, :], size[None, :], 1)
+    st = orc.new_state(1, 1)
+    opts = orc.Opts(K=1, iters=1, prior_a=a, prior_b=tuple(b), accurate_sigma=1)
+    assert orc.fit(opts, np.array([0, smp.shape[1]]), smp, mix, st)[0] == 0
+    P = smp[3:6].T.astype(np.float64)
+    w = smp[6].astype(np.float64)
+    M, W = int((w > 0).sum()), w.sum()
+    assert M < w.size
+    D = P - mix["mu_pos"]
+    scatter = (w[:, None] * D).T @ D / W
+    beta = 1.0 / M
+    Sxx = (beta * np.diag(b[2:]) + scatter) / (beta * a + 1.0)
+    assert np.allclose(_unpack(mix["cov"])[2:, 2:], Sxx, rtol=1e-11, atol=0)
+
+
+def _duff_frame(mu):
+    """Rows (t1, t2, mu) of the branchless orthonormal basis of Duff et al. (2017),
+    written from the published formulas for this test."""
+    s = 1.0 if mu[2] >= 0.0 else -1.0
+    a = -1.0 / (s + mu[2])
+    b = mu[0] * mu[1] * a
+    return np.array([[1.0 + s * mu[0] ** 2 * a, s * b, -s * mu[0]],
+                     [b, s + mu[1] ** 2 * a, -mu[1]],
+                     [mu[0], mu[1], mu[2]]])
+
+
+def test_estep_jacobian_responsibilities_divide_by_sinc(orc):
+    """Reading A2: with estep_jacobian the E-step weighs component k by its solid-angle
+    density, the tangent density divided by sinc |nu_k| (Sec. 3.1). Written out directly
+    for K = 3 with scipy's Gaussian density and geodesic coordinates: the oracle's
+    responsibilities, and through a fit its S0 = sum w r and its new positional means,
+    agree to rounding. The same data under the tangent densities (the default) differ
+    from it, so the test sees which branch ran."""
+    K = 3
+    rng = np.random.default_rng(406)
+    n = 400
+    lobes = _unit(np.array([[0.1, 0.2, 1.0], [0.9, -0.3, 0.2], [-0.4, 0.8, -0.5]]))
+    lab = rng.integers(0, K, n)
+    smp = np.zeros((7, n), dtype=np.float32)
+    smp[0:3] = synth.sample_vmf(rng, lobes[lab], np.full(n, 1.5)).T   # broad: large |nu|
+    smp[3:6] = rng.random((3, n))
+    smp[6] = synth.draw_weights(rng, n)
+    mix = synth.initial_mixtures(np.zeros((1, 3)), np.ones((1, 3)), K)
+    mix["mu_dir"][:] = lobes.ravel()
+    mix["pi"][:] = [0.5, 0.3, 0.2]
+    covs = []
+    for k in range(K):
+        A = rng.normal(size=(5, 5)) * 0.2
+        S = A @ A.T + np.diag([0.6, 0.5, 0.08, 0.09, 0.1])
+        covs.append(S)
+        mix["cov"][15 * k:15 * k + 15] = _pack(S)
+    mus = mix["mu_pos"].reshape(K, 3)
+    W = smp[6].astype(np.float64)
+
+    def direct(jac):
+        R = np.zeros((n, K))
+        for i in range(n):
+            om, p = smp[0:3, i].astype(np.float64), smp[3:6, i].astype(np.float64)
+            dens = np.zeros(K)
+            for k in range(K):
+                v = _duff_frame(lobes[k]) @ om
+                th = np.arctan2(np.hypot(v[0], v[1]), v[2])
+                nu = th / np.hypot(v[0], v[1]) * v[:2]
+                y = np.concatenate([nu, p - mus[k]])
+                dens[k] = mix["pi"][k] * multivariate_normal(np.zeros(5), covs[k]).pdf(y)
+                if jac:
+                    r = np.linalg.norm(nu)
+                    dens[k] /= np.sin(r) / r
+            R[i] = dens / dens.sum()
+        return R
+
+    Rj, Rt = direct(True), direct(False)
+    assert np.abs(Rj - Rt).max() > 1e-2
+    oj = orc.Opts(K=K, estep_jacobian=1, prior_mode=1, prior_scale=0.0)
+    for i in range(0, n, 9):
+        r = orc.responsibilities(oj, smp[0:3, i], smp[3:6, i], mix)
+        assert np.allclose(r, Rj[i], rtol=1e-11, atol=1e-14), (i, r, Rj[i])
+    st = orc.new_state(1, K)
+    m2 = synth.copy_mix(mix)
+    assert orc.fit(oj, np.array([0, n]), smp, m2, st)[0] == 0
+    S0 = (W[:, None] * Rj).sum(0)
+    assert np.allclose(st["s0"], S0, rtol=1e-11)
+    P = smp[3:6].T.astype(np.float64)
+    newx = ((W[:, None] * Rj).T @ P) / S0[:, None]
+    assert np.allclose(m2["mu_pos"].reshape(K, 3), newx, rtol=1e-11)
+
+
+def test_openmp_build_gives_the_same_cells(orc):
+    """The all-cores CPU baseline runs the same oracle source built with OpenMP over
+    cells. Cells are independent, so the result is bitwise the single-threaded one."""
+    wl = synth.workload("cells4k", scale=27 / 4096)
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], 16)
+    m1, s1 = synth.copy_mix(mix0), orc.new_state(C, 16)
+    m4, s4 = synth.copy_mix(mix0), orc.new_state(C, 16)
+    st1 = orc.fit(orc.Opts(K=16, iters=2), b.offsets, b.samples, m1, s1)
+    st4 = orc.fit(orc.Opts(K=16, iters=2), b.offsets, b.samples, m4, s4, threads=4)
+    assert orc.threads_in_use(4) == 4
+    assert np.array_equal(st1, st4)
+    for k in m1:
+        assert np.array_equal(m1[k], m4[k]), k
+    for k in s1:
+        assert np.array_equal(s1[k], s4[k]), k
