@@ -201,12 +201,20 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
 // Shifts the log2 constants of one cell by (max over its components + 1), so that every
 // log2 density the E-step forms is negative (the maximum then reduces over the float bit
 // patterns as integers) and stays small where it matters (no rounding of a large common
-// constant). Inert components get -1. `shift` is the same for all lanes of the cell.
-__device__ inline void set_mirror_shift(float* out, double c2, double shift)
+// constant). Inert components (`usable` false: the cell is gated as BAD_PARAMS) get -1. A
+// usable component of weight zero keeps the constant -inf, so its responsibility is
+// exactly zero, as the E-step of Sec. 3.2 gives (r proportional to pi_k p_k). `shift` is
+// the same for all lanes of the cell.
+__device__ inline void set_mirror_shift(float* out, double c2, double shift, bool usable)
 {
-    const double v = isfinite(c2) ? c2 - shift : -1.0;
-    out[27] = (float)v;
-    out[59] = (float)(v - (double)out[27]);
+    if (!usable || !isfinite(c2)) {
+        out[27] = usable ? -INFINITY : -1.0f;
+        out[59] = 0.0f;
+    } else {
+        const double v = c2 - shift;
+        out[27] = (float)v;
+        out[59] = (float)(v - (double)out[27]);
+    }
     out[kMirShift] = (float)shift;
 }
 

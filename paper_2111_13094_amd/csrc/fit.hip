@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
     // the shift is an FP32 value, so adding it back in FP64 is exact
     const float shift = isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f;
     if (active) {
-        set_mirror_shift(m, c2, (double)shift);
+        set_mirror_shift(m, c2, (double)shift, ok);
         store_mirror(mirror + g * kMirror, m);
     }
     if (c < C && k == 0) {
@@ -188,7 +188,7 @@ __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t 
     float* out = mirror + g * kMirror;
     if (upd) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
     const double cmax = group_max_d((upd && okm) ? c2 : -INFINITY, GM);
-    if (upd) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f));
+    if (upd) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f), okm);
 }
 
 // ---------------------------------------------------------------------------------

@@ -106,16 +106,22 @@ def _ptr(t: torch.Tensor | None, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
-def _need(t: torch.Tensor | None, n: int, what: str):
-    """Size check before a launch: the C ABI takes bare pointers, so a tensor smaller than
-    its documented layout would let a kernel access memory past its end."""
-    if t is not None and t.numel() < n:
+def _need(t: torch.Tensor | None, n: int, what: str, dtype=None):
+    """Size and element-type check before a launch: the C ABI takes bare pointers, so a
+    tensor smaller than its documented layout, or of a narrower element type, would let a
+    kernel access memory past its end."""
+    if t is None:
+        return
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if t.numel() < n:
         raise ValueError(f"{what} has {t.numel()} elements, needs {n}")
 
 
 def _state_ptrs(state: dict, n_cells: int, K: int):
-    for key, n in (("s0", n_cells * K), ("s2", n_cells * K * 15), ("sw", n_cells), ("step", n_cells)):
-        _need(state[key], n, f"state[{key!r}]")
+    for key, n, dt in (("s0", n_cells * K, torch.float64), ("s2", n_cells * K * 15, torch.float64),
+                       ("sw", n_cells, torch.float64), ("step", n_cells, torch.int32)):
+        _need(state[key], n, f"state[{key!r}]", dt)
     st = EmState()
     st.s0, st.s2 = _ptr(state["s0"], torch.float64), _ptr(state["s2"], torch.float64)
     st.sw, st.step = _ptr(state["sw"], torch.float64), _ptr(state["step"], torch.int32)
@@ -161,15 +167,16 @@ def default_opts(K: int = 16, **kw) -> FitOpts:
 
 
 def _mixtures(mix: dict, n_cells: int, K: int) -> Mixtures:
+    for key, n in (("pi", 1), ("mu_dir", 3), ("mu_pos", 3), ("cov", 15)):
+        _need(mix[key], 0, f"mixture array {key}", torch.float64)
+        if mix[key].numel() != n_cells * K * n:
+            raise ValueError(f"mixture array {key} has {mix[key].numel()} values, expected {n_cells * K * n}")
     m = Mixtures()
     m.n_cells, m.K = n_cells, K
     m.weights = _ptr(mix["pi"], torch.float64)
     m.mean_dir = _ptr(mix["mu_dir"], torch.float64)
     m.mean_pos = _ptr(mix["mu_pos"], torch.float64)
     m.cov = _ptr(mix["cov"], torch.float64)
-    for key, n in (("pi", 1), ("mu_dir", 3), ("mu_pos", 3), ("cov", 15)):
-        if mix[key].numel() != n_cells * K * n:
-            raise ValueError(f"mixture array {key} has {mix[key].numel()} values, expected {n_cells * K * n}")
     return m
 
 
@@ -208,15 +215,17 @@ def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, s
     N = samples.shape[1]
     if status is None:
         status = torch.empty(n_cells, dtype=torch.int32, device=samples.device)
-    _need(status, n_cells, "status")
+    _need(status, n_cells, "status", torch.int32)
+    _need(cell_offsets, n_cells + 1, "cell_offsets", torch.int64)
+    _need(samples, 7 * N, "samples", torch.float32)
     nbytes = workspace_bytes(n_cells, K, N, opts)
     if workspace is None:
         workspace = _workspace(nbytes, samples.device)
     m = _mixtures(mix, n_cells, K)
     st = _state_ptrs(state, n_cells, K)
     rc = lib().sdmm_fit_mixtures(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N, C.byref(m),
-                                 C.byref(st), C.byref(opts), _ptr(status, torch.int32), _ptr(workspace),
-                                 workspace.numel(), _stream(stream))
+                                 C.byref(st), C.byref(opts), _ptr(status, torch.int32),
+                                 _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream))
     _check(rc, "sdmm_fit_mixtures")
     return status
 
@@ -234,26 +243,29 @@ def condition_prepare(mix: dict, n_cells: int, K: int, table: torch.Tensor | Non
 def condition(table, n_cells, K, qpos, qcell, stream=None):
     """qpos float32 [3, nq]; qcell int32 [nq]. Returns (cond_w [nq, K], cond_m [nq, K, 2])."""
     nq = qcell.numel()
-    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
-    _need(qpos, 3 * nq, "qpos")
+    _need(qcell, nq, "qcell", torch.int32)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table", torch.float32)
+    _need(qpos, 3 * nq, "qpos", torch.float32)
     cw = torch.empty(nq, K, dtype=torch.float32, device=qcell.device)
     cm = torch.empty(nq, K, 2, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_condition(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
-                                _ptr(qcell, torch.int32), nq, _ptr(cw), _ptr(cm), _stream(stream)), "sdmm_condition")
+                                _ptr(qcell, torch.int32), nq, _ptr(cw, torch.float32), _ptr(cm, torch.float32), _stream(stream)),
+           "sdmm_condition")
     return cw, cm
 
 
 def pdf(table, n_cells, K, qcell, cond_w, cond_m, dirs, nd, stream=None):
     """dirs float32 [3, nq*nd]. Returns pdf float32 [nq*nd]."""
     nq = qcell.numel()
-    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
-    _need(cond_w, nq * K, "cond_w")
-    _need(cond_m, nq * K * 2, "cond_m")
-    _need(dirs, 3 * nq * nd, "dirs")
+    _need(qcell, nq, "qcell", torch.int32)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table", torch.float32)
+    _need(cond_w, nq * K, "cond_w", torch.float32)
+    _need(cond_m, nq * K * 2, "cond_m", torch.float32)
+    _need(dirs, 3 * nq * nd, "dirs", torch.float32)
     out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qcell, torch.int32), nq,
                           _ptr(cond_w, torch.float32), _ptr(cond_m, torch.float32), nd, _ptr(dirs, torch.float32),
-                          _ptr(out), _stream(stream)), "sdmm_pdf")
+                          _ptr(out, torch.float32), _stream(stream)), "sdmm_pdf")
     return out
 
 
@@ -263,18 +275,20 @@ def sample(table, n_cells, K, qcell, cond_w, cond_m, ns, uniforms=None, seed=0, 
     nq = qcell.numel()
     dev = qcell.device
     n = nq * ns
-    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
-    _need(cond_w, nq * K, "cond_w")
-    _need(cond_m, nq * K * 2, "cond_m")
-    _need(uniforms, 3 * n, "uniforms")
+    _need(qcell, nq, "qcell", torch.int32)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table", torch.float32)
+    _need(cond_w, nq * K, "cond_w", torch.float32)
+    _need(cond_m, nq * K * 2, "cond_m", torch.float32)
+    _need(uniforms, 3 * n, "uniforms", torch.float32)
     dirs = torch.empty(3, n, dtype=torch.float32, device=dev)
     pdfv = torch.empty(n, dtype=torch.float32, device=dev)
     valid = torch.empty(n, dtype=torch.uint8, device=dev)
     comp = torch.empty(n, dtype=torch.int32, device=dev) if with_comp else None
     _check(lib().sdmm_sample(_ptr(table, torch.float32), n_cells, K, _ptr(qcell, torch.int32), nq,
                              _ptr(cond_w, torch.float32), _ptr(cond_m, torch.float32), ns,
-                             _ptr(uniforms, torch.float32), seed, _ptr(dirs), _ptr(pdfv), _ptr(valid),
-                             _ptr(comp), _stream(stream)), "sdmm_sample")
+                             _ptr(uniforms, torch.float32), seed, _ptr(dirs, torch.float32),
+                             _ptr(pdfv, torch.float32), _ptr(valid, torch.uint8), _ptr(comp, torch.int32),
+                             _stream(stream)), "sdmm_sample")
     return dirs, pdfv, valid, comp
 
 
@@ -287,25 +301,29 @@ def condition_sample_pdf(table, n_cells, K, qpos, qcell, ns, uniforms=None, seed
         out = (torch.empty(3, n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.uint8, device=dev))
     dirs, pdfv, valid = out
-    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
-    _need(qpos, 3 * nq, "qpos")
-    _need(uniforms, 3 * n, "uniforms")
-    for t, m, what in ((dirs, 3 * n, "dirs"), (pdfv, n, "pdf"), (valid, n, "valid")):
-        _need(t, m, what)
+    _need(qcell, nq, "qcell", torch.int32)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table", torch.float32)
+    _need(qpos, 3 * nq, "qpos", torch.float32)
+    _need(uniforms, 3 * n, "uniforms", torch.float32)
+    for t, m, what, dt in ((dirs, 3 * n, "dirs", torch.float32), (pdfv, n, "pdf", torch.float32),
+                           (valid, n, "valid", torch.uint8)):
+        _need(t, m, what, dt)
     _check(lib().sdmm_condition_sample_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                            _ptr(qcell, torch.int32), nq, ns, _ptr(uniforms, torch.float32), seed,
-                                           _ptr(dirs), _ptr(pdfv), _ptr(valid), _stream(stream)),
+                                           _ptr(dirs, torch.float32), _ptr(pdfv, torch.float32),
+                                           _ptr(valid, torch.uint8), _stream(stream)),
            "sdmm_condition_sample_pdf")
     return dirs, pdfv, valid
 
 
-def _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq):
-    _need(table, n_cells * K * COND_TABLE_STRIDE, "table")
-    _need(btable, n_bsdf * Kb * COND_TABLE_STRIDE, "btable")
-    _need(qpos, 3 * nq, "qpos")
-    _need(bpar, 3 * nq, "bpar")
-    _need(bcell, nq, "bcell")
-    _need(frames, 9 * nq, "frames")
+def _product_checks(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq):
+    _need(qcell, nq, "qcell", torch.int32)
+    _need(table, n_cells * K * COND_TABLE_STRIDE, "table", torch.float32)
+    _need(btable, n_bsdf * Kb * COND_TABLE_STRIDE, "btable", torch.float32)
+    _need(qpos, 3 * nq, "qpos", torch.float32)
+    _need(bpar, 3 * nq, "bpar", torch.float32)
+    _need(bcell, nq, "bcell", torch.int32)
+    _need(frames, 9 * nq, "frames", torch.float32)
 
 
 def product_sample(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, ns, uniforms=None, seed=0,
@@ -321,15 +339,17 @@ def product_sample(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bce
                torch.empty(n, dtype=torch.uint8, device=dev),
                torch.empty(n, dtype=torch.int32, device=dev) if with_pair else None)
     dirs, pdfv, valid, pair = out
-    _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
-    _need(uniforms, 3 * n, "uniforms")
-    for t, m, what in ((dirs, 3 * n, "dirs"), (pdfv, n, "pdf"), (valid, n, "valid"), (pair, n, "pair")):
-        _need(t, m, what)
+    _product_checks(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
+    _need(uniforms, 3 * n, "uniforms", torch.float32)
+    for t, m, what, dt in ((dirs, 3 * n, "dirs", torch.float32), (pdfv, n, "pdf", torch.float32),
+                           (valid, n, "valid", torch.uint8), (pair, n, "pair", torch.int32)):
+        _need(t, m, what, dt)
     _check(lib().sdmm_product_sample(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                      _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
                                      _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
-                                     nq, ns, _ptr(uniforms, torch.float32), seed, _ptr(dirs), _ptr(pdfv), _ptr(valid),
-                                     _ptr(pair), _stream(stream)), "sdmm_product_sample")
+                                     nq, ns, _ptr(uniforms, torch.float32), seed, _ptr(dirs, torch.float32),
+                                     _ptr(pdfv, torch.float32), _ptr(valid, torch.uint8), _ptr(pair, torch.int32),
+                                     _stream(stream)), "sdmm_product_sample")
     return dirs, pdfv, valid, pair
 
 
@@ -337,13 +357,14 @@ def product_pdf(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell,
     """Product density at dirs float32 [3, nq*nd]. Returns pdf [nq*nd]."""
     nq = qcell.numel()
     nd = dirs.shape[1] // max(nq, 1)
-    _product_checks(table, n_cells, K, qpos, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
-    _need(dirs, 3 * nq * nd, "dirs")
+    _product_checks(table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq)
+    _need(dirs, 3 * nq * nd, "dirs", torch.float32)
     out = torch.empty(nq * nd, dtype=torch.float32, device=qcell.device)
     _check(lib().sdmm_product_pdf(_ptr(table, torch.float32), n_cells, K, _ptr(qpos, torch.float32),
                                   _ptr(qcell, torch.int32), _ptr(btable, torch.float32), n_bsdf, Kb,
                                   _ptr(bpar, torch.float32), _ptr(bcell, torch.int32), _ptr(frames, torch.float32),
-                                  nq, nd, _ptr(dirs, torch.float32), _ptr(out), _stream(stream)), "sdmm_product_pdf")
+                                  nq, nd, _ptr(dirs, torch.float32), _ptr(out, torch.float32), _stream(stream)),
+           "sdmm_product_pdf")
     return out
 
 
@@ -391,8 +412,8 @@ def tree_refine(t: dict, samples, split_threshold, mix: dict, state: dict, K, mi
     nl, status = C.c_int32(0), C.c_int32(0)
     tt = _tree(t)
     _check(lib().sdmm_tree_refine(C.byref(tt), _ptr(samples, torch.float32), N, split_threshold, min_init, C.byref(m),
-                                  C.byref(st), _ptr(sorted_), _ptr(offsets, torch.int64), C.byref(nl),
-                                  C.byref(status), _ptr(workspace), workspace.numel(), _stream(stream)),
+                                  C.byref(st), _ptr(sorted_, torch.float32), _ptr(offsets, torch.int64), C.byref(nl),
+                                  C.byref(status), _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)),
            "sdmm_tree_refine")
     return sorted_, offsets[:nl.value + 1], nl.value, status.value
 
@@ -416,9 +437,10 @@ def fit_grad(cell_offsets, samples, mix, opts: FitOpts, workspace=None, stream=N
         workspace = _workspace(nbytes, dev)
     m = _mixtures(mix, n_cells, K)
     rc = lib().sdmm_fit_grad(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N, C.byref(m),
-                             C.byref(opts), _ptr(out["F"]), _ptr(out["alpha"]), _ptr(out["mu_pos"]),
-                             _ptr(out["delta"]), _ptr(out["L"]), _ptr(out["status"]), _ptr(workspace),
-                             workspace.numel(), _stream(stream))
+                             C.byref(opts), _ptr(out["F"], torch.float64), _ptr(out["alpha"], torch.float64),
+                             _ptr(out["mu_pos"], torch.float64), _ptr(out["delta"], torch.float64),
+                             _ptr(out["L"], torch.float64), _ptr(out["status"], torch.int32),
+                             _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream))
     _check(rc, "sdmm_fit_grad")
     return out
 
@@ -431,7 +453,7 @@ def mixture_from_params(alpha, mu_dir0, delta, mu_pos, L, out=None, with_jac=Tru
     for t, m, what in ((alpha, n_cells * K, "alpha"), (mu_dir0, n_cells * K * 3, "mu_dir0"),
                        (delta, n_cells * K * 2, "delta"), (mu_pos, n_cells * K * 3, "mu_pos"),
                        (L, n_cells * K * 15, "L")):
-        _need(t, m, what)
+        _need(t, m, what, torch.float64)
     if out is None:
         out = {"pi": torch.empty(n_cells * K, dtype=torch.float64, device=dev),
                "mu_dir": torch.empty(n_cells * K * 3, dtype=torch.float64, device=dev),
@@ -439,8 +461,9 @@ def mixture_from_params(alpha, mu_dir0, delta, mu_pos, L, out=None, with_jac=Tru
                "cov": torch.empty(n_cells * K * 15, dtype=torch.float64, device=dev)}
     jac = torch.empty(n_cells, K, 4, dtype=torch.float64, device=dev) if with_jac else None
     m = _mixtures(out, n_cells, K)
-    rc = lib().sdmm_mixture_from_params(n_cells, K, _ptr(alpha), _ptr(mu_dir0), _ptr(delta), _ptr(mu_pos),
-                                        _ptr(L), C.byref(m), _ptr(jac) if jac is not None else None,
+    f64 = torch.float64
+    rc = lib().sdmm_mixture_from_params(n_cells, K, _ptr(alpha, f64), _ptr(mu_dir0, f64), _ptr(delta, f64),
+                                        _ptr(mu_pos, f64), _ptr(L, f64), C.byref(m), _ptr(jac, f64),
                                         _stream(stream))
     _check(rc, "sdmm_mixture_from_params")
     return out, jac
@@ -451,8 +474,10 @@ def grad_to_params(L, jac, g_delta, g_L, stream=None):
     n_cells, K = L.shape[0], L.shape[1]
     for t, m, what in ((L, n_cells * K * 15, "L"), (jac, n_cells * K * 4, "jac"), (g_delta, n_cells * K * 2, "g_delta"),
                        (g_L, n_cells * K * 15, "g_L")):
-        _need(t, m, what)
-    rc = lib().sdmm_grad_to_params(n_cells, K, _ptr(L), _ptr(jac), _ptr(g_delta), _ptr(g_L), _stream(stream))
+        _need(t, m, what, torch.float64)
+    f64 = torch.float64
+    rc = lib().sdmm_grad_to_params(n_cells, K, _ptr(L, f64), _ptr(jac, f64), _ptr(g_delta, f64), _ptr(g_L, f64),
+                                   _stream(stream))
     _check(rc, "sdmm_grad_to_params")
 
 
@@ -464,6 +489,7 @@ def params_from_mixture(mix, n_cells, K, stream=None):
     L = torch.empty(n_cells, K, 15, dtype=torch.float64, device=dev)
     status = torch.empty(n_cells, dtype=torch.int32, device=dev)
     m = _mixtures(mix, n_cells, K)
-    rc = lib().sdmm_params_from_mixture(C.byref(m), _ptr(alpha), _ptr(L), _ptr(status), _stream(stream))
+    rc = lib().sdmm_params_from_mixture(C.byref(m), _ptr(alpha, torch.float64), _ptr(L, torch.float64),
+                                        _ptr(status, torch.int32), _stream(stream))
     _check(rc, "sdmm_params_from_mixture")
     return alpha, L, status

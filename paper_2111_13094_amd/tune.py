@@ -6,8 +6,11 @@ computes beyond FP32 rounding:
   * the E-step work-item size P (min_range, with max_ranges large so that P = min_range
     rounded up to a power of two): small items balance the waves across the 256 compute
     units; large items cost fewer records and M-step reads;
-  * the schedule: one E launch then one M launch (SCHED_BATCHED), or the fused launch in
-    which the last wave of each cell runs its M-step (SCHED_FUSED);
+  * the schedule. The default candidates are all SCHED_BATCHED (one E launch, then one M
+    launch): the fused launch, in which the last wave of each cell runs its M-step
+    (SCHED_FUSED), measured 3-5x slower per step on the 4096-cell batch, because each
+    wave's device-scope release and acquire writes back and invalidates the L2 that the
+    sample stream runs through. A caller may still pass fused candidates;
   * the waves per work group of the E-step launch (1, 2 or 4), which changes how soon a
     compute unit can start new items when items end at different times.
 
@@ -30,7 +33,8 @@ _CACHE: dict = {}
 DEFAULT_CANDIDATES = [
     {"schedule": sdmm.SCHED_BATCHED, "min_range": P, "waves_per_block": wpb}
     for P in (128, 256, 512, 1024) for wpb in (1, 2, 4)
-] + [{"schedule": sdmm.SCHED_FUSED, "min_range": P, "waves_per_block": 4} for P in (256, 1024)]
+]
+FUSED_CANDIDATES = [{"schedule": sdmm.SCHED_FUSED, "min_range": P, "waves_per_block": 4} for P in (256, 1024)]
 
 
 def _key(n_cells, K, N, opts):

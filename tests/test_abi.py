@@ -137,9 +137,70 @@ def test_binding_rejects_undersized_product_and_parameter_tensors():
     with pytest.raises(ValueError, match="btable"):  # (the draw count is taken from dirs' shape)
         sdmm.product_pdf(**{**args, "btable": btable[:-1]}, dirs=torch.zeros(3, nq * 2))
     n = n_cells * K
+    f64 = dict(dtype=torch.float64)
     with pytest.raises(ValueError, match="jac"):
-        sdmm.grad_to_params(torch.zeros(n_cells, K, 15), torch.zeros(n * 4 - 1), torch.zeros(n * 2),
-                            torch.zeros(n * 15))
+        sdmm.grad_to_params(torch.zeros(n_cells, K, 15, **f64), torch.zeros(n * 4 - 1, **f64),
+                            torch.zeros(n * 2, **f64), torch.zeros(n * 15, **f64))
     with pytest.raises(ValueError, match="delta"):
-        sdmm.mixture_from_params(torch.zeros(n_cells, K), torch.zeros(n * 3), torch.zeros(n * 2 - 1),
-                                 torch.zeros(n * 3), torch.zeros(n * 15))
+        sdmm.mixture_from_params(torch.zeros(n_cells, K, **f64), torch.zeros(n * 3, **f64),
+                                 torch.zeros(n * 2 - 1, **f64), torch.zeros(n * 3, **f64), torch.zeros(n * 15, **f64))
+
+
+def test_binding_rejects_wrong_element_types():
+    """A tensor of the right element count but a narrower type would let a kernel write
+    past its end (an FP64 kernel into a float32 buffer), so the binding checks the element
+    type of every tensor the caller supplies, before anything reaches the library."""
+    import torch
+    from paper_2111_13094_amd import sdmm
+    K, n_cells, nq, ns = 16, 4, 8, 4
+    n = nq * ns
+    full = n_cells * K * sdmm.COND_TABLE_STRIDE
+    table, qpos, qcell = torch.zeros(full), torch.zeros(3, nq), torch.zeros(nq, dtype=torch.int32)
+    cw, cm = torch.zeros(nq, K), torch.zeros(nq, K, 2)
+    with pytest.raises(TypeError, match="table"):
+        sdmm.condition(table.double(), n_cells, K, qpos, qcell)
+    with pytest.raises(TypeError, match="qcell"):
+        sdmm.condition(table, n_cells, K, qpos, qcell.long())
+    with pytest.raises(TypeError, match="cond_w"):
+        sdmm.pdf(table, n_cells, K, qcell, cw.double(), cm, torch.zeros(3, nq * 2), 2)
+    with pytest.raises(TypeError, match="uniforms"):
+        sdmm.sample(table, n_cells, K, qcell, cw, cm, ns, uniforms=torch.zeros(3, n, dtype=torch.float64))
+    out = (torch.zeros(3, n), torch.zeros(n), torch.zeros(n, dtype=torch.uint8))
+    for i, (what, bad) in enumerate((("dirs", torch.zeros(3, n, dtype=torch.float64)),
+                                     ("pdf", torch.zeros(n, dtype=torch.float64)),
+                                     ("valid", torch.zeros(n, dtype=torch.int32)))):
+        o = list(out)
+        o[i] = bad
+        with pytest.raises(TypeError, match=what):
+            sdmm.condition_sample_pdf(table, n_cells, K, qpos, qcell, ns, out=tuple(o))
+    Kb, n_bsdf = 16, 3
+    args = dict(table=table, n_cells=n_cells, K=K, qpos=qpos, qcell=qcell,
+                btable=torch.zeros(n_bsdf * Kb * sdmm.COND_TABLE_STRIDE), n_bsdf=n_bsdf, Kb=Kb,
+                bpar=torch.zeros(3, nq), bcell=torch.zeros(nq, dtype=torch.int32), frames=torch.zeros(9, nq))
+    pout = (torch.zeros(3, n), torch.zeros(n), torch.zeros(n, dtype=torch.uint8), torch.zeros(n, dtype=torch.int32))
+    for i, (what, bad) in enumerate((("dirs", torch.zeros(3, n, dtype=torch.float64)),
+                                     ("pdf", torch.zeros(n, dtype=torch.float64)),
+                                     ("valid", torch.zeros(n, dtype=torch.int32)),
+                                     ("pair", torch.zeros(n, dtype=torch.float32)))):
+        o = list(pout)
+        o[i] = bad
+        with pytest.raises(TypeError, match=what):
+            sdmm.product_sample(**args, ns=ns, out=tuple(o))
+    with pytest.raises(TypeError, match="frames"):
+        sdmm.product_pdf(**{**args, "frames": torch.zeros(9, nq, dtype=torch.float64)}, dirs=torch.zeros(3, nq * 2))
+    nc = n_cells * K
+    with pytest.raises(TypeError, match="jac"):
+        sdmm.grad_to_params(torch.zeros(n_cells, K, 15, dtype=torch.float64), torch.zeros(nc * 4),
+                            torch.zeros(nc * 2, dtype=torch.float64), torch.zeros(nc * 15, dtype=torch.float64))
+    f64 = dict(dtype=torch.float64)
+    with pytest.raises(TypeError, match="L"):
+        sdmm.mixture_from_params(torch.zeros(n_cells, K, **f64), torch.zeros(nc * 3, **f64),
+                                 torch.zeros(nc * 2, **f64), torch.zeros(nc * 3, **f64), torch.zeros(nc * 15))
+    off = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int64)
+    mix = {"pi": torch.zeros(nc, **f64), "mu_dir": torch.zeros(nc * 3, **f64), "mu_pos": torch.zeros(nc * 3, **f64),
+           "cov": torch.zeros(nc * 15)}
+    with pytest.raises(TypeError, match="cov"):
+        sdmm.fit_mixtures(off, torch.zeros(7, 4), mix, sdmm.new_state(n_cells, K, device="cpu"), sdmm.default_opts(K))
+    with pytest.raises(TypeError, match="cell_offsets"):
+        sdmm.fit_mixtures(off.int(), torch.zeros(7, 4), mix, sdmm.new_state(n_cells, K, device="cpu"),
+                          sdmm.default_opts(K))

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from paper_2111_13094_amd import synth
-from tests.parity_utils import to_torch
+from tests.parity_utils import CUT_LOCUS_BAND, draw_radius, to_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -105,6 +105,9 @@ def _compare(orc, sc, u, got, stats):
                 ambiguous += 1
                 continue
             if gv[q, t] != ov[q, t]:  # only at the cut locus |nu| = pi
+                p = opair[q, t]
+                r = draw_radius(pr["c"][p], pr["C"][p], u[q, t].astype(np.float64))
+                assert abs(r - np.pi) < CUT_LOCUS_BAND, (q, t, gv[q, t], ov[q, t], r)
                 ambiguous += 1
                 continue
             if not ov[q, t]:

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2111_13094_amd import synth
-from tests.parity_utils import to_torch
+from tests.parity_utils import CUT_LOCUS_BAND, draw_radius, to_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_condition_parity(dev, orc, fitted):
     table, qp, qc, cw, cm = _gpu_cond(dev, mix, C, 16, qpos, qcell)
     cw, cm = cw.cpu().numpy(), cm.cpu().numpy()
     for q in range(qpos.shape[0]):
-        pic, m, _ = orc.condition(16, mix, int(qcell[q]), qpos[q].astype(np.float64))
+        pic, m, Sc = orc.condition(16, mix, int(qcell[q]), qpos[q].astype(np.float64))
         assert np.abs(cw[q] - pic).max() < 1e-6, (q, cw[q], pic)
         scale = np.abs(m).max(axis=1, keepdims=True) + 1e-6
         assert (np.abs(cm[q] - m) / scale).max() < 1e-4, (q, cm[q], m)
@@ -95,7 +95,7 @@ def _sample_parity(orc, mix, qpos, qcell, u, got_dirs, got_pdf, got_valid, got_c
     od, op, oc, ov = orc.sample(16, mix, qpos.astype(np.float64), qcell, u.astype(np.float64))
     ambiguous = 0
     for q in range(nq):
-        pic, m, _ = orc.condition(16, mix, int(qcell[q]), qpos[q].astype(np.float64))
+        pic, m, Sc = orc.condition(16, mix, int(qcell[q]), qpos[q].astype(np.float64))
         cdf = np.cumsum(pic)
         for t in range(ns):
             near_cdf = np.min(np.abs(cdf - u[q, t, 0])) < 2e-6
@@ -106,6 +106,8 @@ def _sample_parity(orc, mix, qpos, qcell, u, got_dirs, got_pdf, got_valid, got_c
             if got_valid[q, t] != ov[q, t]:
                 # only at the cut locus |nu| = pi
                 k = oc[q, t]
+                r = draw_radius(m[k], Sc[k], u[q, t].astype(np.float64))
+                assert abs(r - np.pi) < CUT_LOCUS_BAND, (q, t, got_valid[q, t], ov[q, t], r)
                 ambiguous += 1
                 continue
             if not ov[q, t]:

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2111_13094_amd import synth
-from tests.parity_utils import assert_close, compare_mixtures, state_to_torch, to_numpy, to_torch
+from tests.parity_utils import assert_cells_close, positive_counts, state_to_torch, to_numpy, to_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -169,9 +169,7 @@ def test_refine_then_fit_matches_the_oracle(dev, orc):
     om, ost = nview(mix, L), nview(st, L)
     orc.fit(orc.Opts(K=K), off_o, srt_o, om, ost)
     fitted = [l for l in range(L) if off_o[l + 1] - off_o[l] >= 64]
-    worst = compare_mixtures(to_numpy(gmv), om, K, cells=fitted)
-    print(worst)
-    assert_close(worst, rtol=2e-4, ang_tol=2e-5, what="refine + fit")
+    assert_cells_close(to_numpy(gmv), om, K, fitted, positive_counts(srt_o, off_o), what="refine + fit")
 
 
 def test_full_size_refinement(dev, orc):
