@@ -179,6 +179,31 @@ int sdmm_fit_mixtures(const int64_t *cell_offsets, const float *samples, int64_t
                       const sdmm_fit_opts *opts, int32_t *cell_status, void *workspace,
                       size_t workspace_bytes, void *stream);
 
+/* Size of the library's own device workspace for sdmm_fit_mixtures_noalloc: 64 MiB per
+ * device, held from the library's load to the end of the process. */
+#define SDMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * sdmm_fit_mixtures_noalloc -- sdmm_fit_mixtures for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, kernels and results as sdmm_fit_mixtures (bitwise),
+ * without the workspace: the library's static per-device array of
+ * SDMM_NOALLOC_SCRATCH_BYTES takes its place. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the first call on a device looks up that
+ * device's array address once.
+ * Limits: sdmm_fit_workspace_size() of the call must be at most
+ * SDMM_NOALLOC_SCRATCH_BYTES, else SDMM_ENOWORKSPACE and nothing is enqueued (the
+ * 4096-cell, 4.2M-sample batch fits with 512-sample work items, opts->min_range = 512);
+ * opts->schedule SDMM_SCHED_PER_CELL and opts->use_graph = 1 are rejected with
+ * SDMM_EINVAL (the first copies the offsets to the host, the second instantiates
+ * graphs). Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, or threads) race and must be serialised by the caller.
+ * Nothing in the array needs to start at zero: each call resets what it reads.
+ */
+int sdmm_fit_mixtures_noalloc(const int64_t *cell_offsets, const float *samples, int64_t n_samples,
+                              const sdmm_mixtures *mix, const sdmm_em_state *state,
+                              const sdmm_fit_opts *opts, int32_t *cell_status, void *stream);
+
 /* ---- conditioning, pdf, sampling ---- */
 
 /* floats per component in the conditioning table */

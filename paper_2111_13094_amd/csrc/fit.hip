@@ -832,6 +832,64 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
     return enqueue_fit(a, s, nullptr);
 }
 
+namespace sdmm {
+
+// ---------------------------------------------------------------------------------
+// The fit without a caller workspace, for callers that cannot allocate device memory
+// (code under graph capture, serving loops). Its workspace is this file-scope array, one
+// copy per device, held from the library's load to the end of the process. In host code
+// the array's name only stands for the symbol: its device address comes from
+// hipGetSymbolAddress, looked up once per device on the first call with that device
+// current, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[SDMM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch array (nullptr and an error code on
+// failure)
+static int scratch_for_current_device(char** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    int rc = check(hipGetDevice(&dev));
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return SDMM_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        rc = check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (rc) return rc;
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SDMM_OK;
+}
+
+}  // namespace sdmm
+
+extern "C" int sdmm_fit_mixtures_noalloc(const int64_t* cell_offsets, const float* samples, int64_t n_samples,
+                                         const sdmm_mixtures* mix, const sdmm_em_state* state,
+                                         const sdmm_fit_opts* opts, int32_t* cell_status, void* stream)
+{
+    // the per-cell schedule copies the offsets to the host, and the graph cache
+    // instantiates graphs: neither belongs in a call that must not allocate
+    if (!opts || opts->schedule == SDMM_SCHED_PER_CELL || opts->use_graph) return SDMM_EINVAL;
+    // the argument checks of sdmm_fit_mixtures, with the scratch array's size as the
+    // workspace size (they only test the workspace pointer for null: cell_offsets
+    // stands in for it here, before the device address is known)
+    int rc = validate_fit_args(cell_offsets, samples, n_samples, mix, opts, cell_status, cell_offsets,
+                               (size_t)SDMM_NOALLOC_SCRATCH_BYTES);
+    if (rc) return rc;
+    char* ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    return sdmm_fit_mixtures(cell_offsets, samples, n_samples, mix, state, opts, cell_status, ws,
+                             (size_t)SDMM_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 extern "C" const char* sdmm_status_string(int code)
 {
     switch (code) {

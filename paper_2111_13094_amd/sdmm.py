@@ -70,6 +70,7 @@ def lib():
         L.sdmm_fit_workspace_size.argtypes = [i32, i32, i64, P(FitOpts)]
         L.sdmm_fit_workspace_size.restype = sz
         L.sdmm_fit_mixtures.argtypes = [vp, vp, i64, P(Mixtures), P(EmState), P(FitOpts), vp, vp, sz, vp]
+        L.sdmm_fit_mixtures_noalloc.argtypes = [vp, vp, i64, P(Mixtures), P(EmState), P(FitOpts), vp, vp]
         L.sdmm_condition_prepare.argtypes = [P(Mixtures), vp, vp]
         L.sdmm_condition.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp]
         L.sdmm_pdf.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, vp, vp, vp]
@@ -227,6 +228,31 @@ def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, s
                                  C.byref(st), C.byref(opts), _ptr(status, torch.int32),
                                  _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream))
     _check(rc, "sdmm_fit_mixtures")
+    return status
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fit_mixtures_noalloc(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, state: dict,
+                         opts: FitOpts, status: torch.Tensor, stream=None):
+    """sdmm_fit_mixtures_noalloc: fit_mixtures on the library's static per-device
+    workspace (at most NOALLOC_SCRATCH_BYTES; no per-cell schedule, no graph cache).
+    The caller passes every output, including ``status`` (int32 [C])."""
+    n_cells = cell_offsets.numel() - 1
+    K = opts.K
+    if samples.dim() != 2 or samples.shape[0] != 7:
+        raise ValueError("samples must be [7, N]")
+    N = samples.shape[1]
+    _need(status, n_cells, "status", torch.int32)
+    _need(cell_offsets, n_cells + 1, "cell_offsets", torch.int64)
+    _need(samples, 7 * N, "samples", torch.float32)
+    m = _mixtures(mix, n_cells, K)
+    st = _state_ptrs(state, n_cells, K)
+    rc = lib().sdmm_fit_mixtures_noalloc(_ptr(cell_offsets, torch.int64), _ptr(samples, torch.float32), N,
+                                         C.byref(m), C.byref(st), C.byref(opts), _ptr(status, torch.int32),
+                                         _stream(stream))
+    _check(rc, "sdmm_fit_mixtures_noalloc")
     return status
 
 

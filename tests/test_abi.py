@@ -204,3 +204,23 @@ def test_binding_rejects_wrong_element_types():
     with pytest.raises(TypeError, match="cell_offsets"):
         sdmm.fit_mixtures(off.int(), torch.zeros(7, 4), mix, sdmm.new_state(n_cells, K, device="cpu"),
                           sdmm.default_opts(K))
+
+
+def test_noalloc_entry_rejects_on_the_host(lib):
+    """The entry point without a workspace checks its arguments and its size limit before
+    it looks up the device array, so these return without a GPU."""
+    from paper_2111_13094_amd import sdmm
+    m, st = sdmm.Mixtures(), sdmm.EmState()
+    m.n_cells, m.K = 4, 16
+    m.weights = m.mean_dir = m.mean_pos = m.cov = C.c_void_p(256)
+    st.s0 = st.s2 = st.sw = st.step = C.c_void_p(256)
+    p = C.c_void_p(256)
+    o = sdmm.default_opts(16, schedule=sdmm.SCHED_PER_CELL)
+    assert lib.sdmm_fit_mixtures_noalloc(p, p, 100, C.byref(m), C.byref(st), C.byref(o), p, None) == -1
+    o = sdmm.default_opts(16, use_graph=1)
+    assert lib.sdmm_fit_mixtures_noalloc(p, p, 100, C.byref(m), C.byref(st), C.byref(o), p, None) == -1
+    o = sdmm.default_opts(16, min_range=16, max_ranges=1 << 20)
+    n = 1 << 22
+    assert lib.sdmm_fit_workspace_size(4, 16, n, C.byref(o)) > sdmm.NOALLOC_SCRATCH_BYTES
+    assert lib.sdmm_fit_mixtures_noalloc(p, p, n, C.byref(m), C.byref(st), C.byref(o), p, None) == -3
+    assert lib.sdmm_fit_mixtures_noalloc(None, p, 100, C.byref(m), C.byref(st), C.byref(o), p, None) == -1
