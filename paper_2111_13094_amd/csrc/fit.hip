@@ -66,23 +66,22 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
         __shared__ int bad, most;
         if (threadIdx.x == 0) bad = 0, most = 1;
         __syncthreads();
-        // each thread scans a contiguous run of offsets, eight independent loads at a time
+        // thread t checks cells t, t + 256, ...: consecutive threads read consecutive
+        // offsets, eight cells' loads in flight per thread
         int b = 0;
         int64_t m = 1;
-        const int per = (C + blockDim.x - 1) / blockDim.x;
-        const int lo = min(C, (int)threadIdx.x * per), hi = min(C, lo + per);
-        int64_t prev = lo < hi ? off[lo] : 0;
-        for (int c = lo; c < hi; c += 8) {
-            int64_t nx[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) nx[u] = c + u < hi ? off[c + u + 1] : prev;
+        for (int c0 = (int)threadIdx.x; c0 < C; c0 += 8 * (int)blockDim.x) {
+            int64_t lo[8], hi[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                if (c + u < hi) {
-                    b |= nx[u] < prev;
-                    m = max(m, (nx[u] - prev + (int64_t(1) << ps) - 1) >> ps);
-                    prev = nx[u];
-                }
+                const int c = c0 + u * (int)blockDim.x;
+                lo[u] = c < C ? off[c] : 0;
+                hi[u] = c < C ? off[c + 1] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                b |= hi[u] < lo[u];
+                m = max(m, (hi[u] - lo[u] + (int64_t(1) << ps) - 1) >> ps);
             }
         }
         if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;

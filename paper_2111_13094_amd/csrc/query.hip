@@ -9,6 +9,8 @@
 //
 // Lane mapping as in the E-step: a wave holds 64/G queries (or draws) x G component lanes;
 // normalisations and mixture sums are DPP all-reduces inside the G-lane group.
+#include <algorithm>
+
 #include "common.hpp"
 #include "query_common.hpp"
 #include "timing.hpp"
@@ -85,22 +87,41 @@ __global__ void cond_prepare_kernel(int C, int K, const double* __restrict__ pi,
     store();
 }
 
-// pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k| at direction w (0 at the cut locus)
-__device__ __forceinline__ float pdf_component(const float* T, float wk, float m0, float m1, float wx, float wy,
+// pi'_k N2(nu_k - m_k; 0, Sigma'_k) / sinc|nu_k| at direction w (0 at the cut locus), with
+// lc = log2 pi'_k + T[31] (pdf_log_const; -inf for a component of weight zero)
+__device__ __forceinline__ float pdf_component(const float* T, float lc, float m0, float m1, float wx, float wy,
                                                float wz)
 {
-    const float xr = fmaf(T[0], wx, fmaf(T[1], wy, T[2] * wz));
+    // the 1e-18 offset of the log map rides on the rotation's first row
+    const float xr = fmaf(T[0], wx, fmaf(T[1], wy, fmaf(T[2], wz, 1e-18f)));
     const float yr = fmaf(T[3], wx, fmaf(T[4], wy, T[5] * wz));
     const float zr = fmaf(T[6], wx, fmaf(T[7], wy, T[8] * wz));
     float n0, n1;
-    const float f = log_map_f32(xr, yr, zr, n0, n1);
+    const float f = log_map_f32_offset(xr, yr, zr, n0, n1);
     const float r2 = fmaf(n0, n0, n1 * n1);
     const float d0 = n0 - m0, d1 = n1 - m1;
     const float u0 = T[27] * d0;
     const float u1 = fmaf(T[28], d0, T[29] * d1);
     const float q = fmaf(u0, u0, u1 * u1);
-    const float p = wk * __builtin_amdgcn_exp2f(T[31] - q) * f;
-    return (r2 < kCutSq && wk > 0.0f) ? p : 0.0f;
+    const float p = __builtin_amdgcn_exp2f(lc - q) * f;
+    return r2 < kCutSq ? p : 0.0f;
+}
+
+// log2 of the conditioned weight plus the conditional density's log2 normaliser T[31]
+__device__ __forceinline__ float pdf_log_const(const float* T, float wk)
+{
+    return T[31] + __builtin_amdgcn_logf(wk);
+}
+
+// the conditioned weight pi'_k of the lane's component from the log2 weights lw of the
+// group (-inf for none): a log-sum-exp over the group
+template <int G>
+__device__ __forceinline__ float cond_weight(float lw)
+{
+    const float lmax = group_max<G>(lw);
+    const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
+    const float den = group_sum<G>(e);
+    return den > 0.0f ? e * __builtin_amdgcn_rcpf(den) : 0.0f;
 }
 
 // One draw for the group's query: pick the component by the CDF of pi' (prefix sum in
@@ -129,7 +150,7 @@ __device__ __forceinline__ void sample_one(const float* T, bool usable, float wk
     oz = __shfl(w[2], src);
     valid = (sel >= 0) ? __shfl(ok, src) : 0;
     comp_sel = sel;
-    const float c = pdf_component(T, wk, m0, m1, ox, oy, oz);
+    const float c = pdf_component(T, pdf_log_const(T, wk), m0, m1, ox, oy, oz);
     pdf = group_sum<G>(comp < K ? c : 0.0f);
     if (!valid) {
         ox = oy = oz = 0.0f;
@@ -160,10 +181,7 @@ __global__ __launch_bounds__(256) void condition_kernel(const float* __restrict_
         float m0, m1;
         float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
         if (comp >= K || !usable) lw = -INFINITY;
-        const float lmax = group_max<G>(lw);
-        const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
-        const float den = group_sum<G>(e);
-        const float wk = den > 0.0f ? e / den : 0.0f;
+        const float wk = cond_weight<G>(lw);
         if (inq && comp < K) {
             cw[q * K + comp] = wk;
             cm[(q * K + comp) * 2] = usable ? m0 : 0.0f;
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(256) void pdf_kernel(const float* __restrict__ tabl
         const int kk = comp < K ? comp : K - 1;
         const float wk = usable ? cw[q * K + kk] : 0.0f;
         const float m0 = cm[(q * K + kk) * 2], m1 = cm[(q * K + kk) * 2 + 1];
-        const float c = pdf_component(T, wk, m0, m1, dirs[pp], dirs[np + pp], dirs[2 * np + pp]);
+        const float c = pdf_component(T, pdf_log_const(T, wk), m0, m1, dirs[pp], dirs[np + pp], dirs[2 * np + pp]);
         const float tot = group_sum<G>(usable ? c : 0.0f);
         if (inp && comp == 0) pdf_out[p] = tot;
     }
@@ -274,10 +292,8 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
         float m0, m1;
         float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
         if (comp >= K || !usable) lw = -INFINITY;
-        const float lmax = group_max<G>(lw);
-        const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
-        const float den = group_sum<G>(e);
-        const float wk = den > 0.0f ? e / den : 0.0f;
+        const float wk = cond_weight<G>(lw);
+        const float lc = pdf_log_const(T, wk);
         const float cdf = group_inclusive_scan<G>(wk);
         const bool cand = comp < K && usable;
         const uint64_t pos = __ballot(cand && wk > 0.0f) & gmask;
@@ -314,7 +330,7 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int from = base + min(tt + j, tn - 1);
-                    c[j] = pdf_component(T, wk, m0, m1, __shfl(w[0], from), __shfl(w[1], from), __shfl(w[2], from));
+                    c[j] = pdf_component(T, lc, m0, m1, __shfl(w[0], from), __shfl(w[1], from), __shfl(w[2], from));
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -331,6 +347,157 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
                 valid_out[d] = (uint8_t)valid;
             }
         }
+    }
+}
+
+// The same conditioning, draws and pdf as cond_sample_pdf_kernel, in three wave-local
+// phases over QB = S * NQR queries, NQR rounds of S queries with QB * ns <= 64 draws:
+//   A. conditioning, lane = (query slot, component), per round: pi', the CDF of pi' and
+//      m into LDS, with each query's cell and last component of positive weight;
+//   B. the draws, one per lane: uniforms, the component by the CDF, the candidate from
+//      the table row of that component;
+//   C. the pdf, lane = (query slot, component) again: every draw of the query over all
+//      components, four at a time.
+// Phase B runs on every lane instead of on ns of each query's G lanes. Every value is
+// computed by the same arithmetic as in sample_one (the scan, the first CDF entry above
+// u0, draw_candidate, pdf_component and group_sum), so the draws are the same.
+template <int G>
+__global__ __launch_bounds__(256) void cond_sample_pdf_lanes_kernel(const float* __restrict__ table, int C, int K,
+                                                                    const float* __restrict__ qpos,
+                                                                    const int32_t* __restrict__ qcell, int64_t nq,
+                                                                    int ns, int nqr, const float* __restrict__ uniforms,
+                                                                    uint64_t seed, float* __restrict__ dirs_out,
+                                                                    float* __restrict__ pdf_out,
+                                                                    uint8_t* __restrict__ valid_out)
+{
+    constexpr int S = 64 / G, QBMAX = 4 * S, WPB = 4;
+    // per wave: the CDF of pi' (-inf past K and for unusable queries, so that no draw
+    // picks those lanes), the pdf's log constants and the conditioned means of its
+    // queries' components; each query's cell (-1: none) and last component of positive
+    // weight; the draws' directions and validity
+    __shared__ __align__(16) float cdf_s[WPB][QBMAX][G];
+    __shared__ float lc_s[WPB][QBMAX][G], m0_s[WPB][QBMAX][G], m1_s[WPB][QBMAX][G];
+    __shared__ int last_s[WPB][QBMAX], cell_s[WPB][QBMAX];
+    __shared__ float4 w_s[WPB][64];
+    __shared__ int valid_s[WPB][64];
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G, base = lane - comp;
+    const int wv = threadIdx.x >> 6;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = nq * ns;
+    const int QB = S * nqr;
+    // the lane's table row stays in registers while its queries' cell repeats (queries
+    // sorted by cell mostly share one); `row_cell` is the cell it holds
+    float T[kCond];
+    int row_cell = -1;
+    auto row_for = [&](int cell) {
+        if (cell != row_cell) {
+            load_row(table_row(table, cell, K, comp, true), K, T);
+            row_cell = cell;
+        }
+    };
+    for (int64_t qb = wave * QB; qb < nq; qb += nwaves * QB) {
+        // A: conditioning
+        for (int r = 0; r < nqr; ++r) {
+            const int qi = r * S + slot;
+            const int64_t q = qb + qi;
+            const bool inq = q < nq;
+            const int64_t qq = inq ? q : 0;
+            const int qc = qcell[qq];
+            const bool usable = inq && qc >= 0 && qc < C;
+            row_for(usable ? qc : 0);
+            float m0, m1;
+            float lw = cond_component(T, qpos[qq], qpos[nq + qq], qpos[2 * nq + qq], m0, m1);
+            if (comp >= K || !usable) lw = -INFINITY;
+            const float wk = cond_weight<G>(lw);
+            const float cdf = group_inclusive_scan<G>(wk);
+            const uint64_t pos = __ballot(comp < K && usable && wk > 0.0f) & gmask;
+            cdf_s[wv][qi][comp] = (comp < K && usable) ? cdf : -INFINITY;
+            lc_s[wv][qi][comp] = pdf_log_const(T, wk);
+            m0_s[wv][qi][comp] = m0;
+            m1_s[wv][qi][comp] = m1;
+            if (comp == 0) {
+                last_s[wv][qi] = pos ? 63 - __builtin_clzll(pos) - base : -1;
+                cell_s[wv][qi] = usable ? qc : -1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // this wave's LDS writes are done
+        // B: one draw per lane
+        {
+            const int qi = lane / ns, t = lane % ns;
+            const int64_t q = qb + qi;
+            const bool act = qi < QB && q < nq;
+            const int64_t d = act ? q * ns + t : 0;
+            float u0, u1, u2;
+            draw_uniforms(uniforms, nd, d, seed, u0, u1, u2);
+            const int qis = act ? qi : 0;
+            const int qc = cell_s[wv][qis];
+            // the first component whose CDF value exceeds u0, else the last of positive weight
+            int first = -1;
+            const float4* crow = reinterpret_cast<const float4*>(&cdf_s[wv][qis][0]);
+#pragma unroll
+            for (int c4 = G / 4 - 1; c4 >= 0; --c4) {
+                const float4 v = crow[c4];
+                first = u0 < v.w ? 4 * c4 + 3 : first;
+                first = u0 < v.z ? 4 * c4 + 2 : first;
+                first = u0 < v.y ? 4 * c4 + 1 : first;
+                first = u0 < v.x ? 4 * c4 : first;
+            }
+            const int sel = first >= 0 ? first : last_s[wv][qis];
+            const int sk = sel < 0 ? 0 : sel;
+            const float4* row = reinterpret_cast<const float4*>(table_row(table, qc, K, sk, qc >= 0));
+            float R[12];
+#pragma unroll
+            for (int c4 = 0; c4 < 3; ++c4) {
+                const float4 v = row[(int64_t)c4 * K];
+                R[4 * c4] = v.x;
+                R[4 * c4 + 1] = v.y;
+                R[4 * c4 + 2] = v.z;
+                R[4 * c4 + 3] = v.w;
+            }
+            const float4 lp = row[(int64_t)6 * K];  // T24-T27: L' packed and one more
+            float w[3];
+            const int ok = draw_candidate(R, lp.x, lp.y, lp.z, m0_s[wv][qis][sk], m1_s[wv][qis][sk], u1, u2, w);
+            w_s[wv][lane] = make_float4(w[0], w[1], w[2], 0.0f);
+            valid_s[wv][lane] = act && sel >= 0 && ok;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        // C: the pdf of every draw over all components, outputs
+        for (int r = 0; r < nqr; ++r) {
+            const int qi = r * S + slot;
+            const int64_t q = qb + qi;
+            const bool inq = q < nq;
+            const int qc = cell_s[wv][qi];
+            row_for(qc >= 0 ? qc : 0);
+            const float lc = lc_s[wv][qi][comp], m0 = m0_s[wv][qi][comp], m1 = m1_s[wv][qi][comp];
+            float pdf = 0.0f;
+            for (int tt = 0; tt < ns; tt += 4) {  // wave-uniform
+                float c[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float4 wd = w_s[wv][qi * ns + min(tt + j, ns - 1)];
+                    c[j] = pdf_component(T, lc, m0, m1, wd.x, wd.y, wd.z);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float p = group_sum<G>(comp < K ? c[j] : 0.0f);
+                    pdf = comp == tt + j ? p : pdf;
+                }
+            }
+            if (inq && comp < ns) {
+                const int dl = qi * ns + comp;
+                const int valid = valid_s[wv][dl];
+                const float4 wd = w_s[wv][dl];
+                const int64_t d = q * ns + comp;
+                dirs_out[d] = valid ? wd.x : 0.0f;
+                dirs_out[nd + d] = valid ? wd.y : 0.0f;
+                dirs_out[2 * nd + d] = valid ? wd.z : 0.0f;
+                pdf_out[d] = valid ? pdf : 0.0f;
+                valid_out[d] = (uint8_t)valid;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // before the next pass overwrites
     }
 }
 
@@ -403,7 +570,16 @@ extern "C" int sdmm_condition_sample_pdf(const float* table, int32_t n_cells, in
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int G = group_for(K);
     ScopedTimer tm(SDMM_TIMER_QUERY, s);
-    SDMM_DISPATCH_G(G, (cond_sample_pdf_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
-                           table, n_cells, K, qpos, qcell, nq, ns, uniforms, seed, dirs_out, pdf_out, valid_out)));
+    const int S = 64 / G;
+    if (S * ns <= 64) {
+        // draws of up to four rounds of S queries share one pass of the draw phase
+        const int nqr = std::max(1, std::min(4, 64 / (S * ns)));
+        SDMM_DISPATCH_G(G, (cond_sample_pdf_lanes_kernel<g><<<grid_for(nq, S * nqr), 256, 0, s>>>(
+                               table, n_cells, K, qpos, qcell, nq, ns, nqr, uniforms, seed, dirs_out, pdf_out,
+                               valid_out)));
+    } else {
+        SDMM_DISPATCH_G(G, (cond_sample_pdf_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
+                               table, n_cells, K, qpos, qcell, nq, ns, uniforms, seed, dirs_out, pdf_out, valid_out)));
+    }
     return check(hipGetLastError());
 }
