@@ -455,7 +455,8 @@ def bench_cells16k(args, torch):
                        "fitted_cells": int(((status.cpu().numpy() & (1 | 2 | 4 | 32)) == 0).sum())},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                         "kernel": "cond_sample_pdf_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl},
+                         "kernel": ("cond_sample_pdf_lanes_kernel<16>" if (64 // 16) * ns <= 64
+                                    else "cond_sample_pdf_kernel<16>"), "kernel_ms": k_ms, "flops_per_launch": fl},
             "fit": {"value": smp.shape[1] * K / t_fit, "unit": "updates/s", "ms_per_step": t_fit * 1e3}}
 
 

@@ -107,6 +107,26 @@ __device__ __forceinline__ float pdf_component(const float* T, float lc, float m
     return r2 < kCutSq ? p : 0.0f;
 }
 
+// Sums of four values over a row of 16 lanes at once: lane i ends with the sum over the
+// row of value (i & 3). Two exchange steps inside each quad leave lane i with the quad's
+// sum of value (i & 3); two rotations by 4 and 8 lanes then add the four quads. The sums
+// associate differently from group_sum (a different FP32 rounding, same value).
+__device__ __forceinline__ float group_sum4_row16(const float (&c)[4])
+{
+    const int lane = threadIdx.x & 63;
+    const bool b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    // partner lane ^ 2: keep values {0,1} (bit 1 clear) or {2,3}, send the other pair
+    const float k0 = b1 ? c[2] : c[0], k1 = b1 ? c[3] : c[1];
+    const float s0 = b1 ? c[0] : c[2], s1 = b1 ? c[1] : c[3];
+    const float a0 = k0 + dpp_f32<kDppXor2>(s0), a1 = k1 + dpp_f32<kDppXor2>(s1);
+    // partner lane ^ 1: keep value (lane & 3), send the other
+    const float k = b0 ? a1 : a0, sn = b0 ? a0 : a1;
+    float v = k + dpp_f32<kDppXor1>(sn);
+    v += dpp_f32<0x124>(v);  // row_ror:4
+    v += dpp_f32<0x128>(v);  // row_ror:8
+    return v;
+}
+
 // log2 of the conditioned weight plus the conditional density's log2 normaliser T[31]
 __device__ __forceinline__ float pdf_log_const(const float* T, float wk)
 {
@@ -114,13 +134,23 @@ __device__ __forceinline__ float pdf_log_const(const float* T, float wk)
 }
 
 // the conditioned weight pi'_k of the lane's component from the log2 weights lw of the
-// group (-inf for none): a log-sum-exp over the group
+// group (-inf for none): exp2(lw) normalised over the group. Only a group whose sum leaves
+// [2^-100, 2^100] (positions far from every component, extreme covariances, or no usable
+// component) takes the maximum first (the textbook log-sum-exp); the others keep their
+// values.
 template <int G>
 __device__ __forceinline__ float cond_weight(float lw)
 {
-    const float lmax = group_max<G>(lw);
-    const float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
-    const float den = group_sum<G>(e);
+    float e = __builtin_amdgcn_exp2f(lw);
+    float den = group_sum<G>(e);
+    const bool out = !(den >= 0x1p-100f && den <= 0x1p100f);
+    if (__ballot(out)) {
+        const float lmax = group_max<G>(lw);
+        const float e2 = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
+        const float den2 = group_sum<G>(e2);
+        e = out ? e2 : e;
+        den = out ? den2 : den;
+    }
     return den > 0.0f ? e * __builtin_amdgcn_rcpf(den) : 0.0f;
 }
 
@@ -358,9 +388,10 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_kernel(const float* __res
 //      the table row of that component;
 //   C. the pdf, lane = (query slot, component) again: every draw of the query over all
 //      components, four at a time.
-// Phase B runs on every lane instead of on ns of each query's G lanes. Every value is
+// Phase B runs on every lane instead of on ns of each query's G lanes. The draws are
 // computed by the same arithmetic as in sample_one (the scan, the first CDF entry above
-// u0, draw_candidate, pdf_component and group_sum), so the draws are the same.
+// u0, draw_candidate), so they are the same; the pdf sums over the components may
+// associate differently (FP32 rounding).
 template <int G>
 __global__ __launch_bounds__(256) void cond_sample_pdf_lanes_kernel(const float* __restrict__ table, int C, int K,
                                                                     const float* __restrict__ qpos,
@@ -459,8 +490,15 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_lanes_kernel(const float*
             const float4 lp = row[(int64_t)6 * K];  // T24-T27: L' packed and one more
             float w[3];
             const int ok = draw_candidate(R, lp.x, lp.y, lp.z, m0_s[wv][qis][sk], m1_s[wv][qis][sk], u1, u2, w);
+            const int valid = act && sel >= 0 && ok;
             w_s[wv][lane] = make_float4(w[0], w[1], w[2], 0.0f);
-            valid_s[wv][lane] = act && sel >= 0 && ok;
+            valid_s[wv][lane] = valid;
+            if (act) {  // the pass's draws are contiguous: d = qb * ns + lane
+                dirs_out[d] = valid ? w[0] : 0.0f;
+                dirs_out[nd + d] = valid ? w[1] : 0.0f;
+                dirs_out[2 * nd + d] = valid ? w[2] : 0.0f;
+                valid_out[d] = (uint8_t)valid;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         // C: the pdf of every draw over all components, outputs
@@ -474,28 +512,33 @@ __global__ __launch_bounds__(256) void cond_sample_pdf_lanes_kernel(const float*
             float pdf = 0.0f;
             for (int tt = 0; tt < ns; tt += 4) {  // wave-uniform
                 float c[4];
+                const float4* wq = &w_s[wv][qi * ns + tt];
+                if (tt + 4 <= ns) {  // four draws of this query
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float4 wd = w_s[wv][qi * ns + min(tt + j, ns - 1)];
-                    c[j] = pdf_component(T, lc, m0, m1, wd.x, wd.y, wd.z);
+                    for (int j = 0; j < 4; ++j) c[j] = pdf_component(T, lc, m0, m1, wq[j].x, wq[j].y, wq[j].z);
+                } else {  // the last ones, repeated up to four
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float4 wd = wq[min(j, ns - 1 - tt)];
+                        c[j] = pdf_component(T, lc, m0, m1, wd.x, wd.y, wd.z);
+                    }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float p = group_sum<G>(comp < K ? c[j] : 0.0f);
-                    pdf = comp == tt + j ? p : pdf;
+                for (int j = 0; j < 4; ++j) c[j] = comp < K ? c[j] : 0.0f;
+                if constexpr (G == 16) {
+                    // the four sums over the row at once: lane comp ends with the sum for
+                    // draw tt + (comp & 3) (group_sum4_row16), kept by the quad of that draw
+                    const float p = group_sum4_row16(c);
+                    pdf = (comp >> 2) == (tt >> 2) ? p : pdf;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float p = group_sum<G>(c[j]);
+                        pdf = comp == tt + j ? p : pdf;
+                    }
                 }
             }
-            if (inq && comp < ns) {
-                const int dl = qi * ns + comp;
-                const int valid = valid_s[wv][dl];
-                const float4 wd = w_s[wv][dl];
-                const int64_t d = q * ns + comp;
-                dirs_out[d] = valid ? wd.x : 0.0f;
-                dirs_out[nd + d] = valid ? wd.y : 0.0f;
-                dirs_out[2 * nd + d] = valid ? wd.z : 0.0f;
-                pdf_out[d] = valid ? pdf : 0.0f;
-                valid_out[d] = (uint8_t)valid;
-            }
+            if (inq && comp < ns) pdf_out[q * ns + comp] = valid_s[wv][qi * ns + comp] ? pdf : 0.0f;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // before the next pass overwrites
     }

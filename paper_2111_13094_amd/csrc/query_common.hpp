@@ -102,11 +102,14 @@ template <int G>
 __device__ __forceinline__ float group_inclusive_scan(float v)
 {
     const int comp = (threadIdx.x & 63) % G;
+    // row_shr with bound_ctrl reads 0 past the start of a 16-lane row, so a group that spans
+    // whole rows needs no select; a smaller group masks its row neighbours' lanes
 #define SDMM_SCAN_STEP(o)                                                                          \
     if constexpr (G > o) {                                                                         \
         const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + o, \
                                                                    0xF, 0xF, true));               \
-        v += comp >= o ? t : 0.0f;                                                                 \
+        if constexpr (G >= 16) v += t;                                                             \
+        else v += comp >= o ? t : 0.0f;                                                            \
     }
     SDMM_SCAN_STEP(1)
     SDMM_SCAN_STEP(2)
