@@ -3,10 +3,12 @@
 Headline (default): EM sample x component updates per second on the 4096-cell workload
 (16^3 cells of the unit cube, K = 16, cell counts lognormal(6.45, 1) clipped to
 [64, 8192], about 4.2M samples per batch, 8 resident batches, stepwise EM with decay 0.9:
-eta = 0.1 after the first batch), batched schedule (one E launch + one M launch per
-batch over all cells).
+eta = 0.1 after the first batch), batched schedule (setup, one E launch and one M launch
+per batch over all cells) in the launch configuration the autotuner picks on the first
+batch, replayed through the library's hipGraph cache.
 A step is one E+M pass over one resident batch; inputs are generated on the host and
-copied to HBM before the timed region.
+copied to HBM before the timed region. The same steps launched eagerly, with HIP events
+around every E-step and M-step launch, give the roofline's kernel time ("eager").
 
 The JSON line also carries:
   roofline      the E-step statistics kernel (the dominant kernel): algorithmic FP32
@@ -37,9 +39,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# launch configurations the headline run lets the autotuner choose from (schedule, items)
-TUNE_CANDIDATES = ([{"schedule": 0, "min_range": p, "waves_per_block": w} for p in (128, 256, 512) for w in (1, 2, 4)]
-                   + [{"schedule": 2, "min_range": 256, "waves_per_block": 4}])
+# launch configurations the headline run lets the autotuner choose from (batched schedule:
+# work-item size, waves per work group)
+TUNE_CANDIDATES = [{"schedule": 0, "min_range": p, "waves_per_block": w} for p in (256, 512, 1024) for w in (1, 2)]
 
 FLOPS_PER_PAIR = 140.0       # algorithmic FP32 flops per (sample, component) per E+M pass
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (published)
@@ -186,50 +188,64 @@ def bench_cells4k(args, torch):
     opts.max_cell_samples = max_cell
     tuned = None
     if args.tune:
-        # the autotuner's pick on the first batch (untimed), reported beside the timed run;
-        # the timed run uses the library defaults (256-sample items, one wave per work
-        # group, the pick of the tuner and of the sweeps on this workload) so that the
-        # profiler counters in the repository describe the same launches
+        # the autotuner's pick on the first batch (untimed); the timed runs use it
         from paper_2111_13094_amd import tune
         m_t, s_t = fresh()
-        t_opts = tune.tune_fit(offs[0], smps[0], m_t, s_t, opts, candidates=TUNE_CANDIDATES, reps=3)
+        opts = tune.tune_fit(offs[0], smps[0], m_t, s_t, opts, candidates=TUNE_CANDIDATES, reps=3)
         cfg = tune.tuned_config(C, K, N[0], opts)
-        tuned = {"schedule": "fused" if t_opts.schedule == sdmm.SCHED_FUSED else "batched",
-                 "items": int(t_opts.min_range), "waves_per_block": int(t_opts.waves_per_block or 1),
-                 "e_plus_m_ms": cfg["ms"] if cfg else None}
+        tuned = {"items": int(opts.min_range), "waves_per_block": int(opts.waves_per_block or 1),
+                 "e_plus_m_ms": cfg["ms"] if cfg else None, "candidates": len(TUNE_CANDIDATES)}
         del m_t, s_t
     status = torch.empty(C, dtype=torch.int32, device=dev)
     ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
     mix, st = fresh()
     L = sdmm.lib()
+    import ctypes as C_
+
+    def run(o, steps, events):
+        """steps E+M steps over the resident batches (after the warm-up's), timed by the
+        wall clock between two device synchronisations; with events, the library's own
+        HIP events around every E-step and M-step launch."""
+        tot, cnt, mtot, mcnt = C_.c_double(), C_.c_int64(), C_.c_double(), C_.c_int64()
+        if events:
+            L.sdmm_timing_enable(1)
+            L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+            L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
+        _sync(torch)
+        t0 = time.perf_counter()
+        npairs = 0
+        for s_ in range(steps):
+            j = (args.warmup + s_) % n_batches
+            sdmm.fit_mixtures(offs[j], smps[j], mix, st, o, status, ws)
+            npairs += N[j] * K
+        _sync(torch)
+        wall = time.perf_counter() - t0
+        e_ms = m_ms = None
+        if events:
+            L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
+            L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
+            L.sdmm_timing_enable(0)
+            e_ms = tot.value / max(cnt.value, 1)
+            m_ms = mtot.value / max(mcnt.value, 1) if mcnt.value else None
+        return npairs, wall, e_ms, m_ms
+
     for w in range(args.warmup):
         sdmm.fit_mixtures(offs[w % n_batches], smps[w % n_batches], mix, st, opts, status, ws)
-    _sync(torch)
-    L.sdmm_timing_enable(1)
-    import ctypes as C_
-    tot, cnt = C_.c_double(), C_.c_int64()
-    mtot, mcnt = C_.c_double(), C_.c_int64()
-    L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
-    L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
-    _sync(torch)
-    t0 = time.perf_counter()
-    pairs = 0
-    for s in range(args.steps):
-        j = (args.warmup + s) % n_batches
-        sdmm.fit_mixtures(offs[j], smps[j], mix, st, opts, status, ws)
-        pairs += N[j] * K
-    _sync(torch)
-    t1 = time.perf_counter()
-    L.sdmm_timing_read(0, C_.byref(tot), C_.byref(cnt), 1)
-    L.sdmm_timing_read(1, C_.byref(mtot), C_.byref(mcnt), 1)
-    L.sdmm_timing_enable(0)
-    est_ms = tot.value / max(cnt.value, 1)
-    m_ms = mtot.value / max(mcnt.value, 1) if mcnt.value else None
-    wall = t1 - t0
+    # eager launches with event timing: the E-step kernel's duration for the roofline
+    epairs, ewall, est_ms, m_ms = run(opts, args.steps, True)
+    # the headline: the same launches replayed through the library's hipGraph cache (one
+    # graph per batch, all captured before the timed region; a replay records no events)
+    gopts = sdmm.FitOpts.from_buffer_copy(opts)
+    gopts.use_graph = 1 if args.graph else 0
+    if args.graph:
+        for j in range(n_batches):
+            sdmm.fit_mixtures(offs[j], smps[j], mix, st, gopts, status, ws)
+    pairs, wall, _, _ = run(gopts, args.steps, False)
     value = pairs / wall
-    flops_per_launch = FLOPS_PER_PAIR * (pairs / args.steps)
+    flops_per_launch = FLOPS_PER_PAIR * (epairs / args.steps)
     achieved = flops_per_launch / (est_ms * 1e-3) / 1e12
-    traffic = _traffic_record(int(opts.min_range or 256), int(opts.waves_per_block or 1))
+    items, wpb = int(opts.min_range or 256), int(opts.waves_per_block or 1)
+    traffic = _traffic_record(items, wpb)
     out = {
         "metric": "EM sample x component updates/s, 4096 cells K=16 (batched)",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -240,33 +256,17 @@ def bench_cells4k(args, torch):
                                "eta=0.1, FP32 E-step with compensated sums, FP64 M-step",
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
                    "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
-                   "min_range": int(opts.min_range or 256), "max_ranges": int(opts.max_ranges or 65536),
-                   "waves_per_block": int(opts.waves_per_block or 1),
-                   "running_sums": args.sums, "max_cell_samples": max_cell, "autotuned": tuned},
+                   "min_range": items, "max_ranges": int(opts.max_ranges or 65536), "waves_per_block": wpb,
+                   "hipgraph": bool(args.graph), "running_sums": args.sums, "max_cell_samples": max_cell,
+                   "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": ("fused_kernel<16,TwoSum,false>" if opts.schedule == sdmm.SCHED_FUSED
                                 else "estep_kernel<16,TwoSum,false,false>"),
                      "kernel_ms": est_ms, "flops_per_launch": flops_per_launch},
         "mstep_ms": m_ms,
+        "eager": {"value": epairs / ewall, "unit": "updates/s", "ms_per_step": ewall * 1e3 / args.steps},
     }
-    if args.graph:
-        # the same steps replayed through the library's hipGraph cache (one graph per
-        # batch, all captured before the timed region; no per-kernel events in a replay)
-        gopts = sdmm.FitOpts.from_buffer_copy(opts)
-        gopts.use_graph = 1
-        for j in range(n_batches):
-            sdmm.fit_mixtures(offs[j], smps[j], mix, st, gopts, status, ws)
-        _sync(torch)
-        t0 = time.perf_counter()
-        gpairs = 0
-        for s_ in range(args.steps):
-            j = (args.warmup + s_) % n_batches
-            sdmm.fit_mixtures(offs[j], smps[j], mix, st, gopts, status, ws)
-            gpairs += N[j] * K
-        _sync(torch)
-        gw = time.perf_counter() - t0
-        out["hipgraph"] = {"value": gpairs / gw, "unit": "updates/s", "ms_per_step": gw * 1e3 / args.steps}
     if not args.no_plain:
         popts = sdmm.default_opts(K, eta=0.1, schedule=sdmm.SCHED_PER_CELL)
         ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, popts) for n in N), dtype=torch.uint8, device=dev)

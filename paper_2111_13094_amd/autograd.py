@@ -75,6 +75,20 @@ def mixture_from_params(params: dict) -> dict:
     return mix
 
 
+def stationarity(mix: dict, cell_offsets, samples, opts, workspace=None) -> dict:
+    """Gradient of F at fitted mixtures for checking EM stationarity (its blocks vanish at a
+    fixed point of batch MAP-EM), from the FP64 pass (SDMM_FLAG_FP64_SUMS). The default FP32
+    pass agrees with the closed-form gradient only on components whose correlation matrix
+    has condition number <= 1e5, and resolves a fixed point only where it is <= 1e3: its
+    FP32 tangent coordinates carry relative rounding 2^-24, which Sigma^-1 amplifies by
+    about the condition number. Converged components with strong direction-position
+    correlation exceed that, so the check always takes the FP64 pass. Returns the dict of
+    sdmm.fit_grad."""
+    o = type(opts).from_buffer_copy(opts)
+    o.flags |= sdmm.FLAG_FP64_SUMS
+    return sdmm.fit_grad(cell_offsets, samples, mix, o, workspace=workspace)
+
+
 def refine(mix: dict, n_cells: int, K: int, cell_offsets, samples, opts, steps=10, lr=1e-3):
     """Gradient refinement of fitted mixtures: `steps` Adam ascent steps on
     (alpha, delta, mu_pos, L) of the summed F. Returns (refined mixture, F per cell

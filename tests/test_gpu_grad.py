@@ -189,11 +189,13 @@ def test_gradient_vanishes_at_a_batch_em_fixed_point_fp64(dev, orc):
     FP64 rounding amplified by kappa^2 in both implementations."""
     print("case: stationarity after 400 EM iterations (8 cells), FP64 pass", flush=True)
     from paper_2111_13094_amd import sdmm
+    from paper_2111_13094_amd import autograd
     C, b, mix, early, status, beta = _fixed_point(orc)
-    o = sdmm.default_opts(16, prior_mode=sdmm.PRIOR_FIXED, prior_scale=beta, flags=sdmm.FLAG_FP64_SUMS)
+    o = sdmm.default_opts(16, prior_mode=sdmm.PRIOR_FIXED, prior_scale=beta)
     off, smp = dev.from_numpy(b.offsets).cuda(), dev.from_numpy(b.samples).cuda()
-    g_fix = {k: v.cpu().numpy() for k, v in sdmm.fit_grad(off, smp, to_torch(mix), o).items()}
-    g_early = {k: v.cpu().numpy() for k, v in sdmm.fit_grad(off, smp, to_torch(early), o).items()}
+    # the stationarity check of the autograd module takes the FP64 pass
+    g_fix = {k: v.cpu().numpy() for k, v in autograd.stationarity(to_torch(mix), off, smp, o).items()}
+    g_early = {k: v.cpu().numpy() for k, v in autograd.stationarity(to_torch(early), off, smp, o).items()}
     live = [c for c in range(C) if not status[c] & orc.DEAD_COMPONENT]
     assert len(live) >= C // 2
     oo = orc.Opts(K=16, prior_mode=1, prior_scale=beta)
@@ -218,3 +220,113 @@ def test_gradient_vanishes_at_a_batch_em_fixed_point_fp64(dev, orc):
     for key in worst_orc:
         assert worst_orc[key] < 1e-4, (key, worst_orc)
         assert worst_diff[key] < 1e-7, (key, worst_diff)
+
+
+def _fd_params(rng, K, n_per_comp=1):
+    """(block, component, index) triples to difference: for four random components of a
+    cell, one weight logit, one positional coordinate, one tangent direction and two
+    entries of L."""
+    out = []
+    for k in rng.choice(K, 4, replace=False):
+        out += [("alpha", k, 0), ("mu_pos", k, int(rng.integers(3))), ("delta", k, int(rng.integers(2)))]
+        out += [("L", k, int(t)) for t in rng.choice(15, 2, replace=False)]
+    return out
+
+
+def _objective_at(orc, oo, smp, i0, i1, mix, beta, c, K, block, k, idx, h):
+    """F of cell c with one parameter moved by h, in the parameterisation of the
+    adjoint (logits, positions, tangent perturbation of mu_dir, Cholesky factor)."""
+    m = {key: np.ascontiguousarray(v.reshape(-1, K * (v.size // (mix["pi"].size)))[c]).ravel().copy()
+         for key, v in mix.items()}
+    if block == "alpha":
+        a = np.log(m["pi"])
+        a[k] += h
+        e = np.exp(a - a.max())
+        m["pi"] = e / e.sum()
+    elif block == "mu_pos":
+        m["mu_pos"][3 * k + idx] += h
+    elif block == "delta":
+        dl = np.zeros(2)
+        dl[idx] = h
+        w = orc.exp_map(m["mu_dir"][3 * k:3 * k + 3].copy(), dl)
+        m["mu_dir"][3 * k:3 * k + 3] = w / np.linalg.norm(w)
+    else:
+        L = np.linalg.cholesky(_lower(m["cov"][15 * k:15 * k + 15]) + np.tril(_lower(m["cov"][15 * k:15 * k + 15]), -1).T)
+        Lp = np.array([L[d, e] for (d, e) in TRI])
+        Lp[idx] += h
+        U = _lower(Lp)
+        S = U @ U.T
+        m["cov"][15 * k:15 * k + 15] = [S[d, e] for (d, e) in TRI]
+    return orc.objective(oo, smp, i0, i1, m, beta)
+
+
+def test_adjoint_at_the_4096_cell_state_after_8_batches(dev, orc):
+    """The adjoint's own workload: the 4096-cell state after 8 batches (eta = 0.1), the
+    gradient of F on the 9th batch for every cell, fixed prior strength 1e-3 (the
+    benchmark's configuration). On cells 0-63 against the oracle's closed form
+    (Sec. 4.3 objective): the FP64 pass on every component within 1e-7 of each block's
+    largest entry, the FP32 pass within 2e-4 (whitened) where the component's correlation
+    matrix has condition number <= 1e5; and both the oracle's and the FP64 pass's
+    gradients against FP64 central differences of the oracle's F (20 parameters per
+    cell, relative step 1e-6) within 1e-6 of the block's largest entry."""
+    print("case: adjoint at the 4096-cell state after 8 batches, 64 cells vs oracle and FD", flush=True)
+    from paper_2111_13094_amd import sdmm
+    wl = synth.workload("cells4k")
+    C, K = wl["grid"].n_cells, 16
+    mix = to_torch(synth.initial_mixtures(wl["box_lo"], wl["box_size"], K))
+    st = sdmm.new_state(C, K)
+    for j in range(8):
+        b = synth.workload_batch(wl, j)
+        sdmm.fit_mixtures(dev.from_numpy(b.offsets).cuda(), dev.from_numpy(b.samples).cuda(), mix, st,
+                          sdmm.default_opts(K, eta=0.1))
+    b = synth.workload_batch(wl, 8)
+    off, smp = dev.from_numpy(b.offsets).cuda(), dev.from_numpy(b.samples).cuda()
+    beta = 1e-3
+    g32 = {k: v.cpu().numpy() for k, v in sdmm.fit_grad(
+        off, smp, mix, sdmm.default_opts(K, prior_mode=sdmm.PRIOR_FIXED, prior_scale=beta)).items()}
+    g64 = {k: v.cpu().numpy() for k, v in sdmm.fit_grad(
+        off, smp, mix, sdmm.default_opts(K, prior_mode=sdmm.PRIOR_FIXED, prior_scale=beta,
+                                         flags=sdmm.FLAG_FP64_SUMS)).items()}
+    dev.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in mix.items()}
+    oo = orc.Opts(K=K, prior_mode=1, prior_scale=beta)
+    cov = host["cov"].reshape(C, K, 15)
+    rng = np.random.default_rng(5)
+    worst = {"F32": 0.0, "F64": 0.0, "alpha32": 0.0, "mean32": 0.0, "L32": 0.0, "g64": 0.0, "fd_orc": 0.0,
+             "fd_gpu": 0.0}
+    n_ok = n_all = 0
+    h = 1e-6
+    for c in range(64):
+        assert g32["status"][c] == 0 and g64["status"][c] == 0, c
+        i0, i1 = b.offsets[c], b.offsets[c + 1]
+        F = orc.objective(oo, b.samples, i0, i1, host, beta, cell=c)
+        g = orc.grad(oo, b.samples, i0, i1, host, beta, cell=c)
+        worst["F32"] = max(worst["F32"], abs(g32["F"][c] - F) / abs(F))
+        worst["F64"] = max(worst["F64"], abs(g64["F"][c] - F) / abs(F))
+        for key in ("alpha", "mu_pos", "delta", "L"):
+            ref = g[key].reshape(g64[key][c].shape)
+            worst["g64"] = max(worst["g64"], np.abs(g64[key][c] - ref).max() / np.abs(ref).max())
+        worst["alpha32"] = max(worst["alpha32"], np.abs(g32["alpha"][c] - g["alpha"]).max() / np.abs(g["alpha"]).max())
+        ok = np.array([_kappa(cov[c, k]) <= 1e5 for k in range(K)])
+        n_ok += ok.sum()
+        n_all += K
+        gg = {key: g32[key][c] for key in ("alpha", "mu_pos", "delta", "L")}
+        wm_g, wl_g = _whitened(gg, cov[c], K)
+        wm_o, wl_o = _whitened(g, cov[c], K)
+        if ok.any():
+            worst["mean32"] = max(worst["mean32"], np.abs(wm_g - wm_o)[ok].max() / np.abs(wm_o[ok]).max())
+            worst["L32"] = max(worst["L32"], np.abs(wl_g - wl_o)[ok].max() / np.abs(wl_o[ok]).max())
+        # central differences of the oracle's F
+        for block, k, idx in _fd_params(rng, K):
+            fp = _objective_at(orc, oo, b.samples, i0, i1, host, beta, c, K, block, k, idx, h)
+            fm = _objective_at(orc, oo, b.samples, i0, i1, host, beta, c, K, block, k, idx, -h)
+            fd = (fp - fm) / (2 * h)
+            ref = g[block].reshape(g64[block][c].shape)
+            scale = np.abs(ref).max()
+            worst["fd_orc"] = max(worst["fd_orc"], abs(fd - ref[k].ravel()[idx]) / scale)
+            worst["fd_gpu"] = max(worst["fd_gpu"], abs(fd - g64[block][c][k].ravel()[idx]) / scale)
+    print({k: "%.2e" % v for k, v in worst.items()}, f"{n_ok} of {n_all} components with kappa <= 1e5")
+    assert worst["F32"] <= 1e-6 and worst["F64"] <= 1e-10, worst
+    assert worst["g64"] < 1e-7 and worst["alpha32"] < 1e-4, worst
+    assert worst["mean32"] < 2e-4 and worst["L32"] < 2e-4, worst
+    assert worst["fd_orc"] < 1e-6 and worst["fd_gpu"] < 1e-6, worst
