@@ -149,11 +149,11 @@ __device__ __forceinline__ Pair make_pair(const float* R, float lwk, float m0, f
     p.nrm = 0.0f;
     // centre in the frame of mu_k and the log-map Jacobian there:
     // nu = f (x, y), d f / d x = x g, d f / d y = y g, d f / d z = -1, g = (z - f) / s^2
-    const float px = fmaf(R[0], b.cx, fmaf(R[1], b.cy, R[2] * b.cz));
+    const float px = fmaf(R[0], b.cx, fmaf(R[1], b.cy, fmaf(R[2], b.cz, 1e-18f)));
     const float py = fmaf(R[3], b.cx, fmaf(R[4], b.cy, R[5] * b.cz));
     const float pz = fmaf(R[6], b.cx, fmaf(R[7], b.cy, R[8] * b.cz));
     float a0, a1;
-    const float f = log_map_f32(px, py, pz, a0, a1);
+    const float f = log_map_f32_offset(px, py, pz, a0, a1);
     const float s2 = fmaf(px, px, py * py);
     const float g = s2 > 1e-6f ? (pz - f) * __builtin_amdgcn_rcpf(s2) : -2.0f / 3.0f;
     const float J00 = fmaf(px * px, g, f), J01 = px * py * g, J02 = -px;
@@ -238,10 +238,8 @@ __device__ __forceinline__ void product_setup(const float* __restrict__ table, i
     float m0, m1;
     float lw = cond_component(T, x0, x1, x2, m0, m1);
     if (comp >= K || !usable) lw = -INFINITY;
-    float lmax = group_max<G>(lw);
-    float e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
-    float den = group_sum<G>(e);
-    const float lwk = (e > 0.0f && den > 0.0f) ? (lw - lmax) - __builtin_amdgcn_logf(den) : -INFINITY;
+    float wk_unused;
+    const float lwk = cond_log_weight<G>(lw, wk_unused);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Qy.R[i] = T[i];
     const float l0 = T[24], l1 = T[25], l2 = T[26];
@@ -252,11 +250,8 @@ __device__ __forceinline__ void product_setup(const float* __restrict__ table, i
     float bm0, bm1;
     float lb = cond_component(TB, y0, y1, y2, bm0, bm1);
     if (comp >= Kb || !usable) lb = -INFINITY;
-    lmax = group_max<G>(lb);
-    e = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lb - lmax);
-    den = group_sum<G>(e);
-    const float wb = den > 0.0f ? e * __builtin_amdgcn_rcpf(den) : 0.0f;
-    const float lwb = (e > 0.0f && den > 0.0f) ? (lb - lmax) - __builtin_amdgcn_logf(den) : -INFINITY;
+    float wb;
+    const float lwb = cond_log_weight<G>(lb, wb);
     const float w1 = group_max<G>(wb);
     const uint64_t h0 = __ballot(comp < Kb && wb > 0.0f && wb == w1) & gmask;
     const int s0 = h0 ? __builtin_ctzll(h0) - base : -1;
@@ -273,30 +268,49 @@ __device__ __forceinline__ void product_setup(const float* __restrict__ table, i
     Qy.p0 = make_pair(Qy.R, lwk, m0, m1, a00, a01, a11, b0);
     Qy.p1 = make_pair(Qy.R, lwk, m0, m1, a00, a01, a11, b1);
     if (comp >= K) Qy.p0.l = Qy.p1.l = -INFINITY;
-    const float lm = group_max<G>(fmaxf(Qy.p0.l, Qy.p1.l));
-    Qy.any = lm != -INFINITY;
-    const float e0 = Qy.any ? __builtin_amdgcn_exp2f(Qy.p0.l - lm) : 0.0f;
-    const float e1 = Qy.any ? __builtin_amdgcn_exp2f(Qy.p1.l - lm) : 0.0f;
-    const float tot = group_sum<G>(e0 + e1);
+    // pair probabilities: exp2 of the log2 weights normalised over the 2K pairs; a group
+    // whose sum leaves [2^-100, 2^100] takes the group maximum first
+    float e0 = __builtin_amdgcn_exp2f(Qy.p0.l), e1 = __builtin_amdgcn_exp2f(Qy.p1.l);
+    float tot = group_sum<G>(e0 + e1);
+    const bool out = !(tot >= 0x1p-100f && tot <= 0x1p100f);
+    Qy.any = true;
+    if (__ballot(out)) {
+        const float lm = group_max<G>(fmaxf(Qy.p0.l, Qy.p1.l));
+        const bool any = lm != -INFINITY;
+        const float f0 = any ? __builtin_amdgcn_exp2f(Qy.p0.l - lm) : 0.0f;
+        const float f1 = any ? __builtin_amdgcn_exp2f(Qy.p1.l - lm) : 0.0f;
+        const float t2 = group_sum<G>(f0 + f1);
+        e0 = out ? f0 : e0;
+        e1 = out ? f1 : e1;
+        tot = out ? t2 : tot;
+        Qy.any = out ? any : true;
+    }
     const float itot = tot > 0.0f ? __builtin_amdgcn_rcpf(tot) : 0.0f;
     Qy.P0 = e0 * itot;
     Qy.P1 = e1 * itot;
 }
 
-// density of the normalised product mixture at a world direction (step 4, all lanes)
-template <int G>
-__device__ __forceinline__ float product_density(const ProductQuery& Qy, int K, float wx, float wy, float wz)
+// the lane's share of the density of the normalised product mixture at a world direction
+// (step 4): its component's two pairs, 0 past K and at the cut locus
+__device__ __forceinline__ float product_density_lane(const ProductQuery& Qy, int K, int comp, float wx, float wy,
+                                                      float wz)
 {
-    const int comp = (threadIdx.x & 63) % G;
-    const float xr = fmaf(Qy.R[0], wx, fmaf(Qy.R[1], wy, Qy.R[2] * wz));
+    // the 1e-18 offset of the log map rides on the rotation's first row
+    const float xr = fmaf(Qy.R[0], wx, fmaf(Qy.R[1], wy, fmaf(Qy.R[2], wz, 1e-18f)));
     const float yr = fmaf(Qy.R[3], wx, fmaf(Qy.R[4], wy, Qy.R[5] * wz));
     const float zr = fmaf(Qy.R[6], wx, fmaf(Qy.R[7], wy, Qy.R[8] * wz));
     float n0, n1;
-    const float f = log_map_f32(xr, yr, zr, n0, n1);
+    const float f = log_map_f32_offset(xr, yr, zr, n0, n1);
     const float r2 = fmaf(n0, n0, n1 * n1);
-    float v = pair_density(Qy.p0, Qy.P0, n0, n1) + pair_density(Qy.p1, Qy.P1, n0, n1);
-    v = (comp < K && r2 < kCutSq) ? v * f : 0.0f;
-    return group_sum<G>(v);
+    const float v = pair_density(Qy.p0, Qy.P0, n0, n1) + pair_density(Qy.p1, Qy.P1, n0, n1);
+    return (comp < K && r2 < kCutSq) ? v * f : 0.0f;
+}
+
+// density of the normalised product mixture at a world direction (all lanes of the group)
+template <int G>
+__device__ __forceinline__ float product_density(const ProductQuery& Qy, int K, float wx, float wy, float wz)
+{
+    return group_sum<G>(product_density_lane(Qy, K, (threadIdx.x & 63) % G, wx, wy, wz));
 }
 
 __device__ __forceinline__ void load_frame(const float* __restrict__ frames, int64_t nq, int64_t q, float F[9])
@@ -379,10 +393,20 @@ __global__ __launch_bounds__(256) void product_sample_kernel(
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const int from = base + min(tt + k4, tn - 1);
-                    v[k4] = product_density<G>(Qy, K, __shfl(w[0], from), __shfl(w[1], from), __shfl(w[2], from));
+                    v[k4] = product_density_lane(Qy, K, comp, __shfl(w[0], from), __shfl(w[1], from),
+                                                 __shfl(w[2], from));
                 }
+                if constexpr (G == 16) {
+                    // lane comp ends with the sum for draw tt + (comp & 3)
+                    const float p = group_sum4_row16(v);
+                    pdf = (comp >> 2) == (tt >> 2) ? p : pdf;
+                } else {
 #pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) pdf = comp == tt + k4 ? v[k4] : pdf;
+                    for (int k4 = 0; k4 < 4; ++k4) {
+                        const float p = group_sum<G>(v[k4]);
+                        pdf = comp == tt + k4 ? p : pdf;
+                    }
+                }
             }
             if (inq && comp < tn) {
                 const int64_t d = qq * ns + t0 + comp;

@@ -107,51 +107,10 @@ __device__ __forceinline__ float pdf_component(const float* T, float lc, float m
     return r2 < kCutSq ? p : 0.0f;
 }
 
-// Sums of four values over a row of 16 lanes at once: lane i ends with the sum over the
-// row of value (i & 3). Two exchange steps inside each quad leave lane i with the quad's
-// sum of value (i & 3); two rotations by 4 and 8 lanes then add the four quads. The sums
-// associate differently from group_sum (a different FP32 rounding, same value).
-__device__ __forceinline__ float group_sum4_row16(const float (&c)[4])
-{
-    const int lane = threadIdx.x & 63;
-    const bool b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
-    // partner lane ^ 2: keep values {0,1} (bit 1 clear) or {2,3}, send the other pair
-    const float k0 = b1 ? c[2] : c[0], k1 = b1 ? c[3] : c[1];
-    const float s0 = b1 ? c[0] : c[2], s1 = b1 ? c[1] : c[3];
-    const float a0 = k0 + dpp_f32<kDppXor2>(s0), a1 = k1 + dpp_f32<kDppXor2>(s1);
-    // partner lane ^ 1: keep value (lane & 3), send the other
-    const float k = b0 ? a1 : a0, sn = b0 ? a0 : a1;
-    float v = k + dpp_f32<kDppXor1>(sn);
-    v += dpp_f32<0x124>(v);  // row_ror:4
-    v += dpp_f32<0x128>(v);  // row_ror:8
-    return v;
-}
-
 // log2 of the conditioned weight plus the conditional density's log2 normaliser T[31]
 __device__ __forceinline__ float pdf_log_const(const float* T, float wk)
 {
     return T[31] + __builtin_amdgcn_logf(wk);
-}
-
-// the conditioned weight pi'_k of the lane's component from the log2 weights lw of the
-// group (-inf for none): exp2(lw) normalised over the group. Only a group whose sum leaves
-// [2^-100, 2^100] (positions far from every component, extreme covariances, or no usable
-// component) takes the maximum first (the textbook log-sum-exp); the others keep their
-// values.
-template <int G>
-__device__ __forceinline__ float cond_weight(float lw)
-{
-    float e = __builtin_amdgcn_exp2f(lw);
-    float den = group_sum<G>(e);
-    const bool out = !(den >= 0x1p-100f && den <= 0x1p100f);
-    if (__ballot(out)) {
-        const float lmax = group_max<G>(lw);
-        const float e2 = lmax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(lw - lmax);
-        const float den2 = group_sum<G>(e2);
-        e = out ? e2 : e;
-        den = out ? den2 : den;
-    }
-    return den > 0.0f ? e * __builtin_amdgcn_rcpf(den) : 0.0f;
 }
 
 // One draw for the group's query: pick the component by the CDF of pi' (prefix sum in
