@@ -139,9 +139,10 @@ EstepFn estep_function(int G, int acc, bool jac, bool adj);
 // FP64 adjoint pass for G component lanes
 EstepFn adj64_function(int G);
 
-// setup kernel: FP32 mirrors, status reset, per-cell flags and the offsets check
+// setup kernel: FP32 mirrors (full: with the adjoint's twist rates and residues),
+// status reset, per-cell flags and the offsets check
 void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws,
-                  const Layout& L, hipStream_t s);
+                  const Layout& L, hipStream_t s, bool full);
 
 // record tree levels after an E-step pass (all cells, or one cell when cell >= 0, whose
 // samples are [c0, c1)); the pass names the record layout

@@ -78,6 +78,43 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
+// FP64 sum over the whole wave: DPP butterflies inside each row of 16 lanes, then the
+// gfx950 row swaps (permlane16 / permlane32), which hand each lane the value of lane
+// l ^ 16 (l ^ 32) next to its own in a fixed order, so every lane ends with bitwise the
+// same sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <bool ROW32>
+__device__ __forceinline__ double sum_row_pair_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    auto a = ROW32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                   : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto c = ROW32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                   : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double d0 = __longlong_as_double(((long long)c[0] << 32) | a[0]);
+    const double d1 = __longlong_as_double(((long long)c[1] << 32) | a[1]);
+    return d0 + d1;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    v = sum_row_pair_f64<false>(v);
+    return sum_row_pair_f64<true>(v);
+}
+
 // ---------------------------------------------------------------------------------
 // FP32 tangent log map. With w' = R w, theta = angle(w', e_z), s = |w'_xy| = sin theta:
 // nu = (theta / s) w'_xy. theta / s as a function of z = cos theta is smooth on [0, 1];

@@ -15,11 +15,12 @@
 namespace sdmm {
 
 enum { kAccTwoSum = 0, kAccPlain = 1, kAccFp64 = 2 };
-constexpr int kFoldEvery = 32;  // steps between folds of the FP32 block sums
+constexpr int kFoldEvery = 64;  // steps between folds of the FP32 block sums
 
-// running sums: FP32 block sums over kFoldEvery steps, folded by TwoSum into an FP32
-// running total whose rounding error opens the next block (compensated), kept as one
-// plain FP32 sum, or folded into FP64 (precision variants)
+// running sums: FP32 block sums over kFoldEvery steps (a lane's samples of a work item of
+// up to 256 samples fit one block), folded by TwoSum into an FP32 running total whose
+// rounding error opens the next block (compensated), kept as one plain FP32 sum, or
+// folded into FP64 (precision variants)
 template <int ACC>
 struct RunSum;
 
@@ -128,6 +129,7 @@ __device__ __forceinline__ void sum_cell_records(const double* __restrict__ reco
 // 44-58 scaled Linv residue, 59 residue of the shifted log2 constant, 60-61 twist rate
 // residues, 62-63 unused.
 constexpr int kMirShift = 30;
+constexpr int kMirrorLite = 32;  // floats of a mirror that the EM passes read
 
 // Twist of the frame about mu when mu moves along its own tangent directions:
 // phi_j = (d t1 / d mu . t_j) . t2 for the basis of frame64 (Duff et al. 2017), so that
@@ -152,13 +154,16 @@ __device__ __forceinline__ void frame_twist64(const double mu[3], const double R
 // ---------------------------------------------------------------------------------
 // FP32 E-step mirror of one component: R (9), mu_x (3), Linv * sqrt(log2(e)/2) (15),
 // c * log2(e) with c = log pi - log det L - (5/2) log 2 pi (1, returned in c2 and shifted
-// per cell by set_mirror_shift), the frame twist rates (2) used by the adjoint, and the
-// FP32 rounding residues of R, mu_x, the scaled Linv and the shifted constant. With them
-// the adjoint pass forms tangent coordinates to FP32 relative accuracy and the quadratic
-// form in FP64 (its gradients are small differences near stationarity, and for strongly
-// correlated components the quadratic form cancels). Returns false and writes an inert
-// mirror (identity frame and factor) when the component is unusable.
+// per cell by set_mirror_shift), and with FULL the frame twist rates (2) used by the
+// adjoint and the FP32 rounding residues of R, mu_x, the scaled Linv and the shifted
+// constant. With them the adjoint pass forms tangent coordinates to FP32 relative accuracy
+// and the quadratic form in FP64 (its gradients are small differences near stationarity,
+// and for strongly correlated components the quadratic form cancels). The EM passes read
+// only the first kMirrorLite floats, which is all a lite mirror (FULL false) writes.
+// Returns false and writes an inert mirror (identity frame and factor) when the component
+// is unusable.
 // ---------------------------------------------------------------------------------
+template <bool FULL>
 __device__ inline bool write_mirror(double pi, const double* mud, const double* mux, const double* cov,
                                     float* out, double& c2)
 {
@@ -167,7 +172,7 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     double L[15], Li[15], Ld[5];
     ok = ok && chol64<5>(cov, L, Ld);
     if (!ok) {
-        for (int i = 0; i < kMirror; ++i) out[i] = 0.0f;
+        for (int i = 0; i < (FULL ? kMirror : kMirrorLite); ++i) out[i] = 0.0f;
         out[0] = out[4] = out[8] = 1.0f;
         const int diag[5] = {0, 2, 5, 9, 14};
         for (int d = 0; d < 5; ++d) out[12 + diag[d]] = 1.0f;
@@ -184,6 +189,10 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     for (int i = 0; i < 15; ++i) out[12 + i] = (float)(Li[i] * scale);
     c2 = (log(pi) - logdet - 2.5 * kLn2Pi) * kLog2e;
     out[27] = (float)c2;
+    if constexpr (!FULL) {
+        out[28] = out[29] = out[30] = out[31] = 0.0f;
+        return true;
+    }
     double phi[2];
     frame_twist64(mud, R, phi);
     out[28] = (float)phi[0];
@@ -205,25 +214,28 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
 // usable component of weight zero keeps the constant -inf, so its responsibility is
 // exactly zero, as the E-step of Sec. 3.2 gives (r proportional to pi_k p_k). `shift` is
 // the same for all lanes of the cell.
+template <bool FULL>
 __device__ inline void set_mirror_shift(float* out, double c2, double shift, bool usable)
 {
     if (!usable || !isfinite(c2)) {
         out[27] = usable ? -INFINITY : -1.0f;
-        out[59] = 0.0f;
+        if constexpr (FULL) out[59] = 0.0f;
     } else {
         const double v = c2 - shift;
         out[27] = (float)v;
-        out[59] = (float)(v - (double)out[27]);
+        if constexpr (FULL) out[59] = (float)(v - (double)out[27]);
     }
     out[kMirShift] = (float)shift;
 }
 
-// stores a mirror built in registers with 16-byte stores
+// stores a mirror built in registers with 16-byte stores (the lite part only unless FULL)
+template <bool FULL>
 __device__ __forceinline__ void store_mirror(float* __restrict__ dst, const float (&m)[kMirror])
 {
     float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
-    for (int q = 0; q < kMirror / 4; ++q) d4[q] = make_float4(m[4 * q], m[4 * q + 1], m[4 * q + 2], m[4 * q + 3]);
+    for (int q = 0; q < (FULL ? kMirror : kMirrorLite) / 4; ++q)
+        d4[q] = make_float4(m[4 * q], m[4 * q + 1], m[4 * q + 2], m[4 * q + 3]);
 }
 
 struct SampleRegs {
@@ -264,30 +276,25 @@ __device__ __forceinline__ SampleRegs load_sample(const float* const* ch, uint32
     return r;
 }
 
-// W = sum w (FP64 per lane), M = #{w > 0}, negatives = #{w < 0} over [s0, s1), one
-// sample per lane of one wave; every lane returns the totals.
+// W = sum w (FP64 per lane, then a wave reduction), M = #{w > 0}, negatives = #{w < 0}
+// over [s0, s1), one sample per lane of one wave; the counts come from ballots (scalar
+// unit). Every lane returns the totals.
 __device__ __forceinline__ void weight_pass(const float* __restrict__ wch, int64_t s0, int64_t s1, double& W,
                                             double& M, double& neg)
 {
     const int lane = threadIdx.x & 63;
     double sw = 0.0;
-    int cnt = 0, ng = 0;
-    for (int64_t i = s0 + lane; i < s1; i += 64) {
-        const float w = wch[i];
+    uint32_t cnt = 0, ng = 0;
+    for (int64_t b = s0; b < s1; b += 64) {  // wave-uniform trip count
+        const int64_t i = b + lane;
+        const float w = i < s1 ? wch[i] : 0.0f;
         sw += (double)w;
-        cnt += w > 0.0f;
-        ng += w < 0.0f;
+        cnt += (uint32_t)__popcll(__ballot(w > 0.0f));
+        ng += (uint32_t)__popcll(__ballot(w < 0.0f));
     }
-    double c = (double)cnt, g = (double)ng;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        sw += __shfl_xor(sw, o);
-        c += __shfl_xor(c, o);
-        g += __shfl_xor(g, o);
-    }
-    W = sw;
-    M = c;
-    neg = g;
+    W = wave_sum_f64(sw);
+    M = (double)cnt;
+    neg = (double)ng;
 }
 
 // derivative of theta/sin(theta) with respect to z = cos(theta) on the sphere

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
                                                     int GM, int ps, MixPtrs mix, float* __restrict__ mirror,
                                                     int32_t* __restrict__ flags, int32_t* __restrict__ status,
                                                     int32_t* __restrict__ arrive, int32_t* __restrict__ control,
-                                                    int n_cell_blocks, int tree_max)
+                                                    int n_cell_blocks, int tree_max, int full)
 {
     // control[0]: offsets valid; control[1]: most items in a cell; control[2]: record-tree
     // levels launched
@@ -105,14 +105,22 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
     double c2 = -INFINITY;
     bool ok = true;
     float m[kMirror];
-    if (active) ok = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, m, c2);
+    if (active) {
+        ok = full ? write_mirror<true>(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, m, c2)
+                  : write_mirror<false>(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, m, c2);
+    }
     const double cmax = group_max_d(active && ok ? c2 : -INFINITY, GM);
     const int bad = group_or(active && !ok ? 1 : 0, GM);
     // the shift is an FP32 value, so adding it back in FP64 is exact
     const float shift = isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f;
     if (active) {
-        set_mirror_shift(m, c2, (double)shift, ok);
-        store_mirror(mirror + g * kMirror, m);
+        if (full) {
+            set_mirror_shift<true>(m, c2, (double)shift, ok);
+            store_mirror<true>(mirror + g * kMirror, m);
+        } else {
+            set_mirror_shift<false>(m, c2, (double)shift, ok);
+            store_mirror<false>(mirror + g * kMirror, m);
+        }
     }
     if (c < C && k == 0) {
         status[c] = 0;
@@ -175,9 +183,10 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------------
-// Mirror of component g for the next iteration, written in place (keeps the M-step's
-// registers free), with the cell's shift from the group of GM lanes. `upd`: this lane's
-// component was updated; the others keep their mirrors.
+// Lite mirror of component g for the next iteration (the EM passes read no more),
+// written in place (keeps the M-step's registers free), with the cell's shift from the
+// group of GM lanes. `upd`: this lane's component was updated; the others keep their
+// mirrors.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t g, bool upd, float* __restrict__ mirror,
                                                     int GM)
@@ -185,23 +194,61 @@ __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t 
     double c2 = -INFINITY;
     bool okm = true;
     float* out = mirror + g * kMirror;
-    if (upd) okm = write_mirror(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    if (upd) okm = write_mirror<false>(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
     const double cmax = group_max_d((upd && okm) ? c2 : -INFINITY, GM);
-    if (upd) set_mirror_shift(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f), okm);
+    if (upd) set_mirror_shift<false>(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f), okm);
+}
+
+// ---------------------------------------------------------------------------------
+// The small inputs of one component's M-step besides its statistics: the cell's flags,
+// the global offsets check, the cell's step count and blended weight sum, the
+// component's carried S0 and current means. Loaded in one batch, so that a kernel can
+// issue the loads before it sums the records and find them in registers afterwards (the
+// carried S2 is loaded by the update itself, early in its chain).
+// ---------------------------------------------------------------------------------
+struct MstepIn {
+    int fl, gok, step;
+    double sw, s0, mud[3], mux[3];
+};
+
+__device__ __forceinline__ MstepIn load_mstep_in(int c, int64_t g, bool cell_ok, bool act,
+                                                 const int32_t* __restrict__ flags,
+                                                 const int32_t* __restrict__ global_ok, const MixPtrs& mix,
+                                                 const StatePtrs& st)
+{
+    MstepIn in;
+    in.gok = *global_ok;
+    in.fl = cell_ok ? flags[c] : 0;
+    in.step = cell_ok ? st.step[c] : 0;
+    in.sw = cell_ok ? st.sw[c] : 0.0;
+    in.s0 = act ? st.s0[g] : 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        in.mud[d] = act ? mix.mud[3 * g + d] : 0.0;
+        in.mux[d] = act ? mix.mux[3 * g + d] : 0.0;
+    }
+    return in;
 }
 
 // ---------------------------------------------------------------------------------
 // M-step of one component (lane): from its cell's summed statistics (S: the component's,
-// X: the cell's W, M and count of negative weights) it gates the cell, blends
-// (Robbins-Monro) and updates in FP64, and optionally writes the next iteration's
-// mirrors. Each group of G consecutive lanes holds the components of one cell (lane
-// k % G = component k); every lane of the wave takes part (group reductions). c must be
-// a valid cell index even where cell_ok is false.
+// X: the cell's W, M and count of negative weights) and its other inputs `in` (loaded
+// by load_mstep_in for the same c, k) it gates the cell, blends (Robbins-Monro) and
+// updates in FP64, and optionally writes the next iteration's mirrors. Each group of G
+// consecutive lanes holds the components of one cell (lane k % G = component k); every
+// lane of the wave takes part (group reductions). c must be a valid cell index even where
+// cell_ok is false.
 // ---------------------------------------------------------------------------------
 template <int G>
+__device__ __forceinline__ int64_t mstep_component(int c, int k, int K)
+{
+    return (int64_t)c * K + (k < K ? k : 0);
+}
+
+template <int G>
 __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const double (&S)[kStats],
-                                             const double (&X)[3], int32_t* __restrict__ flags,
-                                             const int32_t* __restrict__ global_ok, const MixPtrs& mix,
+                                             const double (&X)[3], const MstepIn& in,
+                                             int32_t* __restrict__ flags, const MixPtrs& mix,
                                              const StatePtrs& st, const DevOpts& o, float* __restrict__ mirror,
                                              int refresh_mirror, int32_t* __restrict__ status)
 {
@@ -212,8 +259,7 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
     // E-step pass, whose statistics accurate_mstep_kernel turns into the covariances
     const bool accurate = (o.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
     const bool act = cell_ok && k < K;
-    const int kk = k < K ? k : 0;
-    const int64_t g = (int64_t)c * K + kk;
+    const int64_t g = mstep_component<G>(c, k, K);
 
     const double W = X[0], Mc = X[1], negs = X[2];
     int fin = isfinite(W);
@@ -221,22 +267,22 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
     const int notfin = group_or(act && !fin ? 1 : 0, GM) | (!isfinite(W) ? 1 : 0);
     int gate = 0, fl = 0;
     if (cell_ok) {
-        fl = flags[c];
-        if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !*global_ok) gate = kBadInput;
+        fl = in.fl;
+        if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !in.gok) gate = kBadInput;
         else if (fl & kBadParams) gate = kBadParams;
         else if (Mc < (double)o.min_samples) gate = kSkippedFew;
         else if (!(W > 0.0)) gate = kSkippedZeroW;
     }
     const bool run = cell_ok && !gate;
 
-    const int j = run ? st.step[c] : 0;
+    const int j = run ? in.step : 0;
     const double eta = rm_eta(o, j);
     const double beta = o.prior_mode == 0 ? eta / fmax(Mc, 1.0) : o.prior_scale;
-    const double hW = j == 0 ? W : (1.0 - eta) * (run ? st.sw[c] : 0.0) + eta * W;
+    const double hW = j == 0 ? W : (1.0 - eta) * (run ? in.sw : 0.0) + eta * W;
 
     double hS0 = 0.0, hS1[5], hS2[15];
     if (run && act) {
-        hS0 = j == 0 ? S[0] : (1.0 - eta) * st.s0[g] + eta * S[0];
+        hS0 = j == 0 ? S[0] : (1.0 - eta) * in.s0 + eta * S[0];
         for (int d = 0; d < 5; ++d) hS1[d] = (j == 0 ? 1.0 : eta) * S[1 + d];
         for (int q = 0; q < 15; ++q) hS2[q] = j == 0 ? S[6 + q] : (1.0 - eta) * st.s2[g * 15 + q] + eta * S[6 + q];
     }
@@ -246,9 +292,7 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
     int dead = 0, cholfail = 0;
     if (run && act) {
         // with the accurate update the second pass forms the covariance
-        const double mu_in[3] = {mix.mud[3 * g], mix.mud[3 * g + 1], mix.mud[3 * g + 2]};
-        const double mux_in[3] = {mix.mux[3 * g], mix.mux[3 * g + 1], mix.mux[3 * g + 2]};
-        component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, mu_in, mux_in, mix.mud + 3 * g,
+        component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, in.mud, in.mux, mix.mud + 3 * g,
                              mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
         mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
@@ -278,13 +322,16 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
                                            int32_t* __restrict__ status)
 {
     const int lane = threadIdx.x & 63;
+    const bool lane_ok = cell_ok && lane < G;
+    const MstepIn in = load_mstep_in(c, mstep_component<G>(c, lane, o.K), lane_ok, lane_ok && lane < o.K, flags,
+                                     global_ok, mix, st);
     double S[kStats], X[3];
     int64_t first = 0, n_items = 0;
     const bool have = cell_ok && cell_items(off, N, c, ps, first, n_items);
     // after the record tree (batched and per-cell schedules) only the top leaders remain
     const int lv = tree && *global_ok ? tree_levels_done(global_ok) : 0;
     sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
-    mstep_update<G>(c, lane, cell_ok && lane < G, S, X, flags, global_ok, mix, st, o, mirror, refresh_mirror, status);
+    mstep_update<G>(c, lane, lane_ok, S, X, in, flags, mix, st, o, mirror, refresh_mirror, status);
 }
 
 // M-step of cells [cell_lo, cell_lo + n_cells), one cell per wave
@@ -320,6 +367,14 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int cb = blockIdx.x * NCW;
+    // the updating wave's other inputs, loaded before the record sums so that their
+    // latency overlaps them
+    const int slot = lane / G, k = lane % G;
+    const int cu = cb + slot;
+    const bool uok = w == 0 && cu < n_cells;
+    const int cuc = cell_lo + (cu < n_cells ? cu : 0);
+    MstepIn in{};
+    if (w == 0) in = load_mstep_in(cuc, mstep_component<G>(cuc, k, o.K), uok, uok && k < o.K, flags, global_ok, mix, st);
     {
         const int cl = cb + w;
         const bool ok = cl < n_cells;
@@ -328,24 +383,21 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
         const bool have = ok && cell_items(off, N, c, ps, first, n_items);
         const int lv = *global_ok ? tree_levels_done(global_ok) : 0;
         double v[NQ];
-        // this phase holds few other registers: eight records per round trip
-        sum_cell_columns<G, kStats, 3, 8>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, v);
+        // six records per round trip (a cell's items at the usual sizes), which leaves
+        // room for the prefetched update inputs
+        sum_cell_columns<G, kStats, 3, 6>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, v);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q * 64 + lane < NCOL) cols[w][q * 64 + lane] = v[q];
     }
     __syncthreads();
     if (w != 0) return;
-    const int slot = lane / G, k = lane % G;
-    const int cl = cb + slot;
-    const bool ok = cl < n_cells;
     double S[kStats], X[3];
 #pragma unroll
     for (int s = 0; s < kStats; ++s) S[s] = cols[slot][s * G + k];
 #pragma unroll
     for (int i = 0; i < 3; ++i) X[i] = cols[slot][kStats * G + i];
-    mstep_update<G>(cell_lo + (ok ? cl : 0), k, ok, S, X, flags, global_ok, mix, st, o, mirror, refresh_mirror,
-                    status);
+    mstep_update<G>(cuc, k, uok, S, X, in, flags, mix, st, o, mirror, refresh_mirror, status);
 }
 
 // ---------------------------------------------------------------------------------
@@ -565,7 +617,7 @@ EstepFn estep_function(int G, int acc, bool jac, bool adj)
 }
 
 void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32_t* status, char* ws, const Layout& L,
-                  hipStream_t s)
+                  hipStream_t s, bool full)
 {
     const int C = mix.n_cells, K = mix.K;
     const int GM = group_pow2(K);
@@ -575,7 +627,7 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
                                             reinterpret_cast<int32_t*>(ws + L.flags), status,
                                             reinterpret_cast<int32_t*>(ws + L.arrive),
                                             reinterpret_cast<int32_t*>(ws + L.global_ok), blocks,
-                                            tree_levels_launched(N, L.P, L.max_cell));
+                                            tree_levels_launched(N, L.P, L.max_cell), full ? 1 : 0);
 }
 
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
@@ -669,7 +721,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
         launch_tree(kTreeFit, a.off, a.N, C, K, L, cell, c0, c1, a.ws, s);
     };
 
-    launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s);
+    launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s, false);
     if (a.opts.schedule == SDMM_SCHED_STEPWISE) {
         launch_stepwise(a.off, a.smp, a.N, a.mix, a.st, a.opts, a.status, L, a.ws, s);
         return check(hipGetLastError());
