@@ -28,7 +28,8 @@ struct StatePtrs {
 };
 
 // Workspace: FP32 mirrors, per-cell flags and arrival counters, the offsets check, and the
-// FP64 records of the E-step (one per record slot; C + W slots with W = ceil(N / P)).
+// records of the E-step (one per record slot; C + W slots with W = ceil(N / P)), sized
+// for FP64 elements (EM passes with FP32 block sums use FP32 elements at the same stride).
 // Records are sized for the larger (adjoint) pass so one workspace serves every call.
 struct Layout {
     int wpb;  // waves per work group of the E-step launch
@@ -132,7 +133,7 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
                       const void* workspace, size_t workspace_bytes);
 
 typedef void (*EstepFn)(const float*, int64_t, const int64_t*, int, int, int64_t, int64_t, const float*, int, int,
-                        double*);
+                        void*);
 
 // E-step kernel for G component lanes, running-sum variant, Jacobian option, adjoint pass
 EstepFn estep_function(int G, int acc, bool jac, bool adj);
@@ -145,10 +146,11 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
                   const Layout& L, hipStream_t s, bool full);
 
 // record tree levels after an E-step pass (all cells, or one cell when cell >= 0, whose
-// samples are [c0, c1)); the pass names the record layout
+// samples are [c0, c1)); the pass names the record layout, rec32 the FP32 element type
+// of EM records (adjoint records are FP64)
 enum TreePass { kTreeFit = 0, kTreeGrad = 1 };
 void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
-                 int64_t c1, char* ws, hipStream_t s);
+                 int64_t c1, char* ws, hipStream_t s, bool rec32);
 
 // stepwise EM of every cell (one wave per cell), after launch_setup
 void launch_stepwise(const int64_t* off, const float* smp, int64_t N, const sdmm_mixtures& mix,

@@ -10,6 +10,8 @@
 // terms sum w r (d nu / d delta)^T (L^-T z)_nu for the adjoint.
 #pragma once
 
+#include <type_traits>
+
 #include "device_math.hpp"
 
 namespace sdmm {
@@ -73,6 +75,12 @@ struct ChunkLayout {
     static __host__ __device__ constexpr int record(int G) { return (kNStat * G + (kNRed - kNStat) + 1) & ~1; }
 };
 
+// Element type of the per-item records: FP32 for the EM passes with FP32 block sums (the
+// item's FP64 total is rounded once; a record's rounding, 2^-24 relative, stays below
+// the FP32 accumulation error within the item), FP64 for the FP64-sum and adjoint passes.
+template <int ACC, bool ADJ>
+using RecordT = typename std::conditional<(ACC == kAccFp64 || ADJ), double, float>::type;
+
 // Sums the records of one cell's items 0, 2^stride_log2, 2 * 2^stride_log2, ... below
 // n_items (record slots from `first`) in item order, one column per lane (all 64 lanes
 // of the wave, which must be uniform in first/n_items), with the loads of several records
@@ -80,38 +88,42 @@ struct ChunkLayout {
 // then the extras) ends in v[q]. With stride 2^(4 L) the summed records are the level-L
 // leaders of the record tree (see tree_kernel). RB0 records per round trip by default
 // (fewer when a record spans many registers).
-template <int G, int NS, int NX, int RB0 = 4>
-__device__ __forceinline__ void sum_cell_columns(const double* __restrict__ records, int64_t first, int64_t n_items,
+template <int G, int NS, int NX, int RB0 = 4, typename RT = double>
+__device__ __forceinline__ void sum_cell_columns(const RT* __restrict__ records, int64_t first, int64_t n_items,
                                                  int PS, int stride_log2, double (&v)[(NS * G + NX + 63) / 64])
 {
     constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
     const int lane = threadIdx.x & 63;
     const int64_t n = (n_items + (int64_t(1) << stride_log2) - 1) >> stride_log2;  // records to sum
-    const int64_t step = (int64_t)PS << stride_log2;                                 // doubles between them
+    const int64_t step = (int64_t)PS << stride_log2;                                 // elements between them
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-    // RB records per round trip; past the last record the loads are skipped and add an
-    // exact zero, so the sum is the same as record by record
-    constexpr int RB = NQ > 6 ? 2 : RB0;
+    // RB records per round trip (twice as many for FP32 records, held as loaded). Every
+    // load is issued, at an index clamped to the cell's last record and the record's last
+    // column (no branch, one wait per round trip); what lies past them adds an exact zero,
+    // so the sum is the same as record by record
+    constexpr int RB = (NQ > 6 ? 2 : RB0) * (sizeof(RT) == 4 ? 2 : 1);
     for (int64_t j = 0; j < n; j += RB) {
-        const double* r0 = records + first * PS + j * step;
-        double a[RB][NQ];
+        const RT* r0 = records + first * PS + j * step;
+        RT a[RB][NQ];
 #pragma unroll
         for (int u = 0; u < RB; ++u)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                a[u][q] = (j + u < n && q * 64 + lane < NCOL) ? r0[u * step + q * 64 + lane] : 0.0;
+            for (int q = 0; q < NQ; ++q) {
+                const int64_t uu = min(j + u, n - 1) - j;
+                a[u][q] = r0[uu * step + min(q * 64 + lane, NCOL - 1)];
+            }
 #pragma unroll
         for (int u = 0; u < RB; ++u)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) v[q] += a[u][q];
+            for (int q = 0; q < NQ; ++q) v[q] += (j + u < n && q * 64 + lane < NCOL) ? (double)a[u][q] : 0.0;
     }
 }
 
 // The same sums handed to lane k < G as its component's statistics S[s] = column
 // s * G + k, and to every lane as the extras X[i] = column NS * G + i.
-template <int G, int NS, int NX>
-__device__ __forceinline__ void sum_cell_records(const double* __restrict__ records, int64_t first, int64_t n_items,
+template <int G, int NS, int NX, typename RT>
+__device__ __forceinline__ void sum_cell_records(const RT* __restrict__ records, int64_t first, int64_t n_items,
                                                  int PS, int stride_log2, double (&S)[NS], double (&X)[NX])
 {
     constexpr int NQ = (NS * G + NX + 63) / 64;
@@ -370,13 +382,15 @@ __device__ __forceinline__ bool cell_items(const int64_t* off, int64_t N, int c,
 }
 
 // E-step of one segment [s0, s1) of a cell by one wave. mirror_cell points at the cell's
-// K FP32 mirrors. Writes the segment record part[] (FP64) from lanes < G.
+// K FP32 mirrors. Writes the segment record part[] (RecordT, from the FP64 totals) from
+// lanes < G.
 template <int G, int ACC, bool JAC, bool ADJ>
 __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int64_t N, int64_t s0, int64_t s1,
                                               const float* __restrict__ mirror_cell, int K,
-                                              double* __restrict__ part)
+                                              RecordT<ACC, ADJ>* __restrict__ part)
 {
     using CL = ChunkLayout<ADJ>;
+    using RT = RecordT<ACC, ADJ>;
     constexpr int NS = CL::kNStat, NR = CL::kNRed;
     constexpr int S = 64 / G;
     const int lane = threadIdx.x & 63;
@@ -590,10 +604,10 @@ __device__ __forceinline__ void estep_segment(const float* __restrict__ smp, int
     }
     if (lane < G) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) part[s * G + comp] = v[s];
+        for (int s = 0; s < NS; ++s) part[s * G + comp] = (RT)v[s];
         if (comp == 0) {
 #pragma unroll
-            for (int s = NS; s < NR; ++s) part[NS * G + (s - NS)] = v[s];
+            for (int s = NS; s < NR; ++s) part[NS * G + (s - NS)] = (RT)v[s];
         }
     }
 }
@@ -636,9 +650,9 @@ __device__ __forceinline__ int tree_levels_done(const int32_t* __restrict__ cont
 }
 
 // the level-`level` leader in level slot t, if any, sums its block (see tree_kernel)
-template <int G, int NS, int NX>
+template <int G, int NS, int NX, typename RT>
 __device__ __forceinline__ void tree_leader(const int64_t* __restrict__ off, int64_t N, int C, int ps, int level,
-                                            int64_t t, double* __restrict__ records, int PS)
+                                            int64_t t, RT* __restrict__ records, int PS)
 {
     constexpr int NCOL = NS * G + NX, NQ = (NCOL + 63) / 64;
     const int psl = ps + kTreeLog2R * level;
@@ -653,35 +667,35 @@ __device__ __forceinline__ void tree_leader(const int64_t* __restrict__ off, int
     const int64_t count = min((int64_t)(1 << kTreeLog2R), (n_items - base + sub - 1) / sub);
     if (count <= 1) return;
     const int lane = threadIdx.x & 63;
-    double* r0 = records + (first + base) * PS;
+    RT* r0 = records + (first + base) * PS;
     const int64_t step = (int64_t)PS * sub;
     double v[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = (q * 64 + lane < NCOL) ? r0[q * 64 + lane] : 0.0;
+    for (int q = 0; q < NQ; ++q) v[q] = (q * 64 + lane < NCOL) ? (double)r0[q * 64 + lane] : 0.0;
     for (int64_t i = 1; i < count; ++i) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            if (q * 64 + lane < NCOL) v[q] += r0[i * step + q * 64 + lane];
+            if (q * 64 + lane < NCOL) v[q] += (double)r0[i * step + q * 64 + lane];
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-        if (q * 64 + lane < NCOL) r0[q * 64 + lane] = v[q];
+        if (q * 64 + lane < NCOL) r0[q * 64 + lane] = (RT)v[q];
 }
 
 // control[0]: offsets valid, control[1]: the largest item count of a cell (setup kernel).
 // A fixed grid strides over the level slots, so a level that is not needed costs one
 // small dispatch.
-template <int G, int NS, int NX>
+template <int G, int NS, int NX, typename RT>
 __global__ __launch_bounds__(256) void tree_kernel(const int64_t* __restrict__ off, int64_t N, int C, int ps,
                                                    int level, int64_t slot_lo, int64_t slot_hi,
-                                                   const int32_t* __restrict__ control, double* __restrict__ records,
+                                                   const int32_t* __restrict__ control, void* __restrict__ records_v,
                                                    int PS)
 {
     if (!control[0] || level > tree_levels(control[1])) return;  // a level this batch does not need
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t t = slot_lo + wave; t < slot_hi; t += nwaves)
-        tree_leader<G, NS, NX>(off, N, C, ps, level, t, records, PS);
+        tree_leader<G, NS, NX, RT>(off, N, C, ps, level, t, static_cast<RT*>(records_v), PS);
 }
 
 // ---------------------------------------------------------------------------------

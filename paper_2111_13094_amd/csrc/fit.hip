@@ -113,13 +113,31 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
     const int bad = group_or(active && !ok ? 1 : 0, GM);
     // the shift is an FP32 value, so adding it back in FP64 is exact
     const float shift = isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f;
-    if (active) {
-        if (full) {
+    if (full) {
+        if (active) {
             set_mirror_shift<true>(m, c2, (double)shift, ok);
             store_mirror<true>(mirror + g * kMirror, m);
-        } else {
+        }
+    } else {
+        // lite mirrors leave through LDS: a lane's own stores would touch 64 lines per
+        // instruction (one 16-byte piece per component); read back in component order,
+        // each store instruction writes eight components' lite mirrors whole
+        __shared__ float4 stage[256][kMirrorLite / 4 + 1];
+        if (active) {
             set_mirror_shift<false>(m, c2, (double)shift, ok);
-            store_mirror<false>(mirror + g * kMirror, m);
+#pragma unroll
+            for (int q = 0; q < kMirrorLite / 4; ++q)
+                stage[threadIdx.x][q] = make_float4(m[4 * q], m[4 * q + 1], m[4 * q + 2], m[4 * q + 3]);
+        }
+        __syncthreads();
+        const int cpb = (int)blockDim.x / GM;  // cells per block
+        const int c_lo = (int)blockIdx.x * cpb, c_hi = min(C, c_lo + cpb);
+        const int64_t g_lo = (int64_t)c_lo * K;
+        const int n = (c_hi - c_lo) * K * (kMirrorLite / 4);
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const int comp = j / (kMirrorLite / 4), part = j % (kMirrorLite / 4);
+            const int src = (comp / K) * GM + comp % K;
+            reinterpret_cast<float4*>(mirror + (g_lo + comp) * kMirror)[part] = stage[src][part];
         }
     }
     if (c < C && k == 0) {
@@ -158,13 +176,14 @@ template <int G, int ACC, bool JAC, bool ADJ>
 __global__ __launch_bounds__(256) void estep_kernel(const float* __restrict__ smp, int64_t N,
                                                     const int64_t* __restrict__ off, int C, int ps, int64_t slot_lo,
                                                     int64_t slot_hi, const float* __restrict__ mirror, int K, int PS,
-                                                    double* __restrict__ records)
+                                                    void* __restrict__ records)
 {
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int c;
     int64_t t, s0, s1, n_items;
     if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
-    estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, records + t * PS);
+    estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
+                                    static_cast<RecordT<ACC, ADJ>*>(records) + t * PS);
 }
 
 // FP64 adjoint pass (verification mode), same work map as estep_kernel
@@ -173,13 +192,13 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
                                                           const int64_t* __restrict__ off, int C, int ps,
                                                           int64_t slot_lo, int64_t slot_hi,
                                                           const float* __restrict__ mirror, int K, int PS,
-                                                          double* __restrict__ records)
+                                                          void* __restrict__ records)
 {
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int c;
     int64_t t, s0, s1, n_items;
     if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
-    estep_segment_adj64<G>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, records + t * PS);
+    estep_segment_adj64<G>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, static_cast<double*>(records) + t * PS);
 }
 
 // ---------------------------------------------------------------------------------
@@ -313,9 +332,9 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
 // M-step of one cell by one wave: all 64 lanes sum the cell's records (in item order,
 // column-parallel), then lanes k < G (lane k = component k) update. cell_ok must be
 // uniform over the wave.
-template <int G>
+template <int G, typename RT>
 __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int64_t N, int c, bool cell_ok, int ps,
-                                           bool tree, const double* __restrict__ records, int PS,
+                                           bool tree, const RT* __restrict__ records, int PS,
                                            int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok,
                                            const MixPtrs& mix, const StatePtrs& st, const DevOpts& o,
                                            float* __restrict__ mirror, int refresh_mirror,
@@ -335,9 +354,9 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
 }
 
 // M-step of cells [cell_lo, cell_lo + n_cells), one cell per wave
-template <int G>
+template <int G, typename RT>
 __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
-                                                    const double* __restrict__ records, int PS,
+                                                    const void* __restrict__ records, int PS,
                                                     int32_t* __restrict__ flags,
                                                     const int32_t* __restrict__ global_ok, MixPtrs mix,
                                                     StatePtrs st, DevOpts o, float* __restrict__ mirror,
@@ -346,7 +365,7 @@ __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ 
 {
     const int cl = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool cell_ok = cl < n_cells;
-    mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, true, records, PS, flags, global_ok, mix, st, o,
+    mstep_cell<G>(off, N, cell_lo + (cell_ok ? cl : 0), cell_ok, ps, true, static_cast<const RT*>(records), PS, flags, global_ok, mix, st, o,
                   mirror, refresh_mirror, status);
 }
 
@@ -356,9 +375,9 @@ __global__ __launch_bounds__(256) void mstep_kernel(const int64_t* __restrict__ 
 // w * G + k = component k of cell w. The FP64 update, which needs one lane per
 // component, then issues once for 64 components instead of once per cell. The sums and
 // the update are those of mstep_kernel, so both give the same results.
-template <int G>
+template <int G, typename RT>
 __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_kernel(
-    const int64_t* __restrict__ off, int64_t N, int ps, const double* __restrict__ records, int PS,
+    const int64_t* __restrict__ off, int64_t N, int ps, const void* __restrict__ records, int PS,
     int32_t* __restrict__ flags, const int32_t* __restrict__ global_ok, MixPtrs mix, StatePtrs st, DevOpts o,
     float* __restrict__ mirror, int refresh_mirror, int32_t* __restrict__ status, int cell_lo, int n_cells)
 {
@@ -383,9 +402,10 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
         const bool have = ok && cell_items(off, N, c, ps, first, n_items);
         const int lv = *global_ok ? tree_levels_done(global_ok) : 0;
         double v[NQ];
-        // six records per round trip (a cell's items at the usual sizes), which leaves
-        // room for the prefetched update inputs
-        sum_cell_columns<G, kStats, 3, 6>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, v);
+        // six FP32 (three FP64) records per round trip, which leaves room for the
+        // prefetched update inputs
+        sum_cell_columns<G, kStats, 3, 3>(static_cast<const RT*>(records), first, have ? n_items : 0, PS,
+                                          kTreeLog2R * lv, v);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q * 64 + lane < NCOL) cols[w][q * 64 + lane] = v[q];
@@ -413,9 +433,9 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
 // keep what it left; one whose S0' / W is at or below the dead threshold keeps its
 // covariance and flags the cell as dead. Cells the first M-step did not step are skipped.
 // ---------------------------------------------------------------------------------
-template <int G>
+template <int G, typename RT>
 __global__ __launch_bounds__(256) void accurate_mstep_kernel(const int64_t* __restrict__ off, int64_t N, int ps,
-                                                             const double* __restrict__ records, int PS,
+                                                             const void* __restrict__ records, int PS,
                                                              const int32_t* __restrict__ flags,
                                                              const int32_t* __restrict__ global_ok, MixPtrs mix,
                                                              StatePtrs st, DevOpts o, float* __restrict__ mirror,
@@ -432,7 +452,8 @@ __global__ __launch_bounds__(256) void accurate_mstep_kernel(const int64_t* __re
     const bool have = stepped && cell_items(off, N, c, ps, first, n_items);
     const int lv = *global_ok ? tree_levels_done(global_ok) : 0;
     double S[kStats], X[3];
-    sum_cell_records<G, kStats, 3>(records, first, have ? n_items : 0, PS, kTreeLog2R * lv, S, X);
+    sum_cell_records<G, kStats, 3>(static_cast<const RT*>(records), first, have ? n_items : 0, PS, kTreeLog2R * lv, S,
+                                   X);
     const bool act = have && k < K;
     const int64_t g = (int64_t)c * K + (k < K ? k : 0);
     int dead = 0, cholfail = 0;
@@ -476,7 +497,7 @@ template <int G, int ACC, bool JAC>
 __global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ smp, int64_t N,
                                                     const int64_t* __restrict__ off, int C, int ps,
                                                     int64_t slot_hi, const float* __restrict__ mirror_in, int K,
-                                                    int PS, double* __restrict__ records,
+                                                    int PS, void* __restrict__ records_v,
                                                     int32_t* __restrict__ arrive, int32_t* __restrict__ flags,
                                                     const int32_t* __restrict__ global_ok, MixPtrs mix, StatePtrs st,
                                                     DevOpts o, float* __restrict__ mirror, int refresh_mirror,
@@ -491,6 +512,7 @@ __global__ __launch_bounds__(256) void fused_kernel(const float* __restrict__ sm
     int c;
     int64_t t, s0, s1, n_items;
     if (!wave_item(w, off, N, C, ps, 0, slot_hi, c, t, s0, s1, n_items)) return;
+    RecordT<ACC, false>* records = static_cast<RecordT<ACC, false>*>(records_v);
     estep_segment<G, ACC, JAC, false>(smp, N, s0, s1, mirror_in + (int64_t)c * K * kMirror, K, records + t * PS);
     __threadfence();
     int done = 0;
@@ -524,47 +546,68 @@ static EstepFn estep_for_g(int acc, bool jac)
 }
 
 typedef void (*FusedFn)(const float*, int64_t, const int64_t*, int, int, int64_t, const float*, int, int,
-                        double*, int32_t*, int32_t*, const int32_t*, MixPtrs, StatePtrs, DevOpts, float*, int,
+                        void*, int32_t*, int32_t*, const int32_t*, MixPtrs, StatePtrs, DevOpts, float*, int,
                         int32_t*);
-typedef void (*MstepFn)(const int64_t*, int64_t, int, const double*, int, int32_t*, const int32_t*, MixPtrs,
+typedef void (*MstepFn)(const int64_t*, int64_t, int, const void*, int, int32_t*, const int32_t*, MixPtrs,
                         StatePtrs, DevOpts, float*, int, int32_t*, int, int);
-typedef void (*AccMstepFn)(const int64_t*, int64_t, int, const double*, int, const int32_t*, const int32_t*, MixPtrs,
+typedef void (*AccMstepFn)(const int64_t*, int64_t, int, const void*, int, const int32_t*, const int32_t*, MixPtrs,
                            StatePtrs, DevOpts, float*, int, int32_t*, int, int);
 
-static AccMstepFn accurate_mstep_function(int G)
+template <typename RT>
+static AccMstepFn accurate_mstep_function_t(int G)
 {
     switch (G) {
-        case 4: return accurate_mstep_kernel<4>;
-        case 8: return accurate_mstep_kernel<8>;
-        case 16: return accurate_mstep_kernel<16>;
-        case 32: return accurate_mstep_kernel<32>;
-        case 64: return accurate_mstep_kernel<64>;
+        case 4: return accurate_mstep_kernel<4, RT>;
+        case 8: return accurate_mstep_kernel<8, RT>;
+        case 16: return accurate_mstep_kernel<16, RT>;
+        case 32: return accurate_mstep_kernel<32, RT>;
+        case 64: return accurate_mstep_kernel<64, RT>;
     }
     return nullptr;
 }
 
-static MstepFn mstep_packed_function(int G)
+// rec32: FP32 records (see RecordT)
+static AccMstepFn accurate_mstep_function(int G, bool rec32)
+{
+    return rec32 ? accurate_mstep_function_t<float>(G) : accurate_mstep_function_t<double>(G);
+}
+
+template <typename RT>
+static MstepFn mstep_packed_function_t(int G)
 {
     switch (G) {
-        case 4: return mstep_packed_kernel<4>;
-        case 8: return mstep_packed_kernel<8>;
-        case 16: return mstep_packed_kernel<16>;
-        case 32: return mstep_packed_kernel<32>;
-        case 64: return mstep_packed_kernel<64>;
+        case 4: return mstep_packed_kernel<4, RT>;
+        case 8: return mstep_packed_kernel<8, RT>;
+        case 16: return mstep_packed_kernel<16, RT>;
+        case 32: return mstep_packed_kernel<32, RT>;
+        case 64: return mstep_packed_kernel<64, RT>;
     }
     return nullptr;
 }
 
-static MstepFn mstep_function(int G)
+// rec32: FP32 records (see RecordT)
+static MstepFn mstep_packed_function(int G, bool rec32)
+{
+    return rec32 ? mstep_packed_function_t<float>(G) : mstep_packed_function_t<double>(G);
+}
+
+template <typename RT>
+static MstepFn mstep_function_t(int G)
 {
     switch (G) {
-        case 4: return mstep_kernel<4>;
-        case 8: return mstep_kernel<8>;
-        case 16: return mstep_kernel<16>;
-        case 32: return mstep_kernel<32>;
-        case 64: return mstep_kernel<64>;
+        case 4: return mstep_kernel<4, RT>;
+        case 8: return mstep_kernel<8, RT>;
+        case 16: return mstep_kernel<16, RT>;
+        case 32: return mstep_kernel<32, RT>;
+        case 64: return mstep_kernel<64, RT>;
     }
     return nullptr;
+}
+
+// rec32: FP32 records (see RecordT)
+static MstepFn mstep_function(int G, bool rec32)
+{
+    return rec32 ? mstep_function_t<float>(G) : mstep_function_t<double>(G);
 }
 
 template <int G>
@@ -637,30 +680,31 @@ void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, 
     if (waves <= 0) return;
     const unsigned blocks = (unsigned)((waves + L.wpb - 1) / L.wpb);
     hipLaunchKernelGGL(est, dim3(blocks), dim3(64 * L.wpb), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
-                       reinterpret_cast<const float*>(ws + L.mirror), K, PS,
-                       reinterpret_cast<double*>(ws + L.records));
+                       reinterpret_cast<const float*>(ws + L.mirror), K, PS, static_cast<void*>(ws + L.records));
 }
 
-typedef void (*TreeFn)(const int64_t*, int64_t, int, int, int, int64_t, int64_t, const int32_t*, double*, int);
+typedef void (*TreeFn)(const int64_t*, int64_t, int, int, int, int64_t, int64_t, const int32_t*, void*, int);
 
-template <int NS, int NX>
+template <int NS, int NX, typename RT>
 static TreeFn tree_function(int G)
 {
     switch (G) {
-        case 4: return tree_kernel<4, NS, NX>;
-        case 8: return tree_kernel<8, NS, NX>;
-        case 16: return tree_kernel<16, NS, NX>;
-        case 32: return tree_kernel<32, NS, NX>;
-        case 64: return tree_kernel<64, NS, NX>;
+        case 4: return tree_kernel<4, NS, NX, RT>;
+        case 8: return tree_kernel<8, NS, NX, RT>;
+        case 16: return tree_kernel<16, NS, NX, RT>;
+        case 32: return tree_kernel<32, NS, NX, RT>;
+        case 64: return tree_kernel<64, NS, NX, RT>;
     }
     return nullptr;
 }
 
 void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, const Layout& L, int cell, int64_t c0,
-                 int64_t c1, char* ws, hipStream_t s)
+                 int64_t c1, char* ws, hipStream_t s, bool rec32)
 {
     const int G = group_for(K);
-    const TreeFn fn = pass == kTreeGrad ? tree_function<kStats + 2, 4>(G) : tree_function<kStats, 3>(G);
+    const TreeFn fn = pass == kTreeGrad ? tree_function<kStats + 2, 4, double>(G)
+                      : rec32           ? tree_function<kStats, 3, float>(G)
+                                        : tree_function<kStats, 3, double>(G);
     const int PS = pass == kTreeGrad ? L.ps_grad : L.ps_fit;
     // a bound from the caller's largest cell (else all samples in one cell); the device
     // skips levels no cell needs
@@ -674,8 +718,7 @@ void launch_tree(TreePass pass, const int64_t* off, int64_t N, int C, int K, con
         }
         const int64_t blocks = std::min<int64_t>((hi - lo + 3) / 4, 256);  // grid-stride: at most 1024 waves
         hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(256), 0, s, off, N, C, L.ps, level, lo, hi,
-                           reinterpret_cast<const int32_t*>(ws + L.global_ok),
-                           reinterpret_cast<double*>(ws + L.records), PS);
+                           reinterpret_cast<const int32_t*>(ws + L.global_ok), static_cast<void*>(ws + L.records), PS);
     }
 }
 
@@ -704,12 +747,13 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
     const bool accurate = (a.opts.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
     EstepFn est = estep_function(G, acc, jac, false);
     FusedFn fused = fused_function(G, acc, jac);
-    MstepFn mstep = mstep_function(G), mstep_packed = mstep_packed_function(G);
-    AccMstepFn acc_mstep = accurate ? accurate_mstep_function(G) : nullptr;
+    const bool rec32 = acc != kAccFp64;  // record element type of these passes (RecordT)
+    MstepFn mstep = mstep_function(G, rec32), mstep_packed = mstep_packed_function(G, rec32);
+    AccMstepFn acc_mstep = accurate ? accurate_mstep_function(G, rec32) : nullptr;
     float* mirror = reinterpret_cast<float*>(a.ws + L.mirror);
     int32_t* flags = reinterpret_cast<int32_t*>(a.ws + L.flags);
     const int32_t* gok = reinterpret_cast<const int32_t*>(a.ws + L.global_ok);
-    double* rec = reinterpret_cast<double*>(a.ws + L.records);
+    void* rec = static_cast<void*>(a.ws + L.records);
 
     // second E-step pass of the accurate update over record slots [lo, hi) on the mirrors
     // the first M-step wrote, then its record tree
@@ -718,7 +762,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
             ScopedTimer tm(SDMM_TIMER_ACCURATE, s);
             launch_estep(est, a.smp, a.N, a.off, C, K, L, lo, hi, L.ps_fit, a.ws, s);
         }
-        launch_tree(kTreeFit, a.off, a.N, C, K, L, cell, c0, c1, a.ws, s);
+        launch_tree(kTreeFit, a.off, a.N, C, K, L, cell, c0, c1, a.ws, s, rec32);
     };
 
     launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s, false);
@@ -742,7 +786,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
                     first = c + (c0 >> L.ps);
                     n_items = c1 > c0 ? (c1 - c0 + L.P - 1) >> L.ps : 1;
                     launch_estep(est, a.smp, a.N, a.off, C, K, L, first, first + n_items, L.ps_fit, a.ws, s);
-                    launch_tree(kTreeFit, a.off, a.N, C, K, L, c, c0, c1, a.ws, s);
+                    launch_tree(kTreeFit, a.off, a.N, C, K, L, c, c0, c1, a.ws, s, rec32);
                 }
                 hipLaunchKernelGGL(mstep, dim3(1), dim3(64), 0, s, a.off, a.N, L.ps, rec, L.ps_fit, flags, gok, mp, sp,
                                    dopt, mirror, refresh1, a.status, c, 1);
@@ -757,7 +801,7 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
                 ScopedTimer tm(SDMM_TIMER_ESTEP, s);
                 launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s);
             }
-            launch_tree(kTreeFit, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s);
+            launch_tree(kTreeFit, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s, rec32);
             {
                 ScopedTimer tm(SDMM_TIMER_MSTEP, s);
                 const int ncw = 64 / G;  // cells per work group

@@ -174,7 +174,7 @@ extern "C" int sdmm_fit_grad(const int64_t* cell_offsets, const float* samples, 
         launch_estep(pass, samples, n_samples, cell_offsets, C,
                      K, L, 0, (int64_t)C + L.W, L.ps_grad, ws, s);
     }
-    launch_tree(kTreeGrad, cell_offsets, n_samples, C, K, L, -1, 0, 0, ws, s);
+    launch_tree(kTreeGrad, cell_offsets, n_samples, C, K, L, -1, 0, 0, ws, s, false);
     const MixPtrs mp{mix->weights, mix->mean_dir, mix->mean_pos, mix->cov};
     auto asm_fn = grad_assemble_kernel<16>;
     switch (group_for(K)) {

@@ -333,8 +333,9 @@ def test_record_tree_schedules(dev, orc):
 def test_max_cell_samples_hint(dev, orc):
     """The caller's bound on samples per cell only sets how many record-tree levels are
     launched. An exact bound gives the same bits as no bound; a bound below the largest
-    cell launches too few levels, and the M-step then sums more records: the same
-    result up to FP64 rounding of the different summation order."""
+    cell launches too few levels, and the M-step then sums the item records instead of
+    the level leaders: the same result up to the FP32 rounding of the leader records
+    (2^-24 relative per leader), held at a tenth of the parity bar."""
     print("case: max_cell_samples hint, 120000-sample cell in 64-sample items", flush=True)
     from paper_2111_13094_amd import sdmm
     wl = synth.workload("single", seed=17)
@@ -355,11 +356,11 @@ def test_max_cell_samples_hint(dev, orc):
     ref = runs[("none", sdmm.SCHED_BATCHED)]
     for key, got in runs.items():
         assert (stats[key] == stats[("none", sdmm.SCHED_BATCHED)]).all(), key
-        for k in ref:
-            if key[0] != "below":
+        if key[0] != "below":
+            for k in ref:
                 assert np.array_equal(got[k], ref[k]), (key, k)
-            else:
-                assert np.allclose(got[k], ref[k], rtol=1e-10, atol=1e-13), (key, k)
+        else:
+            assert_close(compare_mixtures(got, ref, 16), rtol=1e-5, ang_tol=1e-6, what=str(key))
     o = sdmm.default_opts(16, max_cell_samples=-1)
     gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, 16))
     with pytest.raises(RuntimeError):

@@ -4,7 +4,7 @@ step from the initial mixture, every running-sum variant of the E-step against t
 FP64 oracle. The E-step forms products in FP32 in every variant; what differs is how
 the per-lane running sums are kept:
 
-  twosum  FP32 block sums folded every 32 steps by TwoSum into an FP32 running sum, the
+  twosum  FP32 block sums folded every 64 steps by TwoSum into an FP32 running sum, the
           rounding error of each fold opening the next block (compensated)
   plain   one FP32 running sum per lane
   fp64    FP32 block sums folded into an FP64 running sum
