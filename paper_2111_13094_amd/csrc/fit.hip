@@ -172,8 +172,16 @@ __device__ __forceinline__ bool wave_item(int64_t w, const int64_t* __restrict__
 // ---------------------------------------------------------------------------------
 // E-step: one wave per work item (see wave_item)
 // ---------------------------------------------------------------------------------
+// waves per SIMD the E-step needs: the plain-sum EM pass fits five (96 registers), which
+// hides more of each item's start-up latency (cell search, mirror and first loads)
+template <int ACC, bool JAC, bool ADJ>
+constexpr int estep_min_waves()
+{
+    return (ACC == kAccPlain && !JAC && !ADJ) ? 5 : 1;
+}
+
 template <int G, int ACC, bool JAC, bool ADJ>
-__global__ __launch_bounds__(256) void estep_kernel(const float* __restrict__ smp, int64_t N,
+__global__ __launch_bounds__(256, (estep_min_waves<ACC, JAC, ADJ>())) void estep_kernel(const float* __restrict__ smp, int64_t N,
                                                     const int64_t* __restrict__ off, int C, int ps, int64_t slot_lo,
                                                     int64_t slot_hi, const float* __restrict__ mirror, int K, int PS,
                                                     void* __restrict__ records)
@@ -745,7 +753,12 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
                     : (a.opts.flags & SDMM_FLAG_FP64_SUMS) ? kAccFp64 : kAccTwoSum;
     const bool jac = (a.opts.flags & SDMM_FLAG_ESTEP_JACOBIAN) != 0;
     const bool accurate = (a.opts.flags & SDMM_FLAG_ACCURATE_SIGMA) != 0;
-    EstepFn est = estep_function(G, acc, jac, false);
+    // a lane's share of a work item fits one block of the compensated sums when the item
+    // has at most kFoldEvery steps of 64 / G samples: no fold ever runs, the running total
+    // stays zero, and the compensated pass is bit for bit the plain one, which needs fewer
+    // registers
+    const bool one_block = (L.P / (64 / G)) <= kFoldEvery;
+    EstepFn est = estep_function(G, (acc == kAccTwoSum && one_block) ? kAccPlain : acc, jac, false);
     FusedFn fused = fused_function(G, acc, jac);
     const bool rec32 = acc != kAccFp64;  // record element type of these passes (RecordT)
     MstepFn mstep = mstep_function(G, rec32), mstep_packed = mstep_packed_function(G, rec32);
