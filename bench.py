@@ -3,9 +3,10 @@
 Headline (default): EM sample x component updates per second on the 4096-cell workload
 (16^3 cells of the unit cube, K = 16, cell counts lognormal(6.45, 1) clipped to
 [64, 8192], about 4.2M samples per batch, 8 resident batches, stepwise EM with decay 0.9:
-eta = 0.1 after the first batch), batched schedule (setup, one E launch and one M launch
-per batch over all cells) in the launch configuration the autotuner picks on the first
-batch, replayed through the library's hipGraph cache.
+eta = 0.1 after the first batch), batched schedule (one E launch and one M launch per
+batch over all cells; each call's last M-step writes the next call's E-step mirrors, so
+after the first call no setup kernel runs) in the launch configuration the autotuner picks
+on the first batch, replayed through the library's hipGraph cache.
 A step is one E+M pass over one resident batch; inputs are generated on the host and
 copied to HBM before the timed region. The same steps launched eagerly, with HIP events
 around every E-step and M-step launch, give the roofline's kernel time ("eager").
@@ -16,7 +17,8 @@ The JSON line also carries:
                 event-timed duration, against the FP32 vector peak;
   plain         the same updates/s for the plain per-cell GPU EM (one E and one M launch
                 per cell), same tolerance;
-  cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the workload.
+  cpu_baseline  the FP64 oracle, single thread, on a bounded sample of the workload, and
+                its OpenMP build over cells on all host cores ("all_cores").
 
 Other workloads (--workload), each printing its own line: single (1 cell, N = 16384,
 20 iterations, hipGraph), cells16k (16384 cells, geometric counts, then 2^22 query
@@ -196,6 +198,10 @@ def bench_cells4k(args, torch):
         tuned = {"items": int(opts.min_range), "waves_per_block": int(opts.waves_per_block or 1),
                  "e_plus_m_ms": cfg["ms"] if cfg else None, "candidates": len(TUNE_CANDIDATES)}
         del m_t, s_t
+    if args.carry:
+        # a fitting loop whose mixtures change only through its own calls: each call's
+        # last M-step writes the next call's E-step mirrors, so no setup kernel runs
+        opts.flags |= sdmm.FLAG_CARRY_MIRRORS
     status = torch.empty(C, dtype=torch.int32, device=dev)
     ws = torch.empty(max(sdmm.workspace_bytes(C, K, n, opts) for n in N), dtype=torch.uint8, device=dev)
     mix, st = fresh()
@@ -257,7 +263,8 @@ def bench_cells4k(args, torch):
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches,
                    "schedule": "fused" if opts.schedule == sdmm.SCHED_FUSED else "batched",
                    "min_range": items, "max_ranges": int(opts.max_ranges or 65536), "waves_per_block": wpb,
-                   "hipgraph": bool(args.graph), "running_sums": args.sums, "max_cell_samples": max_cell,
+                   "hipgraph": bool(args.graph), "carried_mirrors": bool(args.carry), "running_sums": args.sums,
+                   "max_cell_samples": max_cell,
                    "autotuned": tuned},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
@@ -818,6 +825,8 @@ def main():
                     help="E-step running sums: compensated FP32 (default), plain FP32, FP64 fold")
     ap.add_argument("--tune", type=int, default=1, help="1: let the autotuner pick the launch configuration")
     ap.add_argument("--graph", type=int, default=1, help="1: replay the fit through the library's hipGraph cache")
+    ap.add_argument("--carry", type=int, default=1, help="1: calls carry the E-step mirrors to the next call "
+                                                          "(SDMM_FLAG_CARRY_MIRRORS)")
     ap.add_argument("--sweep", default="", help="comma-separated schedule:items[:waves_per_block] points, "
                                                 "e.g. batched:256:1,fused:512")
     ap.add_argument("--no-plain", action="store_true")

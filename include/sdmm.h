@@ -77,6 +77,23 @@ extern "C" {
                                       Batch steps only: needs eta_mode SDMM_ETA_CONSTANT with
                                       eta = 1 and the batched or per-cell schedule (else
                                       SDMM_EINVAL). Twice the E-step work. */
+#define SDMM_FLAG_CARRY_MIRRORS 16 /* batched schedule, for callers whose mixtures change
+                                      only through these calls (a fitting loop over
+                                      successive batches): the last M-step also writes the
+                                      FP32 E-step mirrors of the new parameters into the
+                                      workspace, and a call with this flag whose workspace's
+                                      previous call did so for the same mixture arrays
+                                      (pointers, n_cells, K) skips the setup kernel that
+                                      would rebuild them: its E-step launch checks the
+                                      offsets and its M-step resets the statuses. The
+                                      library keeps that record on the host; any other call
+                                      on the workspace (another schedule, no flag, a failed
+                                      call, sdmm_fit_grad) clears it. Results are bit for
+                                      bit those without the flag. Changing the mixture
+                                      values between two flagged calls on one workspace
+                                      (other than through these calls) leaves stale mirrors:
+                                      clear the flag for the next call. Ignored by the other
+                                      schedules. */
 
 #define SDMM_SCHED_BATCHED 0  /* per iteration one E launch for all cells, then one M
                                  launch for all cells */

@@ -133,7 +133,7 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
                       const void* workspace, size_t workspace_bytes);
 
 typedef void (*EstepFn)(const float*, int64_t, const int64_t*, int, int, int64_t, int64_t, const float*, int, int,
-                        void*);
+                        void*, int32_t*, int);
 
 // E-step kernel for G component lanes, running-sum variant, Jacobian option, adjoint pass
 EstepFn estep_function(int G, int acc, bool jac, bool adj);
@@ -157,8 +157,16 @@ void launch_stepwise(const int64_t* off, const float* smp, int64_t N, const sdmm
                      const sdmm_em_state& st, const sdmm_fit_opts& opts, int32_t* status, const Layout& L, char* ws,
                      hipStream_t s);
 
-// E-step over the items in record slots [slot_lo, slot_hi), one wave per slot
+// E-step over the items in record slots [slot_lo, slot_hi), one wave per slot; with
+// check, one more work group writes the offsets-check control words (the setup kernel's
+// job when it runs)
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
-                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s);
+                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s, bool check = false);
+
+// Host-side record of which workspace holds E-step mirrors of the current parameters of
+// which mixture arrays: a batched fit with SDMM_FLAG_CARRY_MIRRORS writes them in its
+// last M-step and marks the workspace; any other use of the workspace clears the mark.
+bool mirrors_carried(const void* ws, const sdmm_mixtures& mix);
+void mark_mirrors(const void* ws, const sdmm_mixtures& mix, bool carried);
 
 }  // namespace sdmm

@@ -51,6 +51,47 @@ __device__ __forceinline__ int group_or(int v, int GM)
 }
 
 // ---------------------------------------------------------------------------------
+// One work group's check of the offsets, writing the control words: control[0] offsets
+// non-decreasing within [0, N]; control[1] the most items in a cell; control[2] the
+// record-tree levels launched. Run by the setup kernel's last block, or by the E-step
+// launch's last block when the setup kernel does not run (carried mirrors).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void offsets_check_block(const int64_t* __restrict__ off, int64_t N, int C, int ps,
+                                                    int32_t* __restrict__ control, int tree_max)
+{
+    __shared__ int bad, most;
+    if (threadIdx.x == 0) bad = 0, most = 1;
+    __syncthreads();
+    // thread t checks cells t, t + blockDim, ...: consecutive threads read consecutive
+    // offsets, eight cells' loads in flight per thread
+    int b = 0;
+    int64_t m = 1;
+    for (int c0 = (int)threadIdx.x; c0 < C; c0 += 8 * (int)blockDim.x) {
+        int64_t lo[8], hi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int c = c0 + u * (int)blockDim.x;
+            lo[u] = c < C ? off[c] : 0;
+            hi[u] = c < C ? off[c + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            b |= hi[u] < lo[u];
+            m = max(m, (hi[u] - lo[u] + (int64_t(1) << ps) - 1) >> ps);
+        }
+    }
+    if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;
+    if (b) atomicOr(&bad, 1);
+    atomicMax(&most, (int)min(m, (int64_t)INT32_MAX));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        control[0] = bad ? 0 : 1;
+        control[1] = most;
+        control[2] = tree_max;
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // setup: FP32 mirrors with the per-cell shift, status reset, per-cell flags; the last
 // block checks that the offsets are non-decreasing within [0, N]
 // ---------------------------------------------------------------------------------
@@ -60,39 +101,8 @@ __global__ __launch_bounds__(256) void setup_kernel(const int64_t* __restrict__ 
                                                     int32_t* __restrict__ arrive, int32_t* __restrict__ control,
                                                     int n_cell_blocks, int tree_max, int full)
 {
-    // control[0]: offsets valid; control[1]: most items in a cell; control[2]: record-tree
-    // levels launched
     if ((int)blockIdx.x == n_cell_blocks) {
-        __shared__ int bad, most;
-        if (threadIdx.x == 0) bad = 0, most = 1;
-        __syncthreads();
-        // thread t checks cells t, t + 256, ...: consecutive threads read consecutive
-        // offsets, eight cells' loads in flight per thread
-        int b = 0;
-        int64_t m = 1;
-        for (int c0 = (int)threadIdx.x; c0 < C; c0 += 8 * (int)blockDim.x) {
-            int64_t lo[8], hi[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int c = c0 + u * (int)blockDim.x;
-                lo[u] = c < C ? off[c] : 0;
-                hi[u] = c < C ? off[c + 1] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                b |= hi[u] < lo[u];
-                m = max(m, (hi[u] - lo[u] + (int64_t(1) << ps) - 1) >> ps);
-            }
-        }
-        if (threadIdx.x == 0) b |= off[0] < 0 || off[C] > N;
-        if (b) atomicOr(&bad, 1);
-        atomicMax(&most, (int)min(m, (int64_t)INT32_MAX));
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            control[0] = bad ? 0 : 1;
-            control[1] = most;
-            control[2] = tree_max;
-        }
+        offsets_check_block(off, N, C, ps, control, tree_max);
         return;
     }
     // one cell per group of GM lanes (64 / GM cells per wave), lane k % GM = component k:
@@ -184,8 +194,14 @@ template <int G, int ACC, bool JAC, bool ADJ>
 __global__ __launch_bounds__(256, (estep_min_waves<ACC, JAC, ADJ>())) void estep_kernel(const float* __restrict__ smp, int64_t N,
                                                     const int64_t* __restrict__ off, int C, int ps, int64_t slot_lo,
                                                     int64_t slot_hi, const float* __restrict__ mirror, int K, int PS,
-                                                    void* __restrict__ records)
+                                                    void* __restrict__ records, int32_t* __restrict__ control,
+                                                    int check_tree_max)
 {
+    // check_tree_max >= 0: the launch's last work group checks the offsets instead
+    if (check_tree_max >= 0 && blockIdx.x == gridDim.x - 1) {
+        offsets_check_block(off, N, C, ps, control, check_tree_max);
+        return;
+    }
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int c;
     int64_t t, s0, s1, n_items;
@@ -200,8 +216,13 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
                                                           const int64_t* __restrict__ off, int C, int ps,
                                                           int64_t slot_lo, int64_t slot_hi,
                                                           const float* __restrict__ mirror, int K, int PS,
-                                                          void* __restrict__ records)
+                                                          void* __restrict__ records, int32_t* __restrict__ control,
+                                                          int check_tree_max)
 {
+    if (check_tree_max >= 0 && blockIdx.x == gridDim.x - 1) {
+        offsets_check_block(off, N, C, ps, control, check_tree_max);
+        return;
+    }
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int c;
     int64_t t, s0, s1, n_items;
@@ -234,18 +255,19 @@ __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t 
 // carried S2 is loaded by the update itself, early in its chain).
 // ---------------------------------------------------------------------------------
 struct MstepIn {
-    int fl, gok, step;
+    int fl, gok, step, range_ok;
     double sw, s0, mud[3], mux[3];
 };
 
-__device__ __forceinline__ MstepIn load_mstep_in(int c, int64_t g, bool cell_ok, bool act,
-                                                 const int32_t* __restrict__ flags,
+__device__ __forceinline__ MstepIn load_mstep_in(const int64_t* __restrict__ off, int64_t N, int c, int64_t g,
+                                                 bool cell_ok, bool act, const int32_t* __restrict__ flags,
                                                  const int32_t* __restrict__ global_ok, const MixPtrs& mix,
                                                  const StatePtrs& st)
 {
     MstepIn in;
     in.gok = *global_ok;
     in.fl = cell_ok ? flags[c] : 0;
+    in.range_ok = cell_ok ? (off[c] >= 0 && off[c + 1] >= off[c] && off[c + 1] <= N) : 1;
     in.step = cell_ok ? st.step[c] : 0;
     in.sw = cell_ok ? st.sw[c] : 0.0;
     in.s0 = act ? st.s0[g] : 0.0;
@@ -272,6 +294,10 @@ __device__ __forceinline__ int64_t mstep_component(int c, int k, int K)
     return (int64_t)c * K + (k < K ? k : 0);
 }
 
+// M-step mode bits: write the next pass's mirrors; this is the call's first M-step write
+// of the cell's status (no setup kernel reset it), so it assigns instead of or-ing
+constexpr int kMRefresh = 1, kMFirstStatus = 2;
+
 template <int G>
 __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const double (&S)[kStats],
                                              const double (&X)[3], const MstepIn& in,
@@ -295,7 +321,7 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
     int gate = 0, fl = 0;
     if (cell_ok) {
         fl = in.fl;
-        if (negs > 0.0 || notfin || (fl & kFlagBadRange) || !in.gok) gate = kBadInput;
+        if (negs > 0.0 || notfin || !in.range_ok || !in.gok) gate = kBadInput;
         else if (fl & kBadParams) gate = kBadParams;
         else if (Mc < (double)o.min_samples) gate = kSkippedFew;
         else if (!(W > 0.0)) gate = kSkippedZeroW;
@@ -324,15 +350,17 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
         mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
     }
     const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
-    if (refresh_mirror) refresh_cell_mirror(mix, g, run && act, mirror, GM);  // for the next iteration
+    // for the next iteration, or the next call with carried mirrors
+    if (refresh_mirror & kMRefresh) refresh_cell_mirror(mix, g, run && act, mirror, GM);
     if (cell_ok && k == 0) {
         if (accurate) flags[c] = gate ? (fl & ~kFlagStepped) : (fl | kFlagStepped);
+        const int prev = (refresh_mirror & kMFirstStatus) ? 0 : status[c];
         if (gate) {
-            status[c] |= gate;
+            status[c] = prev | gate;
         } else {
             st.sw[c] = hW;
             st.step[c] = j + 1;
-            status[c] |= (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
+            status[c] = prev | (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
         }
     }
 }
@@ -350,8 +378,8 @@ __device__ __forceinline__ void mstep_cell(const int64_t* __restrict__ off, int6
 {
     const int lane = threadIdx.x & 63;
     const bool lane_ok = cell_ok && lane < G;
-    const MstepIn in = load_mstep_in(c, mstep_component<G>(c, lane, o.K), lane_ok, lane_ok && lane < o.K, flags,
-                                     global_ok, mix, st);
+    const MstepIn in = load_mstep_in(off, N, c, mstep_component<G>(c, lane, o.K), lane_ok, lane_ok && lane < o.K,
+                                     flags, global_ok, mix, st);
     double S[kStats], X[3];
     int64_t first = 0, n_items = 0;
     const bool have = cell_ok && cell_items(off, N, c, ps, first, n_items);
@@ -401,7 +429,9 @@ __global__ __launch_bounds__(64 * (64 / G), G <= 16 ? 4 : 1) void mstep_packed_k
     const bool uok = w == 0 && cu < n_cells;
     const int cuc = cell_lo + (cu < n_cells ? cu : 0);
     MstepIn in{};
-    if (w == 0) in = load_mstep_in(cuc, mstep_component<G>(cuc, k, o.K), uok, uok && k < o.K, flags, global_ok, mix, st);
+    if (w == 0)
+        in = load_mstep_in(off, N, cuc, mstep_component<G>(cuc, k, o.K), uok, uok && k < o.K, flags, global_ok, mix,
+                           st);
     {
         const int cl = cb + w;
         const bool ok = cl < n_cells;
@@ -489,7 +519,7 @@ __global__ __launch_bounds__(256) void accurate_mstep_kernel(const int64_t* __re
         }
     }
     const int any_dead = group_or(dead, G), any_chol = group_or(cholfail, G);
-    if (refresh_mirror) refresh_cell_mirror(mix, g, act, mirror, G);
+    if (refresh_mirror & kMRefresh) refresh_cell_mirror(mix, g, act, mirror, G);
     if (have && k == 0) status[c] |= (any_dead ? kDeadComponent : 0) | (any_chol ? kCholFailKeptPrev : 0);
 }
 
@@ -682,13 +712,16 @@ void launch_setup(const int64_t* off, int64_t N, const sdmm_mixtures& mix, int32
 }
 
 void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, int C, int K, const Layout& L,
-                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s)
+                  int64_t slot_lo, int64_t slot_hi, int PS, char* ws, hipStream_t s, bool check)
 {
     const int64_t waves = slot_hi - slot_lo;
-    if (waves <= 0) return;
-    const unsigned blocks = (unsigned)((waves + L.wpb - 1) / L.wpb);
+    if (waves <= 0 && !check) return;
+    // with the offsets check, one more work group (past every work item) runs it
+    const unsigned blocks = (unsigned)((std::max<int64_t>(waves, 0) + L.wpb - 1) / L.wpb) + (check ? 1u : 0u);
     hipLaunchKernelGGL(est, dim3(blocks), dim3(64 * L.wpb), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
-                       reinterpret_cast<const float*>(ws + L.mirror), K, PS, static_cast<void*>(ws + L.records));
+                       reinterpret_cast<const float*>(ws + L.mirror), K, PS, static_cast<void*>(ws + L.records),
+                       reinterpret_cast<int32_t*>(ws + L.global_ok),
+                       check ? tree_levels_launched(N, L.P, L.max_cell) : -1);
 }
 
 typedef void (*TreeFn)(const int64_t*, int64_t, int, int, int, int64_t, int64_t, const int32_t*, void*, int);
@@ -741,7 +774,12 @@ struct FitArgs {
     char* ws;
 };
 
-static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_t>* host_off)
+// carry_in: the workspace already holds mirrors of the current parameters and the cells'
+// parameter flags (written by the previous call's last M-step), so no setup kernel runs:
+// the first E-step launch checks the offsets and the first M-step assigns the statuses.
+// carry_out: the last M-step writes the mirrors for the next call. Batched schedule only.
+static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_t>* host_off, bool carry_in,
+                       bool carry_out)
 {
     const int C = a.mix.n_cells, K = a.opts.K;
     const int G = group_for(K);
@@ -778,16 +816,17 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
         launch_tree(kTreeFit, a.off, a.N, C, K, L, cell, c0, c1, a.ws, s, rec32);
     };
 
-    launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s, false);
+    if (!carry_in) launch_setup(a.off, a.N, a.mix, a.status, a.ws, L, s, false);
     if (a.opts.schedule == SDMM_SCHED_STEPWISE) {
         launch_stepwise(a.off, a.smp, a.N, a.mix, a.st, a.opts, a.status, L, a.ws, s);
         return check(hipGetLastError());
     }
     for (int it = 0; it < a.opts.iters; ++it) {
-        const int refresh = it + 1 < a.opts.iters;
+        const int refresh = (it + 1 < a.opts.iters || carry_out) ? kMRefresh : 0;
+        const int first_status = (carry_in && it == 0) ? kMFirstStatus : 0;
         // with the accurate update the first M-step always writes mirrors (for the second
         // pass) and the accurate M-step those of the next iteration
-        const int refresh1 = accurate ? 1 : refresh;
+        const int refresh1 = (accurate ? kMRefresh : refresh) | first_status;
         if (a.opts.schedule == SDMM_SCHED_PER_CELL) {
             // host_off is empty when the offsets failed the host check: the M-steps then
             // only report BAD_INPUT (the setup kernel's check agrees)
@@ -812,7 +851,8 @@ static int enqueue_fit(const FitArgs& a, hipStream_t s, const std::vector<int64_
         } else if (a.opts.schedule == SDMM_SCHED_BATCHED) {
             {
                 ScopedTimer tm(SDMM_TIMER_ESTEP, s);
-                launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s);
+                launch_estep(est, a.smp, a.N, a.off, C, K, L, 0, (int64_t)C + L.W, L.ps_fit, a.ws, s,
+                             carry_in && it == 0);
             }
             launch_tree(kTreeFit, a.off, a.N, C, K, L, -1, 0, 0, a.ws, s, rec32);
             {
@@ -850,7 +890,8 @@ int validate_fit_args(const int64_t* cell_offsets, const float* samples, int64_t
     if (opts->waves_per_block < 0 || opts->waves_per_block > 4 || opts->waves_per_block == 3 ||
         opts->max_cell_samples < 0)
         return SDMM_EINVAL;
-    if (opts->flags & ~(SDMM_FLAG_ESTEP_JACOBIAN | SDMM_FLAG_PLAIN_FP32 | SDMM_FLAG_FP64_SUMS | SDMM_FLAG_ACCURATE_SIGMA))
+    if (opts->flags & ~(SDMM_FLAG_ESTEP_JACOBIAN | SDMM_FLAG_PLAIN_FP32 | SDMM_FLAG_FP64_SUMS | SDMM_FLAG_ACCURATE_SIGMA |
+                        SDMM_FLAG_CARRY_MIRRORS))
         return SDMM_EINVAL;
 
     const Layout L = layout_for(mix->n_cells, opts->K, n_samples, opts);
@@ -867,6 +908,33 @@ struct GraphKey {
 };
 static std::mutex g_graph_mu;
 static std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// workspace -> the mixture arrays whose current parameters its mirrors hold
+struct CarryTag {
+    const void *w, *md, *mx, *cv;
+    int32_t C, K;
+};
+static std::mutex g_carry_mu;
+static std::map<const void*, CarryTag> g_carry;
+
+bool mirrors_carried(const void* ws, const sdmm_mixtures& mix)
+{
+    std::lock_guard<std::mutex> lk(g_carry_mu);
+    auto it = g_carry.find(ws);
+    if (it == g_carry.end()) return false;
+    const CarryTag& t = it->second;
+    return t.w == mix.weights && t.md == mix.mean_dir && t.mx == mix.mean_pos && t.cv == mix.cov &&
+           t.C == mix.n_cells && t.K == mix.K;
+}
+
+void mark_mirrors(const void* ws, const sdmm_mixtures& mix, bool carried)
+{
+    std::lock_guard<std::mutex> lk(g_carry_mu);
+    if (carried)
+        g_carry[ws] = CarryTag{mix.weights, mix.mean_dir, mix.mean_pos, mix.cov, mix.n_cells, mix.K};
+    else
+        g_carry.erase(ws);
+}
 
 }  // namespace sdmm
 
@@ -900,6 +968,12 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     FitArgs a{cell_offsets, samples, n_samples, *mix, *state, *opts, cell_status,
               reinterpret_cast<char*>(workspace)};
+    // carried mirrors (batched schedule): reuse them when this workspace's last call wrote
+    // them for these mixture arrays, and write them for the next call
+    const bool carry_out = (opts->flags & SDMM_FLAG_CARRY_MIRRORS) && opts->schedule == SDMM_SCHED_BATCHED;
+    const bool carry_in = carry_out && mirrors_carried(workspace, *mix);
+    // the mark is taken down before any enqueue, so a failing call never leaves it up
+    mark_mirrors(workspace, *mix, false);
 
     if (opts->schedule == SDMM_SCHED_PER_CELL) {
         std::vector<int64_t> host_off(mix->n_cells + 1);
@@ -911,21 +985,22 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
         bool ok = host_off[0] >= 0 && host_off[mix->n_cells] <= n_samples;
         for (int c = 0; c < mix->n_cells && ok; ++c) ok = host_off[c + 1] >= host_off[c];
         if (!ok) host_off.clear();
-        return enqueue_fit(a, s, &host_off);
+        return enqueue_fit(a, s, &host_off, false, false);
     }
 
     if (opts->use_graph && s != nullptr) {
         GraphKey key;
-        key.bytes.resize(sizeof(FitArgs) + sizeof(void*));
+        key.bytes.resize(sizeof(FitArgs) + sizeof(void*) + 1);
         memcpy(key.bytes.data(), &a, sizeof(FitArgs));
         memcpy(key.bytes.data() + sizeof(FitArgs), &s, sizeof(void*));
+        key.bytes[sizeof(FitArgs) + sizeof(void*)] = carry_in ? 1 : 0;
         std::lock_guard<std::mutex> lk(g_graph_mu);
         auto it = g_graphs.find(key);
         if (it == g_graphs.end()) {
             hipGraph_t graph;
             rc = check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             if (rc) return rc;
-            rc = enqueue_fit(a, s, nullptr);
+            rc = enqueue_fit(a, s, nullptr, carry_in, carry_out);
             const hipError_t e2 = hipStreamEndCapture(s, &graph);
             if (rc) return rc;
             if ((rc = check(e2))) return rc;
@@ -935,9 +1010,13 @@ extern "C" int sdmm_fit_mixtures(const int64_t* cell_offsets, const float* sampl
             if (rc) return rc;
             it = g_graphs.emplace(key, exec).first;
         }
-        return check(hipGraphLaunch(it->second, s));
+        rc = check(hipGraphLaunch(it->second, s));
+        if (!rc && carry_out) mark_mirrors(workspace, *mix, true);
+        return rc;
     }
-    return enqueue_fit(a, s, nullptr);
+    rc = enqueue_fit(a, s, nullptr, carry_in, carry_out);
+    if (!rc && carry_out) mark_mirrors(workspace, *mix, true);
+    return rc;
 }
 
 namespace sdmm {

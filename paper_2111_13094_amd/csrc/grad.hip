@@ -166,6 +166,7 @@ extern "C" int sdmm_fit_grad(const int64_t* cell_offsets, const float* samples, 
     const int C = mix->n_cells, K = mix->K;
     const Layout L = layout_for(C, K, n_samples, opts);
     char* ws = reinterpret_cast<char*>(workspace);
+    mark_mirrors(workspace, *mix, false);  // the setup below rewrites the workspace
     launch_setup(cell_offsets, n_samples, *mix, cell_status, ws, L, s, true);
     {
         ScopedTimer tm(SDMM_TIMER_GRAD, s);

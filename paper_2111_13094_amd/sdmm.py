@@ -22,7 +22,7 @@ OK, EINVAL, EDEVICE, ENOWORKSPACE = 0, -1, -2, -3
 SKIPPED_FEW, SKIPPED_ZERO_W, BAD_INPUT, DEAD_COMPONENT, CHOL_FAIL_KEPT_PREV, BAD_PARAMS = 1, 2, 4, 8, 16, 32
 ETA_CONSTANT, ETA_PAPER = 0, 1
 PRIOR_ETA_OVER_M, PRIOR_FIXED = 0, 1
-FLAG_ESTEP_JACOBIAN, FLAG_PLAIN_FP32, FLAG_FP64_SUMS, FLAG_ACCURATE_SIGMA = 1, 2, 4, 8
+FLAG_ESTEP_JACOBIAN, FLAG_PLAIN_FP32, FLAG_FP64_SUMS, FLAG_ACCURATE_SIGMA, FLAG_CARRY_MIRRORS = 1, 2, 4, 8, 16
 SCHED_BATCHED, SCHED_PER_CELL, SCHED_FUSED, SCHED_STEPWISE = 0, 1, 2, 3
 COND_TABLE_STRIDE = 32
 
@@ -221,6 +221,8 @@ def fit_mixtures(cell_offsets: torch.Tensor, samples: torch.Tensor, mix: dict, s
     _need(samples, 7 * N, "samples", torch.float32)
     nbytes = workspace_bytes(n_cells, K, N, opts)
     if workspace is None:
+        if opts.flags & FLAG_CARRY_MIRRORS:
+            raise ValueError("FLAG_CARRY_MIRRORS needs a workspace that the caller keeps between calls")
         workspace = _workspace(nbytes, samples.device)
     m = _mixtures(mix, n_cells, K)
     st = _state_ptrs(state, n_cells, K)

@@ -51,6 +51,10 @@ def _apply(opts, cand):
 
 
 def _time_once(cell_offsets, samples, mix, state, opts, workspace, reps):
+    # the copies are fresh arrays every time: carried mirrors would never apply, so every
+    # candidate is timed with its setup kernel
+    opts = type(opts).from_buffer_copy(opts)
+    opts.flags &= ~sdmm.FLAG_CARRY_MIRRORS
     m = {k: v.clone() for k, v in mix.items()}
     st = {k: v.clone() for k, v in state.items()}
     status = torch.empty(cell_offsets.numel() - 1, dtype=torch.int32, device=samples.device)

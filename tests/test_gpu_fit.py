@@ -523,7 +523,7 @@ def test_accurate_sigma_argument_checks(dev, orc):
             assert np.array_equal(v, mix0[k])
     gm, gst = to_torch(mix0), state_to_torch(orc.new_state(1, 16))
     with pytest.raises(RuntimeError, match="invalid argument"):
-        _gpu_fit(dev, b, gm, gst, flags=16)
+        _gpu_fit(dev, b, gm, gst, flags=32)  # no such flag
 
 
 # --- stepwise (per-sample) EM ---------------------------------------------------------
