@@ -241,6 +241,7 @@ __device__ __forceinline__ double log_det5(const double* L)
     const double p = L[0] * L[2] * L[5] * L[9] * L[14];
     if (p > 0x1p-1000 && p < 0x1p1000) return log(p);
     double s = 0.0;
+#pragma unroll
     for (int d = 0; d < 5; ++d) s += log(L[tri(d, d)]);
     return s;
 }
@@ -289,6 +290,27 @@ __device__ __forceinline__ void tri_inv64(const double* L, double* Li, const dou
             Li[tri(d, e)] = -s * Li[tri(d, d)];
         }
     }
+}
+
+// The EM part of a component's FP32 E-step mirror (floats 0-27: frame R, mu_x, the
+// inverse factor scaled by sqrt(log2(e) / 2), and c2 = (log pi - log det L -
+// (5/2) log 2 pi) log2(e), also returned in FP64) from its weight, frame, positional mean
+// and packed covariance factor L with the reciprocals Ld of its diagonal; Li receives
+// L^-1 (unscaled).
+__device__ __forceinline__ void mirror_core(double pi, const double* R, const double* mux, const double* L,
+                                            const double* Ld, float* out, double& c2, double* Li)
+{
+    tri_inv64<5>(L, Li, Ld);
+    const double logdet = log_det5(L);
+    const double scale = sqrt(0.5 * kLog2e);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = (float)R[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[9 + d] = (float)mux[d];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) out[12 + i] = (float)(Li[i] * scale);
+    c2 = (log(pi) - logdet - 2.5 * kLn2Pi) * kLog2e;
+    out[27] = (float)c2;
 }
 
 }  // namespace sdmm

@@ -172,39 +172,22 @@ __device__ __forceinline__ void frame_twist64(const double mu[3], const double R
 // and the quadratic form in FP64 (its gradients are small differences near stationarity,
 // and for strongly correlated components the quadratic form cancels). The EM passes read
 // only the first kMirrorLite floats, which is all a lite mirror (FULL false) writes.
-// Returns false and writes an inert mirror (identity frame and factor) when the component
-// is unusable.
 // ---------------------------------------------------------------------------------
+
+// The mirror of a component from its weight, frame R (rows t1, t2, mu), positional mean and
+// packed covariance factor L with the reciprocals Ld of its diagonal (mud, the directional
+// mean, is read only with FULL, for the twist rates).
 template <bool FULL>
-__device__ inline bool write_mirror(double pi, const double* mud, const double* mux, const double* cov,
-                                    float* out, double& c2)
+__device__ __forceinline__ void mirror_from_factor(double pi, const double* mud, const double* R, const double* mux,
+                                                   const double* L, const double* Ld, float* out, double& c2)
 {
-    bool ok = isfinite(pi) && pi >= 0.0;
-    for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[d]) && isfinite(mux[d]);
-    double L[15], Li[15], Ld[5];
-    ok = ok && chol64<5>(cov, L, Ld);
-    if (!ok) {
-        for (int i = 0; i < (FULL ? kMirror : kMirrorLite); ++i) out[i] = 0.0f;
-        out[0] = out[4] = out[8] = 1.0f;
-        const int diag[5] = {0, 2, 5, 9, 14};
-        for (int d = 0; d < 5; ++d) out[12 + diag[d]] = 1.0f;
-        c2 = -INFINITY;
-        return false;
-    }
-    double R[9];
-    frame64(mud, R);
-    tri_inv64<5>(L, Li, Ld);
-    const double logdet = log_det5(L);
-    const double scale = sqrt(0.5 * kLog2e);
-    for (int i = 0; i < 9; ++i) out[i] = (float)R[i];
-    for (int d = 0; d < 3; ++d) out[9 + d] = (float)mux[d];
-    for (int i = 0; i < 15; ++i) out[12 + i] = (float)(Li[i] * scale);
-    c2 = (log(pi) - logdet - 2.5 * kLn2Pi) * kLog2e;
-    out[27] = (float)c2;
+    double Li[15];
+    mirror_core(pi, R, mux, L, Ld, out, c2, Li);
     if constexpr (!FULL) {
         out[28] = out[29] = out[30] = out[31] = 0.0f;
-        return true;
+        return;
     }
+    const double scale = sqrt(0.5 * kLog2e);
     double phi[2];
     frame_twist64(mud, R, phi);
     out[28] = (float)phi[0];
@@ -216,6 +199,29 @@ __device__ inline bool write_mirror(double pi, const double* mud, const double* 
     out[60] = (float)(phi[0] - (double)out[28]);
     out[61] = (float)(phi[1] - (double)out[29]);
     out[62] = out[63] = 0.0f;
+}
+
+// The mirror of a component from its parameters; returns false and writes an inert mirror
+// (identity frame and factor) when the component is unusable.
+template <bool FULL>
+__device__ inline bool write_mirror(double pi, const double* mud, const double* mux, const double* cov,
+                                    float* out, double& c2)
+{
+    bool ok = isfinite(pi) && pi >= 0.0;
+    for (int d = 0; d < 3; ++d) ok = ok && isfinite(mud[d]) && isfinite(mux[d]);
+    double L[15], Ld[5];
+    ok = ok && chol64<5>(cov, L, Ld);
+    if (!ok) {
+        for (int i = 0; i < (FULL ? kMirror : kMirrorLite); ++i) out[i] = 0.0f;
+        out[0] = out[4] = out[8] = 1.0f;
+        const int diag[5] = {0, 2, 5, 9, 14};
+        for (int d = 0; d < 5; ++d) out[12 + diag[d]] = 1.0f;
+        c2 = -INFINITY;
+        return false;
+    }
+    double R[9];
+    frame64(mud, R);
+    mirror_from_factor<FULL>(pi, mud, R, mux, L, Ld, out, c2);
     return true;
 }
 

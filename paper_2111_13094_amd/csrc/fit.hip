@@ -231,18 +231,21 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------------
-// Lite mirror of component g for the next iteration (the EM passes read no more),
+// Lite mirror of component g for the next iteration (the EM passes read no more), written in
+// place; with have, the update has already written it (from its own factorisation and
+// frame, the values the stored parameters give again) and c2 is its unshifted constant,
+// else it is built from the parameters.
 // written in place (keeps the M-step's registers free), with the cell's shift from the
 // group of GM lanes. `upd`: this lane's component was updated; the others keep their
 // mirrors.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ void refresh_cell_mirror(const MixPtrs& mix, int64_t g, bool upd, float* __restrict__ mirror,
-                                                    int GM)
+                                                    int GM, double c2 = -INFINITY, bool have = false)
 {
-    double c2 = -INFINITY;
     bool okm = true;
     float* out = mirror + g * kMirror;
-    if (upd) okm = write_mirror<false>(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    if (upd && !have) okm = write_mirror<false>(mix.pi[g], mix.mud + 3 * g, mix.mux + 3 * g, mix.cov + 15 * g, out, c2);
+    if (!upd) c2 = -INFINITY;
     const double cmax = group_max_d((upd && okm) ? c2 : -INFINITY, GM);
     if (upd) set_mirror_shift<false>(out, c2, (double)(isfinite(cmax) ? (float)(cmax + 1.0) : 0.0f), okm);
 }
@@ -343,15 +346,20 @@ __device__ __forceinline__ void mstep_update(int c, int k, bool cell_ok, const d
     const double sum0 = group_sum_d(bar0, GM);
 
     int dead = 0, cholfail = 0;
+    // the next mirror, written by the update when it replaces the covariance
+    double c2m = -INFINITY;
+    bool have_m = false;
     if (run && act) {
+        const double pi_new = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
         // with the accurate update the second pass forms the covariance
         component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, !accurate, in.mud, in.mux, mix.mud + 3 * g,
-                             mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail);
-        mix.pi[g] = (beta * o.prior_q + bar0) / ((double)K * beta * o.prior_q + sum0);
+                             mix.mux + 3 * g, mix.cov + 15 * g, st.s0 + g, st.s2 + 15 * g, dead, cholfail,
+                             (refresh_mirror & kMRefresh) ? mirror + g * kMirror : nullptr, pi_new, c2m, have_m);
+        mix.pi[g] = pi_new;
     }
     const int any_dead = group_or(dead, GM), any_chol = group_or(cholfail, GM);
     // for the next iteration, or the next call with carried mirrors
-    if (refresh_mirror & kMRefresh) refresh_cell_mirror(mix, g, run && act, mirror, GM);
+    if (refresh_mirror & kMRefresh) refresh_cell_mirror(mix, g, run && act, mirror, GM, c2m, have_m);
     if (cell_ok && k == 0) {
         if (accurate) flags[c] = gate ? (fl & ~kFlagStepped) : (fl | kFlagStepped);
         const int prev = (refresh_mirror & kMFirstStatus) ? 0 : status[c];

@@ -26,12 +26,18 @@ __device__ __forceinline__ double rm_eta(const DevOpts& o, int j)
 // hS0 and T C T^T. The weight is left to the caller (it needs the cell's sum of bar0).
 // When fac is given, the Cholesky factor of a replacing covariance (15 packed values) and
 // the reciprocals of its diagonal (5) are written there too.
+// With mir given, when the covariance is replaced the update also writes the EM part of the
+// component's next E-step mirror there (floats 0-31, see mirror_core) from its own
+// factorisation and frame, with the new weight pi_mir, returns its unshifted constant in
+// c2_mir and sets mir_ok.
 __device__ inline void component_map_update(double hS0, const double* hS1, const double* hS2, double hW,
                                             double beta, double bar0, const DevOpts& o, bool cov_update,
                                             const double mu_in[3], const double mux_in[3], double* mud,
                                             double* mux, double* cov, double* s0, double* s2, int& dead,
-                                            int& cholfail, double* fac = nullptr)
+                                            int& cholfail, float* mir, double pi_mir, double& c2_mir, bool& mir_ok,
+                                            double* fac = nullptr)
 {
+    mir_ok = false;
     if (!(bar0 > o.dead_threshold)) {
         dead = 1;
         *s0 = hS0;
@@ -48,9 +54,11 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
     exp_map64(Ro, m[0], m[1], tr, mun);
     const double inn = 1.0 / sqrt(mun[0] * mun[0] + mun[1] * mun[1] + mun[2] * mun[2]);
     for (int i = 0; i < 3; ++i) mun[i] *= inn;
+    double muxn[3];
     for (int i = 0; i < 3; ++i) {
         mud[i] = mun[i];
-        mux[i] = mux_in[i] + m[2 + i];
+        muxn[i] = mux_in[i] + m[2 + i];
+        mux[i] = muxn[i];
     }
     *s0 = hS0;
     if (!cov_update) return;
@@ -98,9 +106,28 @@ __device__ inline void component_map_update(double hS0, const double* hS1, const
             for (int q = 0; q < 15; ++q) fac[q] = Lt[q];
             for (int d = 0; d < 5; ++d) fac[15 + d] = Lti[d];
         }
+        if (mir) {
+            double Li[15];
+            mirror_core(pi_mir, Rn, muxn, Lt, Lti, mir, c2_mir, Li);
+            mir[28] = mir[29] = mir[30] = mir[31] = 0.0f;
+            mir_ok = true;
+        }
     } else {
         cholfail = 1;
     }
+}
+
+// the same update without the mirror
+__device__ __forceinline__ void component_map_update(double hS0, const double* hS1, const double* hS2, double hW,
+                                                     double beta, double bar0, const DevOpts& o, bool cov_update,
+                                                     const double mu_in[3], const double mux_in[3], double* mud,
+                                                     double* mux, double* cov, double* s0, double* s2, int& dead,
+                                                     int& cholfail, double* fac = nullptr)
+{
+    double c2;
+    bool ok;
+    component_map_update(hS0, hS1, hS2, hW, beta, bar0, o, cov_update, mu_in, mux_in, mud, mux, cov, s0, s2, dead,
+                         cholfail, nullptr, 0.0, c2, ok, fac);
 }
 
 }  // namespace sdmm
