@@ -180,7 +180,29 @@ __device__ __forceinline__ bool wave_item(int64_t w, const int64_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------------
-// E-step: one wave per work item (see wave_item)
+// XCD-aware work map of an E-step launch: work groups go to the eight XCDs in turn (group
+// b to XCD b % 8), so the launch cuts its n_slots record slots into eight contiguous
+// chunks and the groups of XCD x serve chunk x in order. The items of a cell (consecutive
+// slots) then run on one XCD and share its L2: the cell's mirrors come from HBM once per
+// cell instead of once per item. Returns the wave's slot offset, or -1 past its chunk.
+// ---------------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int64_t xcd_chunk(int64_t n_slots)
+{
+    return (n_slots + kXcds - 1) / kXcds;
+}
+
+__device__ __forceinline__ int64_t xcd_slot(int64_t group, int wpb, int wave, int64_t n_slots)
+{
+    const int64_t per = xcd_chunk(n_slots);
+    const int64_t i = (group / kXcds) * wpb + wave;  // position in the chunk
+    const int64_t w = (group % kXcds) * per + i;
+    return (i < per && w < n_slots) ? w : -1;
+}
+
+// ---------------------------------------------------------------------------------
+// E-step: one wave per work item (see wave_item), slots by the XCD-aware map
 // ---------------------------------------------------------------------------------
 // waves per SIMD the E-step needs: the plain-sum EM pass fits five (96 registers), which
 // hides more of each item's start-up latency (cell search, mirror and first loads)
@@ -202,10 +224,11 @@ __global__ __launch_bounds__(256, (estep_min_waves<ACC, JAC, ADJ>())) void estep
         offsets_check_block(off, N, C, ps, control, check_tree_max);
         return;
     }
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = xcd_slot(blockIdx.x, blockDim.x >> 6, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                               slot_hi - slot_lo);
     int c;
     int64_t t, s0, s1, n_items;
-    if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
+    if (w < 0 || !wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
     estep_segment<G, ACC, JAC, ADJ>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K,
                                     static_cast<RecordT<ACC, ADJ>*>(records) + t * PS);
 }
@@ -223,10 +246,11 @@ __global__ __launch_bounds__(256) void estep_adj64_kernel(const float* __restric
         offsets_check_block(off, N, C, ps, control, check_tree_max);
         return;
     }
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = xcd_slot(blockIdx.x, blockDim.x >> 6, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                               slot_hi - slot_lo);
     int c;
     int64_t t, s0, s1, n_items;
-    if (!wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
+    if (w < 0 || !wave_item(w, off, N, C, ps, slot_lo, slot_hi, c, t, s0, s1, n_items)) return;
     estep_segment_adj64<G>(smp, N, s0, s1, mirror + (int64_t)c * K * kMirror, K, static_cast<double*>(records) + t * PS);
 }
 
@@ -724,8 +748,11 @@ void launch_estep(EstepFn est, const float* smp, int64_t N, const int64_t* off, 
 {
     const int64_t waves = slot_hi - slot_lo;
     if (waves <= 0 && !check) return;
-    // with the offsets check, one more work group (past every work item) runs it
-    const unsigned blocks = (unsigned)((std::max<int64_t>(waves, 0) + L.wpb - 1) / L.wpb) + (check ? 1u : 0u);
+    // the XCD-aware map (xcd_slot): eight chunks of xcd_chunk(waves) slots, each served by
+    // its XCD's groups; with the offsets check, one more work group (past every work item)
+    // runs it
+    const int64_t per = xcd_chunk(std::max<int64_t>(waves, 0));
+    const unsigned blocks = (unsigned)(kXcds * ((per + L.wpb - 1) / L.wpb)) + (check ? 1u : 0u);
     hipLaunchKernelGGL(est, dim3(blocks), dim3(64 * L.wpb), 0, s, smp, N, off, C, L.ps, slot_lo, slot_hi,
                        reinterpret_cast<const float*>(ws + L.mirror), K, PS, static_cast<void*>(ws + L.records),
                        reinterpret_cast<int32_t*>(ws + L.global_ok),
