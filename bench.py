@@ -390,7 +390,7 @@ def bench_accurate(args, torch):
                    "n_cells": C, "K": K, "samples_per_batch": int(np.mean(N)), "batches": n_batches},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "estep_kernel<16,TwoSum,false,false>", "kernel_ms": ms["estep_kernel_avg"],
+                     "kernel": _estep_kernel_name(256), "kernel_ms": ms["estep_kernel_avg"],
                      "flops_per_launch": FLOPS_PER_PAIR * per_launch},
         "kernel_ms": ms,
         "first_order": {"value": fpairs / fwall, "unit": "updates/s", "ms_per_step": fwall * 1e3 / args.steps,
@@ -738,7 +738,7 @@ def bench_grad(args, torch):
                        "n_cells": C, "K": K, "samples": int(N), "cells_with_gradient": int(ok.sum())},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                         "kernel": "estep_kernel<16,TwoSum,false,true>", "kernel_ms": k_ms,
+                         "kernel": "estep_kernel<16, 0, false, true>", "kernel_ms": k_ms,
                          "flops_per_launch": fl, "note": "140 flop/pair of the statistics pass; the adjoint "
                                                          "terms are extra work not counted"},
             "fp64_mode_ms": k64_ms,
