@@ -51,9 +51,14 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _kernel_source_hash():
+    """Hash of the code (comment lines and trailing comments dropped) of the sources that
+    build the E-step kernel, so that a counter record names the kernel it was taken on."""
     h = hashlib.sha256()
     for f in ("estep.hpp", "device_math.hpp", "fit.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2111_13094_amd", "csrc", f), "rb").read())
+        for line in open(os.path.join(ROOT, "paper_2111_13094_amd", "csrc", f)):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

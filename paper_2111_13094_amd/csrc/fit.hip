@@ -5,17 +5,19 @@
 // (Sec. 3.2, 3.4), Robbins-Monro averaging and MAP updates (Sec. 4.3), one independent
 // mixture per spatial cell updated only with at least min_samples vertices (Sec. 4.2).
 //
-// Kernels per call:  setup (FP32 mirrors, status reset, offset checks), then per
-// iteration: estep (persistent waves) -> mstep (grouped cells).
+// Kernels per call: setup (FP32 mirrors, status reset, offset checks; skipped when the
+// previous call carried the mirrors), then per iteration: estep (one wave per work item)
+// -> mstep (grouped cells).
 //
 // E-step work split: each cell's samples are cut, from the cell's first sample, into
 // items of at most P = 2^ps samples; item j of cell c gets the record slot
 // c + off[c]/P + j. For non-decreasing offsets these slots increase strictly from cell to
 // cell and stay below C + ceil(N/P), so a wave recovers its cell from its slot by a
 // 64-ary search over c + off[c]/P. The wave streams its item with one (sample,
-// component) pair per lane (64/G sample slots x G component lanes) and writes one FP64
-// record; the M-step sums a cell's records in item order. A cell's results depend only
-// on its own samples and P, and items of at most P samples keep the waves balanced.
+// component) pair per lane (64/G sample slots x G component lanes) and writes one
+// record (FP32, or FP64 for the FP64-sum pass); the M-step sums a cell's records in item
+// order. A cell's results depend only on its own samples and P, and items of at most P
+// samples keep the waves balanced.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
