@@ -558,7 +558,7 @@ def bench_product(args, torch):
                        "bsdf_fit_status": int(bst.cpu().numpy()[0])},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                         "kernel": "product_sample_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl}}
+                         "kernel": "product_sample_lanes_kernel<16>", "kernel_ms": k_ms, "flops_per_launch": fl}}
 
 
 def bench_tree(args, torch):

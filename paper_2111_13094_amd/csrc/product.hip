@@ -7,10 +7,9 @@
 //   1. both mixtures conditioned on their inputs (radiance: the position; BSDF: its three
 //      inputs), weights by a DPP log-sum-exp;
 //   2. the two BSDF components of largest weight (lowest index on ties) by two group
-//      maxima; every BSDF lane rotates its own component to world (mean F mu_b, offset and
-//      covariance carried into the frame of F mu_b by the in-plane rotation between the
-//      frames) and forms its centre exp(m) and exp-map Jacobian; the two kept ones are
-//      broadcast;
+//      maxima; every BSDF lane rotates its own component to world (frame rows F t1, F t2,
+//      F mu_b, in which offset and covariance keep their local values) and forms its
+//      centre exp(m) and exp-map Jacobian; the two kept ones are broadcast;
 //   3. lane k forms its two pairs: the BSDF component moved into the tangent space of
 //      mu_k (centre a = log_mu_k(centre), covariance J S J^T with J the log-map Jacobian
 //      at the centre times the exp-map Jacobian), and the product of the two 2-D
@@ -18,6 +17,8 @@
 //   4. draws: pair by a group prefix sum over lanes (pair order 2k + j), Box-Muller,
 //      nu = c + L_C z, cut-locus discard, exp map; the pdf of the normalised product
 //      mixture at the drawn direction (one log map per lane, two 2-D quadratic forms).
+#include <algorithm>
+
 #include "common.hpp"
 #include "query_common.hpp"
 #include "timing.hpp"
@@ -28,26 +29,9 @@ constexpr float kLog2eF = 1.4426950408889634f;
 constexpr float kLog2TwoPi = 2.6514961294723187f;  // log2(2 pi)
 constexpr float kHalfLog2e = 0.72134752044448170f;
 
-// FP32 frame of a unit vector, rows (t1, t2, mu): the branchless basis the mixtures use
-__device__ __forceinline__ void frame_f32(float mx, float my, float mz, float R[9])
-{
-    const float sg = copysignf(1.0f, mz);
-    const float a = -1.0f / (sg + mz);
-    const float b = mx * my * a;
-    R[0] = fmaf(sg * mx * mx, a, 1.0f);
-    R[1] = sg * b;
-    R[2] = -sg * mx;
-    R[3] = b;
-    R[4] = fmaf(my * my, a, sg);
-    R[5] = -my;
-    R[6] = mx;
-    R[7] = my;
-    R[8] = mz;
-}
-
 // A BSDF component rotated to world and prepared for the pairs: its offset and
-// covariance in the frame of the rotated mean, its centre exp(m) and the world-space
-// exp-map Jacobian D = d exp / d nu at m (3 x 2), and its log2 weight.
+// covariance in the rotated frame, its centre exp(m) and the world-space exp-map
+// Jacobian D = d exp / d nu at m (3 x 2), and its log2 weight.
 struct BsdfWorld {
     float m0, m1, s00, s01, s11;
     float cx, cy, cz;
@@ -56,35 +40,25 @@ struct BsdfWorld {
 };
 
 // rotates the component of table row TB (conditioned offset bm0, bm1) by F (row-major,
-// world = F local) and prepares it
+// world = F local) and prepares it. The rotated frame rows F t1, F t2, F mu are an
+// orthonormal frame about the rotated mean in which the offset and the covariance keep
+// their local values, so the component needs no frame of its own.
 __device__ __forceinline__ BsdfWorld rotate_bsdf(const float* TB, float bm0, float bm1, const float* F, float lw)
 {
     BsdfWorld o;
-    const float mw0 = fmaf(F[0], TB[6], fmaf(F[1], TB[7], F[2] * TB[8]));
-    const float mw1 = fmaf(F[3], TB[6], fmaf(F[4], TB[7], F[5] * TB[8]));
-    const float mw2 = fmaf(F[6], TB[6], fmaf(F[7], TB[7], F[8] * TB[8]));
     float Rw[9];
-    frame_f32(mw0, mw1, mw2, Rw);
-    // Q_ij = t_i(F mu) . F t_j(mu)
-    float Q[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const float f0 = fmaf(F[0], TB[3 * j], fmaf(F[1], TB[3 * j + 1], F[2] * TB[3 * j + 2]));
-        const float f1 = fmaf(F[3], TB[3 * j], fmaf(F[4], TB[3 * j + 1], F[5] * TB[3 * j + 2]));
-        const float f2 = fmaf(F[6], TB[3 * j], fmaf(F[7], TB[3 * j + 1], F[8] * TB[3 * j + 2]));
-        Q[j] = fmaf(Rw[0], f0, fmaf(Rw[1], f1, Rw[2] * f2));
-        Q[2 + j] = fmaf(Rw[3], f0, fmaf(Rw[4], f1, Rw[5] * f2));
-    }
-    o.m0 = fmaf(Q[0], bm0, Q[1] * bm1);
-    o.m1 = fmaf(Q[2], bm0, Q[3] * bm1);
-    // S = L' L'^T, then Q S Q^T
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            Rw[3 * r + i] = fmaf(F[3 * i], TB[3 * r], fmaf(F[3 * i + 1], TB[3 * r + 1], F[3 * i + 2] * TB[3 * r + 2]));
+    o.m0 = bm0;
+    o.m1 = bm1;
+    // S = L' L'^T
     const float l0 = TB[24], l1 = TB[25], l2 = TB[26];
-    const float a00 = l0 * l0, a01 = l0 * l1, a11 = fmaf(l1, l1, l2 * l2);
-    const float t00 = fmaf(Q[0], a00, Q[1] * a01), t01 = fmaf(Q[0], a01, Q[1] * a11);
-    const float t10 = fmaf(Q[2], a00, Q[3] * a01), t11 = fmaf(Q[2], a01, Q[3] * a11);
-    o.s00 = fmaf(t00, Q[0], t01 * Q[1]);
-    o.s01 = fmaf(t10, Q[0], t11 * Q[1]);
-    o.s11 = fmaf(t10, Q[2], t11 * Q[3]);
+    o.s00 = l0 * l0;
+    o.s01 = l0 * l1;
+    o.s11 = fmaf(l1, l1, l2 * l2);
     // centre and exp-map Jacobian at m: w = Rw^T v, v = (nu sinc r, cos r),
     // dv/dnu = [[s + n0^2 c, n0 n1 c], [n0 n1 c, s + n1^2 c], [-n0 s, -n1 s]]
     const float r2 = fmaf(o.m0, o.m0, o.m1 * o.m1);
@@ -421,6 +395,218 @@ __global__ __launch_bounds__(256) void product_sample_kernel(
     }
 }
 
+// The same set-up, draws and pdf as product_sample_kernel in three wave-local phases over
+// QB = S * nqr queries (nqr <= 2 rounds of S queries, QB * ns <= 64 draws), as in the
+// fused query kernel:
+//   A. set-up, lane = (query slot, component), per round (steps 1-3): the lane's two
+//      pairs (mean, scaled inverse factor, normaliser, probability) and the pair CDF
+//      into LDS, with each query's cell, last component of positive weight and its pair;
+//   B. the draws, one per lane: uniforms, the component by the first CDF entry above u0
+//      and the pair within it, then the candidate from the pair's mean and the factor
+//      taken back from its inverse, in the frame of the component's table row;
+//   C. the pdf, lane = (query slot, component) again: every draw of the query over the
+//      lane's two pairs, four at a time.
+// Phase B runs on QB * ns lanes where product_sample_kernel draws on ns of each query's G
+// lanes. Pair choices are the same as there; a candidate differs by the rounding of the
+// recovered factor.
+constexpr int kProdWpb = 2;   // waves per work group (LDS: about 8.6 KB per wave)
+constexpr int kProdRounds = 2;
+constexpr int kPairF = 7;     // per pair: c0, c1, i0, i1, i2, nrm, probability
+
+template <int G>
+__global__ __launch_bounds__(64 * kProdWpb) void product_sample_lanes_kernel(
+    const float* __restrict__ table, int C, int K, const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
+    const float* __restrict__ btable, int CB, int Kb, const float* __restrict__ bpar,
+    const int32_t* __restrict__ bcell, const float* __restrict__ frames, int64_t nq, int ns, int nqr,
+    const float* __restrict__ uniforms, uint64_t seed, float* __restrict__ dirs_out, float* __restrict__ pdf_out,
+    uint8_t* __restrict__ valid_out, int32_t* __restrict__ pair_out)
+{
+    constexpr int S = 64 / G, QBMAX = kProdRounds * S, WPB = kProdWpb;
+    // per wave: the pair CDF of its queries (-inf on lanes no draw may pick), each lane's
+    // two pairs by field ([round][field][lane]), each query's cell (-1: none), last
+    // component of positive weight and the pair used past it, and the draws' directions
+    // with their validity in .w
+    __shared__ __align__(16) float cdf_s[WPB][QBMAX][G];
+    __shared__ float pd_s[WPB][kProdRounds][2 * kPairF][64];
+    __shared__ int last_s[WPB][QBMAX], jl_s[WPB][QBMAX], cell_s[WPB][QBMAX];
+    __shared__ float4 w_s[WPB][64];
+    const int lane = threadIdx.x & 63, comp = lane % G, slot = lane / G, base = lane - comp;
+    const int wv = threadIdx.x >> 6;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = nq * ns;
+    const int QB = S * nqr;
+    for (int64_t qb = wave * QB; qb < nq; qb += nwaves * QB) {
+        // A: set-up
+        for (int r = 0; r < nqr; ++r) {
+            const int qi = r * S + slot;
+            const int64_t q = qb + qi;
+            const bool inq = q < nq;
+            const int64_t qq = inq ? q : 0;
+            // channel strides (and below the generator's round keys) are formed where they
+            // are used, by scalar instructions, instead of being held across the loop in
+            // scalar registers that spill
+            int64_t nqo = nq;
+            asm volatile("" : "+s"(nqo));
+            float F[9];
+            load_frame(frames, nqo, qq, F);
+            const int qc = qcell[qq], bc = bcell[qq];
+            ProductQuery Qy;
+            product_setup<G>(table, C, K, btable, CB, Kb, qc, bc, inq, qpos[qq], qpos[nqo + qq], qpos[2 * nqo + qq],
+                             bpar[qq], bpar[nqo + qq], bpar[2 * nqo + qq], F, Qy);
+            const float s = Qy.P0 + Qy.P1;
+            const float cdf = group_inclusive_scan<G>(s);
+            const bool cand = comp < K && Qy.any;
+            const uint64_t pos = __ballot(cand && s > 0.0f) & gmask;
+            const int last_pos = pos ? 63 - __builtin_clzll(pos) - base : -1;
+            const int j_last = __shfl(Qy.P1 > 0.0f ? 1 : 0, base + (last_pos < 0 ? 0 : last_pos));
+            cdf_s[wv][qi][comp] = cand ? cdf : -INFINITY;
+            float* pd = &pd_s[wv][r][0][lane];
+            pd[0 * 64] = Qy.p0.c0;
+            pd[1 * 64] = Qy.p0.c1;
+            pd[2 * 64] = Qy.p0.i0;
+            pd[3 * 64] = Qy.p0.i1;
+            pd[4 * 64] = Qy.p0.i2;
+            pd[5 * 64] = Qy.p0.nrm;
+            pd[6 * 64] = Qy.P0;
+            pd[7 * 64] = Qy.p1.c0;
+            pd[8 * 64] = Qy.p1.c1;
+            pd[9 * 64] = Qy.p1.i0;
+            pd[10 * 64] = Qy.p1.i1;
+            pd[11 * 64] = Qy.p1.i2;
+            pd[12 * 64] = Qy.p1.nrm;
+            pd[13 * 64] = Qy.P1;
+            if (comp == 0) {
+                last_s[wv][qi] = last_pos;
+                jl_s[wv][qi] = j_last;
+                cell_s[wv][qi] = (inq && qc >= 0 && qc < C && bc >= 0 && bc < CB) ? qc : -1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // this wave's LDS writes are done
+        // B: one draw per lane
+        {
+            const int qi = lane / ns, t = lane % ns;
+            const int64_t q = qb + qi;
+            const bool act = qi < QB && q < nq;
+            const int64_t d = act ? q * ns + t : 0;
+            uint64_t key = seed;
+            int64_t ndo = nd;
+            asm volatile("" : "+s"(key), "+s"(ndo));
+            float u0, u1, u2;
+            draw_uniforms(uniforms, ndo, d, key, u0, u1, u2);
+            const int qis = act ? qi : 0;
+            // the first component whose CDF value exceeds u0, else the last of positive weight
+            int first = -1;
+            const float4* crow = reinterpret_cast<const float4*>(&cdf_s[wv][qis][0]);
+#pragma unroll
+            for (int c4 = G / 4 - 1; c4 >= 0; --c4) {
+                const float4 v = crow[c4];
+                first = u0 < v.w ? 4 * c4 + 3 : first;
+                first = u0 < v.z ? 4 * c4 + 2 : first;
+                first = u0 < v.y ? 4 * c4 + 1 : first;
+                first = u0 < v.x ? 4 * c4 : first;
+            }
+            const bool hit = first >= 0;
+            const int sel = hit ? first : last_s[wv][qis];
+            const int sk = sel < 0 ? 0 : sel;
+            const float* pd = &pd_s[wv][qis / S][0][(qis % S) * G + sk];
+            // the pair within the component: the first unless u0 lies past its share of the CDF
+            const float P0 = pd[6 * 64], P1 = pd[13 * 64];
+            const float cdfv = cdf_s[wv][qis][sk];
+            const int jh = (u0 < (cdfv - (P0 + P1)) + P0 && P0 > 0.0f) || !(P1 > 0.0f) ? 0 : 1;
+            const int j = hit ? jh : jl_s[wv][qis];
+            const float* pj = pd + (j ? kPairF * 64 : 0);
+            const float c0 = pj[0], c1 = pj[64], i0 = pj[2 * 64], i1 = pj[3 * 64], i2 = pj[4 * 64];
+            // the factor of C from its scaled inverse (i = L^-1 sqrt(log2(e) / 2))
+            constexpr float kap = 0.84932180028801904f, ikap = 1.1774100225154747f;
+            const float L0 = kap * __builtin_amdgcn_rcpf(i0), L2 = kap * __builtin_amdgcn_rcpf(i2);
+            const float L1 = -i1 * L0 * L2 * ikap;
+            const int qc = cell_s[wv][qis];
+            const float4* row = reinterpret_cast<const float4*>(table_row(table, qc, K, sk, qc >= 0));
+            float R[12];
+#pragma unroll
+            for (int c4 = 0; c4 < 3; ++c4) {
+                const float4 v = row[(int64_t)c4 * K];
+                R[4 * c4] = v.x;
+                R[4 * c4 + 1] = v.y;
+                R[4 * c4 + 2] = v.z;
+                R[4 * c4 + 3] = v.w;
+            }
+            float w[3];
+            const int ok = draw_candidate(R, L0, L1, L2, c0, c1, u1, u2, w);
+            const int valid = act && sel >= 0 && ok;
+            w_s[wv][lane] = make_float4(w[0], w[1], w[2], valid ? 1.0f : 0.0f);
+            if (act) {  // the pass's draws are contiguous: d = qb * ns + lane
+                dirs_out[d] = valid ? w[0] : 0.0f;
+                dirs_out[ndo + d] = valid ? w[1] : 0.0f;
+                dirs_out[2 * ndo + d] = valid ? w[2] : 0.0f;
+                valid_out[d] = (uint8_t)valid;
+                if (pair_out) pair_out[d] = sel >= 0 ? 2 * sel + j : -1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        // C: the pdf of every draw over the lane's two pairs, outputs
+        for (int r = 0; r < nqr; ++r) {
+            const int qi = r * S + slot;
+            const int64_t q = qb + qi;
+            const bool inq = q < nq;
+            const int qc = cell_s[wv][qi];
+            ProductQuery Qy;
+            const float4* row = reinterpret_cast<const float4*>(table_row(table, qc, K, comp, qc >= 0));
+            float R[12];
+#pragma unroll
+            for (int c4 = 0; c4 < 3; ++c4) {
+                const float4 v = row[(int64_t)c4 * K];
+                R[4 * c4] = v.x;
+                R[4 * c4 + 1] = v.y;
+                R[4 * c4 + 2] = v.z;
+                R[4 * c4 + 3] = v.w;
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Qy.R[i] = R[i];
+            const float* pd = &pd_s[wv][r][0][lane];
+            Qy.p0.c0 = pd[0 * 64];
+            Qy.p0.c1 = pd[1 * 64];
+            Qy.p0.i0 = pd[2 * 64];
+            Qy.p0.i1 = pd[3 * 64];
+            Qy.p0.i2 = pd[4 * 64];
+            Qy.p0.nrm = pd[5 * 64];
+            Qy.P0 = pd[6 * 64];
+            Qy.p1.c0 = pd[7 * 64];
+            Qy.p1.c1 = pd[8 * 64];
+            Qy.p1.i0 = pd[9 * 64];
+            Qy.p1.i1 = pd[10 * 64];
+            Qy.p1.i2 = pd[11 * 64];
+            Qy.p1.nrm = pd[12 * 64];
+            Qy.P1 = pd[13 * 64];
+            float pdf = 0.0f;
+            for (int tt = 0; tt < ns; tt += 4) {  // wave-uniform
+                const float4* wq = &w_s[wv][qi * ns + tt];
+                float v[4];
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const float4 wd = wq[min(k4, ns - 1 - tt)];  // past the last draw: repeat it
+                    v[k4] = product_density_lane(Qy, K, comp, wd.x, wd.y, wd.z);
+                }
+                if constexpr (G == 16) {
+                    // lane comp ends with the sum for draw tt + (comp & 3)
+                    const float p = group_sum4_row16(v);
+                    pdf = (comp >> 2) == (tt >> 2) ? p : pdf;
+                } else {
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) {
+                        const float p = group_sum<G>(v[k4]);
+                        pdf = comp == tt + k4 ? p : pdf;
+                    }
+                }
+            }
+            if (inq && comp < ns) pdf_out[q * ns + comp] = w_s[wv][qi * ns + comp].w != 0.0f ? pdf : 0.0f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // before the next pass overwrites
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void product_pdf_kernel(
     const float* __restrict__ table, int C, int K, const float* __restrict__ qpos, const int32_t* __restrict__ qcell,
@@ -473,9 +659,18 @@ extern "C" int sdmm_product_sample(const float* table, int32_t n_cells, int32_t 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int G = group_for(K > Kb ? K : Kb);
     ScopedTimer tm(SDMM_TIMER_PRODUCT, s);
-    SDMM_DISPATCH_G(G, (product_sample_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
-                           table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq, ns, uniforms,
-                           seed, dirs_out, pdf_out, valid_out, pair_out)));
+    const int S = 64 / G;
+    if (S * ns <= 64) {
+        // the draws of up to two rounds of S queries share one pass of the draw phase
+        const int nqr = std::max(1, std::min(kProdRounds, 64 / (S * ns)));
+        SDMM_DISPATCH_G(G, (product_sample_lanes_kernel<g><<<grid_for(nq, S * nqr, kProdWpb), 64 * kProdWpb, 0, s>>>(
+                               table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq, ns, nqr,
+                               uniforms, seed, dirs_out, pdf_out, valid_out, pair_out)));
+    } else {
+        SDMM_DISPATCH_G(G, (product_sample_kernel<g><<<grid_for(nq, 64 / g), 256, 0, s>>>(
+                               table, n_cells, K, qpos, qcell, btable, n_bsdf, Kb, bpar, bcell, frames, nq, ns,
+                               uniforms, seed, dirs_out, pdf_out, valid_out, pair_out)));
+    }
     return check(hipGetLastError());
 }
 

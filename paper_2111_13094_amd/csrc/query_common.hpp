@@ -213,12 +213,13 @@ __device__ __forceinline__ void load_row(const float* src, int K, float* T)
     }
 }
 
-// grid for a wave-strided loop over `items` work units of S per wave
-inline unsigned grid_for(int64_t items, int S)
+// grid for a wave-strided loop over `items` work units of S per wave, in work groups of
+// wpb waves
+inline unsigned grid_for(int64_t items, int S, int wpb = 4)
 {
     const int64_t waves = (items + S - 1) / S;
-    int64_t blocks = (waves + 3) / 4;
-    const int64_t cap = 256 * 32;  // 256 CUs x 32 waves of 256-thread blocks
+    int64_t blocks = (waves + wpb - 1) / wpb;
+    const int64_t cap = 256 * 128 / wpb;  // 256 CUs x 128 waves
     if (blocks > cap) blocks = cap;
     return (unsigned)(blocks < 1 ? 1 : blocks);
 }

@@ -180,20 +180,24 @@ def test_product_pdf_parity(dev, orc, scene):
     print("worst pdf relative %.2e" % worst)
 
 
-@pytest.mark.parametrize("K,Kb", [(5, 12), (32, 3), (16, 1)])
-def test_product_other_component_counts(dev, orc, K, Kb):
+@pytest.mark.parametrize("K,Kb,ns", [(5, 12, 6), (32, 3, 6), (16, 1, 6), (4, 3, 4), (6, 8, 3), (16, 16, 20),
+                                     (64, 2, 1)])
+def test_product_other_component_counts(dev, orc, K, Kb, ns):
     """K not a power of two with more BSDF than radiance lanes, a 32-lane group with a
-    3-component BSDF model, and a single BSDF component (the second pair is empty)."""
-    print(f"case: product sampling K={K} Kb={Kb}", flush=True)
+    3-component BSDF model, a single BSDF component (the second pair is empty), groups of
+    4, 8 and 64 lanes, and more draws per query than one wave pass holds (the kernel that
+    draws on the query's own lanes)."""
+    print(f"case: product sampling K={K} Kb={Kb} ns={ns}", flush=True)
     wl = synth.workload("single", seed=4)
     b = synth.make_batch(9, [4096], wl["box_lo"], wl["box_size"], wl["lobes"])
     mix = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
     orc.fit(orc.Opts(K=K, iters=3), b.offsets, b.samples, mix, orc.new_state(1, K))
     qpos, qcell = synth.make_queries(3, wl["box_lo"], wl["box_size"], 48)
+    qpos, qcell = qpos[:45], qcell[:45]  # a ragged last wave pass
     bpar, bcell, F = synth.bsdf_queries(5, qcell.size, 2)
     sc = dict(C=1, K=K, mix=mix, CB=2, Kb=Kb, bmix=synth.bsdf_mixtures(6, 2, Kb), qpos=qpos.astype(np.float32),
               qcell=qcell, bpar=bpar.astype(np.float32), bcell=bcell, F=F.astype(np.float32))
-    nq, ns = qcell.size, 6
+    nq = qcell.size
     g = _gpu_inputs(dev, sc)
     u = synth.make_uniforms(44 + K, nq * ns).reshape(nq, ns, 3)
     got = _gpu_sample(dev, sc, g, ns, uniforms=u)
@@ -227,7 +231,7 @@ def test_product_invalid_indices_give_zero(dev, orc, scene):
 
 def test_product_full_size_sampled_queries(dev, orc):
     """The launch configuration of the product benchmark: 16384 radiance cells (the
-    initial mixtures, K = 16), 8 BSDF models of 16 components, 2^22 queries, 2 draws
+    initial mixtures, K = 16), 8 BSDF models of 16 components, 2^22 queries, 4 draws
     each; 48 sampled queries recomputed by the oracle."""
     print("case: product sampling at full size (2^22 queries), 48 sampled queries", flush=True)
     wl = synth.workload("cells16k")
@@ -239,7 +243,7 @@ def test_product_full_size_sampled_queries(dev, orc):
     bpar, bcell, F = synth.bsdf_queries(6, nq, 8)
     sc = dict(C=C, K=16, mix=mix, CB=8, Kb=16, bmix=synth.bsdf_mixtures(7, 8, 16), qpos=qpos.astype(np.float32),
               qcell=qcell, bpar=bpar.astype(np.float32), bcell=bcell, F=F.astype(np.float32))
-    ns = 2
+    ns = 4
     g = _gpu_inputs(dev, sc)
     seed = 99
     gd, gp, gv, gpair = _gpu_sample(dev, sc, g, ns, uniforms=None, seed=seed)
