@@ -1,0 +1,111 @@
+"""The 16384-cell workload at full size, in the launch configuration of its benchmark
+(`bench.py --workload cells16k`): one batched E+M step over its 16.6M samples (counts
+16 + Geom(1/1009) - 1 clipped to [16, 32768], so the largest cells run 128 work items),
+then the fused conditioning + sampling + pdf call at 2^22 query positions (256 per cell)
+with 4 draws each from the device Philox4x32-10 generator.
+
+The oracle recomputes 16 cells chosen across the count range (the largest included), each
+fitted alone from the same initial mixture, and then 3 queries in each of those cells on
+its own fits with the generator's uniforms for those draws. Both sides therefore carry
+their own fit into the query path: a draw whose component choice sits within 1e-5 of a
+CDF boundary (the two fits' conditioned weights differ by about 1e-7) or whose radius sits
+at the cut locus has two correct outcomes and is checked for validity only."""
+import numpy as np
+import pytest
+
+from paper_2111_13094_amd import synth
+from tests.parity_utils import (CUT_LOCUS_BAND, assert_cells_close, draw_radius, positive_counts, state_to_torch,
+                                to_numpy, to_torch)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_13094_amd import sdmm
+    sdmm.lib()
+    return torch
+
+
+def test_full_size_cells16k_fit_and_queries(dev, orc):
+    print("case: cells16k full size, one step + 2^22 queries x 4 draws, 16 sampled cells", flush=True)
+    from paper_2111_13094_amd import sdmm
+    K, ns, seed = 16, 4, 2024
+    wl = synth.workload("cells16k")
+    b = synth.workload_batch(wl)
+    C = wl["grid"].n_cells
+    mix0 = synth.initial_mixtures(wl["box_lo"], wl["box_size"], K)
+    gm, gst = to_torch(mix0), state_to_torch(orc.new_state(C, K))
+    off, smp = dev.from_numpy(b.offsets).cuda(), dev.from_numpy(b.samples).cuda()
+    s_g = sdmm.fit_mixtures(off, smp, gm, gst, sdmm.default_opts(K)).cpu().numpy()
+    got = to_numpy(gm)
+
+    order = np.argsort(wl["counts"], kind="stable")
+    cells = sorted(set(order[np.linspace(0, C - 1, 16).astype(int)].tolist()))
+    assert order[-1] in cells
+    fits = []
+    for c in cells:
+        i0, i1 = b.offsets[c], b.offsets[c + 1]
+        sub = np.ascontiguousarray(b.samples[:, i0:i1])
+        mc = {k: np.ascontiguousarray(v.reshape(C, -1)[c]) for k, v in mix0.items()}
+        s_o = orc.fit(orc.Opts(K=K), np.array([0, i1 - i0]), sub, mc, orc.new_state(1, K))
+        assert s_o[0] == s_g[c], (c, s_o[0], s_g[c])
+        gc = {k: v.reshape(C, -1)[c] for k, v in got.items()}
+        assert_cells_close(gc, mc, K, [0], positive_counts(sub, np.array([0, i1 - i0])), what=f"n={i1 - i0}")
+        fits.append(mc)
+
+    # the benchmark's queries through the fused call on the device's fit
+    qpos, qcell = synth.make_queries(7, wl["box_lo"], wl["box_size"], 256)
+    nq = qcell.size
+    assert nq == 1 << 22
+    table = sdmm.condition_prepare(gm, C, K)
+    qp = dev.from_numpy(np.ascontiguousarray(qpos.T)).cuda()
+    qc = dev.from_numpy(qcell).cuda()
+    d, p, v = sdmm.condition_sample_pdf(table, C, K, qp, qc, ns, uniforms=None, seed=seed)
+    gd = d.cpu().numpy().T.reshape(nq, ns, 3)
+    gp, gv = p.cpu().numpy().reshape(nq, ns), v.cpu().numpy().reshape(nq, ns)
+
+    # three queries in each sampled cell (queries are sorted by cell, 256 per cell), on
+    # the oracle's own fits of those cells
+    rng = np.random.default_rng(5)
+    pick = np.concatenate([c * 256 + rng.choice(256, 3, replace=False) for c in cells])
+    assert np.array_equal(qcell[pick], np.repeat(cells, 3))
+    omix = {k: np.concatenate([f[k] for f in fits]) for k in fits[0]}
+    oq = np.repeat(np.arange(len(cells), dtype=np.int32), 3)
+    u = orc.draw_uniforms(seed, nq * ns).reshape(nq, ns, 3)[pick]
+    od, op, oc, ov = orc.sample(K, omix, qpos[pick].astype(np.float64), oq, u)
+    ambiguous, worst_ang, worst_pdf = 0, 0.0, 0.0
+    for i, q in enumerate(pick):
+        pic, m, Sc = orc.condition(K, omix, int(oq[i]), qpos[q].astype(np.float64))
+        cdf = np.cumsum(pic)
+        for t in range(ns):
+            near_cdf = np.min(np.abs(cdf - u[i, t, 0])) < 1e-5
+            if gv[q, t] != ov[i, t]:
+                k = oc[i, t]
+                r = draw_radius(m[k], Sc[k], u[i, t])
+                assert near_cdf or abs(r - np.pi) < CUT_LOCUS_BAND, (q, t, gv[q, t], ov[i, t], r)
+                ambiguous += 1
+                continue
+            if not ov[i, t]:
+                assert np.all(gd[q, t] == 0) and gp[q, t] == 0
+                continue
+            a, bb = gd[q, t].astype(np.float64), od[i, t]
+            ang = np.arctan2(np.linalg.norm(np.cross(a, bb)), a @ bb)
+            if ang >= 1e-5:  # another component: only where the choice is ambiguous
+                assert near_cdf, (q, t, ang)
+                ambiguous += 1
+                continue
+            rel = abs(gp[q, t] - op[i, t]) / op[i, t]
+            worst_ang, worst_pdf = max(worst_ang, ang), max(worst_pdf, rel)
+            assert rel < 1e-4, (q, t, gp[q, t], op[i, t])
+    print("worst direction angle %.2e rad, worst pdf relative %.2e, ambiguous %d of %d" %
+          (worst_ang, worst_pdf, ambiguous, pick.size * ns))
+    assert ambiguous <= 2, ambiguous
+    # the whole launch: every valid draw has a unit direction and a positive pdf
+    val = gv.astype(bool)
+    assert val.mean() > 0.9
+    assert np.all(np.abs(np.linalg.norm(gd[val], axis=-1) - 1.0) < 1e-5)
+    assert np.all(gp[val] > 0) and np.all(gp[~val] == 0) and np.all(gd[~val] == 0)
