@@ -1,9 +1,8 @@
 """The 16384-cell workload at full size, in the launch configuration of its benchmark
 (`bench.py --workload cells16k`): one batched E+M step over its 16.6M samples (counts
 16 + Geom(1/1009) - 1 clipped to [16, 32768]; the largest, 8930 samples, runs 35 work
-items),
-then the fused conditioning + sampling + pdf call at 2^22 query positions (256 per cell)
-with 4 draws each from the device Philox4x32-10 generator.
+items), then the fused conditioning + sampling + pdf call at 2^22 query positions (256
+per cell) with 4 draws each from the device Philox4x32-10 generator.
 
 The oracle recomputes 16 cells chosen across the count range (the largest included), each
 fitted alone from the same initial mixture, and then 3 queries in each of those cells on
