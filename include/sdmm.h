@@ -491,6 +491,16 @@ int sdmm_timing_enable(int enable);
  * synchronises on the recorded events. SDMM_EINVAL for an unknown class. */
 int sdmm_timing_read(int kernel_class, double *total_ms, int64_t *launches, int reset);
 
+/* Device microbenchmark of the vector FMA rate the library's code generation reaches
+ * (measurement support, not a step of the method): n_groups work groups of 256 threads,
+ * each thread running `iters` rounds of 16 independent FMA chains in FP32 (bits = 32,
+ * built without packed FP32 like every kernel here) or FP64 (bits = 64), and storing its
+ * sum in out (device memory, n_groups * 256 floats or doubles). The work is
+ * n_groups * 256 * iters * 16 FMAs (2 flop each). Writes the kernel time in milliseconds
+ * (HIP events on the stream; the call synchronises on them) to *ms. SDMM_EINVAL for other
+ * bits, n_groups < 1, iters < 1 or a null pointer. */
+int sdmm_probe_fma(int32_t bits, int32_t n_groups, int32_t iters, void *out, double *ms, void *stream);
+
 /* ---- helpers ---- */
 
 /* Static description of an SDMM_OK / SDMM_E* code. */

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libsdmm.so")
-SOURCES = ["fit.hip", "query.hip", "product.hip", "tree.hip", "stepwise.hip", "grad.hip", "params.hip", "timing.hip"]
+SOURCES = ["fit.hip", "query.hip", "product.hip", "tree.hip", "stepwise.hip", "grad.hip", "params.hip", "timing.hip",
+           "probe.hip"]
 ARCH = os.environ.get("SDMM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

@@ -88,6 +88,7 @@ def lib():
         L.sdmm_mixture_from_params.argtypes = [i32, i32, vp, vp, vp, vp, vp, P(Mixtures), vp, vp]
         L.sdmm_grad_to_params.argtypes = [i32, i32, vp, vp, vp, vp, vp]
         L.sdmm_params_from_mixture.argtypes = [P(Mixtures), vp, vp, vp, vp]
+        L.sdmm_probe_fma.argtypes = [i32, i32, i32, vp, P(C.c_double), vp]
         L.sdmm_status_string.argtypes = [C.c_int]
         L.sdmm_status_string.restype = C.c_char_p
         L.sdmm_version.restype = C.c_char_p
@@ -521,3 +522,14 @@ def params_from_mixture(mix, n_cells, K, stream=None):
                                         _ptr(status, torch.int32), _stream(stream))
     _check(rc, "sdmm_params_from_mixture")
     return alpha, L, status
+
+
+def probe_fma(bits=32, n_groups=4096, iters=256, device="cuda", stream=None):
+    """Measured vector FMA rate (sdmm_probe_fma) in TFLOP/s: FP32 as the library's kernels
+    are built (no packed FP32) for bits=32, FP64 for bits=64."""
+    dt = torch.float32 if bits == 32 else torch.float64
+    out = torch.empty(n_groups * 256, dtype=dt, device=device)
+    ms = C.c_double()
+    rc = lib().sdmm_probe_fma(int(bits), int(n_groups), int(iters), _ptr(out, dt), C.byref(ms), _stream(stream))
+    _check(rc, "sdmm_probe_fma")
+    return n_groups * 256.0 * iters * 16 * 2 / (ms.value * 1e-3) / 1e12

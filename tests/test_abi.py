@@ -67,6 +67,12 @@ def test_workspace_size_and_argument_errors(lib):
     o.K = 8  # K mismatch between options and mixtures
     assert lib.sdmm_fit_mixtures(C.c_void_p(256), C.c_void_p(256), 100, C.byref(m), C.byref(st), C.byref(o),
                                  C.c_void_p(256), C.c_void_p(256), need, None) == -1
+    # the FMA probe refuses other widths, empty launches and null pointers on the host
+    ms = C.c_double()
+    assert lib.sdmm_probe_fma(16, 1, 1, C.c_void_p(256), C.byref(ms), None) == -1
+    assert lib.sdmm_probe_fma(32, 0, 1, C.c_void_p(256), C.byref(ms), None) == -1
+    assert lib.sdmm_probe_fma(64, 1, 0, C.c_void_p(256), C.byref(ms), None) == -1
+    assert lib.sdmm_probe_fma(32, 1, 1, None, C.byref(ms), None) == -1
 
 
 def test_struct_layouts_match_the_header(tmp_path):
