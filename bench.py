@@ -190,6 +190,25 @@ def measured_ceiling(torch, bits, achieved):
             "unit": "TFLOP/s", "frac": (achieved / best) if achieved else None}
 
 
+def measured_copy_rate(torch, achieved, mib=1024):
+    """HBM rate of a plain device copy of `mib` MiB (read + write bytes over the event-timed
+    copy), best of three after a warm-up, and the kernel's achieved rate as a fraction of
+    it. Measured after the timed region."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = max(best, 2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9)
+    return {"kind": "device copy (read + write)", "value": best, "unit": "GB/s",
+            "frac": (achieved / best) if achieved else None}
+
+
 def bench_cells4k(args, torch):
     from paper_2111_13094_amd import sdmm, synth
     n_batches = 8
@@ -905,6 +924,8 @@ def main():
     if roof.get("bound") == "alu":
         roof["measured_ceiling"] = measured_ceiling(torch, 64 if roof.get("peak") == 78.6 else 32,
                                                     roof.get("achieved"))
+    elif roof.get("bound") == "hbm":
+        roof["measured_ceiling"] = measured_copy_rate(torch, roof.get("achieved"))
     print(json.dumps(out))
 
 
