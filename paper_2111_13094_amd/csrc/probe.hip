@@ -20,6 +20,8 @@ __global__ __launch_bounds__(256) void fma_probe_kernel(int iters, T m, T c, T* 
     T a[kProbeChains];
 #pragma unroll
     for (int j = 0; j < kProbeChains; ++j) a[j] = (T)(tid & 255) * (T)1e-3 + (T)j;
+    // four rounds (64 FMAs) per loop trip, so that loop control is a small share of the issue
+#pragma unroll 4
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int j = 0; j < kProbeChains; ++j) a[j] = fma(a[j], m, c);

@@ -524,7 +524,7 @@ def params_from_mixture(mix, n_cells, K, stream=None):
     return alpha, L, status
 
 
-def probe_fma(bits=32, n_groups=4096, iters=256, device="cuda", stream=None):
+def probe_fma(bits=32, n_groups=8192, iters=1024, device="cuda", stream=None):
     """Measured vector FMA rate (sdmm_probe_fma) in TFLOP/s: FP32 as the library's kernels
     are built (no packed FP32) for bits=32, FP64 for bits=64."""
     dt = torch.float32 if bits == 32 else torch.float64
