@@ -5,7 +5,7 @@ Both sides start from the same FP64 masters (an oracle fit of the radiance cells
 BSDF models) and the same FP32 query inputs. Tolerances: sampled directions 1e-5 rad
 and their pdf relative 2e-4; pdf at given directions relative 2e-4 wherever it exceeds
 1e-6 of the query's largest value. The FP32 chain behind them: conditioning (relative
-1e-6 in the offsets), the in-plane rotation and the transfer Jacobian (1e-6), the 2x2
+1e-6 in the offsets), the rotation to world and the transfer Jacobian (1e-6), the 2x2
 products and Cholesky factors of C (relative 1e-6 times cond(S), up to ~1e2 here), then
 a quadratic form q of up to ~30 whose absolute error of a few 1e-6 changes exp(-q/2) by
 as much relative, and log2 normalisers from the hardware logarithm (1 ulp). Measured on
