@@ -82,12 +82,12 @@ def _traffic_record(items, waves_per_block):
     return None
 
 
-def _estep_kernel_name(items, G=16):
-    """The E-step kernel the library launches for the compensated sums: items whose lane
-    share fits one fold block (64 steps of 64 / G samples) run the plain-sum kernel, bit
-    for bit the same."""
+def _estep_kernel_name(items, G=16, adjoint=False):
+    """The E-step kernel the library launches for the compensated sums (of the EM pass, or
+    of the adjoint's pass): items whose lane share fits one fold block (64 steps of 64 / G
+    samples) run the plain-sum kernel, bit for bit the same."""
     acc = 1 if items // (64 // G) <= 64 else 0
-    return f"estep_kernel<{G}, {acc}, false, false>"
+    return f"estep_kernel<{G}, {acc}, false, {'true' if adjoint else 'false'}>"
 
 
 def _sync(torch):
@@ -777,7 +777,7 @@ def bench_grad(args, torch):
                        "n_cells": C, "K": K, "samples": int(N), "cells_with_gradient": int(ok.sum())},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                         "kernel": "estep_kernel<16, 0, false, true>", "kernel_ms": k_ms,
+                         "kernel": _estep_kernel_name(256, adjoint=True), "kernel_ms": k_ms,
                          "flops_per_launch": fl, "note": "140 flop/pair of the statistics pass; the adjoint "
                                                          "terms are extra work not counted"},
             "fp64_mode_ms": k64_ms,

@@ -604,6 +604,7 @@ template <int G, bool ADJ>
 static EstepFn estep_for_g(int acc, bool jac)
 {
     if constexpr (ADJ) {
+        if (acc == kAccPlain) return estep_kernel<G, kAccPlain, false, true>;
         return estep_kernel<G, kAccTwoSum, false, true>;
     } else {
         if (jac) {

@@ -170,8 +170,13 @@ extern "C" int sdmm_fit_grad(const int64_t* cell_offsets, const float* samples, 
     launch_setup(cell_offsets, n_samples, *mix, cell_status, ws, L, s, true);
     {
         ScopedTimer tm(SDMM_TIMER_GRAD, s);
-        const EstepFn pass = (opts->flags & SDMM_FLAG_FP64_SUMS) ? adj64_function(group_for(K))
-                                                                 : estep_function(group_for(K), kAccTwoSum, false, true);
+        // as in the fit: a work item that fits one block of the compensated sums runs the
+        // plain-sum pass, bit for bit the same with fewer registers
+        const int G = group_for(K);
+        const bool one_block = (L.P / (64 / G)) <= kFoldEvery;
+        const EstepFn pass = (opts->flags & SDMM_FLAG_FP64_SUMS)
+                                 ? adj64_function(G)
+                                 : estep_function(G, one_block ? kAccPlain : kAccTwoSum, false, true);
         launch_estep(pass, samples, n_samples, cell_offsets, C,
                      K, L, 0, (int64_t)C + L.W, L.ps_grad, ws, s);
     }
