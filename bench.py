@@ -8,7 +8,9 @@ batch over all cells; each call's last M-step writes the next call's E-step mirr
 after the first call no setup kernel runs) in the launch configuration the autotuner picks
 on the first batch, replayed through the library's hipGraph cache.
 A step is one E+M pass over one resident batch; inputs are generated on the host and
-copied to HBM before the timed region. The same steps launched eagerly, with HIP events
+copied to HBM before the timed region. The default warm-up (200 untimed steps, about
+40 ms) lets the GPU clock settle: from an idle GPU the E kernel takes about 200 us for
+its first steps and settles near 150 us after some 200 steps. The same steps launched eagerly, with HIP events
 around every E-step and M-step launch, give the roofline's kernel time ("eager").
 
 The JSON line also carries:
@@ -878,7 +880,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps first (the GPU clock settles over the first ~50 ms of load)")
     ap.add_argument("--workload", default="cells4k", choices=["cells4k", "cells16k", "grad", "huge", "single",
                                                                     "accurate", "product", "tree", "stepwise"])
     ap.add_argument("--schedule", default="batched", choices=["batched", "fused"])
