@@ -105,10 +105,20 @@ __device__ __forceinline__ BsdfWorld shfl_bsdf(const BsdfWorld& v, int src)
 struct Pair {
     float l;             // log2 weight (-inf: empty)
     float c0, c1;        // mean
-    float L0, L1, L2;    // Cholesky factor of C
-    float i0, i1, i2;    // its inverse times sqrt(log2(e) / 2)
+    float i0, i1, i2;    // inverse of the Cholesky factor of C times sqrt(log2(e) / 2)
     float nrm;           // -log2(2 pi det L_C)
 };
+
+constexpr float kKap = 0.84932180028801904f;   // sqrt(log2(e) / 2)
+constexpr float kIKap = 1.1774100225154747f;   // its reciprocal
+
+// the Cholesky factor L = (l0; l1 l2) of a pair's C from its scaled inverse (the draws)
+__device__ __forceinline__ void pair_factor(float i0, float i1, float i2, float& l0, float& l1, float& l2)
+{
+    l0 = kKap * __builtin_amdgcn_rcpf(i0);
+    l2 = kKap * __builtin_amdgcn_rcpf(i2);
+    l1 = -i1 * l0 * l2 * kIKap;
+}
 
 __device__ __forceinline__ Pair make_pair(const float* R, float lwk, float m0, float m1, float a00, float a01,
                                           float a11, const BsdfWorld& b)
@@ -116,8 +126,6 @@ __device__ __forceinline__ Pair make_pair(const float* R, float lwk, float m0, f
     Pair p;
     p.l = -INFINITY;
     p.c0 = p.c1 = 0.0f;
-    p.L0 = p.L2 = 1.0f;
-    p.L1 = 0.0f;
     p.i0 = p.i2 = 1.0f;
     p.i1 = 0.0f;
     p.nrm = 0.0f;
@@ -155,27 +163,25 @@ __device__ __forceinline__ Pair make_pair(const float* R, float lwk, float m0, f
     const float si00 = S11 * idet, si01 = -S01 * idet, si11 = S00 * idet;
     const float d0 = m0 - a0, d1 = m1 - a1;
     const float q = fmaf(d0, fmaf(si00, d0, si01 * d1), d1 * fmaf(si01, d0, si11 * d1));
-    // C = A S^-1 B, c = B S^-1 m + A S^-1 a
+    // C = A S^-1 B and c = m - A S^-1 (m - a) (equal to B S^-1 m + A S^-1 a, since
+    // A S^-1 + B S^-1 = I)
     const float as00 = fmaf(a00, si00, a01 * si01), as01 = fmaf(a00, si01, a01 * si11);
     const float as10 = fmaf(a01, si00, a11 * si01), as11 = fmaf(a01, si01, a11 * si11);
-    const float bs00 = fmaf(b00, si00, b01 * si01), bs01 = fmaf(b00, si01, b01 * si11);
-    const float bs10 = fmaf(b01, si00, b11 * si01), bs11 = fmaf(b01, si01, b11 * si11);
     const float C00 = fmaf(as00, b00, as01 * b01);
     const float C01 = 0.5f * (fmaf(as00, b01, as01 * b11) + fmaf(as10, b00, as11 * b01));
     const float C11 = fmaf(as10, b01, as11 * b11);
-    const float L0s = C00, L2s = fmaf(-C01, C01 * __builtin_amdgcn_rcpf(C00), C11);
-    if (!(ok && L0s > 0.0f && L2s > 0.0f)) return p;
-    p.c0 = fmaf(bs00, m0, fmaf(bs01, m1, fmaf(as00, a0, as01 * a1)));
-    p.c1 = fmaf(bs10, m0, fmaf(bs11, m1, fmaf(as10, a0, as11 * a1)));
-    p.L0 = __builtin_amdgcn_sqrtf(L0s);
-    p.L1 = C01 * __builtin_amdgcn_rcpf(p.L0);
-    p.L2 = __builtin_amdgcn_sqrtf(L2s);
-    const float r0 = __builtin_amdgcn_rcpf(p.L0), r2i = __builtin_amdgcn_rcpf(p.L2);
-    constexpr float kap = 0.84932180028801904f;  // sqrt(log2(e) / 2)
-    p.i0 = r0 * kap;
-    p.i1 = -p.L1 * r0 * r2i * kap;
-    p.i2 = r2i * kap;
-    p.nrm = -kLog2TwoPi - __builtin_amdgcn_logf(p.L0 * p.L2);
+    const float rc = __builtin_amdgcn_rcpf(C00);
+    const float L2s = fmaf(-C01, C01 * rc, C11);  // the factor's last pivot squared
+    if (!(ok && C00 > 0.0f && L2s > 0.0f)) return p;
+    p.c0 = m0 - fmaf(as00, d0, as01 * d1);
+    p.c1 = m1 - fmaf(as10, d0, as11 * d1);
+    // inverse factor from the pivots' reciprocal square roots: L0 = sqrt(C00),
+    // L1 = C01 / L0, L2 = sqrt(L2s); (L^-1)_10 = -L1 / (L0 L2) = -(C01 / C00) / L2
+    const float r0 = __builtin_amdgcn_rsqf(C00), r2 = __builtin_amdgcn_rsqf(L2s);
+    p.i0 = kKap * r0;
+    p.i2 = kKap * r2;
+    p.i1 = -C01 * rc * p.i2;
+    p.nrm = __builtin_amdgcn_logf(r0 * r2) - kLog2TwoPi;
     p.l = lwk + b.lw - kHalfLog2e * q - kLog2TwoPi - 0.5f * __builtin_amdgcn_logf(det);
     return p;
 }
@@ -353,13 +359,17 @@ __global__ __launch_bounds__(256) void product_sample_kernel(
             float R[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) R[i] = __shfl(Qy.R[i], src);
-            const float a0 = __shfl(Qy.p0.L0, src), a1 = __shfl(Qy.p0.L1, src), a2 = __shfl(Qy.p0.L2, src);
+            // both pairs' means and scaled inverse factors from the lane that holds them, then
+            // this draw's pair (j) and its factor
+            const float a0 = __shfl(Qy.p0.i0, src), a1 = __shfl(Qy.p0.i1, src), a2 = __shfl(Qy.p0.i2, src);
             const float ac0 = __shfl(Qy.p0.c0, src), ac1 = __shfl(Qy.p0.c1, src);
-            const float b0 = __shfl(Qy.p1.L0, src), b1 = __shfl(Qy.p1.L1, src), b2 = __shfl(Qy.p1.L2, src);
+            const float b0 = __shfl(Qy.p1.i0, src), b1 = __shfl(Qy.p1.i1, src), b2 = __shfl(Qy.p1.i2, src);
             const float bc0 = __shfl(Qy.p1.c0, src), bc1 = __shfl(Qy.p1.c1, src);
+            const float c0 = j ? bc0 : ac0, c1 = j ? bc1 : ac1;
+            float l0, l1, l2;
+            pair_factor(j ? b0 : a0, j ? b1 : a1, j ? b2 : a2, l0, l1, l2);
             float w[3];
-            const int ok = draw_candidate(R, j ? b0 : a0, j ? b1 : a1, j ? b2 : a2, j ? bc0 : ac0, j ? bc1 : ac1,
-                                          ul1, ul2, w);
+            const int ok = draw_candidate(R, l0, l1, l2, c0, c1, ul1, ul2, w);
             const int valid = sel >= 0 && ok;
             float pdf = 0.0f;
             for (int tt = 0; tt < tn; tt += 4) {
@@ -518,10 +528,8 @@ __global__ __launch_bounds__(64 * kProdWpb) void product_sample_lanes_kernel(
             const int j = hit ? jh : jl_s[wv][qis];
             const float* pj = pd + (j ? kPairF * 64 : 0);
             const float c0 = pj[0], c1 = pj[64], i0 = pj[2 * 64], i1 = pj[3 * 64], i2 = pj[4 * 64];
-            // the factor of C from its scaled inverse (i = L^-1 sqrt(log2(e) / 2))
-            constexpr float kap = 0.84932180028801904f, ikap = 1.1774100225154747f;
-            const float L0 = kap * __builtin_amdgcn_rcpf(i0), L2 = kap * __builtin_amdgcn_rcpf(i2);
-            const float L1 = -i1 * L0 * L2 * ikap;
+            float L0, L1, L2;
+            pair_factor(i0, i1, i2, L0, L1, L2);
             const int qc = cell_s[wv][qis];
             const float4* row = reinterpret_cast<const float4*>(table_row(table, qc, K, sk, qc >= 0));
             float R[12];
