@@ -10,7 +10,8 @@ on the first batch, replayed through the library's hipGraph cache.
 A step is one E+M pass over one resident batch; inputs are generated on the host and
 copied to HBM before the timed region. The default warm-up (200 untimed steps, about
 40 ms) lets the GPU clock settle: from an idle GPU the E kernel takes about 200 us for
-its first steps and settles near 150 us after some 200 steps. The same steps launched eagerly, with HIP events
+its first steps and settles near 150 us after some 200 steps. The autotuner times its
+candidates after as many untimed steps on scratch copies of the mixtures. The same steps launched eagerly, with HIP events
 around every E-step and M-step launch, give the roofline's kernel time ("eager").
 
 The JSON line also carries:
@@ -240,8 +241,14 @@ def bench_cells4k(args, torch):
     opts.max_cell_samples = max_cell
     tuned = None
     if args.tune:
-        # the autotuner's pick on the first batch (untimed); the timed runs use it
+        # the autotuner's pick on the first batch (untimed); the timed runs use it. It times
+        # its candidates after the same number of untimed steps on scratch copies, so that
+        # every candidate runs at the settled clock
         from paper_2111_13094_amd import tune
+        m_w, s_w = fresh()
+        for w in range(args.warmup):
+            sdmm.fit_mixtures(offs[w % n_batches], smps[w % n_batches], m_w, s_w, opts)
+        del m_w, s_w
         m_t, s_t = fresh()
         opts = tune.tune_fit(offs[0], smps[0], m_t, s_t, opts, candidates=TUNE_CANDIDATES, reps=3)
         cfg = tune.tuned_config(C, K, N[0], opts)
