@@ -85,49 +85,203 @@ __global__ void tree_init_kernel(TreePtrs t, int levels, double lo0, double lo1,
 
 // ---------------------------------------------------------------------------------
 // point location: left where p[axis] < split, else right; child indices exceed their
-// parent's, so the walk ends within max_nodes steps. After the first round a sample
-// resumes from the node it reached in the previous round (node_of), which is still its
-// leaf unless that leaf was split; its position is read only when it has to move. The
-// axis, split, left child and leaf index of a node are loaded together (with the
-// position, when every sample starts at the root): one memory round trip per level, the
-// entries that turn out not to be needed simply not used.
+// parent's, so a walk ends within max_nodes steps. The oldest nodes, the top of the tree,
+// are staged in LDS by every work group (one 8-byte entry per node, indices below
+// kLocStaged), so the upper levels of a walk cost one LDS read each; below them a node's
+// axis, split, left child and leaf index are loaded from global memory together (one
+// memory round trip per level). Each thread walks kLocPer samples side by side, so their
+// reads overlap, and issues the next tile's first loads before it walks the current one.
+// After the first round a sample resumes from the node it reached in the previous round
+// (node_of), which is still its leaf unless that leaf was split: its position is read
+// only when it has to move, and its node index is written only when it changes.
+//
+// A staged entry holds the split rounded up to FP32: for an FP32 coordinate p and an FP64
+// split s, p < s exactly when p < f, f the least FP32 value not below s (every FP32 value
+// below s is at most the greatest one below f), so the walk takes the FP64 comparison's
+// branch with an FP32 comparison.
 // ---------------------------------------------------------------------------------
-__global__ void locate_kernel(TreePtrs t, const float* __restrict__ smp, int64_t N, int from_root,
-                              int32_t* __restrict__ node_of, int32_t* __restrict__ leaf_of)
+constexpr int kLocThreads = 256;
+constexpr int kLocPer = 4;                       // samples per thread per tile
+constexpr int kLocTile = kLocThreads * kLocPer;  // samples per work group per tile
+constexpr int kLocStaged = 1024;                 // nodes staged in LDS
+constexpr int kLocMaxGroups = 256 * 8;           // 8 work groups per CU
+constexpr int32_t kUnstaged = INT32_MIN;         // an inner node whose child index does not fit the code
+
+struct alignas(8) StagedNode {
+    float split;   // the split rounded up to FP32
+    int32_t code;  // inner node: 4 left + axis; leaf: -(leaf index) - 1; or kUnstaged
+};
+
+__device__ __forceinline__ float round_up_f32(double s)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int32_t n = from_root ? 0 : node_of[i];
-    int32_t ax = t.axis[n], lf = t.left[n], leaf = t.leaf[n];
-    double sp = t.split[n];
-    float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
-    if (from_root) {  // every sample moves: its position comes with the root's entries
-        q0 = smp[3 * N + i];
-        q1 = smp[4 * N + i];
-        q2 = smp[5 * N + i];
-    }
-    // the loads above and in the loop complete together at these empty statements (the
-    // compiler would otherwise issue the later ones only after the axis came back)
-    asm volatile("" ::"v"(ax), "v"(lf), "v"(sp), "v"(leaf), "v"(q0), "v"(q1), "v"(q2));
-    if (ax >= 0) {
-        if (!from_root) {
-            q0 = smp[3 * N + i];
-            q1 = smp[4 * N + i];
-            q2 = smp[5 * N + i];
-        }
-        const double p0 = (double)q0, p1 = (double)q1, p2 = (double)q2;
-        for (int32_t s = 0; s < t.max_nodes && ax >= 0; ++s) {
-            const double pa = ax == 0 ? p0 : (ax == 1 ? p1 : p2);
-            n = pa < sp ? lf : lf + 1;
-            ax = t.axis[n];
-            lf = t.left[n];
-            sp = t.split[n];
-            leaf = t.leaf[n];
-            asm volatile("" ::"v"(ax), "v"(lf), "v"(sp), "v"(leaf));
+    float f = (float)s;
+    if ((double)f < s) f = __int_as_float(__float_as_int(f) + (f >= 0.0f ? 1 : -1));
+    return f;
+}
+
+// the loads that start a tile: the positions when every sample starts at the root, else
+// the nodes the samples reached before (a lane past the end loads the last sample's)
+template <bool FromRoot>
+__device__ __forceinline__ void loc_first_loads(const float* __restrict__ smp, const int32_t* __restrict__ node_of,
+                                                int64_t N, int64_t b, float (&p0)[kLocPer], float (&p1)[kLocPer],
+                                                float (&p2)[kLocPer], int32_t (&pn)[kLocPer])
+{
+#pragma unroll
+    for (int r = 0; r < kLocPer; ++r) {
+        const int64_t ic = min(b + r * kLocThreads, N - 1);
+        if (FromRoot) {
+            p0[r] = smp[3 * N + ic];
+            p1[r] = smp[4 * N + ic];
+            p2[r] = smp[5 * N + ic];
+        } else {
+            pn[r] = node_of[ic];
         }
     }
-    node_of[i] = n;
-    leaf_of[i] = leaf;
+}
+
+template <bool FromRoot>
+__global__ __launch_bounds__(kLocThreads) void locate_kernel(TreePtrs t, const float* __restrict__ smp, int64_t N,
+                                                             int32_t* __restrict__ node_of,
+                                                             int32_t* __restrict__ leaf_of)
+{
+    __shared__ StagedNode top[kLocStaged];
+    const int32_t ns = max(1, min(min(t.counts[0], t.max_nodes), kLocStaged));
+    {
+        constexpr int kPer = kLocStaged / kLocThreads;
+        int32_t ax[kPer], lf[kPer], lv[kPer];
+        double sp[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {  // all loads first, then the LDS writes
+            const int k = min(j * kLocThreads + (int)threadIdx.x, ns - 1);
+            ax[j] = t.axis[k];
+            lf[j] = t.left[k];
+            lv[j] = t.leaf[k];
+            sp[j] = t.split[k];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = j * kLocThreads + (int)threadIdx.x;
+            const int32_t code = ax[j] < 0 ? -lv[j] - 1 : (lf[j] < (1 << 29) ? 4 * lf[j] + ax[j] : kUnstaged);
+            if (k < ns) top[k] = StagedNode{round_up_f32(sp[j]), code};
+        }
+    }
+    __syncthreads();
+    // a lane past the end walks the last sample's path again and stores nothing
+    const int64_t stride = (int64_t)gridDim.x * kLocTile;
+    int64_t base = (int64_t)blockIdx.x * kLocTile + threadIdx.x;
+    float p0[kLocPer], p1[kLocPer], p2[kLocPer];  // first loads of the next tile
+    int32_t pn[kLocPer];
+    if (base < N) loc_first_loads<FromRoot>(smp, node_of, N, base, p0, p1, p2, pn);
+    for (; base < N; base += stride) {
+        int32_t n[kLocPer], n0[kLocPer];
+        float q0[kLocPer], q1[kLocPer], q2[kLocPer];
+        if (FromRoot) {
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) {
+                n0[r] = 0;
+                q0[r] = p0[r];
+                q1[r] = p1[r];
+                q2[r] = p2[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) n0[r] = pn[r];
+        }
+        if (base + stride < N) loc_first_loads<FromRoot>(smp, node_of, N, base + stride, p0, p1, p2, pn);
+        if (!FromRoot) {
+            // a sample at an inner node moves: only then is its position read
+            int32_t c[kLocPer];
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) c[r] = top[min(n0[r], ns - 1)].code;
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) {
+                const bool staged = n0[r] < ns && c[r] != kUnstaged;
+                const bool inner = staged ? c[r] >= 0 : t.axis[n0[r]] >= 0;
+                const int64_t ic = min(base + r * kLocThreads, N - 1);
+                q0[r] = q1[r] = q2[r] = 0.0f;
+                if (inner) {
+                    q0[r] = smp[3 * N + ic];
+                    q1[r] = smp[4 * N + ic];
+                    q2[r] = smp[5 * N + ic];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kLocPer; ++r) n[r] = n0[r];
+        // the staged levels: a step per LDS read
+        for (int32_t s = 0; s <= ns; ++s) {
+            bool more = false;
+            StagedNode e[kLocPer];
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) e[r] = top[min(n[r], ns - 1)];
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) {
+                const bool go = n[r] < ns && e[r].code >= 0;
+                const float t01 = (e[r].code & 1) ? q1[r] : q0[r];
+                const float pa = (e[r].code & 2) ? q2[r] : t01;
+                const int32_t to = (e[r].code >> 2) + (pa < e[r].split ? 0 : 1);
+                n[r] = go ? to : n[r];
+                more |= go;
+            }
+            if (!more) break;
+        }
+        // the levels below: a step per global round trip (only where a walk left the
+        // staged nodes, so that the other waves never wait for the next tile's loads)
+        int32_t lv[kLocPer];
+        bool staged[kLocPer], below = false;
+#pragma unroll
+        for (int r = 0; r < kLocPer; ++r) {
+            const int32_t c = top[min(n[r], ns - 1)].code;
+            staged[r] = n[r] < ns && c != kUnstaged;  // then a leaf
+            lv[r] = -c - 1;
+            below |= !staged[r];
+        }
+        if (below) {
+            int32_t ax[kLocPer], lf[kLocPer];
+            double sp[kLocPer];
+#pragma unroll
+            for (int r = 0; r < kLocPer; ++r) {
+                ax[r] = -1;
+                lf[r] = -1;
+                sp[r] = 0.0;
+                if (!staged[r]) {
+                    ax[r] = t.axis[n[r]];
+                    lf[r] = t.left[n[r]];
+                    sp[r] = t.split[n[r]];
+                    lv[r] = t.leaf[n[r]];
+                }
+            }
+            for (int32_t s = 0; s < t.max_nodes; ++s) {
+                // the loads above and below complete together at these empty statements
+                // (the compiler would otherwise issue the later ones only after the axis
+                // came back)
+#pragma unroll
+                for (int r = 0; r < kLocPer; ++r)
+                    asm volatile("" ::"v"(ax[r]), "v"(lf[r]), "v"(sp[r]), "v"(lv[r]));
+                bool more = false;
+#pragma unroll
+                for (int r = 0; r < kLocPer; ++r) {
+                    if (ax[r] >= 0) {
+                        const float pa = ax[r] == 0 ? q0[r] : (ax[r] == 1 ? q1[r] : q2[r]);
+                        n[r] = (double)pa < sp[r] ? lf[r] : lf[r] + 1;
+                        ax[r] = t.axis[n[r]];
+                        lf[r] = t.left[n[r]];
+                        sp[r] = t.split[n[r]];
+                        lv[r] = t.leaf[n[r]];
+                        more = true;
+                    }
+                }
+                if (!more) break;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kLocPer; ++r) {
+            const int64_t i = base + r * kLocThreads;
+            if (i >= N) continue;
+            if (FromRoot || n[r] != n0[r]) node_of[i] = n[r];
+            leaf_of[i] = lv[r];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -705,17 +859,18 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
     if ((rc = check(hipMemcpyAsync(counts, tree->counts, sizeof(counts), hipMemcpyDeviceToHost, s)))) return rc;
     if ((rc = check(hipStreamSynchronize(s)))) return rc;
     int32_t L = counts[1];
-    if (L < 1 || L > tree->max_leaves || counts[0] > tree->max_nodes) return SDMM_EINVAL;
+    if (L < 1 || L > tree->max_leaves || counts[0] < 1 || counts[0] > tree->max_nodes) return SDMM_EINVAL;
     set_active_kernel<<<blocks_for(L, 256), 256, 0, s>>>(act, L, ctl);
 
     const int32_t* sorted_vals = v0;
+    const unsigned loc_groups = std::min<unsigned>(blocks_for(N, kLocTile), kLocMaxGroups);
     for (int round = 0;; ++round) {
         // locate, sort by leaf, segments
         if (round == 0) {  // the full location of every sample from the root is timed
             ScopedTimer tm(SDMM_TIMER_TREE, s);
-            locate_kernel<<<blocks_for(N, 256), 256, 0, s>>>(tp, samples, N, 1, nodeof, k0);
+            locate_kernel<true><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
         } else {
-            locate_kernel<<<blocks_for(N, 256), 256, 0, s>>>(tp, samples, N, 0, nodeof, k0);
+            locate_kernel<false><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
         }
         int bits = 1;
         while ((int64_t(1) << bits) < L) ++bits;

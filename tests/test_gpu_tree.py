@@ -136,6 +136,53 @@ def test_tree_refine_twice_matches_the_oracle(dev, orc):
     _assert_refine_equal(t_gpu, t_orc, (srt_g, off_g, L, status_g, gm, gst), (srt_o, off_o, status_o, mix, st))
 
 
+def test_refine_of_a_tree_deeper_than_the_staged_top(dev, orc):
+    """Walks that leave the work group's LDS copy of the oldest 1024 nodes and go on in
+    global memory: a first refinement grows the tree to about 4900 nodes, and a second
+    iteration's samples are located from the root through both parts (and split a few
+    leaves further, with a ragged last tile)."""
+    print("case: refine 400000 samples (c = 250), then 300001 more from the root (c = 150)", flush=True)
+    from paper_2111_13094_amd import sdmm
+    t_gpu, t_orc, g, o = _refine_both(dev, orc, _samples(400000, 11), 250, 4096)
+    assert t_orc.n_nodes > 4 * 1024
+    _assert_refine_equal(t_gpu, t_orc, g, o)
+    smp2 = _samples(300001, 12)
+    mix, st = o[3], o[4]
+    gm, gst = g[4], g[5]
+    srt_g, off_g, L, status_g = sdmm.tree_refine(t_gpu, dev.from_numpy(smp2).cuda(), 150, gm, gst, K)
+    n_before = t_orc.n_nodes
+    status_o, srt_o, off_o = orc.tree_refine(t_orc, smp2, 150, K, mix, st)
+    assert t_orc.n_nodes > n_before
+    _assert_refine_equal(t_gpu, t_orc, (srt_g, off_g, L, status_g, gm, gst), (srt_o, off_o, status_o, mix, st))
+
+
+def test_locate_on_and_beside_split_planes(dev, orc):
+    """Positions on a split plane and one FP32 step to either side of it, against FP64
+    splits on an FP32 value, one FP64 step to either side of that value, halfway to the
+    next FP32 value, and on it: every sample must take the FP64 comparison's branch (the
+    threshold is never reached, so only the location, the reordering and the leaf
+    initialisation run)."""
+    print("case: 60000 samples on and beside the split planes of a depth-2 tree", flush=True)
+    t_orc = orc.tree_init(64, 2, [0, 0, 0], [1, 1, 1])
+    rng = np.random.default_rng(13)
+    inner = np.flatnonzero(t_orc.axis[:t_orc.n_nodes] >= 0)
+    mid = t_orc.split[inner]
+    assert np.array_equal(mid, mid.astype(np.float32))
+    up32 = np.nextafter(mid.astype(np.float32), np.float32(2)).astype(np.float64)
+    choice = np.stack([mid, np.nextafter(mid, 2.0), np.nextafter(mid, -1.0), 0.5 * (mid + up32), up32])
+    t_orc.split[inner] = choice[rng.integers(0, 5, inner.size), np.arange(inner.size)]
+    n = 60000
+    base = np.array([0.25, 0.5, 0.75], dtype=np.float32)[rng.integers(0, 3, (3, n))]
+    step = rng.integers(-1, 2, (3, n))
+    pos = np.where(step > 0, np.nextafter(base, np.float32(2)),
+                   np.where(step < 0, np.nextafter(base, np.float32(-1)), base))
+    smp = _samples(n, 14)
+    smp[3:6] = pos
+    t_gpu, t_orc, g, o = _refine_both(dev, orc, smp, 1 << 30, 64, t_orc=t_orc)
+    assert t_orc.n_leaves == 64
+    _assert_refine_equal(t_gpu, t_orc, g, o)
+
+
 def test_tree_capacity_constant_positions_and_empty_input(dev, orc):
     print("case: capacity 70 leaves; constant positions; no samples", flush=True)
     t_gpu, t_orc, g, o = _refine_both(dev, orc, _samples(120000, 7), 1000, 70)
