@@ -23,7 +23,7 @@
 namespace sdmm {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;                       // keys per thread per block
+constexpr int kSortItems = 16;                      // keys per thread per block
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
 constexpr int kRadixBits = 8, kRadix = 1 << kRadixBits;
 constexpr int kMaxRounds = 64;
@@ -87,24 +87,25 @@ __global__ void tree_init_kernel(TreePtrs t, int levels, double lo0, double lo1,
 // point location: left where p[axis] < split, else right; child indices exceed their
 // parent's, so a walk ends within max_nodes steps. The oldest nodes, the top of the tree,
 // are staged in LDS by every work group (one 8-byte entry per node, indices below
-// kLocStaged), so the upper levels of a walk cost one LDS read each; below them a node's
-// axis, split, left child and leaf index are loaded from global memory together (one
-// memory round trip per level). Each thread walks kLocPer samples side by side, so their
-// reads overlap, and issues the next tile's first loads before it walks the current one.
-// After the first round a sample resumes from the node it reached in the previous round
-// (node_of), which is still its leaf unless that leaf was split: its position is read
-// only when it has to move, and its node index is written only when it changes.
+// kLocStaged: the whole tree while it has no more nodes than that), so a walk costs one
+// LDS read per level there; below them a node's axis, split, left child and leaf index
+// are loaded from global memory together (one memory round trip per level). Each thread
+// walks kLocPer samples side by side, so their reads overlap, and issues the next tile's
+// first loads before it walks the current one. After the first round a sample resumes
+// from the node it reached in the previous round (node_of), which is still its leaf
+// unless that leaf was split: its position is read only when it has to move, and its
+// node index is written only when it changes.
 //
 // A staged entry holds the split rounded up to FP32: for an FP32 coordinate p and an FP64
 // split s, p < s exactly when p < f, f the least FP32 value not below s (every FP32 value
 // below s is at most the greatest one below f), so the walk takes the FP64 comparison's
 // branch with an FP32 comparison.
 // ---------------------------------------------------------------------------------
-constexpr int kLocThreads = 256;
+constexpr int kLocThreads = 512;
 constexpr int kLocPer = 4;                       // samples per thread per tile
 constexpr int kLocTile = kLocThreads * kLocPer;  // samples per work group per tile
-constexpr int kLocStaged = 1024;                 // nodes staged in LDS
-constexpr int kLocMaxGroups = 256 * 8;           // 8 work groups per CU
+constexpr int kLocStaged = 4096;                 // nodes staged in LDS (32 KB)
+constexpr int kLocMaxGroups = 256 * 4;           // 4 work groups per CU
 constexpr int32_t kUnstaged = INT32_MIN;         // an inner node whose child index does not fit the code
 
 struct alignas(8) StagedNode {
@@ -148,10 +149,12 @@ __global__ __launch_bounds__(kLocThreads) void locate_kernel(TreePtrs t, const f
     const int32_t ns = max(1, min(min(t.counts[0], t.max_nodes), kLocStaged));
     {
         constexpr int kPer = kLocStaged / kLocThreads;
+        const int jn = (ns + kLocThreads - 1) / kLocThreads;  // the same in every lane
         int32_t ax[kPer], lf[kPer], lv[kPer];
         double sp[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {  // all loads first, then the LDS writes
+            if (j >= jn) break;
             const int k = min(j * kLocThreads + (int)threadIdx.x, ns - 1);
             ax[j] = t.axis[k];
             lf[j] = t.left[k];
@@ -160,6 +163,7 @@ __global__ __launch_bounds__(kLocThreads) void locate_kernel(TreePtrs t, const f
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
+            if (j >= jn) break;
             const int k = j * kLocThreads + (int)threadIdx.x;
             const int32_t code = ax[j] < 0 ? -lv[j] - 1 : (lf[j] < (1 << 29) ? 4 * lf[j] + ax[j] : kUnstaged);
             if (k < ns) top[k] = StagedNode{round_up_f32(sp[j]), code};
@@ -481,17 +485,21 @@ __global__ void segment_kernel(const int32_t* __restrict__ keys, int64_t N, int3
 }
 
 // ---------------------------------------------------------------------------------
-// split statistics: one work group of 256 threads per leaf of the round with more than c
-// samples; FP64 sums reduced in a fixed order (lanes by butterfly, then the four waves)
+// split statistics: one work group of kStatThreads per leaf of the round with more than c
+// samples (16 waves, so that the few large leaves of the first rounds keep enough loads in
+// flight); FP64 sums reduced in a fixed order (lanes by butterfly, then the waves in order)
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void split_stats_kernel(const float* __restrict__ smp, int64_t N,
+constexpr int kStatThreads = 1024;
+
+__global__ __launch_bounds__(kStatThreads) void split_stats_kernel(const float* __restrict__ smp, int64_t N,
                                                           const int32_t* __restrict__ perm,
                                                           const int64_t* __restrict__ off, int32_t L, int32_t c,
                                                           const int32_t* __restrict__ act, int32_t* __restrict__ want,
                                                           int32_t* __restrict__ sax, double* __restrict__ spos)
 {
-    __shared__ double ls1[4][3], lsq[4][3];
-    __shared__ float lmn[4][3], lmx[4][3];
+    constexpr int W = kStatThreads / 64;
+    __shared__ double ls1[W][3], lsq[W][3];
+    __shared__ float lmn[W][3], lmx[W][3];
     const int l = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (l >= L) return;
@@ -506,21 +514,24 @@ __global__ __launch_bounds__(256) void split_stats_kernel(const float* __restric
     // samples are loaded together (indices clamped into the leaf, so every load is in
     // bounds) and then added in the thread's sample order
     constexpr int U = 4;
-    for (int64_t j0 = a + threadIdx.x; j0 < b; j0 += U * 256) {
-        int32_t idx[U];
+    int32_t idx[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = j0 + u * 256;
-            idx[u] = perm[j < b ? j : b - 1];
-        }
+    for (int u = 0; u < U; ++u) idx[u] = perm[min(a + threadIdx.x + u * kStatThreads, b - 1)];
+    for (int64_t j0 = a + threadIdx.x; j0 < b; j0 += U * kStatThreads) {
         float xs[U][3];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int d = 0; d < 3; ++d) xs[u][d] = smp[(3 + d) * N + idx[u]];
+        // the next step's indices are on their way while these positions are added
+        const int64_t jn = j0 + U * kStatThreads;
+        if (jn < b) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) idx[u] = perm[min(jn + u * kStatThreads, b - 1)];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (j0 + u * 256 >= b) break;
+            if (j0 + u * kStatThreads >= b) break;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float xf = xs[u][d];
@@ -551,11 +562,17 @@ __global__ __launch_bounds__(256) void split_stats_kernel(const float* __restric
         }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int d = 0; d < 3; ++d) {
-            s1[d] = ((ls1[0][d] + ls1[1][d]) + ls1[2][d]) + ls1[3][d];
-            sq[d] = ((lsq[0][d] + lsq[1][d]) + lsq[2][d]) + lsq[3][d];
-            mn[d] = fminf(fminf(lmn[0][d], lmn[1][d]), fminf(lmn[2][d], lmn[3][d]));
-            mx[d] = fmaxf(fmaxf(lmx[0][d], lmx[1][d]), fmaxf(lmx[2][d], lmx[3][d]));
+        for (int d = 0; d < 3; ++d) {  // the waves' results in wave order
+            s1[d] = ls1[0][d];
+            sq[d] = lsq[0][d];
+            mn[d] = lmn[0][d];
+            mx[d] = lmx[0][d];
+            for (int q = 1; q < W; ++q) {
+                s1[d] += ls1[q][d];
+                sq[d] += lsq[q][d];
+                mn[d] = fminf(mn[d], lmn[q][d]);
+                mx[d] = fmaxf(mx[d], lmx[q][d]);
+            }
         }
         const double Md = (double)M;
         int ax = 0;
@@ -855,8 +872,17 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
     const int K = mix->K;
     int rc;
 
-    int32_t counts[2];
-    if ((rc = check(hipMemcpyAsync(counts, tree->counts, sizeof(counts), hipMemcpyDeviceToHost, s)))) return rc;
+    // the words read back once per round land in pinned memory (a pageable destination
+    // would be staged by the runtime), one buffer per host thread, kept for its lifetime
+    thread_local int32_t* pinned = nullptr;
+    if (!pinned && (rc = check(hipHostMalloc((void**)&pinned, 4 * sizeof(int32_t), hipHostMallocPortable)))) {
+        pinned = nullptr;
+        return rc;
+    }
+    int32_t* counts = pinned;
+    int32_t* c2 = pinned + 2;
+    if ((rc = check(hipMemcpyAsync(counts, tree->counts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s))))
+        return rc;
     if ((rc = check(hipStreamSynchronize(s)))) return rc;
     int32_t L = counts[1];
     if (L < 1 || L > tree->max_leaves || counts[0] < 1 || counts[0] > tree->max_nodes) return SDMM_EINVAL;
@@ -894,10 +920,9 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
         segment_kernel<<<blocks_for(std::max<int64_t>(N, (int64_t)L + 1), 256), 256, 0, s>>>(kin, N, L, off);
         if (round == kMaxRounds) break;
         // statistics and decisions
-        split_stats_kernel<<<L, 256, 0, s>>>(samples, N, vin, off, L, split_threshold, act, want, sax, spos);
+        split_stats_kernel<<<L, kStatThreads, 0, s>>>(samples, N, vin, off, L, split_threshold, act, want, sax, spos);
         split_decide_kernel<<<1, 1024, 0, s>>>(tp, L, want, sax, spos, act, parent, ctl);
-        int32_t c2[2];
-        if ((rc = check(hipMemcpyAsync(c2, ctl, sizeof(c2), hipMemcpyDeviceToHost, s)))) return rc;
+        if ((rc = check(hipMemcpyAsync(c2, ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s)))) return rc;
         if ((rc = check(hipStreamSynchronize(s)))) return rc;
         if (c2[0] == 0) break;
         copy_leaves_kernel<<<c2[0], 64, 0, s>>>(L, c2[0], parent, K, mp, sp);
@@ -907,8 +932,7 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
     if ((rc = check(hipMemcpyAsync(cell_offsets_out, off, ((size_t)L + 1) * 8, hipMemcpyDeviceToDevice, s))))
         return rc;
     init_leaves_kernel<<<L, 64, 0, s>>>(tp, L, off, min_init, K, mp, sp);
-    int32_t c2[2];
-    if ((rc = check(hipMemcpyAsync(c2, ctl, sizeof(c2), hipMemcpyDeviceToHost, s)))) return rc;
+    if ((rc = check(hipMemcpyAsync(c2, ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s)))) return rc;
     if ((rc = check(hipStreamSynchronize(s)))) return rc;
     *n_leaves_out = L;
     if (status_out) *status_out = c2[1];

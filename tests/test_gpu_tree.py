@@ -137,21 +137,21 @@ def test_tree_refine_twice_matches_the_oracle(dev, orc):
 
 
 def test_refine_of_a_tree_deeper_than_the_staged_top(dev, orc):
-    """Walks that leave the work group's LDS copy of the oldest 1024 nodes and go on in
-    global memory: a first refinement grows the tree to about 4900 nodes, and a second
-    iteration's samples are located from the root through both parts (and split a few
-    leaves further, with a ragged last tile)."""
-    print("case: refine 400000 samples (c = 250), then 300001 more from the root (c = 150)", flush=True)
+    """Walks that leave the work group's LDS copy of the oldest 4096 nodes and go on in
+    global memory: a first refinement grows the tree to about 7700 nodes, and a second
+    iteration's samples are located from the root through both parts (and split further,
+    with a ragged last tile)."""
+    print("case: refine 400000 samples (c = 150), then 300001 more from the root (c = 90)", flush=True)
     from paper_2111_13094_amd import sdmm
-    t_gpu, t_orc, g, o = _refine_both(dev, orc, _samples(400000, 11), 250, 4096)
-    assert t_orc.n_nodes > 4 * 1024
+    t_gpu, t_orc, g, o = _refine_both(dev, orc, _samples(400000, 11), 150, 8192)
+    assert t_orc.n_nodes > 7000
     _assert_refine_equal(t_gpu, t_orc, g, o)
     smp2 = _samples(300001, 12)
     mix, st = o[3], o[4]
     gm, gst = g[4], g[5]
-    srt_g, off_g, L, status_g = sdmm.tree_refine(t_gpu, dev.from_numpy(smp2).cuda(), 150, gm, gst, K)
+    srt_g, off_g, L, status_g = sdmm.tree_refine(t_gpu, dev.from_numpy(smp2).cuda(), 90, gm, gst, K)
     n_before = t_orc.n_nodes
-    status_o, srt_o, off_o = orc.tree_refine(t_orc, smp2, 150, K, mix, st)
+    status_o, srt_o, off_o = orc.tree_refine(t_orc, smp2, 90, K, mix, st)
     assert t_orc.n_nodes > n_before
     _assert_refine_equal(t_gpu, t_orc, (srt_g, off_g, L, status_g, gm, gst), (srt_o, off_o, status_o, mix, st))
 
