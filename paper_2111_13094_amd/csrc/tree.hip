@@ -291,6 +291,23 @@ __global__ __launch_bounds__(kLocThreads) void locate_kernel(TreePtrs t, const f
 // ---------------------------------------------------------------------------------
 // stable LSD radix sort of (leaf index, sample index) by leaf index, 8 bits per pass
 // ---------------------------------------------------------------------------------
+// the valid lanes of the wave whose digit equals this lane's (meaningful for valid lanes):
+// one comparison when every valid lane holds the same digit, as in runs of samples of one
+// leaf, else one ballot per digit bit
+__device__ __forceinline__ uint64_t digit_peers(int digit, bool valid)
+{
+    const uint64_t vm = __ballot(valid);
+    const int d0 = __builtin_amdgcn_readfirstlane(digit);
+    if (__all(!valid || digit == d0)) return vm;
+    uint64_t peers = vm;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint64_t m = __ballot((digit >> b) & 1);
+        peers &= ((digit >> b) & 1) ? m : ~m;
+    }
+    return peers;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const int32_t* __restrict__ keys, int64_t N,
                                                                   int shift, int32_t* __restrict__ hist, int B)
 {
@@ -314,12 +331,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const int32_t*
         const int64_t i = base + (int64_t)it * kSortThreads + threadIdx.x;
         const bool valid = i < N;
         const int digit = valid ? (kv[it] >> shift) & (kRadix - 1) : 0;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const uint64_t m = __ballot((digit >> b) & 1);
-            peers &= ((digit >> b) & 1) ? m : ~m;
-        }
+        const uint64_t peers = digit_peers(digit, valid);
         if (valid && (peers & lt) == 0) atomicAdd(&h[digit], __popcll(peers));
     }
     __syncthreads();
@@ -442,12 +454,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const int32
         const int32_t key = kv[it];
         const int32_t val = vv[it];
         const int digit = (key >> shift) & (kRadix - 1);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const uint64_t m = __ballot((digit >> b) & 1);
-            peers &= ((digit >> b) & 1) ? m : ~m;
-        }
+        const uint64_t peers = digit_peers(digit, valid);
         const int rank = __popcll(peers & lt);
         if (valid && rank == 0) wcount[w][digit] = __popcll(peers);
         __syncthreads();
