@@ -476,6 +476,89 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const int32
     }
 }
 
+// ---------------------------------------------------------------------------------
+// the order by leaf after a round's splits follows from the previous round's: a sample
+// stays in its leaf, or goes to the left child, which keeps the parent's leaf index, or to
+// the right child, whose index is at least the previous leaf count and grows with the
+// parent's. So the samples now below that count keep their relative order, and the others
+// follow them in theirs: a stable partition of the previous permutation (two launches and
+// a one-group scan of the tiles' counts) takes the place of the radix sort.
+// ---------------------------------------------------------------------------------
+
+// cnt[b] = the samples of tile b (in the previous order) now in a leaf >= L_old; cnt[B] = 0
+__global__ __launch_bounds__(kSortThreads) void part_count_kernel(const int32_t* __restrict__ perm,
+                                                                  const int32_t* __restrict__ leaf_of, int64_t N,
+                                                                  int32_t L_old, int32_t* __restrict__ cnt, int B)
+{
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    int32_t pv[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + threadIdx.x;
+        pv[it] = perm[min(i, N - 1)];
+    }
+    int32_t c = 0;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + threadIdx.x;
+        c += (i < N && leaf_of[pv[it]] >= L_old) ? 1 : 0;
+    }
+    int32_t total;
+    (void)block_exclusive_scan_256(c, total);
+    if (threadIdx.x == 0) {
+        cnt[blockIdx.x] = total;
+        if (blockIdx.x == 0) cnt[B] = 0;
+    }
+}
+
+// after the exclusive scan of cnt (cnt[B] = all such samples): position j of the previous
+// order goes to j - t_j, or to N - cnt[B] + t_j if its new leaf is >= L_old, t_j being the
+// number of such samples before j
+__global__ __launch_bounds__(kSortThreads) void part_scatter_kernel(const int32_t* __restrict__ perm,
+                                                                    const int32_t* __restrict__ leaf_of, int64_t N,
+                                                                    int32_t L_old, const int32_t* __restrict__ cnt,
+                                                                    int B, int32_t* __restrict__ kout,
+                                                                    int32_t* __restrict__ vout)
+{
+    constexpr int W = kSortThreads / 64;
+    __shared__ int32_t wt[W];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    const int64_t first_up = N - (int64_t)cnt[B];
+    int32_t pv[kSortItems], kv[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + threadIdx.x;
+        pv[it] = perm[min(i, N - 1)];
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) kv[it] = leaf_of[pv[it]];
+    int64_t run = cnt[blockIdx.x];  // such samples before the current step
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile + (int64_t)it * kSortThreads + threadIdx.x;
+        const bool valid = i < N, up = valid && kv[it] >= L_old;
+        const uint64_t m = __ballot(up);
+        if (lane == 0) wt[w] = __popcll(m);
+        __syncthreads();
+        int64_t tj = run + __popcll(m & lt);
+        int32_t all = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            tj += q < w ? wt[q] : 0;
+            all += wt[q];
+        }
+        if (valid) {
+            const int64_t dst = up ? first_up + tj : i - tj;
+            kout[dst] = kv[it];
+            vout[dst] = pv[it];
+        }
+        run += all;
+        __syncthreads();
+    }
+}
+
 // off[l] = first sorted position of leaf l (off[L] = N), for leaves 0..L
 __global__ void segment_kernel(const int32_t* __restrict__ keys, int64_t N, int32_t L, int64_t* __restrict__ off)
 {
@@ -897,33 +980,46 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
 
     const int32_t* sorted_vals = v0;
     const unsigned loc_groups = std::min<unsigned>(blocks_for(N, kLocTile), kLocMaxGroups);
+    int32_t L_old = L;  // the leaf count before the last round's splits
+    const int32_t *kin = k0, *vin = nullptr;
     for (int round = 0;; ++round) {
-        // locate, sort by leaf, segments
+        // locate, order by leaf, segments
         if (round == 0) {  // the full location of every sample from the root is timed
             ScopedTimer tm(SDMM_TIMER_TREE, s);
             locate_kernel<true><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
         } else {
             locate_kernel<false><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
         }
-        int bits = 1;
-        while ((int64_t(1) << bits) < L) ++bits;
-        const int passes = (bits + kRadixBits - 1) / kRadixBits;
-        const int32_t *kin = k0, *vin = nullptr;
-        int32_t *kout = k1, *vout = v1;
-        for (int p = 0; p < passes && N > 0; ++p) {
-            radix_hist_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, N, p * kRadixBits, hist, TL.B);
-            const int64_t nh = (int64_t)kRadix * TL.B;
-            const unsigned nt = (unsigned)((nh + kScanTile - 1) / kScanTile);
-            scan_tile_sums_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
-            scan_sums_kernel<<<1, 1024, 0, s>>>(tsum, nt);
-            scan_apply_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
-            radix_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, vin, N, p * kRadixBits, hist, TL.B, kout, vout);
-            kin = kout;
+        if (round == 0) {  // a stable LSD radix sort from the sample order
+            int bits = 1;
+            while ((int64_t(1) << bits) < L) ++bits;
+            const int passes = (bits + kRadixBits - 1) / kRadixBits;
+            kin = k0;
+            vin = nullptr;
+            int32_t *kout = k1, *vout = v1;
+            for (int p = 0; p < passes && N > 0; ++p) {
+                radix_hist_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, N, p * kRadixBits, hist, TL.B);
+                const int64_t nh = (int64_t)kRadix * TL.B;
+                const unsigned nt = (unsigned)((nh + kScanTile - 1) / kScanTile);
+                scan_tile_sums_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+                scan_sums_kernel<<<1, 1024, 0, s>>>(tsum, nt);
+                scan_apply_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+                radix_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, vin, N, p * kRadixBits, hist, TL.B, kout,
+                                                                    vout);
+                kin = kout;
+                vin = vout;
+                kout = (kout == k1) ? k0 : k1;
+                vout = (vout == v1) ? v0 : v1;
+            }
+        } else if (N > 0) {  // a stable partition of the previous order (k0 holds the new leaves)
+            int32_t* vout = (vin == v0) ? v1 : v0;
+            part_count_kernel<<<TL.B, kSortThreads, 0, s>>>(vin, k0, N, L_old, hist, TL.B);
+            scan_sums_kernel<<<1, 1024, 0, s>>>(hist, (int64_t)TL.B + 1);
+            part_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(vin, k0, N, L_old, hist, TL.B, k1, vout);
+            kin = k1;
             vin = vout;
-            kout = (kout == k1) ? k0 : k1;
-            vout = (vout == v1) ? v0 : v1;
         }
-        sorted_vals = vin;
+        sorted_vals = N > 0 ? vin : v0;
         segment_kernel<<<blocks_for(std::max<int64_t>(N, (int64_t)L + 1), 256), 256, 0, s>>>(kin, N, L, off);
         if (round == kMaxRounds) break;
         // statistics and decisions
@@ -933,6 +1029,7 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
         if ((rc = check(hipStreamSynchronize(s)))) return rc;
         if (c2[0] == 0) break;
         copy_leaves_kernel<<<c2[0], 64, 0, s>>>(L, c2[0], parent, K, mp, sp);
+        L_old = L;
         L += c2[0];
     }
     if (N > 0) gather_kernel<<<blocks_for(N, 256), 256, 0, s>>>(samples, N, sorted_vals, sorted_out);
