@@ -337,7 +337,10 @@ size_t sdmm_tree_workspace_size(int64_t n_samples, int32_t max_leaves);
  * index order within a leaf; cell_offsets_out [device] int64[max_leaves + 1], of which
  * the first n_leaves + 1 entries are written; n_leaves_out, status_out [host] int32
  * (status_out may be NULL). The call synchronises the stream once per round. Means and
- * variances are FP64 sums over each leaf's samples.
+ * variances are FP64 sums over each leaf's samples. SDMM_EINVAL for bad arguments, or
+ * when the tree's counts (read from the device) are out of range, in which case only the
+ * workspace has been written. The call keeps one pinned 16-byte host buffer per host
+ * thread for the counts it reads back.
  */
 int sdmm_tree_refine(const sdmm_tree *tree, const float *samples, int64_t n_samples, int32_t split_threshold,
                      int32_t min_init, const sdmm_mixtures *mix, const sdmm_em_state *state,

@@ -774,10 +774,11 @@ __global__ void copy_leaves_kernel(int32_t leaves_before, int32_t n_split, const
     }
 }
 
-__global__ void set_active_kernel(int32_t* __restrict__ act, int32_t L, int32_t* __restrict__ ctl)
+__global__ void set_active_kernel(int32_t* __restrict__ act, const int32_t* __restrict__ counts, int32_t max_leaves,
+                                  int32_t* __restrict__ ctl)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < L) act[l] = 1;
+    if (l < min(counts[1], max_leaves)) act[l] = 1;
     if (l == 0) ctl[0] = ctl[1] = 0;
 }
 
@@ -971,53 +972,59 @@ extern "C" int sdmm_tree_refine(const sdmm_tree* tree, const float* samples, int
     }
     int32_t* counts = pinned;
     int32_t* c2 = pinned + 2;
+
+    // what needs no leaf count on the host is queued ahead of its readback, so that the GPU
+    // works while the host waits: the location of every sample from the root, the active
+    // flags (from the count on the device) and the first pass of the radix sort. Only the
+    // workspace is written before the tree's counts are checked.
+    const unsigned loc_groups = std::min<unsigned>(blocks_for(N, kLocTile), kLocMaxGroups);
+    {  // the full location of every sample from the root is timed
+        ScopedTimer tm(SDMM_TIMER_TREE, s);
+        locate_kernel<true><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
+    }
+    set_active_kernel<<<blocks_for(tree->max_leaves, 256), 256, 0, s>>>(act, tree->counts, tree->max_leaves, ctl);
+    // the first round's stable LSD radix sort from the sample order, 8 bits per pass
+    const int32_t *kin = k0, *vin = nullptr;
+    int32_t *kout = k1, *vout = v1;
+    auto sort_pass = [&](int p) {
+        radix_hist_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, N, p * kRadixBits, hist, TL.B);
+        const int64_t nh = (int64_t)kRadix * TL.B;
+        const unsigned nt = (unsigned)((nh + kScanTile - 1) / kScanTile);
+        scan_tile_sums_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+        scan_sums_kernel<<<1, 1024, 0, s>>>(tsum, nt);
+        scan_apply_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
+        radix_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, vin, N, p * kRadixBits, hist, TL.B, kout, vout);
+        kin = kout;
+        vin = vout;
+        kout = (kout == k1) ? k0 : k1;
+        vout = (vout == v1) ? v0 : v1;
+    };
+    if (N > 0) sort_pass(0);
     if ((rc = check(hipMemcpyAsync(counts, tree->counts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s))))
         return rc;
     if ((rc = check(hipStreamSynchronize(s)))) return rc;
     int32_t L = counts[1];
     if (L < 1 || L > tree->max_leaves || counts[0] < 1 || counts[0] > tree->max_nodes) return SDMM_EINVAL;
-    set_active_kernel<<<blocks_for(L, 256), 256, 0, s>>>(act, L, ctl);
+    {
+        int bits = 1;
+        while ((int64_t(1) << bits) < L) ++bits;
+        const int passes = (bits + kRadixBits - 1) / kRadixBits;
+        for (int p = 1; p < passes && N > 0; ++p) sort_pass(p);
+    }
 
     const int32_t* sorted_vals = v0;
-    const unsigned loc_groups = std::min<unsigned>(blocks_for(N, kLocTile), kLocMaxGroups);
     int32_t L_old = L;  // the leaf count before the last round's splits
-    const int32_t *kin = k0, *vin = nullptr;
     for (int round = 0;; ++round) {
-        // locate, order by leaf, segments
-        if (round == 0) {  // the full location of every sample from the root is timed
-            ScopedTimer tm(SDMM_TIMER_TREE, s);
-            locate_kernel<true><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
-        } else {
+        if (round > 0 && N > 0) {
+            // locate from the nodes reached before, then a stable partition of the
+            // previous order (k0 holds the new leaves)
             locate_kernel<false><<<loc_groups, kLocThreads, 0, s>>>(tp, samples, N, nodeof, k0);
-        }
-        if (round == 0) {  // a stable LSD radix sort from the sample order
-            int bits = 1;
-            while ((int64_t(1) << bits) < L) ++bits;
-            const int passes = (bits + kRadixBits - 1) / kRadixBits;
-            kin = k0;
-            vin = nullptr;
-            int32_t *kout = k1, *vout = v1;
-            for (int p = 0; p < passes && N > 0; ++p) {
-                radix_hist_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, N, p * kRadixBits, hist, TL.B);
-                const int64_t nh = (int64_t)kRadix * TL.B;
-                const unsigned nt = (unsigned)((nh + kScanTile - 1) / kScanTile);
-                scan_tile_sums_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
-                scan_sums_kernel<<<1, 1024, 0, s>>>(tsum, nt);
-                scan_apply_kernel<<<nt, 256, 0, s>>>(hist, nh, tsum);
-                radix_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(kin, vin, N, p * kRadixBits, hist, TL.B, kout,
-                                                                    vout);
-                kin = kout;
-                vin = vout;
-                kout = (kout == k1) ? k0 : k1;
-                vout = (vout == v1) ? v0 : v1;
-            }
-        } else if (N > 0) {  // a stable partition of the previous order (k0 holds the new leaves)
-            int32_t* vout = (vin == v0) ? v1 : v0;
+            int32_t* pout = (vin == v0) ? v1 : v0;
             part_count_kernel<<<TL.B, kSortThreads, 0, s>>>(vin, k0, N, L_old, hist, TL.B);
             scan_sums_kernel<<<1, 1024, 0, s>>>(hist, (int64_t)TL.B + 1);
-            part_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(vin, k0, N, L_old, hist, TL.B, k1, vout);
+            part_scatter_kernel<<<TL.B, kSortThreads, 0, s>>>(vin, k0, N, L_old, hist, TL.B, k1, pout);
             kin = k1;
-            vin = vout;
+            vin = pout;
         }
         sorted_vals = N > 0 ? vin : v0;
         segment_kernel<<<blocks_for(std::max<int64_t>(N, (int64_t)L + 1), 256), 256, 0, s>>>(kin, N, L, off);
