@@ -183,6 +183,31 @@ def test_locate_on_and_beside_split_planes(dev, orc):
     _assert_refine_equal(t_gpu, t_orc, g, o)
 
 
+def test_refine_rejects_a_tree_with_counts_out_of_range(dev, orc):
+    """The counts are read from the device after the first round's location and sort pass
+    are queued: a tree whose counts are out of range is rejected with SDMM_EINVAL and left
+    as it was, and the same tree refines normally once its counts are restored."""
+    print("case: refine with leaf count 0, then node count above capacity, then restored", flush=True)
+    from paper_2111_13094_amd import sdmm
+    t_orc = orc.tree_init(64, 1, [0, 0, 0], [1, 1, 1])
+    t_gpu = _gpu_tree(dev, t_orc)
+    mix, st = _store(64)
+    gm, gst = to_torch(mix), state_to_torch(st)
+    smp = dev.from_numpy(_samples(20000, 15)).cuda()
+    before = {k: v.clone() for k, v in t_gpu.items() if hasattr(v, "clone")}
+    for bad in ([t_orc.n_nodes, 0], [t_gpu["max_nodes"] + 1, t_orc.n_leaves]):
+        t_gpu["counts"].copy_(dev.tensor(bad, dtype=dev.int32))
+        with pytest.raises(RuntimeError, match="sdmm_tree_refine"):
+            sdmm.tree_refine(t_gpu, smp, 500, gm, gst, K)
+        for k, v in before.items():
+            if k != "counts":
+                assert dev.equal(t_gpu[k], v), k
+    t_gpu["counts"].copy_(before["counts"])
+    srt_g, off_g, L, status_g = sdmm.tree_refine(t_gpu, smp, 500, gm, gst, K)
+    status_o, srt_o, off_o = orc.tree_refine(t_orc, smp.cpu().numpy(), 500, K, mix, st)
+    _assert_refine_equal(t_gpu, t_orc, (srt_g, off_g, L, status_g, gm, gst), (srt_o, off_o, status_o, mix, st))
+
+
 def test_tree_capacity_constant_positions_and_empty_input(dev, orc):
     print("case: capacity 70 leaves; constant positions; no samples", flush=True)
     t_gpu, t_orc, g, o = _refine_both(dev, orc, _samples(120000, 7), 1000, 70)
