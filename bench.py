@@ -56,11 +56,12 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (published)
 HBM_PEAK_GBS = 8000.0
 
 
-def _kernel_source_hash():
+def _kernel_source_hash(files=("estep.hpp", "device_math.hpp", "fit.hip")):
     """Hash of the code (comment lines and trailing comments dropped) of the sources that
-    build the E-step kernel, so that a counter record names the kernel it was taken on."""
+    build a kernel (by default the E-step's), so that a counter record names the kernel it
+    was taken on."""
     h = hashlib.sha256()
-    for f in ("estep.hpp", "device_math.hpp", "fit.hip"):
+    for f in files:
         for line in open(os.path.join(ROOT, "paper_2111_13094_amd", "csrc", f)):
             code = line.split("//", 1)[0].rstrip()
             if code:
@@ -83,6 +84,29 @@ def _traffic_record(items, waves_per_block):
         if rec.get("items") == items and rec.get("waves_per_block") == waves_per_block:
             return rec.get("bytes_per_launch")
     return None
+
+
+def _tree_traffic_record():
+    """HBM bytes per launch of the first-round point location of the tree workload from
+    the committed counter summary, if it was taken on the current tree source; else None."""
+    path = os.path.join(ROOT, "profiles", "tree_locate_traffic.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != _kernel_source_hash(("tree.hip", "common.hpp")):
+        return None
+    return data.get("bytes_per_launch")
+
+
+def _copy_probe(torch, dev, mib):
+    """A plain device copy of known size, to scale the HBM byte counters of a profiler run."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    _sync(torch)
+    return src.numel() * 4
 
 
 def _estep_kernel_name(items, G=16, adjoint=False):
@@ -352,13 +376,7 @@ def bench_cells4k(args, torch):
         out["cpu_baseline"] = cpu_baseline(wl, batches[0], target_s=args.cpu_seconds)
         out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(wl, batches, target_s=args.cpu_seconds)
     if args.copy_probe:
-        # a plain device copy of known size, to scale the HBM byte counters of a profiler run
-        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        _sync(torch)
-        out["copy_probe_bytes"] = src.numel() * 4
+        out["copy_probe_bytes"] = _copy_probe(torch, dev, args.copy_probe_mib)
     return out
 
 
@@ -653,7 +671,10 @@ def bench_tree(args, torch):
     loc_bytes = 20.0 * N
     achieved = loc_bytes / (loc_ms * 1e-3) / 1e9
     r_ms, f_ms = float(np.mean(refine_ms)), float(np.mean(fit_ms))
-    return {"metric": "kD-tree refinement: samples/s (locate, split rounds, reorder by leaf, initialise), "
+    traffic = _tree_traffic_record()
+    extra = {"copy_probe_bytes": _copy_probe(torch, dev, args.copy_probe_mib)} if args.copy_probe else {}
+    return {**extra,
+            "metric": "kD-tree refinement: samples/s (locate, split rounds, reorder by leaf, initialise), "
                       "16.6M samples, c=16000",
             "value": N / (r_ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": r_ms, "higher_is_better": True, "scaling": "weak",
@@ -663,7 +684,7 @@ def bench_tree(args, torch):
                                    "the host call, which synchronises once per round",
                        "samples": N, "leaves": leaves, "max_leaves": max_leaves, "fit_after_refine_ms": f_ms},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "locate_kernel (first round)",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "locate_kernel (first round)",
                          "kernel_ms": loc_ms, "bytes_per_launch": loc_bytes}}
 
 

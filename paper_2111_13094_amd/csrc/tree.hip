@@ -782,10 +782,19 @@ __global__ void set_active_kernel(int32_t* __restrict__ act, const int32_t* __re
     if (l == 0) ctl[0] = ctl[1] = 0;
 }
 
+// Work groups go to the eight XCDs in turn (group b to XCD b % 8), each XCD with its own
+// L2. The groups of one XCD take consecutive ranges of the output, so that a source line
+// a run of gathered samples only partly covers is fetched into one L2, not into two.
+__device__ __forceinline__ int64_t xcd_block_order(int64_t b, int64_t nb)
+{
+    const int64_t x = b % 8, q = b / 8, per = nb / 8, extra = nb % 8;
+    return x * per + (x < extra ? x : extra) + q;
+}
+
 __global__ void gather_kernel(const float* __restrict__ smp, int64_t N, const int32_t* __restrict__ perm,
                               float* __restrict__ out)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = xcd_block_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int32_t i = perm[j];
 #pragma unroll
