@@ -4,14 +4,15 @@
 // arXiv 2111.13094, Sec. 4.2 "Refinement of the spatial kD-tree", Sec. 4.3
 // "Initialization").
 //
-// Refinement runs in rounds. Each round: every sample is located in the current tree
-// (one thread per sample); a stable LSD radix sort by leaf index gives a permutation
-// with each leaf's samples contiguous and in index order; each leaf of the round with
-// more than c samples gets its FP64 position sums, minima and maxima from one wave
-// (fixed reduction order); one work group decides the splits in leaf order (a block
-// prefix sum numbers the new nodes and leaves); new leaves get copies of their parent's
-// mixture and Robbins-Monro state. The host reads the number of splits after each round
-// and stops when a round makes none; the last round's sort is the final order.
+// Refinement runs in rounds. Each round: every sample is located in the current tree;
+// the samples are ordered by leaf index, each leaf's samples contiguous and in index
+// order (a stable LSD radix sort in the first round, a stable partition of the previous
+// order after it); each leaf of the round with more than c samples gets its FP64 position
+// sums, minima and maxima from one work group (fixed reduction order); one work group
+// decides the splits in leaf order (a block prefix sum numbers the new nodes and leaves);
+// new leaves get copies of their parent's mixture and Robbins-Monro state. The host reads
+// the number of splits after each round and stops when a round makes none; the last
+// round's order is the final one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
