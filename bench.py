@@ -28,10 +28,14 @@ The JSON line also carries:
 
 Other workloads (--workload), each printing its own line: single (1 cell, N = 16384,
 20 iterations, hipGraph), cells16k (16384 cells, geometric counts, then 2^22 query
-positions x 4 draws through the fused conditioning + sampling + pdf kernel), huge
+positions x 4 draws through the fused conditioning + sampling + pdf kernel), product
+(the same queries, product-sampled with a conditioned 16-component BSDF mixture), huge
 (1 cell, 2^24 samples, K = 32, the three running-sum variants), grad (the adjoint on
-the 4096-cell state after 8 batches, plus 10 refinement steps). --sweep times launch
-configurations of the headline workload.
+the 4096-cell state after 8 batches, plus 10 refinement steps), accurate (the two-pass
+covariance update), stepwise (per-sample EM on the 4096-cell batches), tree (kD-tree
+refinement of the cells16k samples; its roofline is the first-round point location,
+with the HBM traffic of the committed counter summary while the tree source is
+unchanged). --sweep times launch configurations of the headline workload.
 """
 from __future__ import annotations
 
